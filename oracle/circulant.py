@@ -1,0 +1,163 @@
+"""T. Chan's optimal circulant and the 2-level block preconditioner (paper Sec. 3).
+
+Test infrastructure only.
+
+Two independent routes are provided so that each pins the other:
+
+* brute force (``two_level_dense``): build the full-box BTTB matrix d^3 G over
+  all 3N box unknowns, replace every l x l Toeplitz block along x by the
+  Frobenius-nearest circulant (average of each wrapped diagonal — the property
+  eq. Chan is derived from), then do the same along y; P = alpha~^{-1} I - C2
+  (Sec. 3.1, the definition of C_B2 with the constant diagonal).
+* formula (``two_level_blocks``): eq. Chan applied to the signed-offset kernel
+  along x then along y, a 2-D DFT over the two circulant levels, and for each
+  of the l*m Fourier modes the dense 3n x 3n block (Toeplitz along z) that the
+  permutation of Sec. 3 exposes; this is Algorithms 2-3 of Sec. 3.1 applied to
+  all six components with their parities handled implicitly by using signed
+  offsets (no first-row / first-column sign bookkeeping).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from .fftmatvec import kernel_signed
+from .physics import COMP6
+
+FULL = np.zeros((3, 3), dtype=int)
+for _c, (_a, _b) in enumerate(COMP6):
+    FULL[_a, _b] = FULL[_b, _a] = _c
+
+
+def chan_column(t_signed):
+    """Eq. Chan: first column of T. Chan's circulant from Toeplitz t_p, p in (-l, l).
+
+    ``t_signed[..., p + l - 1] = t_p`` along the last axis; returns
+    c_p = ((l - p) t_p + p t_{p - l}) / l for p = 0 .. l-1 (last axis).
+    """
+    L2 = t_signed.shape[-1]
+    l = (L2 + 1) // 2
+    p = np.arange(l)
+    pos = t_signed[..., l - 1 + p]
+    neg = np.zeros_like(pos)
+    neg[..., 1:] = t_signed[..., p[1:] - 1]  # t_{p - l} sits at index p - 1
+    return ((l - p) * pos + p * neg) / l
+
+
+def toeplitz_from_signed(t_signed):
+    """Dense Toeplitz T[i, j] = t_{i-j} from t_p, p in (-l, l)."""
+    L2 = t_signed.shape[-1]
+    l = (L2 + 1) // 2
+    i = np.arange(l)
+    return t_signed[(i[:, None] - i[None, :]) + l - 1]
+
+
+def circulant_from_column(c):
+    l = c.shape[-1]
+    i = np.arange(l)
+    return c[(i[:, None] - i[None, :]) % l]
+
+
+def average_wrapped(T, ax_i: int, ax_j: int):
+    """Replace, for every other index, the l x l slice on axes (ax_i, ax_j) by the
+    average over its wrapped diagonals ((i - j) mod l fixed): the Frobenius-nearest
+    circulant of that slice (each wrapped diagonal is one free parameter)."""
+    Tm = np.moveaxis(T, (ax_i, ax_j), (-2, -1))
+    l = Tm.shape[-1]
+    i = np.arange(l)
+    dmat = (i[:, None] - i[None, :]) % l
+    out = np.empty_like(Tm)
+    for dd in range(l):
+        sel = dmat == dd
+        out[..., sel] = Tm[..., sel].mean(axis=-1, keepdims=True)
+    return np.moveaxis(out, (-2, -1), (ax_i, ax_j))
+
+
+def bttb_full(shape, k: float, d: float):
+    """d^3 G between every pair of box voxels: [3][nz][ny][nx][3][nz][ny][nx], zero self term."""
+    nz, ny, nx = shape
+    Ks = kernel_signed(shape, k, d)  # [6][2nz-1][2ny-1][2nx-1]
+    iz, iy, ix = np.arange(nz), np.arange(ny), np.arange(nx)
+    dz = (iz[:, None] - iz[None, :]) + nz - 1
+    dy = (iy[:, None] - iy[None, :]) + ny - 1
+    dx = (ix[:, None] - ix[None, :]) + nx - 1
+    T = np.empty((3, nz, ny, nx, 3, nz, ny, nx), dtype=np.complex128)
+    for a in range(3):
+        for b in range(3):
+            Kc = Ks[FULL[a, b]]
+            blk = Kc[dz[:, None, None, :, None, None], dy[None, :, None, None, :, None],
+                     dx[None, None, :, None, None, :]]
+            T[a, :, :, :, b] = blk
+    return T
+
+
+def two_level_dense(shape, k: float, d: float, alpha_tilde_inv: complex):
+    """Brute-force P = alpha~^{-1} I - C2(d^3 G) over the whole box: (3N x 3N), box order."""
+    nz, ny, nx = shape
+    T = bttb_full(shape, k, d)
+    C1 = average_wrapped(T, 3, 7)  # x level
+    C2 = average_wrapped(C1, 2, 6)  # y level
+    n3 = 3 * nz * ny * nx
+    P = -C2.reshape(n3, n3)
+    P[np.arange(n3), np.arange(n3)] += alpha_tilde_inv
+    return P
+
+
+def two_level_generator(shape, k: float, d: float):
+    """c2_c(qbar, pbar, s): eq. Chan along x then y of the signed kernel.
+
+    Returns complex128 [6][2nz-1][ny][nx] (s index s + nz - 1)."""
+    Ks = kernel_signed(shape, k, d)  # [6][2nz-1][2ny-1][2nx-1]
+    c1 = chan_column(Ks)  # along x -> [6][2nz-1][2ny-1][nx]
+    c2 = chan_column(np.moveaxis(c1, 2, -1))  # along y -> [6][2nz-1][nx][ny]
+    return np.moveaxis(c2, -1, 2)
+
+
+def two_level_blocks(shape, k: float, d: float, alpha_tilde_inv: complex):
+    """Per-mode blocks B(wy, wx) = alpha~^{-1} I - [lambda_ab(w, iz - jz)]: [ny][nx][3nz][3nz].
+
+    Unknown order inside a block is (component a, z index iz), a-major.
+    """
+    nz, ny, nx = shape
+    c2 = two_level_generator(shape, k, d)
+    lam = np.fft.fft2(c2, axes=(2, 3))  # [6][2nz-1][ny][nx]
+    iz = np.arange(nz)
+    ds = (iz[:, None] - iz[None, :]) + nz - 1
+    B = np.empty((ny, nx, 3 * nz, 3 * nz), dtype=np.complex128)
+    for a in range(3):
+        for b in range(3):
+            L = lam[FULL[a, b]][ds]  # [nz][nz][ny][nx]
+            B[:, :, a * nz:(a + 1) * nz, b * nz:(b + 1) * nz] = -np.moveaxis(L, (0, 1), (2, 3))
+    idx = np.arange(3 * nz)
+    B[:, :, idx, idx] += alpha_tilde_inv
+    return B
+
+
+def invert_blocks(B):
+    """Explicit inverses of every mode block (LU with partial pivoting per block)."""
+    out = np.empty_like(B)
+    eye = np.eye(B.shape[-1], dtype=B.dtype)
+    for j in range(B.shape[0]):
+        for i in range(B.shape[1]):
+            lu = sla.lu_factor(B[j, i])
+            out[j, i] = sla.lu_solve(lu, eye)
+    return out
+
+
+def apply_blocks(vbox, mask, Binv):
+    """z = M P^{-1} (M v) with P given by its per-mode inverse blocks."""
+    m = mask.astype(np.float64)[None]
+    nz = vbox.shape[1]
+    V = np.fft.fft2(vbox * m, axes=(2, 3))  # [3][nz][ny][nx]
+    Vm = np.moveaxis(V, (2, 3), (0, 1)).reshape(V.shape[2], V.shape[3], 3 * nz)
+    Z = np.einsum("yxij,yxj->yxi", Binv, Vm)
+    Z = np.moveaxis(Z.reshape(V.shape[2], V.shape[3], 3, nz), (0, 1), (2, 3))
+    return m * np.fft.ifft2(Z, axes=(2, 3))
+
+
+def apply_dense(vbox, mask, P):
+    """z = M P^{-1} (M v) with the dense brute-force P (LU solve)."""
+    m = mask.astype(np.float64)[None]
+    z = np.linalg.solve(P, (vbox * m).ravel()).reshape(vbox.shape)
+    return m * z

@@ -1,0 +1,87 @@
+"""The five benchmark workloads (synthetic hexagonal ice prisms) and their seeds.
+
+All prisms use the grid mode of :func:`hex_prism_grid` (cubic grid, longest
+extent spans it).  Refractive index 1.31 is ice in the visible; eps = m^2.
+
+* c1: x = 2, aspect 1, 16^3, m = 1.31, +z / x-pol, tol 1e-6.
+* c2: x = 20, aspect 1, 128^3, m = 1.31, +z / (x-pol, y-pol), tol 1e-5.
+* c3: x = 40, aspect 2, 256^3, m = 1.31+0.001i (and 1.78), +z / x-pol, tol 1e-5.
+* c4: 16 prisms from ``default_rng(1903)``: per prism aspect ~ U[0.5, 2] then
+  x ~ U[5, 20] (drawn in that order); grid = element of {32,...,96} nearest to
+  32 + 64 (x - 5) / 15; then 64 Gaussian directions, 2 polarisations each.
+* c5: x = 10, aspect 1, 64^3, eps_j = 1.7161 (1 + delta_j), delta_j ~ U[-0.05, 0.05]
+  from ``default_rng(9802)`` over occupied voxels in C order; dense check grid
+  12^3 at the same k d (x = 1.875).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .geometry import hex_prism_grid
+from .incidence import plane_wave_z, random_directions
+
+C4_GRIDS = (32, 40, 48, 56, 64, 72, 80, 96)
+
+
+def config_c1():
+    s = hex_prism_grid(2.0, 1.0, 16, 1.31, name="c1_hex16")
+    dirs, pols = plane_wave_z(("x",))
+    return dict(name="c1", scatterer=s, dirs=dirs, pols=pols, tol=1e-6, restart=30)
+
+
+def config_c2():
+    s = hex_prism_grid(20.0, 1.0, 128, 1.31, name="c2_hex128")
+    dirs, pols = plane_wave_z(("x", "y"))
+    return dict(name="c2", scatterer=s, dirs=dirs, pols=pols, tol=1e-5, restart=30)
+
+
+def config_c3(case: int = 0):
+    m = 1.31 + 0.001j if case == 0 else 1.78
+    s = hex_prism_grid(40.0, 2.0, 256, m, name=f"c3_hex256_m{case}")
+    dirs, pols = plane_wave_z(("x",))
+    return dict(name="c3", scatterer=s, dirs=dirs, pols=pols, tol=1e-5, restart=30)
+
+
+def c4_grid_for(x: float) -> int:
+    target = 32.0 + 64.0 * (x - 5.0) / 15.0
+    return min(C4_GRIDS, key=lambda g: (abs(g - target), g))
+
+
+def config_c4(n_prisms: int = 16, n_dirs: int = 64, seed: int = 1903):
+    rng = np.random.default_rng(seed)
+    prisms = []
+    for i in range(n_prisms):
+        aspect = rng.uniform(0.5, 2.0)
+        x = rng.uniform(5.0, 20.0)
+        g = c4_grid_for(x)
+        s = hex_prism_grid(x, aspect, g, 1.31, name=f"c4_p{i}_g{g}")
+        dirs, pols = random_directions(n_dirs, rng)
+        prisms.append(dict(scatterer=s, dirs=dirs, pols=pols))
+    return dict(name="c4", prisms=prisms, tol=1e-5, restart=30)
+
+
+def _jitter_eps(s, seed):
+    rng = np.random.default_rng(seed)
+    occ = s.mask.astype(bool)
+    delta = rng.uniform(-0.05, 0.05, size=int(occ.sum()))
+    eps = np.ones(s.mask.shape, dtype=np.complex128)
+    eps[occ] = 1.7161 * (1.0 + delta)
+    s.eps = eps
+    return s
+
+
+def config_c5():
+    s = _jitter_eps(hex_prism_grid(10.0, 1.0, 64, 1.31, name="c5_hex64"), 9802)
+    dirs, pols = plane_wave_z(("x",))
+    fd_rng = np.random.default_rng(4242)
+    occ_idx = np.flatnonzero(s.mask.ravel())
+    fd_voxels = np.sort(fd_rng.choice(occ_idx, size=32, replace=False))
+    return dict(name="c5", scatterer=s, dirs=dirs, pols=pols, tol=1e-5, restart=30,
+                fd_voxels=fd_voxels)
+
+
+def config_c5_dense():
+    s = _jitter_eps(hex_prism_grid(1.875, 1.0, 12, 1.31, name="c5_hex12"), 9802)
+    dirs, pols = plane_wave_z(("x",))
+    return dict(name="c5_dense", scatterer=s, dirs=dirs, pols=pols, tol=1e-10, restart=30)
