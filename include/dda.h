@@ -1,0 +1,208 @@
+/*
+ * dda.h — C-ABI of the MI355X (gfx950) preconditioned discrete dipole approximation solver.
+ *
+ * Method: Groth, Polimeridis & White, "Preconditioning the discrete dipole
+ * approximation".  A voxelised non-magnetic dielectric body with per-voxel
+ * relative permittivity eps is illuminated by a plane wave; the unknown
+ * polarisation coefficients c (Sec. 2.1, the pulse-basis expansion and the
+ * collocation system) solve
+ *
+ *     [diag(alpha^{-1}) - d^3 G] c = E^inc                (Sec. 2.2, 3x3 block system)
+ *
+ * where alpha is the LDR polarisability with the voxel volume omitted
+ * (Sec. 2.1), G the dyadic Green tensor between voxel centres (Sec. 2,
+ * midpoint rule eq. midpoint) and E^inc = pol * exp(i k dir . r).  The
+ * off-diagonal part is applied by a zero-padded 3-D FFT convolution (the
+ * BTTB structure, Sec. 1 and 2.2); the system is solved by restarted GMRES,
+ * optionally right-preconditioned by the 2-level circulant approximation
+ * C_B2 = alpha~^{-1} I - d^3 C~_B2 (Sec. 3, eq. Chan applied along x and y,
+ * dense 3n x 3n blocks along z, Sec. 3.1).
+ *
+ * Conventions (all functions):
+ *  - Grid nx x ny x nz, arrays C-ordered [nz][ny][nx] (x fastest).  Voxel
+ *    (ix,iy,iz) has centre ((ix-(nx-1)/2) d, (iy-(ny-1)/2) d, (iz-(nz-1)/2) d).
+ *  - complex numbers are interleaved (re, im) pairs of double: a "c128" array
+ *    of n entries is 2n doubles.
+ *  - A field vector is c128 [3][nz][ny][nx] (component-major); a batch of
+ *    nrhs vectors is c128 [nrhs][3][nz][ny][nx].  Entries at air voxels
+ *    (mask == 0) carry no unknowns: outputs hold 0 there.
+ *  - Pointers named *_dev are device (HIP) memory owned by the caller; *_host
+ *    are host memory owned by the caller.  Nothing is retained after a call
+ *    returns except inside the opaque handle.
+ *  - nx, ny, nz must each factor into 2, 3, 5 and 7 (the FFT radices) and be
+ *    at most 512.
+ *  - Every function returns a dda_status; on a negative status a
+ *    human-readable reason is available from dda_last_error() (per thread).
+ *    No C++ exception crosses this boundary.
+ *  - Work is enqueued on the HIP stream given to dda_create.  dda_solve,
+ *    dda_grad_cext, dda_cross_sections and dda_build_preconditioner return
+ *    after their work has completed (they produce host results);
+ *    dda_apply_operator / dda_apply_preconditioner are stream-ordered and do
+ *    not synchronise.
+ *  - A handle is not thread-safe; distinct handles may be used concurrently.
+ */
+#ifndef DDA_H
+#define DDA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dda_problem dda_problem;
+
+typedef enum {
+  DDA_OK = 0,
+  DDA_NOT_CONVERGED = 1,  /* warning: iteration cap reached; outputs hold the last iterate */
+  DDA_EINVAL = -1,        /* bad argument (message says which) */
+  DDA_ENOMEM = -2,        /* a device allocation failed or would exceed the size limits */
+  DDA_EDEVICE = -3,       /* a HIP call failed, or a non-finite residual appeared */
+  DDA_ESTATE = -4,        /* call made in the wrong state (e.g. no preconditioner built) */
+  DDA_EUNSUPPORTED = -5   /* grid size outside what the FFT supports */
+} dda_status;
+
+typedef struct {
+  int restart;      /* GMRES restart length m of GMRES(m); default 30 */
+  int max_iter;     /* cap on total GMRES iterations (inner ones in refinement mode); default 2000 */
+  double tol;       /* stop when ||b - A x||_2 / ||b||_2 <= tol (true residual, FP64); default 1e-5 */
+  int precond;      /* 0: none; 2: 2-level circulant preconditioner (Sec. 3); default 2 */
+  int precision;    /* 0: everything in FP64;
+                       1: operator and preconditioner applied in FP32 (complex64) inside
+                          FP64 iterative refinement; Krylov basis, Arnoldi and the refinement
+                          residual stay FP64.  default 0 */
+  double inner_tol; /* precision 1: relative tolerance of each inner solve; default 1e-4 */
+  int max_refine;   /* precision 1: cap on refinement steps; default 30 */
+  int max_rhs;      /* largest nrhs accepted by dda_solve / dda_apply_*; sizes the workspace; default 1 */
+} dda_options;
+
+typedef struct {
+  int iters;           /* GMRES iterations (summed over refinement steps) */
+  int cycles;          /* GMRES restart cycles */
+  int refinements;     /* outer refinement steps (precision 1), else 0 */
+  int converged;       /* 1 if rel_residual <= tol */
+  double rel_residual; /* final true residual ||b - A x|| / ||b||, FP64 */
+  double seconds;      /* wall-clock time of the call */
+} dda_stats;
+
+/* Fill *opt with the defaults listed above. */
+void dda_default_options(dda_options *opt);
+
+/* Reason for the last failure on this thread ("" if none).  Static storage. */
+const char *dda_last_error(void);
+
+/*
+ * Create a problem: uploads nothing from the host; copies mask_dev (uint8
+ * [nz][ny][nx], non-zero = occupied) and eps_dev (c128 [nz][ny][nx], relative
+ * permittivity, read at occupied voxels only) into the handle, then assembles
+ * the operator: the Green tensor d^3 G at every signed voxel offset (the
+ * content of Algorithm 1, evaluated directly at signed offsets), its circulant
+ * embedding on the 2nx x 2ny x 2nz grid and its FFT, kept as one octant of
+ * six components (the per-level parities of Table 1 give the rest).
+ *  k > 0: wavenumber; d > 0: voxel edge; opt may be NULL (defaults);
+ *  stream: a hipStream_t (NULL = default stream).
+ * Errors: EINVAL (sizes < 1, k or d <= 0, no occupied voxel, an occupied voxel
+ * with eps == 1 or eps == -2 where the polarisability is undefined);
+ * EUNSUPPORTED (a dimension not 7-smooth or > 512); ENOMEM; EDEVICE.
+ */
+dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const double *eps_dev,
+                      double k, double d, const dda_options *opt, void *stream,
+                      dda_problem **out);
+
+/*
+ * Build the 2-level circulant preconditioner (Sec. 3, 3.1): eq. Chan along x
+ * then y on the signed-offset kernel, FFTs along x and y, one dense 3nz x 3nz
+ * block per Fourier mode with alpha~^{-1} on its diagonal, and explicit block
+ * inverses by Gauss-Jordan elimination with partial pivoting.  alpha~ is the
+ * LDR polarisability of the mean occupied permittivity (the "ice" value for a
+ * homogeneous body, Sec. 3.1) with lattice factor S = s_bar.  Only the
+ * (nx/2+1)(ny/2+1) modes with non-negative frequencies are inverted; the
+ * block symmetries under x, y and z reflections supply the rest exactly.
+ * Stored in FP64 (precision 0) or FP32 (precision 1).
+ * Errors: EINVAL (s_bar outside [0,1]); ENOMEM; EDEVICE (a singular block).
+ */
+dda_status dda_build_preconditioner(dda_problem *p, double s_bar);
+
+/*
+ * Solve for nrhs incident plane waves at once.
+ *  dir_host, pol_host: double [nrhs][3]; unit propagation directions and real
+ *    unit polarisations orthogonal to them (|.| = 1 and dir.pol = 0 within 1e-9).
+ *    Each wave has its own LDR factor S = sum_j (dir_j pol_j)^2 (Sec. 2.1), hence
+ *    its own diagonal.
+ *  x0_dev: optional initial guess c128 [nrhs][3][nz][ny][nx] (NULL = zero).
+ *  c_dev: optional output polarisations c128 [nrhs][3][nz][ny][nx] (NULL = not returned).
+ *  cext, cabs, csca: optional host double [nrhs] (NULL = not computed):
+ *    C_ext = 4 pi k d^3 sum Im(E^inc* . c),
+ *    C_abs = 4 pi k d^3 sum |c|^2 (-Im alpha^{-1} - (2/3)(k d)^3),
+ *    C_sca = 4 pi k d^3 [(2/3)(k d)^3 sum |c|^2 + sum_{i!=j} c_i^H d^3 Im G(r_i - r_j) c_j]
+ *    (Draine-Flatau forms for this scaling; |E_0| = 1; area in length units^2).
+ *  stats: optional host dda_stats [nrhs].
+ * Returns OK when every right-hand side reached tol, NOT_CONVERGED (outputs
+ * valid) when some hit max_iter / max_refine.  Errors: EINVAL (nrhs < 1 or
+ * > max_rhs, bad vectors), ESTATE (opt.precond == 2 and no preconditioner
+ * built), EDEVICE (non-finite residual, HIP failure).
+ */
+dda_status dda_solve(dda_problem *p, int nrhs, const double *dir_host, const double *pol_host,
+                     const double *x0_dev, double *c_dev, double *cext, double *cabs,
+                     double *csca, dda_stats *stats);
+
+/*
+ * y = A x for the full-box operator: on occupied voxels
+ * y = alpha^{-1} x - d^3 G * (M x) (the system matrix of Sec. 2.2), and y = x
+ * at air voxels.  x_dev, y_dev: c128 [nrhs][3][nz][ny][nx] (must not alias);
+ * dir/pol as in dda_solve (they fix alpha^{-1} through S).  fp32 != 0 runs
+ * the FFT product in FP32 with FP64 input and output.
+ */
+dda_status dda_apply_operator(dda_problem *p, int nrhs, const double *dir_host,
+                              const double *pol_host, const double *x_dev, double *y_dev,
+                              int fp32);
+
+/*
+ * y = M P^{-1} M x with P the 2-level circulant preconditioner and M the
+ * occupancy mask (air entries of y are 0).  x_dev, y_dev: c128
+ * [nrhs][3][nz][ny][nx] (may alias).  fp32 selects the FP32 blocks and must
+ * match the precision the preconditioner was built in (else ESTATE).
+ */
+dda_status dda_apply_preconditioner(dda_problem *p, int nrhs, const double *x_dev,
+                                    double *y_dev, int fp32);
+
+/*
+ * Cross sections (formulas as in dda_solve) of given polarisations c_dev
+ * (c128 [nrhs][3][nz][ny][nx]) for the waves dir/pol.  Host outputs [nrhs],
+ * each optional.
+ */
+dda_status dda_cross_sections(dda_problem *p, int nrhs, const double *dir_host,
+                              const double *pol_host, const double *c_dev, double *cext,
+                              double *cabs, double *csca);
+
+/*
+ * Gradient of C_ext with respect to the per-voxel permittivity, by one forward
+ * and one adjoint solve with the same operator and preconditioner (the
+ * matrix is complex symmetric, Sec. 2.2, so the adjoint system is A lambda =
+ * conj(E^inc)).  grad_dev: c128 [nz][ny][nx] receiving dC/dRe(eps) +
+ * i dC/dIm(eps) at occupied voxels and 0 in air.  cext: optional host double.
+ * stats: optional host dda_stats [2] (forward, adjoint).
+ */
+dda_status dda_grad_cext(dda_problem *p, const double *dir_host, const double *pol_host,
+                         double *grad_dev, double *cext, dda_stats *stats);
+
+/* Release every device allocation of the handle (NULL is a no-op). */
+void dda_destroy(dda_problem *p);
+
+/*
+ * Per-kernel timing with HIP events recorded around every launch on the
+ * handle's stream.  Enabling resets the counters.  dda_profile_get returns,
+ * for kernel kind idx in [0, dda_profile_count()), its name (static storage),
+ * the number of launches, their summed duration in ms, and the algorithmic
+ * bytes one launch moves (read + write, per the traffic model of the kernel).
+ */
+dda_status dda_profile_enable(dda_problem *p, int on);
+int dda_profile_count(dda_problem *p);
+dda_status dda_profile_get(dda_problem *p, int idx, const char **name, long long *launches,
+                           double *total_ms, double *bytes_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDA_H */

@@ -1,0 +1,294 @@
+// Internal declarations shared by the HIP sources of the DDA library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/dda.h"
+
+// ----------------------------------------------------------------------------- complex helpers
+
+template <typename T> struct C2;
+template <> struct C2<double> { using type = double2; };
+template <> struct C2<float> { using type = float2; };
+template <typename T> using cplx = typename C2<T>::type;
+
+template <typename T> __host__ __device__ __forceinline__ cplx<T> mk(T re, T im) {
+  cplx<T> r; r.x = re; r.y = im; return r;
+}
+template <typename V> __host__ __device__ __forceinline__ V cadd(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename V> __host__ __device__ __forceinline__ V csub(V a, V b) { V r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename V> __host__ __device__ __forceinline__ V cmul(V a, V b) {
+  V r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+// conj(a) * b
+template <typename V> __host__ __device__ __forceinline__ V cmulcj(V a, V b) {
+  V r; r.x = a.x * b.x + a.y * b.y; r.y = a.x * b.y - a.y * b.x; return r;
+}
+template <typename V, typename S> __host__ __device__ __forceinline__ V cscale(V a, S s) { V r; r.x = a.x * s; r.y = a.y * s; return r; }
+template <typename V> __host__ __device__ __forceinline__ V cconj(V a) { V r; r.x = a.x; r.y = -a.y; return r; }
+// multiply by -i (sign = -1) or +i (sign = +1)
+template <typename V> __host__ __device__ __forceinline__ V cmuli(V a, int sign) {
+  V r; if (sign > 0) { r.x = -a.y; r.y = a.x; } else { r.x = a.y; r.y = -a.x; } return r;
+}
+__host__ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  double den = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+template <typename V> __device__ __forceinline__ V ldc(const V *p) { return *p; }
+
+__device__ __forceinline__ float2 to_c(double2 a, float2) { return make_float2((float)a.x, (float)a.y); }
+__device__ __forceinline__ double2 to_c(double2 a, double2) { return a; }
+__device__ __forceinline__ double2 to_d(float2 a) { return make_double2((double)a.x, (double)a.y); }
+__device__ __forceinline__ double2 to_d(double2 a) { return a; }
+
+// LDR polarisability coefficients (Sec. 2.1) and its inverse with the voxel volume omitted:
+// 1/alpha = (4 pi / 3)(eps + 2)/(eps - 1) + (b1 + eps b2 + eps b3 S)(k d)^2 - (2i/3)(k d)^3.
+#define DDA_B1 (-1.891531)
+#define DDA_B2 (0.1648469)
+#define DDA_B3 (-1.7700004)
+#define DDA_PI 3.14159265358979323846
+
+__host__ __device__ __forceinline__ double2 ldr_alpha_inv(double2 eps, double kd, double S) {
+  double2 num = make_double2(eps.x + 2.0, eps.y);
+  double2 den = make_double2(eps.x - 1.0, eps.y);
+  double2 q = cdiv(num, den);
+  double f = 4.0 * DDA_PI / 3.0;
+  double kd2 = kd * kd;
+  double2 r;
+  r.x = f * q.x + (DDA_B1 + eps.x * (DDA_B2 + DDA_B3 * S)) * kd2;
+  r.y = f * q.y + eps.y * (DDA_B2 + DDA_B3 * S) * kd2 - (2.0 / 3.0) * kd2 * kd;
+  return r;
+}
+// d(1/alpha)/d eps = -4 pi / (eps - 1)^2 + (b2 + b3 S)(k d)^2
+__host__ __device__ __forceinline__ double2 ldr_dalpha_inv(double2 eps, double kd, double S) {
+  double2 em1 = make_double2(eps.x - 1.0, eps.y);
+  double2 sq = cmul(em1, em1);
+  double2 t = cdiv(make_double2(-4.0 * DDA_PI, 0.0), sq);
+  t.x += (DDA_B2 + DDA_B3 * S) * kd * kd;
+  return t;
+}
+
+// Six unique tensor components, order xx, xy, xz, yy, yz, zz (Algorithm 1).
+// Parity bit mask per component: bit a set when the component is odd under
+// reflection of axis a (odd iff exactly one of its two indices is that axis).
+__host__ __device__ __forceinline__ int comp_odd_mask(int c) {
+  // xx:0, xy: x|y, xz: x|z, yy:0, yz: y|z, zz:0
+  const int m[6] = {0, 3, 5, 0, 6, 0};
+  return m[c];
+}
+__host__ __device__ __forceinline__ int comp_index(int a, int b) {
+  const int t[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+  return t[a][b];
+}
+
+// ----------------------------------------------------------------------------- error handling
+
+namespace dda {
+
+void set_error(const char *fmt, ...);
+const char *get_error();
+
+struct Fail {
+  dda_status st;
+};
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess) {                                                              \
+      ::dda::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                       __LINE__);                                                        \
+      throw ::dda::Fail{DDA_EDEVICE};                                                    \
+    }                                                                                    \
+  } while (0)
+
+#define REQUIRE(cond, status, ...)        \
+  do {                                    \
+    if (!(cond)) {                        \
+      ::dda::set_error(__VA_ARGS__);      \
+      throw ::dda::Fail{status};          \
+    }                                     \
+  } while (0)
+
+// ----------------------------------------------------------------------------- FFT plans
+
+constexpr int kMaxRadices = 16;
+constexpr int kMaxFft = 1024;
+
+struct FftPlan {
+  int n = 0;
+  int nrad = 0;
+  int rad[kMaxRadices] = {0};
+  double2 *tw64 = nullptr;  // exp(-2 pi i t / n), t in [0, n)
+  float2 *tw32 = nullptr;
+};
+
+// Device-side copy of a plan, passed by value to kernels.
+struct FftDesc {
+  int n;
+  int nrad;
+  int rad[kMaxRadices];
+};
+
+bool factor_7smooth(int n, FftPlan &plan);
+void plan_create(FftPlan &plan, int n);
+void plan_destroy(FftPlan &plan);
+inline FftDesc desc(const FftPlan &p) {
+  FftDesc d;
+  d.n = p.n;
+  d.nrad = p.nrad;
+  for (int i = 0; i < kMaxRadices; ++i) d.rad[i] = p.rad[i];
+  return d;
+}
+
+// ----------------------------------------------------------------------------- profiling
+
+struct Profiler {
+  bool on = false;
+  struct Kind {
+    std::string name;
+    long long launches = 0;
+    double total_ms = 0.0;
+    double bytes = 0.0;
+  };
+  std::vector<Kind> kinds;
+  struct Pending {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  int kind_id(const char *name, double bytes);
+  void begin(hipStream_t s, int kind, hipEvent_t *a, hipEvent_t *b);
+  void collect();  // after a stream sync
+  void reset();
+  void destroy();
+  hipEvent_t get_event();
+};
+
+// RAII timer around one launch; no-op when profiling is off.
+struct KTimer {
+  Profiler *prof;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  KTimer(Profiler *p, hipStream_t s, const char *name, double bytes);
+  ~KTimer();
+};
+
+}  // namespace dda
+
+// ----------------------------------------------------------------------------- problem handle
+
+struct dda_problem {
+  int nx = 0, ny = 0, nz = 0;
+  long long N = 0;       // voxels in the box
+  long long n_occ = 0;   // occupied voxels
+  double k = 0.0, d = 0.0;
+  hipStream_t st = nullptr;
+  dda_options opt{};
+  int R = 1;             // max right-hand sides
+  size_t lds_max = 65536;      // device LDS per workgroup
+  size_t lds_zpass = 98304;    // LDS budget of the fused z pass
+
+  uint8_t *mask = nullptr;      // [N]
+  double2 *eps = nullptr;       // [N]
+  double2 eps_mean{0.0, 0.0};   // mean permittivity over occupied voxels
+
+  dda::FftPlan px, py, pz;   // padded lengths 2nx, 2ny, 2nz
+  dda::FftPlan ux, uy;       // unpadded nx, ny (preconditioner)
+
+  // operator kernel: FFT of the circulant embedding, octant [6][nz+1][ny+1][nx+1]
+  double2 *khat64 = nullptr;
+  float2 *khat32 = nullptr;
+  double2 *khatI64 = nullptr;   // same for d^3 Im G (scattering sum)
+
+  // FFT workspaces (sized for R right-hand sides, FP64 elements)
+  void *w0 = nullptr;  // [R][3][nz][ny][2nx]
+  void *w1 = nullptr;  // [R][3][nz][2ny][2nx]
+  size_t w0_elems = 0, w1_elems = 0;
+
+  double2 *ainv = nullptr;   // [R][N] per-RHS 1/alpha
+  double *Sdev = nullptr;    // [R] lattice factor per RHS
+
+  // preconditioner
+  int prec_built = 0;
+  int prec_fp32 = 0;
+  double2 ati{0.0, 0.0};     // alpha~^{-1}
+  int hh = 0, n2 = 0;        // ceil(nz/2), 3*hh
+  int umx = 0, umy = 0;      // nx/2+1, ny/2+1
+  double2 *binv64 = nullptr; // [umy][umx][2][n2][n2], column-major inverse blocks
+  float2 *binv32 = nullptr;
+
+  // Krylov state (FP64)
+  double2 *V = nullptr;      // [restart+1][R][3N]
+  double2 *work = nullptr;   // [R][3N]  w / z scratch
+  double2 *work2 = nullptr;  // [R][3N]
+  double2 *bvec = nullptr;   // [R][3N] right-hand side
+  double2 *xvec = nullptr;   // [R][3N] iterate
+  double2 *rvec = nullptr;   // [R][3N] residual of the GMRES iterate
+  double2 *xref = nullptr;   // [R][3N] refinement residual (right-hand side of the inner solve)
+  double2 *rref = nullptr;   // [R][3N] refinement correction
+  double2 *H = nullptr;      // [R][restart+1][restart]
+  double2 *givens = nullptr; // [R][restart][2] (c real in .x, s complex)
+  double2 *gvec = nullptr;   // [R][restart+1]
+  double2 *hcol = nullptr;   // [R][restart+1] projections
+  double2 *hcol2 = nullptr;  // [R][restart+1]
+  double2 *ycoef = nullptr;  // [R][restart+1]
+  double *partial = nullptr; // reduction partials
+  size_t partial_elems = 0;
+  double *dscal = nullptr;   // [R][16] device scalars
+  double *hpin = nullptr;    // pinned host mirror [R][16]
+  int *dflag = nullptr;      // device error flags [4]
+
+  dda::Profiler prof;
+};
+
+// ----------------------------------------------------------------------------- internal entry points
+
+namespace dda {
+
+// fft.hip — plain (setup) transforms on FP64 arrays, in place
+void fft_rows_plain(dda_problem *p, const FftPlan &pl, double2 *data, long long rows, int inverse);
+void fft_strided_plain(dda_problem *p, const FftPlan &pl, double2 *data, long long batch,
+                       long long width, int inverse);
+
+// operator.hip
+void operator_setup(dda_problem *p);
+void setup_alpha(dda_problem *p, int nrhs, const double *S_host);
+void setup_rhs(dda_problem *p, int nrhs, const double *dir, const double *pol, double2 *b,
+               int conjugate);
+// y = A x (FP64 in/out), prec: 0 FP64, 1 FP32 internal; kernel 0 = operator, 1 = Im-kernel conv
+void apply_operator(dda_problem *p, int nrhs, const double2 *x, double2 *y, int fp32,
+                    const double *xscale_dev);
+void apply_imag_conv(dda_problem *p, int nrhs, const double2 *x, double2 *y);
+
+// precond.hip
+void precond_build(dda_problem *p, double s_bar);
+void apply_precond(dda_problem *p, int nrhs, const double2 *x, double2 *y, int fp32,
+                   const double *xscale_dev);
+void precond_free(dda_problem *p);
+
+// krylov.hip
+void krylov_alloc(dda_problem *p);
+// Solve A x = b for nrhs RHS (b, x device [nrhs][3N]; x holds the initial guess).
+void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp32, double tol,
+                 int maxit, dda_stats *st);
+// Full solve including refinement mode.
+dda_status solve_system(dda_problem *p, int nrhs, const double2 *b, double2 *x, dda_stats *st);
+void residual(dda_problem *p, int nrhs, const double2 *b, const double2 *x, double2 *r,
+              double *rel_host);
+
+// xsec.hip
+void cross_sections(dda_problem *p, int nrhs, const double *dir, const double *pol,
+                    const double2 *c, double *cext, double *cabs, double *csca);
+void grad_kernel(dda_problem *p, const double2 *c, const double2 *lam, double S, double2 *grad);
+
+// reductions (krylov.hip): per-RHS sums of n-length arrays
+int reduce_blocks(long long n);
+
+}  // namespace dda

@@ -1,0 +1,291 @@
+// FFT kernels along the contiguous (x) axis, a strided axis, and the fused z pass of the
+// BTTB product.  Included by the translation units that launch them.
+#pragma once
+
+#include "fft_engine.h"
+
+namespace dda {
+
+// ---------------------------------------------------------------------------- row (x-axis) FFT
+
+enum RowMode {
+  ROW_PLAIN = 0,  // in/out: T work rows (setup transforms)
+  ROW_OP_FWD,     // in: FP64 field rows (masked, optionally scaled), zero-padded; out: T rows
+  ROW_OP_INV,     // in: T rows; out: y = M (alpha^{-1} x - conv) + (1 - M) x, FP64
+  ROW_IMG_INV,    // in: T rows; out: y = M conv, FP64
+  ROW_PC_FWD,     // in: FP64 field rows, masked; out: T rows (unpadded)
+  ROW_PC_INV      // in: T rows; out: y = M * scale * v, FP64
+};
+
+struct RowArgs {
+  FftDesc pl;
+  long long rows;      // number of rows transformed
+  int tw;              // rows per workgroup (LDS columns)
+  int n_in, n_out;     // valid input length (zero padded to n), output length written
+  long long in_stride, out_stride;
+  int sign;
+  const uint8_t *mask; // [N]
+  long long vox_rows;  // nz * ny: rows per component block
+  long long rhs_rows;  // 3 * nz * ny: rows per right-hand side
+  int nx;
+  long long N;
+  const double2 *ainv; // [R][N]
+  const double2 *xin;  // FP64 field rows for ROW_OP_INV
+  const double *xscale;// per-RHS input scale, or null
+  double scale;        // output scale of the transform
+};
+
+template <typename T, int MODE, typename TI, typename TO>
+__global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
+                                                          const cplx<T> *__restrict__ tw,
+                                                          RowArgs a) {
+  using V = cplx<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V *s = reinterpret_cast<V *>(smem_raw);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int n = a.pl.n;
+  const int ld = a.tw + 1;
+  const long long row0 = (long long)blockIdx.x * a.tw;
+  const int tot_in = a.tw * n;
+  for (int e = tid; e < tot_in; e += nt) {
+    const int c = e / n;
+    const int i = e - c * n;
+    const long long row = row0 + c;
+    V val = mk<T>((T)0, (T)0);
+    if (row < a.rows && i < a.n_in) {
+      if constexpr (MODE == ROW_OP_FWD || MODE == ROW_PC_FWD) {
+        const long long vox = (row % a.vox_rows) * a.nx + i;
+        double2 xv = in[row * a.in_stride + i];
+        if (!a.mask[vox]) xv = make_double2(0.0, 0.0);
+        if (a.xscale) xv = cscale(xv, a.xscale[row / a.rhs_rows]);
+        val = to_c(xv, V{});
+      } else {
+        val = in[row * a.in_stride + i];
+      }
+    }
+    s[i * ld + c] = val;
+  }
+  __syncthreads();
+  lds_fft<V, EptOf<T>::value>(s, ld, a.tw, a.pl, tw, a.sign, tid, nt);
+  const int tot_out = a.tw * a.n_out;
+  for (int e = tid; e < tot_out; e += nt) {
+    const int c = e / a.n_out;
+    const int i = e - c * a.n_out;
+    const long long row = row0 + c;
+    if (row >= a.rows) continue;
+    const V v = s[i * ld + c];
+    if constexpr (MODE == ROW_PLAIN) {
+      out[row * a.out_stride + i] = v;
+    } else if constexpr (MODE == ROW_OP_INV || MODE == ROW_IMG_INV || MODE == ROW_PC_INV) {
+      const long long vox = (row % a.vox_rows) * a.nx + i;
+      const double2 conv = cscale(to_d(v), a.scale);
+      double2 y = make_double2(0.0, 0.0);
+      if constexpr (MODE == ROW_OP_INV) {
+        const long long r = row / a.rhs_rows;
+        double2 xv = a.xin[row * a.out_stride + i];
+        if (a.xscale) xv = cscale(xv, a.xscale[r]);
+        if (a.mask[vox]) y = csub(cmul(a.ainv[r * a.N + vox], xv), conv);
+        else y = xv;
+      } else {
+        if (a.mask[vox]) y = conv;
+      }
+      out[row * a.out_stride + i] = y;
+    } else {
+      out[row * a.out_stride + i] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- strided-axis FFT
+
+// Data [batch][len][width] (width contiguous); transform along len.
+struct StrArgs {
+  FftDesc pl;
+  long long batch;
+  long long width;
+  int tw;                 // columns per workgroup
+  long long ntiles;       // ceil(width / tw)
+  int n_in, n_out;
+  long long in_bstride, out_bstride;  // elements between batches
+  int sign;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kFftThreads) k_fft_strided(const cplx<T> *in, cplx<T> *out,
+                                                             const cplx<T> *__restrict__ tw,
+                                                             StrArgs a) {
+  using V = cplx<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V *s = reinterpret_cast<V *>(smem_raw);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int n = a.pl.n;
+  const int ld = a.tw + 1;
+  const long long b = blockIdx.x / a.ntiles;
+  const long long c0 = (blockIdx.x - b * a.ntiles) * (long long)a.tw;
+  const V *src = in + b * a.in_bstride;
+  const int tot = a.tw * n;
+  for (int e = tid; e < tot; e += nt) {
+    const int i = e / a.tw;
+    const int c = e - i * a.tw;
+    V val = mk<T>((T)0, (T)0);
+    if (i < a.n_in && c0 + c < a.width) val = src[(long long)i * a.width + c0 + c];
+    s[i * ld + c] = val;
+  }
+  __syncthreads();
+  lds_fft<V, EptOf<T>::value>(s, ld, a.tw, a.pl, tw, a.sign, tid, nt);
+  V *dst = out + b * a.out_bstride;
+  const int toto = a.tw * a.n_out;
+  for (int e = tid; e < toto; e += nt) {
+    const int i = e / a.tw;
+    const int c = e - i * a.tw;
+    if (c0 + c < a.width) dst[(long long)i * a.width + c0 + c] = s[i * ld + c];
+  }
+}
+
+// ---------------------------------------------------------------------------- fused z pass
+
+// Data [R][3][nz][plane] with plane = 2ny * 2nx (after the x and y transforms).  For a
+// tile of `tw` consecutive (ky, kx) columns of one right-hand side: zero-pad each of
+// the three components to 2nz along z, FFT, multiply by the 3x3 symmetric kernel
+// spectrum (six components, read from the stored octant with the per-axis parity
+// signs), inverse FFT, write the first nz entries back in place.
+struct ZArgs {
+  FftDesc pl;       // length 2nz
+  int nz, ny, nx;
+  long long plane;  // 4 nx ny
+  int tw;
+  long long ntiles;
+};
+
+template <typename T, int EPT>
+__global__ void __launch_bounds__(768) k_zpass(cplx<T> *data, const cplx<T> *__restrict__ tw,
+                                                const cplx<T> *__restrict__ khat, ZArgs a) {
+  using V = cplx<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V *s = reinterpret_cast<V *>(smem_raw);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int n = a.pl.n;
+  const int ncols = 3 * a.tw;
+  const int ld = ncols + 1;
+  const long long r = blockIdx.x / a.ntiles;
+  const long long c0 = (blockIdx.x - r * a.ntiles) * (long long)a.tw;
+  V *base = data + r * 3LL * a.nz * a.plane;
+  const int tot = 3 * a.tw * n;
+  for (int e = tid; e < tot; e += nt) {
+    const int i = e / ncols;
+    const int cc = e - i * ncols;
+    const int comp = cc / a.tw;
+    const int c = cc - comp * a.tw;
+    V val = mk<T>((T)0, (T)0);
+    if (i < a.nz && c0 + c < a.plane) val = base[((long long)comp * a.nz + i) * a.plane + c0 + c];
+    s[i * ld + cc] = val;
+  }
+  __syncthreads();
+  lds_fft<V, EPT>(s, ld, ncols, a.pl, tw, -1, tid, nt);
+  // pointwise 3x3 multiply
+  const int L2x = 2 * a.nx;
+  const long long ox_n = a.nx + 1, oy_n = a.ny + 1;
+  const long long cstride = (long long)(a.nz + 1) * oy_n * ox_n;
+  for (int e = tid; e < a.tw * n; e += nt) {
+    const int i = e / a.tw;
+    const int c = e - i * a.tw;
+    const long long kyx = c0 + c;
+    if (kyx >= a.plane) continue;
+    const int ky = (int)(kyx / L2x);
+    const int kx = (int)(kyx - (long long)ky * L2x);
+    int mir = 0;
+    int ox = kx, oy = ky, oz = i;
+    if (kx > a.nx) { ox = L2x - kx; mir |= 1; }
+    if (ky > a.ny) { oy = 2 * a.ny - ky; mir |= 2; }
+    if (i > a.nz) { oz = n - i; mir |= 4; }
+    const long long o = ((long long)oz * oy_n + oy) * ox_n + ox;
+    V K[6];
+#pragma unroll
+    for (int cc = 0; cc < 6; ++cc) {
+      V kv = khat[cc * cstride + o];
+      if (__popc(comp_odd_mask(cc) & mir) & 1) { kv.x = -kv.x; kv.y = -kv.y; }
+      K[cc] = kv;
+    }
+    V* row = s + i * ld;
+    const V x0 = row[c], x1 = row[a.tw + c], x2 = row[2 * a.tw + c];
+    row[c] = cadd(cadd(cmul(K[0], x0), cmul(K[1], x1)), cmul(K[2], x2));
+    row[a.tw + c] = cadd(cadd(cmul(K[1], x0), cmul(K[3], x1)), cmul(K[4], x2));
+    row[2 * a.tw + c] = cadd(cadd(cmul(K[2], x0), cmul(K[4], x1)), cmul(K[5], x2));
+  }
+  __syncthreads();
+  lds_fft<V, EPT>(s, ld, ncols, a.pl, tw, +1, tid, nt);
+  const int toto = 3 * a.tw * a.nz;
+  for (int e = tid; e < toto; e += nt) {
+    const int i = e / ncols;
+    const int cc = e - i * ncols;
+    const int comp = cc / a.tw;
+    const int c = cc - comp * a.tw;
+    if (c0 + c < a.plane) base[((long long)comp * a.nz + i) * a.plane + c0 + c] = s[i * ld + cc];
+  }
+}
+
+// ---------------------------------------------------------------------------- host helpers
+
+inline void set_lds_limit(const void *fn, size_t bytes) {
+  if (bytes > 48 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T> inline const cplx<T> *tw_of(const FftPlan &p);
+template <> inline const double2 *tw_of<double>(const FftPlan &p) { return p.tw64; }
+template <> inline const float2 *tw_of<float>(const FftPlan &p) { return p.tw32; }
+
+// Columns per 32 KB tile for a transform of length n.
+template <typename T> inline int tile_cols(int n) {
+  const int elems = kFftThreads * EptOf<T>::value;
+  int t = elems / n;
+  return t < 1 ? 1 : t;
+}
+
+template <typename T> inline size_t tile_lds(int n, int cols) {
+  return (size_t)n * (size_t)(cols + 1) * sizeof(cplx<T>);
+}
+
+// Launch a row transform.  `a` must have pl, rows, n_in, n_out, strides and sign set.
+template <typename T, int MODE, typename TI, typename TO>
+inline void launch_rows(dda_problem *p, const FftPlan &pl, const TI *in, TO *out, RowArgs a,
+                        const char *name, double bytes) {
+  a.pl = desc(pl);
+  a.tw = tile_cols<T>(pl.n);
+  if (a.rows < a.tw) a.tw = (int)a.rows;
+  const long long blocks = (a.rows + a.tw - 1) / a.tw;
+  const size_t lds = tile_lds<T>(pl.n, a.tw);
+  auto fn = k_fft_rows<T, MODE, TI, TO>;
+  set_lds_limit((const void *)fn, lds);
+  KTimer t(&p->prof, p->st, name, bytes);
+  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kFftThreads), lds, p->st, in, out,
+                     tw_of<T>(pl), a);
+  HIPCHK(hipGetLastError());
+}
+
+template <typename T>
+inline void launch_strided(dda_problem *p, const FftPlan &pl, const cplx<T> *in, cplx<T> *out,
+                           long long batch, long long width, int n_in, int n_out,
+                           long long in_bstride, long long out_bstride, int sign,
+                           const char *name, double bytes) {
+  StrArgs a;
+  a.pl = desc(pl);
+  a.batch = batch;
+  a.width = width;
+  a.tw = tile_cols<T>(pl.n);
+  if (a.tw > width) a.tw = (int)width;
+  a.ntiles = (width + a.tw - 1) / a.tw;
+  a.n_in = n_in;
+  a.n_out = n_out;
+  a.in_bstride = in_bstride;
+  a.out_bstride = out_bstride;
+  a.sign = sign;
+  const size_t lds = tile_lds<T>(pl.n, a.tw);
+  auto fn = k_fft_strided<T>;
+  set_lds_limit((const void *)fn, lds);
+  KTimer t(&p->prof, p->st, name, bytes);
+  hipLaunchKernelGGL(fn, dim3((unsigned)(a.ntiles * batch)), dim3(kFftThreads), lds, p->st, in,
+                     out, tw_of<T>(pl), a);
+  HIPCHK(hipGetLastError());
+}
+
+}  // namespace dda

@@ -1,0 +1,542 @@
+// Restarted GMRES(m), right-preconditioned, FP64 Arnoldi with classical Gram-Schmidt
+// applied twice, per-RHS Hessenberg / Givens updates on the device, and the FP32-inner /
+// FP64-outer iterative refinement driver.  The paper runs GMRES to 1e-5 (Sec. 4); restarts
+// are the variant it recommends for memory (Sec. 4-5).  All reductions are fixed-order
+// (block partials, then one ordered pass), so results repeat bit for bit.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "common.h"
+
+namespace dda {
+
+constexpr int kRedThreads = 256;
+constexpr int kCH = 8;  // vectors per multi-dot sweep
+constexpr int kMaxM = 32;
+
+int reduce_blocks(long long n) {
+  long long b = (n + 1023) / 1024;
+  return (int)std::max<long long>(1, std::min<long long>(1024, b));
+}
+
+// partial[(r * kMaxM + i) * B + blk] = sum_{n in block} conj(V_i[n]) w[n], i in [0, nvec)
+__global__ void __launch_bounds__(kRedThreads) k_multidot(const double2 *V, long long vs_r,
+                                                          long long vs_j, int nvec,
+                                                          const double2 *w, long long ws_r,
+                                                          long long n3, const int *active,
+                                                          double2 *partial, int B) {
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  __shared__ double2 sh[kCH][kRedThreads];
+  const double2 *wr = w + r * ws_r;
+  for (int i0 = 0; i0 < nvec; i0 += kCH) {
+    double2 acc[kCH];
+#pragma unroll
+    for (int q = 0; q < kCH; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
+         n += (long long)gridDim.x * blockDim.x) {
+      const double2 wv = wr[n];
+#pragma unroll
+      for (int q = 0; q < kCH; ++q)
+        if (i0 + q < nvec) acc[q] = cadd(acc[q], cmulcj(V[r * vs_r + (i0 + q) * vs_j + n], wv));
+    }
+#pragma unroll
+    for (int q = 0; q < kCH; ++q) sh[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s)
+#pragma unroll
+        for (int q = 0; q < kCH; ++q) sh[q][threadIdx.x] = cadd(sh[q][threadIdx.x], sh[q][threadIdx.x + s]);
+      __syncthreads();
+    }
+    if ((int)threadIdx.x < kCH && i0 + (int)threadIdx.x < nvec)
+      partial[((long long)r * kMaxM + i0 + threadIdx.x) * B + blockIdx.x] = sh[threadIdx.x][0];
+    __syncthreads();
+  }
+}
+
+// out[r * kMaxM + i] (+)= sum_b partial[(r * kMaxM + i) * B + b]   (ordered tree)
+__global__ void k_finalize(const double2 *partial, int B, double2 *out, int accumulate,
+                           const int *active) {
+  const int i = blockIdx.x, r = blockIdx.y;
+  if (!active[r]) return;
+  __shared__ double2 sh[kRedThreads];
+  double2 acc = make_double2(0.0, 0.0);
+  for (int b = threadIdx.x; b < B; b += blockDim.x)
+    acc = cadd(acc, partial[((long long)r * kMaxM + i) * B + b]);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = cadd(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (accumulate) out[r * kMaxM + i] = cadd(out[r * kMaxM + i], sh[0]);
+    else out[r * kMaxM + i] = sh[0];
+  }
+}
+
+// w -= sum_i V_i c_i (c = coef[r * kMaxM + i]); if nrm_partial: partial ||w||^2 (in .x)
+__global__ void __launch_bounds__(kRedThreads) k_multiaxpy(const double2 *V, long long vs_r,
+                                                           long long vs_j, int nvec,
+                                                           const double2 *coef, double2 *w,
+                                                           long long ws_r, long long n3,
+                                                           const int *active,
+                                                           double2 *nrm_partial, int B) {
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  __shared__ double2 c[kMaxM];
+  __shared__ double sh[kRedThreads];
+  if ((int)threadIdx.x < nvec) c[threadIdx.x] = coef[r * kMaxM + threadIdx.x];
+  __syncthreads();
+  double2 *wr = w + r * ws_r;
+  double acc = 0.0;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
+       n += (long long)gridDim.x * blockDim.x) {
+    double2 v = wr[n];
+    for (int i = 0; i < nvec; ++i) v = csub(v, cmul(V[r * vs_r + i * vs_j + n], c[i]));
+    wr[n] = v;
+    acc += v.x * v.x + v.y * v.y;
+  }
+  if (!nrm_partial) return;
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nrm_partial[((long long)r * kMaxM) * B + blockIdx.x] = make_double2(sh[0], 0.0);
+}
+
+// out = sum_i V_i y_i  (y = coef[r * kMaxM + i]; zero coefficients beyond a RHS's cut)
+__global__ void k_combine(const double2 *V, long long vs_r, long long vs_j, int nvec,
+                          const double2 *coef, double2 *out, long long os_r, long long n3) {
+  const int r = blockIdx.y;
+  __shared__ double2 c[kMaxM];
+  if ((int)threadIdx.x < nvec) c[threadIdx.x] = coef[r * kMaxM + threadIdx.x];
+  __syncthreads();
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
+       n += (long long)gridDim.x * blockDim.x) {
+    double2 v = make_double2(0.0, 0.0);
+    for (int i = 0; i < nvec; ++i) v = cadd(v, cmul(V[r * vs_r + i * vs_j + n], c[i]));
+    out[r * os_r + n] = v;
+  }
+}
+
+// out = a + s * b (per element), s = +1 or -1; optional partial ||out||^2
+__global__ void __launch_bounds__(kRedThreads) k_axpby(const double2 *a, const double2 *b,
+                                                       double s, double2 *out, long long n3,
+                                                       long long st_r, const int *active,
+                                                       double2 *nrm_partial, int B) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  __shared__ double sh[kRedThreads];
+  double acc = 0.0;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
+       n += (long long)gridDim.x * blockDim.x) {
+    const long long o = r * st_r + n;
+    const double2 v = make_double2(a[o].x + s * b[o].x, a[o].y + s * b[o].y);
+    out[o] = v;
+    acc += v.x * v.x + v.y * v.y;
+  }
+  if (!nrm_partial) return;
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int q = blockDim.x / 2; q > 0; q >>= 1) {
+    if ((int)threadIdx.x < q) sh[threadIdx.x] += sh[threadIdx.x + q];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nrm_partial[((long long)r * kMaxM) * B + blockIdx.x] = make_double2(sh[0], 0.0);
+}
+
+// partial ||a||^2
+__global__ void __launch_bounds__(kRedThreads) k_norm2(const double2 *a, long long n3,
+                                                       long long st_r, double2 *nrm_partial,
+                                                       int B) {
+  const int r = blockIdx.y;
+  __shared__ double sh[kRedThreads];
+  double acc = 0.0;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
+       n += (long long)gridDim.x * blockDim.x) {
+    const double2 v = a[r * st_r + n];
+    acc += v.x * v.x + v.y * v.y;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int q = blockDim.x / 2; q > 0; q >>= 1) {
+    if ((int)threadIdx.x < q) sh[threadIdx.x] += sh[threadIdx.x + q];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nrm_partial[((long long)r * kMaxM) * B + blockIdx.x] = make_double2(sh[0], 0.0);
+}
+
+// out[n] = in[n] * scal[r]  (scal from the device scalars)
+__global__ void k_scale(const double2 *in, double2 *out, long long n3, long long ins_r,
+                        long long outs_r, const double *scal, int sstride, const int *active) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const double s = scal[r * sstride];
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
+       n += (long long)gridDim.x * blockDim.x) {
+    const double2 v = in[r * ins_r + n];
+    out[r * outs_r + n] = make_double2(v.x * s, v.y * s);
+  }
+}
+
+// Start of a cycle: g = (beta, 0, ...), scal = 1/beta with beta = sqrt(rn2)
+__global__ void k_cycle_init(const double2 *rn2, double2 *g, int m, double *dscal, const int *active,
+                             int nrhs) {
+  const int r = threadIdx.x;
+  if (r >= nrhs || !active[r]) return;
+  const double beta = sqrt(rn2[r * kMaxM].x);
+  for (int i = 0; i <= m; ++i) g[r * (m + 1) + i] = make_double2(0.0, 0.0);
+  g[r * (m + 1)] = make_double2(beta, 0.0);
+  dscal[r * 8 + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
+}
+
+// Column j of the Hessenberg matrix from the two projections and ||w||^2, previous
+// rotations, a new rotation, the updated residual estimate |g_{j+1}| and 1/h_{j+1,j}.
+__global__ void k_arnoldi(int j, int m, double2 *H, double2 *giv, double2 *g, const double2 *h1,
+                          const double2 *h2, const double2 *nrm2, double *dscal, const int *active,
+                          int nrhs) {
+  const int r = threadIdx.x;
+  if (r >= nrhs || !active[r]) return;
+  double2 *Hr = H + (long long)r * (m + 1) * m;
+  double2 *gr = g + r * (m + 1);
+  double2 *cs = giv + (long long)r * m * 2;
+  for (int i = 0; i <= j; ++i) Hr[i * m + j] = cadd(h1[r * kMaxM + i], h2[r * kMaxM + i]);
+  const double hn = sqrt(nrm2[r * kMaxM].x);
+  Hr[(j + 1) * m + j] = make_double2(hn, 0.0);
+  for (int i = 0; i < j; ++i) {
+    const double c = cs[2 * i].x;
+    const double2 s = cs[2 * i + 1];
+    const double2 a = Hr[i * m + j], b = Hr[(i + 1) * m + j];
+    const double2 t = cadd(cscale(a, c), cmul(s, b));
+    Hr[(i + 1) * m + j] = csub(cscale(b, c), cmulcj(s, a));
+    Hr[i * m + j] = t;
+  }
+  const double2 a = Hr[j * m + j], b = Hr[(j + 1) * m + j];
+  const double aa = sqrt(a.x * a.x + a.y * a.y), bb = sqrt(b.x * b.x + b.y * b.y);
+  const double den = sqrt(aa * aa + bb * bb);
+  double c;
+  double2 s;
+  if (den == 0.0) { c = 1.0; s = make_double2(0.0, 0.0); }
+  else if (aa == 0.0) { c = 0.0; s = make_double2(1.0, 0.0); }
+  else {
+    c = aa / den;
+    const double2 ph = make_double2(a.x / aa, a.y / aa);
+    s = cscale(cmul(ph, cconj(b)), 1.0 / den);
+  }
+  cs[2 * j] = make_double2(c, 0.0);
+  cs[2 * j + 1] = s;
+  Hr[j * m + j] = cadd(cscale(a, c), cmul(s, b));
+  Hr[(j + 1) * m + j] = make_double2(0.0, 0.0);
+  const double2 gj = gr[j];
+  gr[j + 1] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));  // -conj(s) g_j
+  gr[j] = cscale(gj, c);
+  const double2 e = gr[j + 1];
+  dscal[r * 8 + 0] = sqrt(e.x * e.x + e.y * e.y);
+  dscal[r * 8 + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+  dscal[r * 8 + 2] = hn;
+}
+
+// y = H(0:jc, 0:jc)^{-1} g(0:jc) (upper triangular), zero beyond jc; ycoef[r * kMaxM + i]
+__global__ void k_trisolve(const double2 *H, const double2 *g, int m, const int *jcut,
+                           double2 *y, int nrhs) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  const double2 *Hr = H + (long long)r * (m + 1) * m;
+  const double2 *gr = g + r * (m + 1);
+  const int jc = jcut[r];
+  for (int i = 0; i < kMaxM; ++i) y[r * kMaxM + i] = make_double2(0.0, 0.0);
+  for (int i = jc - 1; i >= 0; --i) {
+    double2 acc = gr[i];
+    for (int q = i + 1; q < jc; ++q) acc = csub(acc, cmul(Hr[i * m + q], y[r * kMaxM + q]));
+    y[r * kMaxM + i] = cdiv(acc, Hr[i * m + i]);
+  }
+}
+
+// ----------------------------------------------------------------------------- host side
+
+static inline dim3 grid_r(int B, int nrhs) { return dim3((unsigned)B, (unsigned)nrhs); }
+
+struct Kry {
+  dda_problem *p;
+  int nrhs, B, m;
+  long long n3;
+  double2 *partial;
+  int *d_active;
+  int *d_jcut;
+};
+
+static void sync_active(dda_problem *p, int *d, const std::vector<int> &h) {
+  HIPCHK(hipMemcpyAsync(d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, p->st));
+}
+
+// ||a_r||^2 into hcol2[r * kMaxM] (device), for every RHS
+static void norm2_dev(Kry &K, const double2 *a, long long st_r, double2 *dst, const int *act) {
+  dda_problem *p = K.p;
+  {
+    KTimer t(&p->prof, p->st, "kry_norm", 16.0 * K.n3 * K.nrhs);
+    hipLaunchKernelGGL(k_norm2, grid_r(K.B, K.nrhs), dim3(kRedThreads), 0, p->st, a, K.n3, st_r,
+                       K.partial, K.B);
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(1, K.nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B, dst,
+                     0, act);
+  HIPCHK(hipGetLastError());
+}
+
+static void read_scalars(dda_problem *p, const double2 *src, int nrhs, std::vector<double> &out) {
+  std::vector<double2> tmp(nrhs * kMaxM);
+  HIPCHK(hipMemcpyAsync(tmp.data(), src, sizeof(double2) * nrhs * kMaxM, hipMemcpyDeviceToHost, p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
+  out.resize(nrhs);
+  for (int r = 0; r < nrhs; ++r) out[r] = tmp[r * kMaxM].x;
+}
+
+void residual(dda_problem *p, int nrhs, const double2 *b, const double2 *x, double2 *r,
+              double *rel_host) {
+  const long long n3 = 3 * p->N;
+  Kry K{p, nrhs, reduce_blocks(n3), p->opt.restart, n3, reinterpret_cast<double2 *>(p->partial),
+        p->dflag + 4, p->dflag + 4 + p->R};
+  std::vector<int> all(nrhs, 1);
+  sync_active(p, K.d_active, all);
+  apply_operator(p, nrhs, x, p->work, 0, nullptr);
+  {
+    KTimer t(&p->prof, p->st, "kry_residual", 48.0 * n3 * nrhs);
+    hipLaunchKernelGGL(k_axpby, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, b, p->work, -1.0, r,
+                       n3, n3, nullptr, K.partial, K.B);
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(1, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
+                     p->hcol2, 0, K.d_active);
+  HIPCHK(hipGetLastError());
+  std::vector<double> rn2, bn2;
+  read_scalars(p, p->hcol2, nrhs, rn2);
+  norm2_dev(K, b, n3, p->hcol2, K.d_active);
+  read_scalars(p, p->hcol2, nrhs, bn2);
+  for (int q = 0; q < nrhs; ++q) rel_host[q] = bn2[q] > 0 ? std::sqrt(rn2[q] / bn2[q]) : std::sqrt(rn2[q]);
+}
+
+void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp32, double tol,
+                 int maxit, dda_stats *st) {
+  const int m = p->opt.restart;
+  const long long n3 = 3 * p->N;
+  Kry K{p, nrhs, reduce_blocks(n3), m, n3, reinterpret_cast<double2 *>(p->partial), p->dflag + 4,
+        p->dflag + 4 + p->R};
+  const long long vs_r = n3, vs_j = (long long)p->R * n3;  // V is [m+1][R][n3]
+  const bool prec = p->opt.precond == 2;
+  std::vector<int> all(nrhs, 1), act(nrhs, 1), incyc(nrhs, 0), jcut(nrhs, 0), iters(nrhs, 0);
+  std::vector<int> cycles(nrhs, 0), conv(nrhs, 0);
+  std::vector<double> bn2, rn2, rel(nrhs, 0.0);
+  sync_active(p, K.d_active, all);
+  norm2_dev(K, b, n3, p->hcol2, K.d_active);
+  read_scalars(p, p->hcol2, nrhs, bn2);
+  // initial residual r = b - A x
+  auto true_residual = [&](void) {
+    sync_active(p, K.d_active, all);
+    apply_operator(p, nrhs, x, p->work, fp32, nullptr);
+    {
+      KTimer t(&p->prof, p->st, "kry_residual", 48.0 * n3 * nrhs);
+      hipLaunchKernelGGL(k_axpby, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, b, p->work, -1.0,
+                         p->rvec, n3, n3, nullptr, K.partial, K.B);
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
+                       p->hcol2, 0, K.d_active);
+    HIPCHK(hipGetLastError());
+    read_scalars(p, p->hcol2, nrhs, rn2);
+    for (int r = 0; r < nrhs; ++r) {
+      rel[r] = bn2[r] > 0 ? std::sqrt(rn2[r] / bn2[r]) : 0.0;
+      REQUIRE(std::isfinite(rel[r]), DDA_EDEVICE, "non-finite residual for right-hand side %d", r);
+    }
+  };
+  true_residual();
+  for (int r = 0; r < nrhs; ++r)
+    if (rel[r] <= tol || bn2[r] == 0.0) { act[r] = 0; conv[r] = 1; }
+  std::vector<double> hp(8 * nrhs);
+  while (true) {
+    bool any = false;
+    for (int r = 0; r < nrhs; ++r) any = any || (act[r] && iters[r] < maxit);
+    if (!any) break;
+    for (int r = 0; r < nrhs; ++r) {
+      incyc[r] = act[r] && iters[r] < maxit;
+      jcut[r] = 0;
+      if (incyc[r]) cycles[r] += 1;
+    }
+    sync_active(p, K.d_active, incyc);
+    // v0 = r / ||r||, g = beta e1
+    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, p->st, p->hcol2, p->gvec, m, p->dscal,
+                       K.d_active, nrhs);
+    hipLaunchKernelGGL(k_scale, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->rvec, p->V, n3, n3,
+                       vs_r, p->dscal + 1, 8, K.d_active);
+    HIPCHK(hipGetLastError());
+    int jused = 0;
+    for (int j = 0; j < m; ++j) {
+      double2 *vj = p->V + (long long)j * vs_j;
+      double2 *w = p->V + (long long)(j + 1) * vs_j;
+      // basis block j is contiguous [nrhs][n3]: transform it in place of a copy
+      const double2 *z = vj;
+      if (prec) {
+        apply_precond(p, nrhs, vj, p->work2, fp32, nullptr);
+        z = p->work2;
+      }
+      apply_operator(p, nrhs, z, w, fp32, nullptr);
+      // CGS2
+      for (int pass = 0; pass < 2; ++pass) {
+        double2 *hdst = pass == 0 ? p->hcol : p->hcol2;
+        {
+          KTimer t(&p->prof, p->st, "kry_multidot", 16.0 * n3 * (j + 2) * nrhs);
+          hipLaunchKernelGGL(k_multidot, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r,
+                             vs_j, j + 1, w, vs_r, n3, K.d_active, K.partial, K.B);
+        }
+        hipLaunchKernelGGL(k_finalize, dim3(j + 1, nrhs), dim3(kRedThreads), 0, p->st, K.partial,
+                           K.B, hdst, 0, K.d_active);
+        {
+          KTimer t(&p->prof, p->st, "kry_multiaxpy", 16.0 * n3 * (j + 3) * nrhs);
+          hipLaunchKernelGGL(k_multiaxpy, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V,
+                             vs_r, vs_j, j + 1, hdst, w, vs_r, n3, K.d_active,
+                             pass == 1 ? K.partial : nullptr, K.B);
+        }
+        HIPCHK(hipGetLastError());
+      }
+      hipLaunchKernelGGL(k_finalize, dim3(1, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
+                         p->ycoef, 0, K.d_active);
+      hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, p->st, j, m, p->H, p->givens, p->gvec,
+                         p->hcol, p->hcol2, p->ycoef, p->dscal, K.d_active, nrhs);
+      hipLaunchKernelGGL(k_scale, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, w, w, n3, vs_r,
+                         vs_r, p->dscal + 1, 8, K.d_active);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(hp.data(), p->dscal, sizeof(double) * 8 * nrhs, hipMemcpyDeviceToHost,
+                            p->st));
+      HIPCHK(hipStreamSynchronize(p->st));
+      jused = j + 1;
+      bool left = false;
+      for (int r = 0; r < nrhs; ++r) {
+        if (!incyc[r]) continue;
+        iters[r] += 1;
+        const double est = hp[8 * r] / std::sqrt(bn2[r]);
+        REQUIRE(std::isfinite(est), DDA_EDEVICE, "non-finite residual estimate (RHS %d)", r);
+        const bool brk = hp[8 * r + 2] == 0.0;
+        if (est <= tol || brk || iters[r] >= maxit || j == m - 1) {
+          jcut[r] = j + 1;
+          incyc[r] = 0;
+        } else {
+          left = true;
+        }
+      }
+      sync_active(p, K.d_active, incyc);
+      if (!left) break;
+    }
+    (void)jused;
+    // x += P^{-1} (V y)
+    HIPCHK(hipMemcpyAsync(K.d_jcut, jcut.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, p->st));
+    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, p->st, p->H, p->gvec, m, K.d_jcut, p->ycoef,
+                       nrhs);
+    int jmax = 0;
+    for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jcut[r]);
+    {
+      KTimer t(&p->prof, p->st, "kry_combine", 16.0 * n3 * (jmax + 1) * nrhs);
+      hipLaunchKernelGGL(k_combine, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r, vs_j,
+                         jmax, p->ycoef, p->work2, n3, n3);
+    }
+    HIPCHK(hipGetLastError());
+    if (prec) apply_precond(p, nrhs, p->work2, p->work2, fp32, nullptr);
+    hipLaunchKernelGGL(k_axpby, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, x, p->work2, 1.0, x,
+                       n3, n3, nullptr, nullptr, K.B);
+    HIPCHK(hipGetLastError());
+    true_residual();
+    for (int r = 0; r < nrhs; ++r) {
+      if (!act[r]) continue;
+      if (rel[r] <= tol) { act[r] = 0; conv[r] = 1; }
+    }
+  }
+  for (int r = 0; r < nrhs; ++r) {
+    st[r].iters += iters[r];
+    st[r].cycles += cycles[r];
+    st[r].rel_residual = rel[r];
+    st[r].converged = conv[r];
+  }
+}
+
+dda_status solve_system(dda_problem *p, int nrhs, const double2 *b, double2 *x, dda_stats *st) {
+  const long long n3 = 3 * p->N;
+  const int B = reduce_blocks(n3);
+  for (int r = 0; r < nrhs; ++r) st[r] = dda_stats{0, 0, 0, 0, 0.0, 0.0};
+  if (p->opt.precision == 0) {
+    gmres_solve(p, nrhs, b, x, 0, p->opt.tol, p->opt.max_iter, st);
+  } else {
+    // FP64 refinement: r = b - A x (FP64); inner FP32 solve A d = r; x += d
+    std::vector<double> rel(nrhs);
+    std::vector<int> done(nrhs, 0);
+    for (int it = 0; it <= p->opt.max_refine; ++it) {
+      residual(p, nrhs, b, x, p->xref, rel.data());
+      bool all = true;
+      for (int r = 0; r < nrhs; ++r) {
+        st[r].rel_residual = rel[r];
+        REQUIRE(std::isfinite(rel[r]), DDA_EDEVICE, "non-finite refinement residual (RHS %d)", r);
+        if (rel[r] <= p->opt.tol) { st[r].converged = 1; done[r] = 1; }
+        all = all && done[r];
+      }
+      int used = 0;
+      for (int r = 0; r < nrhs; ++r) used = std::max(used, st[r].iters);
+      if (all || it == p->opt.max_refine || used >= p->opt.max_iter) break;
+      // inner solve from zero; the correction of converged RHS is dropped
+      HIPCHK(hipMemsetAsync(p->rref, 0, sizeof(double2) * n3 * nrhs, p->st));
+      std::vector<dda_stats> inner(nrhs, dda_stats{0, 0, 0, 0, 0.0, 0.0});
+      gmres_solve(p, nrhs, p->xref, p->rref, 1, p->opt.inner_tol, p->opt.max_iter - used, inner.data());
+      std::vector<double> keep(nrhs);
+      for (int r = 0; r < nrhs; ++r) {
+        st[r].iters += inner[r].iters;
+        st[r].cycles += inner[r].cycles;
+        if (!done[r]) st[r].refinements += 1;
+        keep[r] = done[r] ? 0.0 : 1.0;
+      }
+      // x += keep_r * d
+      double *ks = p->dscal + 8 * p->R;
+      HIPCHK(hipMemcpyAsync(ks, keep.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, p->st));
+      hipLaunchKernelGGL(k_scale, grid_r(B, nrhs), dim3(kRedThreads), 0, p->st, p->rref, p->rref, n3,
+                         n3, n3, ks, 1, nullptr);
+      hipLaunchKernelGGL(k_axpby, grid_r(B, nrhs), dim3(kRedThreads), 0, p->st, x, p->rref, 1.0, x,
+                         n3, n3, nullptr, nullptr, B);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(p->st));
+    }
+  }
+  bool ok = true;
+  for (int r = 0; r < nrhs; ++r) ok = ok && st[r].converged;
+  return ok ? DDA_OK : DDA_NOT_CONVERGED;
+}
+
+void krylov_alloc(dda_problem *p) {
+  const int m = p->opt.restart;
+  const int R = p->R;
+  const long long n3 = 3 * p->N;
+  HIPCHK(hipMalloc(&p->V, sizeof(double2) * (size_t)R * (m + 1) * n3));
+  HIPCHK(hipMemsetAsync(p->V, 0, sizeof(double2) * (size_t)R * (m + 1) * n3, p->st));
+  HIPCHK(hipMalloc(&p->work, sizeof(double2) * (size_t)R * n3));
+  HIPCHK(hipMalloc(&p->work2, sizeof(double2) * (size_t)R * n3));
+  HIPCHK(hipMalloc(&p->bvec, sizeof(double2) * (size_t)R * n3));
+  HIPCHK(hipMalloc(&p->xvec, sizeof(double2) * (size_t)R * n3));
+  HIPCHK(hipMalloc(&p->rvec, sizeof(double2) * (size_t)R * n3));
+  if (p->opt.precision == 1) {
+    HIPCHK(hipMalloc(&p->xref, sizeof(double2) * (size_t)R * n3));
+    HIPCHK(hipMalloc(&p->rref, sizeof(double2) * (size_t)R * n3));
+  }
+  HIPCHK(hipMalloc(&p->H, sizeof(double2) * (size_t)R * (m + 1) * m));
+  HIPCHK(hipMalloc(&p->givens, sizeof(double2) * (size_t)R * m * 2));
+  HIPCHK(hipMalloc(&p->gvec, sizeof(double2) * (size_t)R * (m + 1)));
+  HIPCHK(hipMalloc(&p->hcol, sizeof(double2) * (size_t)R * kMaxM));
+  HIPCHK(hipMalloc(&p->hcol2, sizeof(double2) * (size_t)R * kMaxM));
+  HIPCHK(hipMalloc(&p->ycoef, sizeof(double2) * (size_t)R * kMaxM));
+  const int B = reduce_blocks(n3);
+  p->partial_elems = std::max<size_t>((size_t)R * kMaxM * B * 2, (size_t)R * 512 * 4);
+  HIPCHK(hipMalloc(&p->partial, sizeof(double) * p->partial_elems));
+  HIPCHK(hipMalloc(&p->dscal, sizeof(double) * 16 * R));
+  std::vector<double> init(16 * R, 0.0);
+  for (int r = 0; r < R; ++r) init[r * 8 + 7] = 1.0;  // unit scale slot
+  HIPCHK(hipMemcpy(p->dscal, init.data(), sizeof(double) * 16 * R, hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc(&p->dflag, sizeof(int) * (4 + 2 * R)));
+  HIPCHK(hipMemset(p->dflag, 0, sizeof(int) * (4 + 2 * R)));
+}
+
+}  // namespace dda

@@ -1,0 +1,353 @@
+// The DDA operator: problem setup (polarisability, incident field), the Green-tensor
+// kernel spectrum, and the five-pass zero-padded FFT product (Sec. 1, 2.1-2.2).
+#include <cmath>
+
+#include "fft_kernels.h"
+
+namespace dda {
+
+// d^3 G_ab at displacement (x, y, z), six components xx xy xz yy yz zz (Sec. 2:
+// G = e^{ikr}/r [k^2 (I - rr^T) + (ikr - 1)/r^2 (I - 3 rr^T)]).
+__device__ __forceinline__ void green6_d3(double x, double y, double z, double k, double d3,
+                                          double2 g[6]) {
+  const double r2 = x * x + y * y + z * z;
+  const double r = sqrt(r2);
+  const double ir = 1.0 / r;
+  const double h[3] = {x * ir, y * ir, z * ir};
+  double sn, cs;
+  sincos(k * r, &sn, &cs);
+  const double2 e = make_double2(cs * ir * d3, sn * ir * d3);
+  const double k2 = k * k;
+  const double ir2 = ir * ir;
+  const double kr = k * r;
+  int c = 0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = a; b < 3; ++b) {
+      const double P = h[a] * h[b];
+      const double dl = (a == b) ? 1.0 : 0.0;
+      const double re = k2 * (dl - P) - (dl - 3.0 * P) * ir2;
+      const double im = kr * (dl - 3.0 * P) * ir2;
+      g[c++] = cmul(e, make_double2(re, im));
+    }
+}
+
+// Embedding of K(p, q, s) = d^3 G(p d, q d, s d) on the (2nx, 2ny, 2nz) circulant grid:
+// index i <-> offset i (i < n), i - 2n (i > n); index n (offset +-n, never used) and the
+// origin hold 0.  part = 1 keeps only d^3 Im G (as a real-valued kernel).
+__global__ void k_green_pad(double2 *out, int nx, int ny, int nz, double k, double d, int part) {
+  const long long Lx = 2LL * nx, Ly = 2LL * ny, Lz = 2LL * nz;
+  const long long tot = Lx * Ly * Lz;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  const int ix = (int)(idx % Lx);
+  const int iy = (int)((idx / Lx) % Ly);
+  const int iz = (int)(idx / (Lx * Ly));
+  double2 g[6];
+  bool zero = (ix == nx) || (iy == ny) || (iz == nz) || (ix == 0 && iy == 0 && iz == 0);
+  if (!zero) {
+    const int p = ix < nx ? ix : ix - 2 * nx;
+    const int q = iy < ny ? iy : iy - 2 * ny;
+    const int s = iz < nz ? iz : iz - 2 * nz;
+    green6_d3(p * d, q * d, s * d, k, d * d * d, g);
+    if (part == 1)
+      for (int c = 0; c < 6; ++c) g[c] = make_double2(g[c].y, 0.0);
+  } else {
+    for (int c = 0; c < 6; ++c) g[c] = make_double2(0.0, 0.0);
+  }
+  for (int c = 0; c < 6; ++c) out[c * tot + idx] = g[c];
+}
+
+template <typename TO>
+__global__ void k_extract_octant(const double2 *full, TO *oct, int nx, int ny, int nz) {
+  const long long ox_n = nx + 1, oy_n = ny + 1, oz_n = nz + 1;
+  const long long per = ox_n * oy_n * oz_n;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 6 * per) return;
+  const int c = (int)(idx / per);
+  const long long rem = idx - c * per;
+  const int ox = (int)(rem % ox_n);
+  const int oy = (int)((rem / ox_n) % oy_n);
+  const int oz = (int)(rem / (ox_n * oy_n));
+  const long long Lx = 2LL * nx, Ly = 2LL * ny, Lz = 2LL * nz;
+  const double2 v = full[c * Lx * Ly * Lz + ((long long)oz * Ly + oy) * Lx + ox];
+  oct[idx] = to_c(v, TO{});
+}
+
+// Occupancy, invalid permittivities and the occupied-permittivity sum, per block.
+__global__ void k_validate(const uint8_t *mask, const double2 *eps, long long N, double *partial) {
+  __shared__ double sh[4][256];
+  double occ = 0, bad = 0, sr = 0, si = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (mask[i]) {
+      const double2 e = eps[i];
+      occ += 1.0;
+      sr += e.x;
+      si += e.y;
+      const double d1 = fabs(e.x - 1.0) + fabs(e.y), d2 = fabs(e.x + 2.0) + fabs(e.y);
+      if (d1 < 1e-12 || d2 < 1e-12 || !isfinite(e.x) || !isfinite(e.y)) bad += 1.0;
+    }
+  }
+  sh[0][threadIdx.x] = occ;
+  sh[1][threadIdx.x] = bad;
+  sh[2][threadIdx.x] = sr;
+  sh[3][threadIdx.x] = si;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 4; ++q) partial[blockIdx.x * 4 + q] = sh[q][0];
+}
+
+__global__ void k_alpha(const uint8_t *mask, const double2 *eps, long long N, double kd,
+                        const double *S, double2 *ainv) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= N) return;
+  ainv[r * N + i] = mask[i] ? ldr_alpha_inv(eps[i], kd, S[r]) : make_double2(0.0, 0.0);
+}
+
+// b[r][a][v] = pol_a exp(+-i k dir . r_v) on occupied voxels, 0 in air.
+__global__ void k_incident(const uint8_t *mask, int nx, int ny, int nz, double k, double d,
+                           const double *dirpol, int conj, double2 *b) {
+  const long long N = (long long)nx * ny * nz;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= N) return;
+  const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long long)nx * ny));
+  const double x = (ix - 0.5 * (nx - 1)) * d, y = (iy - 0.5 * (ny - 1)) * d,
+               z = (iz - 0.5 * (nz - 1)) * d;
+  const double *dp = dirpol + 6 * r;
+  const double ph = k * (dp[0] * x + dp[1] * y + dp[2] * z);
+  double sn, cs;
+  sincos(ph, &sn, &cs);
+  if (conj) sn = -sn;
+  double2 *br = b + (long long)r * 3 * N;
+  for (int a = 0; a < 3; ++a) {
+    double2 v = make_double2(0.0, 0.0);
+    if (mask[i]) v = make_double2(dp[3 + a] * cs, dp[3 + a] * sn);
+    br[a * N + i] = v;
+  }
+}
+
+static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+void setup_alpha(dda_problem *p, int nrhs, const double *S_host) {
+  HIPCHK(hipMemcpyAsync(p->Sdev, S_host, sizeof(double) * nrhs, hipMemcpyHostToDevice, p->st));
+  KTimer t(&p->prof, p->st, "alpha_setup", 33.0 * p->N * nrhs);
+  hipLaunchKernelGGL(k_alpha, dim3(nblk(p->N, 256), nrhs), dim3(256), 0, p->st, p->mask, p->eps,
+                     p->N, p->k * p->d, p->Sdev, p->ainv);
+  HIPCHK(hipGetLastError());
+}
+
+void setup_rhs(dda_problem *p, int nrhs, const double *dir, const double *pol, double2 *b,
+               int conjugate) {
+  std::vector<double> dp(6 * nrhs);
+  for (int r = 0; r < nrhs; ++r)
+    for (int a = 0; a < 3; ++a) {
+      dp[6 * r + a] = dir[3 * r + a];
+      dp[6 * r + 3 + a] = pol[3 * r + a];
+    }
+  double *dd = p->dscal + 8 * p->R;  // scratch area after the per-RHS scalars
+  HIPCHK(hipMemcpyAsync(dd, dp.data(), sizeof(double) * 6 * nrhs, hipMemcpyHostToDevice, p->st));
+  KTimer t(&p->prof, p->st, "incident_field", 49.0 * p->N * nrhs);
+  hipLaunchKernelGGL(k_incident, dim3(nblk(p->N, 256), nrhs), dim3(256), 0, p->st, p->mask,
+                     p->nx, p->ny, p->nz, p->k, p->d, dd, conjugate, b);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(p->st));  // dp is host-local
+}
+
+static void kernel_spectrum(dda_problem *p, int part) {
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const long long L3 = 8LL * p->N;
+  double2 *tmp = nullptr;
+  HIPCHK(hipMalloc(&tmp, sizeof(double2) * 6 * L3));
+  try {
+    hipLaunchKernelGGL(k_green_pad, dim3(nblk(L3, 256)), dim3(256), 0, p->st, tmp, nx, ny, nz, p->k,
+                       p->d, part);
+    HIPCHK(hipGetLastError());
+    fft_rows_plain(p, p->px, tmp, 6LL * (2 * nz) * (2 * ny), 0);
+    fft_strided_plain(p, p->py, tmp, 6LL * (2 * nz), 2LL * nx, 0);
+    fft_strided_plain(p, p->pz, tmp, 6LL, 4LL * nx * ny, 0);
+    const long long oct = 6LL * (nx + 1) * (ny + 1) * (nz + 1);
+    if (part == 0) {
+      hipLaunchKernelGGL(k_extract_octant<double2>, dim3(nblk(oct, 256)), dim3(256), 0, p->st, tmp,
+                         p->khat64, nx, ny, nz);
+      hipLaunchKernelGGL(k_extract_octant<float2>, dim3(nblk(oct, 256)), dim3(256), 0, p->st, tmp,
+                         p->khat32, nx, ny, nz);
+    } else {
+      hipLaunchKernelGGL(k_extract_octant<double2>, dim3(nblk(oct, 256)), dim3(256), 0, p->st, tmp,
+                         p->khatI64, nx, ny, nz);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(p->st));
+  } catch (...) {
+    (void)hipFree(tmp);
+    throw;
+  }
+  HIPCHK(hipFree(tmp));
+}
+
+void operator_setup(dda_problem *p) {
+  // validation and mean permittivity
+  const int nb = 1024;
+  double *part = nullptr;
+  HIPCHK(hipMalloc(&part, sizeof(double) * 4 * nb));
+  hipLaunchKernelGGL(k_validate, dim3(nb), dim3(256), 0, p->st, p->mask, p->eps, p->N, part);
+  std::vector<double> h(4 * nb);
+  hipError_t e1 = hipGetLastError();
+  hipError_t e2 = hipMemcpyAsync(h.data(), part, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, p->st);
+  hipError_t e3 = hipStreamSynchronize(p->st);
+  (void)hipFree(part);
+  REQUIRE(e1 == hipSuccess && e2 == hipSuccess && e3 == hipSuccess, DDA_EDEVICE,
+          "validation kernel failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3)));
+  double occ = 0, bad = 0, sr = 0, si = 0;
+  for (int b = 0; b < nb; ++b) {
+    occ += h[4 * b];
+    bad += h[4 * b + 1];
+    sr += h[4 * b + 2];
+    si += h[4 * b + 3];
+  }
+  REQUIRE(occ > 0, DDA_EINVAL, "the mask has no occupied voxel");
+  REQUIRE(bad == 0, DDA_EINVAL,
+          "%.0f occupied voxel(s) have eps = 1, eps = -2 or a non-finite eps (polarisability undefined)",
+          bad);
+  p->n_occ = (long long)occ;
+  p->eps_mean = make_double2(sr / occ, si / occ);
+
+  const long long oct = 6LL * (p->nx + 1) * (p->ny + 1) * (p->nz + 1);
+  HIPCHK(hipMalloc(&p->khat64, sizeof(double2) * oct));
+  HIPCHK(hipMalloc(&p->khat32, sizeof(float2) * oct));
+  kernel_spectrum(p, 0);
+}
+
+static void ensure_imag_spectrum(dda_problem *p) {
+  if (p->khatI64) return;
+  const long long oct = 6LL * (p->nx + 1) * (p->ny + 1) * (p->nz + 1);
+  HIPCHK(hipMalloc(&p->khatI64, sizeof(double2) * oct));
+  kernel_spectrum(p, 1);
+}
+
+// ----------------------------------------------------------------------------- the product
+
+template <typename T>
+static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat) {
+  const int n = p->pz.n;
+  constexpr int EPT = EptOf<T>::value;
+  ZArgs a;
+  a.pl = desc(p->pz);
+  a.nz = p->nz;
+  a.ny = p->ny;
+  a.nx = p->nx;
+  a.plane = 4LL * p->nx * p->ny;
+  // columns per tile: three components of tw columns in at most the LDS budget
+  const size_t budget = std::min<size_t>(p->lds_zpass, p->lds_max);
+  int tw = (int)(budget / (sizeof(cplx<T>) * (size_t)n * 3)) ;
+  while (tw > 1 && (size_t)n * (3 * tw + 1) * sizeof(cplx<T>) > budget) --tw;
+  if (tw < 1) tw = 1;
+  while (tw > 1 && ((3LL * tw * n + EPT - 1) / EPT) > 768) --tw;
+  if (tw > a.plane) tw = (int)a.plane;
+  a.tw = tw;
+  a.ntiles = (a.plane + tw - 1) / tw;
+  int threads = (int)((3LL * tw * n + EPT - 1) / EPT);
+  threads = ((threads + 63) / 64) * 64;
+  if (threads > 768) threads = 768;
+  const size_t lds = (size_t)n * (3 * tw + 1) * sizeof(cplx<T>);
+  auto fn = k_zpass<T, EPT>;
+  set_lds_limit((const void *)fn, lds);
+  const double sz = sizeof(cplx<T>);
+  const double bytes = nrhs * (2.0 * 3.0 * a.plane * p->nz * sz) +
+                       6.0 * (p->nx + 1) * (p->ny + 1) * (p->nz + 1) * sz;
+  KTimer t(&p->prof, p->st, sizeof(T) == 8 ? "zpass_f64" : "zpass_f32", bytes);
+  hipLaunchKernelGGL(fn, dim3((unsigned)(a.ntiles * nrhs)), dim3(threads), lds, p->st, w1,
+                     tw_of<T>(p->pz), khat, a);
+  HIPCHK(hipGetLastError());
+}
+
+// kind 0: DDA operator; kind 1: Im G convolution (scattering sum)
+template <typename T>
+static void op_passes(dda_problem *p, int nrhs, const double2 *x, double2 *y,
+                      const cplx<T> *khat, const double *xscale, int kind) {
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const double sz = sizeof(cplx<T>);
+  cplx<T> *w0 = reinterpret_cast<cplx<T> *>(p->w0);
+  cplx<T> *w1 = reinterpret_cast<cplx<T> *>(p->w1);
+  const long long rows = (long long)nrhs * 3 * nz * ny;
+  const double fsuf = sizeof(T) == 8 ? 0 : 1;
+  (void)fsuf;
+  // P1: x rows (masked) -> zero-padded length-2nx FFT
+  {
+    RowArgs a{};
+    a.rows = rows;
+    a.n_in = nx;
+    a.n_out = 2 * nx;
+    a.in_stride = nx;
+    a.out_stride = 2 * nx;
+    a.sign = -1;
+    a.mask = p->mask;
+    a.vox_rows = (long long)nz * ny;
+    a.rhs_rows = 3LL * nz * ny;
+    a.nx = nx;
+    a.N = p->N;
+    a.xscale = xscale;
+    launch_rows<T, ROW_OP_FWD, double2, cplx<T>>(
+        p, p->px, x, w0, a, sizeof(T) == 8 ? "op_x_fwd_f64" : "op_x_fwd_f32",
+        rows * (16.0 * nx + 1.0 * nx + sz * 2 * nx));
+  }
+  // P2: y transform, ny rows zero-padded to 2ny
+  launch_strided<T>(p, p->py, w0, w1, (long long)nrhs * 3 * nz, 2LL * nx, ny, 2 * ny,
+                    (long long)ny * 2 * nx, 4LL * ny * nx, -1,
+                    sizeof(T) == 8 ? "op_y_fwd_f64" : "op_y_fwd_f32",
+                    nrhs * 3.0 * nz * 2 * nx * (ny + 2.0 * ny) * sz);
+  // P3: z transform, kernel multiply, inverse z transform (in place)
+  zpass<T>(p, nrhs, w1, khat);
+  // P4: inverse y transform, keep ny rows
+  launch_strided<T>(p, p->py, w1, w0, (long long)nrhs * 3 * nz, 2LL * nx, 2 * ny, ny,
+                    4LL * ny * nx, (long long)ny * 2 * nx, +1,
+                    sizeof(T) == 8 ? "op_y_inv_f64" : "op_y_inv_f32",
+                    nrhs * 3.0 * nz * 2 * nx * (2.0 * ny + ny) * sz);
+  // P5: inverse x transform, keep nx, diagonal and mask epilogue
+  {
+    RowArgs a{};
+    a.rows = rows;
+    a.n_in = 2 * nx;
+    a.n_out = nx;
+    a.in_stride = 2 * nx;
+    a.out_stride = nx;
+    a.sign = +1;
+    a.mask = p->mask;
+    a.vox_rows = (long long)nz * ny;
+    a.rhs_rows = 3LL * nz * ny;
+    a.nx = nx;
+    a.N = p->N;
+    a.ainv = p->ainv;
+    a.xin = x;
+    a.xscale = xscale;
+    a.scale = 1.0 / (8.0 * (double)p->N);
+    if (kind == 0)
+      launch_rows<T, ROW_OP_INV, cplx<T>, double2>(
+          p, p->px, w0, y, a, sizeof(T) == 8 ? "op_x_inv_f64" : "op_x_inv_f32",
+          rows * (sz * 2 * nx + 16.0 * nx + 1.0 * nx + 16.0 * nx) + nrhs * 16.0 * p->N);
+    else
+      launch_rows<T, ROW_IMG_INV, cplx<T>, double2>(p, p->px, w0, y, a, "imag_x_inv",
+                                                    rows * (sz * 2 * nx + 1.0 * nx + 16.0 * nx));
+  }
+}
+
+void apply_operator(dda_problem *p, int nrhs, const double2 *x, double2 *y, int fp32,
+                    const double *xscale) {
+  if (fp32)
+    op_passes<float>(p, nrhs, x, y, p->khat32, xscale, 0);
+  else
+    op_passes<double>(p, nrhs, x, y, p->khat64, xscale, 0);
+}
+
+void apply_imag_conv(dda_problem *p, int nrhs, const double2 *x, double2 *y) {
+  ensure_imag_spectrum(p);
+  op_passes<double>(p, nrhs, x, y, p->khatI64, nullptr, 1);
+}
+
+}  // namespace dda

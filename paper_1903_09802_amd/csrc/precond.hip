@@ -1,0 +1,530 @@
+// The 2-level circulant preconditioner (Sec. 3, 3.1): setup and application.
+//
+// Setup.  eq. Chan along x then y on the signed-offset kernel K(p, q, s) = d^3 G(p d,
+// q d, s d) gives the generator c2_ab(pbar, qbar, s) (pbar < nx, qbar < ny, |s| < nz);
+// its 2-D DFT over (pbar, qbar) gives lambda_ab(wx, wy, s).  For every Fourier mode the
+// preconditioner is the dense 3nz x 3nz matrix
+//     B(w)[(a, iz), (b, jz)] = alpha~^{-1} delta - lambda_ab(w, iz - jz)
+// (Toeplitz along z).  Exact symmetries reduce the work:
+//   * B(-wx, wy) = Sx B(wx, wy) Sx and B(wx, -wy) = Sy B Sy, Sx = diag(-1, 1, 1) per
+//     component (the x / y parities of the six kernel blocks), so only modes with
+//     0 <= wx <= nx/2, 0 <= wy <= ny/2 are inverted;
+//   * B commutes with the z reflection (a, iz) -> s_a (a, nz-1-iz), s = (1, 1, -1), so
+//     each B splits into an even and an odd half of size 3 ceil(nz/2) (a padding entry is
+//     set to the identity when nz is odd).
+// The halves are inverted explicitly (Gauss-Jordan with partial pivoting, blocked) and
+// stored column-major so the application is a coalesced matrix-vector product.
+#include <algorithm>
+#include <cmath>
+
+#include "fft_kernels.h"
+
+namespace dda {
+
+__device__ __forceinline__ void green6_chan(double x, double y, double z, double k, double d3,
+                                            double w, double2 acc[6]) {
+  const double r2 = x * x + y * y + z * z;
+  if (r2 == 0.0 || w == 0.0) return;
+  const double r = sqrt(r2);
+  const double ir = 1.0 / r;
+  const double h[3] = {x * ir, y * ir, z * ir};
+  double sn, cs;
+  sincos(k * r, &sn, &cs);
+  const double2 e = make_double2(cs * ir * d3 * w, sn * ir * d3 * w);
+  const double k2 = k * k, ir2 = ir * ir, kr = k * r;
+  int c = 0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = a; b < 3; ++b) {
+      const double P = h[a] * h[b];
+      const double dl = (a == b) ? 1.0 : 0.0;
+      acc[c] = cadd(acc[c], cmul(e, make_double2(k2 * (dl - P) - (dl - 3.0 * P) * ir2,
+                                                 kr * (dl - 3.0 * P) * ir2)));
+      ++c;
+    }
+}
+
+// gen[c][s + nz - 1][qbar][pbar] = sum over p in {pbar, pbar - nx}, q in {qbar, qbar - ny} of
+// wx(p) wy(q) K_c(p, q, s), with wx(pbar) = (nx - pbar)/nx, wx(pbar - nx) = pbar/nx (eq. Chan).
+__global__ void k_chan_gen(double2 *gen, int nx, int ny, int nz, double k, double d) {
+  const long long S = 2LL * nz - 1;
+  const long long tot = S * ny * nx;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  const int pb = (int)(idx % nx);
+  const int qb = (int)((idx / nx) % ny);
+  const int si = (int)(idx / ((long long)nx * ny));
+  const int s = si - (nz - 1);
+  double2 acc[6];
+  for (int c = 0; c < 6; ++c) acc[c] = make_double2(0.0, 0.0);
+  const double d3 = d * d * d;
+  const int ps[2] = {pb, pb - nx};
+  const double wxs[2] = {(double)(nx - pb) / nx, (double)pb / nx};
+  const int qs[2] = {qb, qb - ny};
+  const double wys[2] = {(double)(ny - qb) / ny, (double)qb / ny};
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      const double w = wxs[u] * wys[v];
+      if (w == 0.0) continue;
+      green6_chan(ps[u] * d, qs[v] * d, s * d, k, d3, w, acc);
+    }
+  for (int c = 0; c < 6; ++c) gen[c * tot + idx] = acc[c];
+}
+
+// Assemble the transposed half-blocks X = B_sigma^T (row-major) for matrices
+// [m0, m0 + count) of the list (mode u = m / 2, half = m % 2: 0 even, 1 odd).
+__global__ void k_assemble(const double2 *lam, double2 *out, long long m0, int nx, int ny,
+                           int nz, int umx, int hh, int n2, double2 ati) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2 *L = reinterpret_cast<double2 *>(smem_raw);  // [6][2nz-1]
+  const long long m = m0 + blockIdx.x;
+  const long long u = m / 2;
+  const int half = (int)(m % 2);
+  const int uy = (int)(u / umx), ux = (int)(u % umx);
+  const long long S = 2LL * nz - 1;
+  const long long plane = (long long)nx * ny;
+  for (int e = threadIdx.x; e < 6 * S; e += blockDim.x) {
+    const int c = e / (int)S;
+    const int s = e - c * (int)S;
+    L[e] = lam[((long long)c * S + s) * plane + (long long)uy * nx + ux];
+  }
+  __syncthreads();
+  const double sig = half == 0 ? 1.0 : -1.0;
+  const int h = nz / 2;
+  double2 *X = out + (long long)blockIdx.x * n2 * n2;
+  for (long long e = threadIdx.x; e < (long long)n2 * n2; e += blockDim.x) {
+    const int row = (int)(e / n2), col = (int)(e % n2);
+    // X[row][col] = B_sigma[col][row]: B row index (a, iz) = col, column index (b, jz) = row
+    const int a = col / hh, iz = col % hh;
+    const int b = row / hh, jz = row % hh;
+    const double sa = a == 2 ? -1.0 : 1.0, sb = b == 2 ? -1.0 : 1.0;
+    const bool vr = (iz < h) || (sig * sa > 0.0);
+    const bool vc = (jz < h) || (sig * sb > 0.0);
+    double2 val = make_double2(0.0, 0.0);
+    if (!vr || !vc) {
+      if (row == col) val = make_double2(1.0, 0.0);
+    } else {
+      const int cab = comp_index(a, b);
+      // B[(a,iz),(b,jz)] = ati delta - lambda_ab(iz - jz)
+      double2 t = L[cab * S + (iz - jz) + (nz - 1)];
+      val = make_double2(-t.x, -t.y);
+      if (a == b && iz == jz) val = cadd(val, ati);
+      if (jz < h) {
+        const int jm = nz - 1 - jz;
+        double2 t2 = L[cab * S + (iz - jm) + (nz - 1)];
+        double2 v2 = make_double2(-t2.x, -t2.y);
+        if (a == b && iz == jm) v2 = cadd(v2, ati);
+        val = cadd(val, cscale(v2, sig * sb));
+      }
+    }
+    X[e] = val;
+  }
+}
+
+// Batched in-place inverse of row-major n x n complex matrices, one workgroup each:
+// Gauss-Jordan elimination with partial pivoting, blocked by NB columns.  For each panel
+// the NB pivot steps run in LDS on the n x NB panel (recording the multipliers F); the
+// other columns then receive the panel's row swaps, a short recurrence over the NB
+// pivot rows and a rank-NB update of the remaining rows.  Column interchanges are undone
+// at the end.  A zero pivot sets flag[0].
+template <int NB>
+__global__ void __launch_bounds__(256) k_gj_inverse(double2 *mats, int n, int *flag) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2 *P = reinterpret_cast<double2 *>(smem_raw);  // [n][NB]
+  double2 *F = P + (size_t)n * NB;                      // [n][NB]
+  int *pivall = reinterpret_cast<int *>(F + (size_t)n * NB);  // [n]
+  __shared__ double2 ipv_s[NB];
+  __shared__ double red_v[256];
+  __shared__ int red_i[256];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double2 *A = mats + (long long)blockIdx.x * n * n;
+  for (int k0 = 0; k0 < n; k0 += NB) {
+    const int kb = min(NB, n - k0);
+    for (int e = tid; e < n * NB; e += nt) {
+      const int i = e / NB, c = e % NB;
+      P[e] = c < kb ? A[(long long)i * n + k0 + c] : make_double2(0.0, 0.0);
+      F[e] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kb; ++kk) {
+      const int k = k0 + kk;
+      // pivot: argmax |P[i][kk]| over i >= k (ties -> smallest i)
+      double bv = -1.0;
+      int bi = k;
+      for (int i = k + tid; i < n; i += nt) {
+        const double2 v = P[i * NB + kk];
+        const double m2 = v.x * v.x + v.y * v.y;
+        if (m2 > bv) { bv = m2; bi = i; }
+      }
+      red_v[tid] = bv;
+      red_i[tid] = bi;
+      __syncthreads();
+      for (int s = nt / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+          const double ov = red_v[tid + s];
+          const int oi = red_i[tid + s];
+          if (ov > red_v[tid] || (ov == red_v[tid] && oi < red_i[tid])) {
+            red_v[tid] = ov;
+            red_i[tid] = oi;
+          }
+        }
+        __syncthreads();
+      }
+      const int pr = red_i[0];
+      if (tid < NB && pr != k) {
+        double2 t = P[k * NB + tid]; P[k * NB + tid] = P[pr * NB + tid]; P[pr * NB + tid] = t;
+        t = F[k * NB + tid]; F[k * NB + tid] = F[pr * NB + tid]; F[pr * NB + tid] = t;
+      }
+      if (tid == 0) pivall[k] = pr;
+      __syncthreads();
+      const double2 pv = P[k * NB + kk];
+      const double pm = pv.x * pv.x + pv.y * pv.y;
+      double2 ipv = make_double2(0.0, 0.0);
+      if (pm > 0.0) ipv = make_double2(pv.x / pm, -pv.y / pm);
+      else if (tid == 0) atomicExch(flag, 1);
+      for (int i = tid; i < n; i += nt) F[i * NB + kk] = (i == k) ? make_double2(0.0, 0.0) : P[i * NB + kk];
+      if (tid == 0) ipv_s[kk] = ipv;
+      __syncthreads();
+      if (tid < kb) P[k * NB + tid] = (tid == kk) ? ipv : cmul(P[k * NB + tid], ipv);
+      __syncthreads();
+      for (int e = tid; e < n * kb; e += nt) {
+        const int i = e / kb, c = e % kb;
+        if (i == k) continue;
+        const double2 f = F[i * NB + kk];
+        if (c == kk) P[i * NB + c] = make_double2(-(f.x * ipv.x - f.y * ipv.y), -(f.x * ipv.y + f.y * ipv.x));
+        else P[i * NB + c] = csub(P[i * NB + c], cmul(f, P[k * NB + c]));
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < n * kb; e += nt) {
+      const int i = e / kb, c = e % kb;
+      A[(long long)i * n + k0 + c] = P[i * NB + c];
+    }
+    // trailing columns: one thread per column
+    for (int jj = tid; jj < n - kb; jj += nt) {
+      const int j = jj < k0 ? jj : jj + kb;
+      for (int kk = 0; kk < kb; ++kk) {
+        const int k = k0 + kk, pr = pivall[k];
+        if (pr != k) {
+          double2 t = A[(long long)k * n + j];
+          A[(long long)k * n + j] = A[(long long)pr * n + j];
+          A[(long long)pr * n + j] = t;
+        }
+      }
+      double2 aK[NB], tv[NB];
+#pragma unroll
+      for (int kk = 0; kk < NB; ++kk)
+        aK[kk] = kk < kb ? A[(long long)(k0 + kk) * n + j] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int kk = 0; kk < NB; ++kk) {
+        if (kk >= kb) { tv[kk] = make_double2(0.0, 0.0); continue; }
+        const double2 t = cmul(aK[kk], ipv_s[kk]);
+        tv[kk] = t;
+#pragma unroll
+        for (int k2 = 0; k2 < NB; ++k2)
+          if (k2 != kk && k2 < kb) aK[k2] = csub(aK[k2], cmul(F[(k0 + k2) * NB + kk], t));
+        aK[kk] = t;
+      }
+#pragma unroll
+      for (int kk = 0; kk < NB; ++kk)
+        if (kk < kb) A[(long long)(k0 + kk) * n + j] = aK[kk];
+      for (int i = 0; i < n; ++i) {
+        if (i >= k0 && i < k0 + kb) continue;
+        double2 acc = A[(long long)i * n + j];
+#pragma unroll
+        for (int kk = 0; kk < NB; ++kk) acc = csub(acc, cmul(F[i * NB + kk], tv[kk]));
+        A[(long long)i * n + j] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  // undo the column interchanges, last first (each thread owns whole rows)
+  for (int i = tid; i < n; i += nt) {
+    for (int k = n - 1; k >= 0; --k) {
+      const int pr = pivall[k];
+      if (pr != k) {
+        double2 t = A[(long long)i * n + k];
+        A[(long long)i * n + k] = A[(long long)i * n + pr];
+        A[(long long)i * n + pr] = t;
+      }
+    }
+  }
+}
+
+__global__ void k_to_f32(const double2 *in, float2 *out, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
+static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+void precond_free(dda_problem *p) {
+  if (p->binv64) (void)hipFree(p->binv64);
+  if (p->binv32) (void)hipFree(p->binv32);
+  p->binv64 = nullptr;
+  p->binv32 = nullptr;
+  p->prec_built = 0;
+}
+
+void precond_build(dda_problem *p, double s_bar) {
+  precond_free(p);
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  p->ati = ldr_alpha_inv(p->eps_mean, p->k * p->d, s_bar);
+  p->hh = (nz + 1) / 2;
+  p->n2 = 3 * p->hh;
+  p->umx = nx / 2 + 1;
+  p->umy = ny / 2 + 1;
+  const long long U = (long long)p->umx * p->umy;
+  const long long nmat = 2 * U;
+  const long long msz = (long long)p->n2 * p->n2;
+  const int fp32 = p->opt.precision == 1;
+  const size_t final_bytes = (size_t)nmat * msz * (fp32 ? sizeof(float2) : sizeof(double2));
+  size_t freeb = 0, totb = 0;
+  HIPCHK(hipMemGetInfo(&freeb, &totb));
+  REQUIRE(final_bytes < (size_t)(0.85 * (double)freeb), DDA_ENOMEM,
+          "preconditioner blocks need %.2f GB, %.2f GB free", final_bytes / 1e9, freeb / 1e9);
+
+  // generator and its 2-D DFT
+  const long long S = 2LL * nz - 1;
+  const long long gtot = 6 * S * (long long)nx * ny;
+  double2 *gen = nullptr, *scratch = nullptr;
+  HIPCHK(hipMalloc(&gen, sizeof(double2) * gtot));
+  try {
+    hipLaunchKernelGGL(k_chan_gen, dim3(nblk(S * nx * ny, 256)), dim3(256), 0, p->st, gen, nx, ny,
+                       nz, p->k, p->d);
+    HIPCHK(hipGetLastError());
+    fft_rows_plain(p, p->ux, gen, 6 * S * ny, 0);
+    fft_strided_plain(p, p->uy, gen, 6 * S, nx, 0);
+
+    if (fp32) HIPCHK(hipMalloc(&p->binv32, final_bytes));
+    else HIPCHK(hipMalloc(&p->binv64, final_bytes));
+    long long chunk = nmat;
+    if (fp32) {
+      chunk = std::max<long long>(1, (long long)((1ULL << 31) / (msz * sizeof(double2))));
+      chunk = std::min(chunk, nmat);
+      HIPCHK(hipMalloc(&scratch, sizeof(double2) * chunk * msz));
+    }
+    const size_t lds_asm = sizeof(double2) * 6 * S;
+    set_lds_limit((const void *)k_assemble, lds_asm);
+    constexpr int NB = 8;
+    const size_t lds_gj = sizeof(double2) * 2 * (size_t)p->n2 * NB + sizeof(int) * p->n2;
+    set_lds_limit((const void *)k_gj_inverse<NB>, lds_gj);
+    REQUIRE(lds_gj <= p->lds_max && lds_asm <= p->lds_max, DDA_EUNSUPPORTED,
+            "preconditioner blocks too large for LDS (nz = %d)", nz);
+    HIPCHK(hipMemsetAsync(p->dflag, 0, sizeof(int) * 4, p->st));
+    for (long long m0 = 0; m0 < nmat; m0 += chunk) {
+      const long long cnt = std::min(chunk, nmat - m0);
+      double2 *dst = fp32 ? scratch : p->binv64 + m0 * msz;
+      {
+        KTimer t(&p->prof, p->st, "pc_assemble", 16.0 * cnt * msz);
+        hipLaunchKernelGGL(k_assemble, dim3((unsigned)cnt), dim3(256), lds_asm, p->st, gen, dst, m0,
+                           nx, ny, nz, p->umx, p->hh, p->n2, p->ati);
+        HIPCHK(hipGetLastError());
+      }
+      {
+        KTimer t(&p->prof, p->st, "pc_gj_inverse", 32.0 * cnt * msz);
+        hipLaunchKernelGGL(k_gj_inverse<NB>, dim3((unsigned)cnt), dim3(256), lds_gj, p->st, dst,
+                           p->n2, p->dflag);
+        HIPCHK(hipGetLastError());
+      }
+      if (fp32) {
+        hipLaunchKernelGGL(k_to_f32, dim3(nblk(cnt * msz, 256)), dim3(256), 0, p->st, dst,
+                           p->binv32 + m0 * msz, cnt * msz);
+        HIPCHK(hipGetLastError());
+      }
+    }
+    int hflag[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(hflag, p->dflag, sizeof(int) * 4, hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    REQUIRE(hflag[0] == 0, DDA_EDEVICE, "a preconditioner block is singular");
+  } catch (...) {
+    if (gen) (void)hipFree(gen);
+    if (scratch) (void)hipFree(scratch);
+    precond_free(p);
+    throw;
+  }
+  HIPCHK(hipFree(gen));
+  if (scratch) HIPCHK(hipFree(scratch));
+  p->prec_built = 1;
+  p->prec_fp32 = fp32;
+}
+
+// ----------------------------------------------------------------------------- application
+
+// One workgroup per (unique mode, chunk of rc right-hand sides).  Gathers the
+// (+-wx, +-wy) mode vectors of each RHS, applies the Sx / Sy sign flips that map
+// them onto the stored mode, folds into the even / odd z halves, multiplies by
+// both stored inverse halves (read once for all vectors), unfolds, flips back and
+// writes in place.
+template <typename T>
+__global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__restrict__ binv,
+                                                 int nx, int ny, int nz, int umx, int hh, int n2,
+                                                 int nrhs, int rc, long long nchunks) {
+  using V = cplx<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V *Ub = reinterpret_cast<V *>(smem_raw);  // [2][nv][n2]
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const long long u = blockIdx.x / nchunks;
+  const int r0 = (int)(blockIdx.x - u * nchunks) * rc;
+  const int nr = min(rc, nrhs - r0);
+  const int uy = (int)(u / umx), ux = (int)(u % umx);
+  const int mxs[2] = {ux, (nx - ux) % nx};
+  const int mys[2] = {uy, (ny - uy) % ny};
+  const int nmx = (mxs[1] != mxs[0]) ? 2 : 1;
+  const int nmy = (mys[1] != mys[0]) ? 2 : 1;
+  const int nmode = nmx * nmy;
+  const int nv = nmode * nr;
+  const long long plane = (long long)nx * ny;
+  const int h = nz / 2;
+  // gather + fold
+  for (int e = tid; e < nv * 3 * hh; e += nt) {
+    const int vi = e / (3 * hh);
+    const int rem = e - vi * 3 * hh;
+    const int a = rem / hh, iz = rem - a * hh;
+    const int mode = vi / nr, r = r0 + vi % nr;
+    const int fx = mode % nmx, fy = mode / nmx;
+    const long long off = (long long)mys[fy] * nx + mxs[fx];
+    const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
+    const T sa = a == 2 ? (T)-1 : (T)1;
+    const long long cb = ((long long)r * 3 + a) * nz;
+    const V v1 = W[(cb + iz) * plane + off];
+    const V v2 = W[(cb + (nz - 1 - iz)) * plane + off];
+    const V vp = cscale(cadd(v1, cscale(v2, sa)), (T)0.5 * flip);
+    const V vm = cscale(csub(v1, cscale(v2, sa)), (T)0.5 * flip);
+    Ub[(0 * nv + vi) * n2 + a * hh + iz] = vp;
+    Ub[(1 * nv + vi) * n2 + a * hh + iz] = vm;
+  }
+  __syncthreads();
+  constexpr int MAXV = 16;
+  V acc[2][MAXV];
+  const int rows_per = (n2 + nt - 1) / nt;
+  for (int rp = 0; rp < rows_per; ++rp) {
+    const int i = tid + rp * nt;
+    const bool act = i < n2;
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+      for (int v = 0; v < MAXV; ++v) acc[hf][v] = mk<T>((T)0, (T)0);
+    if (act) {
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+        const V *M = binv + ((u * 2 + hf) * (long long)n2) * n2;
+        const V *Uh = Ub + (long long)hf * nv * n2;
+        for (int j = 0; j < n2; ++j) {
+          const V m = M[(long long)j * n2 + i];
+#pragma unroll
+          for (int v = 0; v < MAXV; ++v)
+            if (v < nv) acc[hf][v] = cadd(acc[hf][v], cmul(m, Uh[v * n2 + j]));
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+        for (int v = 0; v < MAXV; ++v)
+          if (v < nv) Ub[((long long)hf * nv + v) * n2 + i] = acc[hf][v];
+    }
+    __syncthreads();
+  }
+  // unfold + flip + scatter
+  for (int e = tid; e < nv * 3 * hh; e += nt) {
+    const int vi = e / (3 * hh);
+    const int rem = e - vi * 3 * hh;
+    const int a = rem / hh, iz = rem - a * hh;
+    const int mode = vi / nr, r = r0 + vi % nr;
+    const int fx = mode % nmx, fy = mode / nmx;
+    const long long off = (long long)mys[fy] * nx + mxs[fx];
+    const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
+    const T sa = a == 2 ? (T)-1 : (T)1;
+    const long long cb = ((long long)r * 3 + a) * nz;
+    const V wp = Ub[(0 * nv + vi) * n2 + a * hh + iz];
+    const V wm = Ub[(1 * nv + vi) * n2 + a * hh + iz];
+    W[(cb + iz) * plane + off] = cscale(cadd(wp, wm), flip);
+    if (iz < h) W[(cb + (nz - 1 - iz)) * plane + off] = cscale(csub(wp, wm), sa * flip);
+  }
+}
+
+template <typename T>
+static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, const cplx<T> *binv,
+                     const double *xscale) {
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const double sz = sizeof(cplx<T>);
+  cplx<T> *W = reinterpret_cast<cplx<T> *>(p->w0);
+  const long long rows = (long long)nrhs * 3 * nz * ny;
+  const char *suf = sizeof(T) == 8 ? "f64" : "f32";
+  char nm[64];
+  {
+    RowArgs a{};
+    a.rows = rows;
+    a.n_in = nx;
+    a.n_out = nx;
+    a.in_stride = nx;
+    a.out_stride = nx;
+    a.sign = -1;
+    a.mask = p->mask;
+    a.vox_rows = (long long)nz * ny;
+    a.rhs_rows = 3LL * nz * ny;
+    a.nx = nx;
+    a.N = p->N;
+    a.xscale = xscale;
+    snprintf(nm, sizeof nm, "pc_x_fwd_%s", suf);
+    launch_rows<T, ROW_PC_FWD, double2, cplx<T>>(p, p->ux, x, W, a, nm,
+                                                 rows * (16.0 * nx + 1.0 * nx + sz * nx));
+  }
+  snprintf(nm, sizeof nm, "pc_y_fwd_%s", suf);
+  launch_strided<T>(p, p->uy, W, W, (long long)nrhs * 3 * nz, nx, ny, ny, (long long)ny * nx,
+                    (long long)ny * nx, -1, nm, 2.0 * rows * nx * sz);
+  {
+    const long long U = (long long)p->umx * p->umy;
+    // right-hand sides per workgroup: up to 4 mode copies x rc vectors <= 16, LDS <= 64 KB
+    int rc = std::max(1, std::min(4, nrhs));
+    while (rc > 1 && (size_t)2 * 4 * rc * p->n2 * sizeof(cplx<T>) > 65536) --rc;
+    const long long nchunks = (nrhs + rc - 1) / rc;
+    const size_t lds = (size_t)2 * 4 * rc * p->n2 * sizeof(cplx<T>);
+    int threads = ((p->n2 + 63) / 64) * 64;
+    threads = std::min(512, std::max(64, threads));
+    auto fn = k_pc_gemv<T>;
+    set_lds_limit((const void *)fn, lds);
+    snprintf(nm, sizeof nm, "pc_gemv_%s", suf);
+    const double bytes = (double)U * 2.0 * p->n2 * p->n2 * sz * nchunks + 2.0 * rows * nx * sz;
+    KTimer t(&p->prof, p->st, nm, bytes);
+    hipLaunchKernelGGL(fn, dim3((unsigned)(U * nchunks)), dim3(threads), lds, p->st, W, binv, nx, ny,
+                       nz, p->umx, p->hh, p->n2, nrhs, rc, nchunks);
+    HIPCHK(hipGetLastError());
+  }
+  snprintf(nm, sizeof nm, "pc_y_inv_%s", suf);
+  launch_strided<T>(p, p->uy, W, W, (long long)nrhs * 3 * nz, nx, ny, ny, (long long)ny * nx,
+                    (long long)ny * nx, +1, nm, 2.0 * rows * nx * sz);
+  {
+    RowArgs a{};
+    a.rows = rows;
+    a.n_in = nx;
+    a.n_out = nx;
+    a.in_stride = nx;
+    a.out_stride = nx;
+    a.sign = +1;
+    a.mask = p->mask;
+    a.vox_rows = (long long)nz * ny;
+    a.rhs_rows = 3LL * nz * ny;
+    a.nx = nx;
+    a.N = p->N;
+    a.scale = 1.0 / ((double)nx * ny);
+    snprintf(nm, sizeof nm, "pc_x_inv_%s", suf);
+    launch_rows<T, ROW_PC_INV, cplx<T>, double2>(p, p->ux, W, y, a, nm,
+                                                 rows * (sz * nx + 1.0 * nx + 16.0 * nx));
+  }
+}
+
+void apply_precond(dda_problem *p, int nrhs, const double2 *x, double2 *y, int fp32,
+                   const double *xscale) {
+  REQUIRE(p->prec_built, DDA_ESTATE, "preconditioner not built");
+  REQUIRE(fp32 == p->prec_fp32, DDA_ESTATE, "preconditioner was built in %s",
+          p->prec_fp32 ? "FP32" : "FP64");
+  if (fp32)
+    pc_apply<float>(p, nrhs, x, y, p->binv32, xscale);
+  else
+    pc_apply<double>(p, nrhs, x, y, p->binv64, xscale);
+}
+
+}  // namespace dda

@@ -1,0 +1,162 @@
+// Runtime pieces: error reporting, FFT plans (radix factorisation + twiddle tables),
+// per-kernel event profiling, and the plain (setup) FFT launchers.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "fft_kernels.h"
+
+namespace dda {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+const char *get_error() { return g_err; }
+
+// ----------------------------------------------------------------------------- plans
+
+bool factor_7smooth(int n, FftPlan &plan) {
+  plan.n = n;
+  plan.nrad = 0;
+  int m = n;
+  auto push = [&](int r) {
+    if (plan.nrad >= kMaxRadices) return false;
+    plan.rad[plan.nrad++] = r;
+    m /= r;
+    return true;
+  };
+  while (m % 8 == 0) if (!push(8)) return false;
+  while (m % 4 == 0) if (!push(4)) return false;
+  while (m % 2 == 0) if (!push(2)) return false;
+  while (m % 7 == 0) if (!push(7)) return false;
+  while (m % 5 == 0) if (!push(5)) return false;
+  while (m % 3 == 0) if (!push(3)) return false;
+  return m == 1;
+}
+
+void plan_create(FftPlan &plan, int n) {
+  REQUIRE(n >= 1 && n <= kMaxFft, DDA_EUNSUPPORTED, "FFT length %d outside [1, %d]", n, kMaxFft);
+  REQUIRE(factor_7smooth(n, plan), DDA_EUNSUPPORTED,
+          "FFT length %d has a prime factor above 7 (grid dimensions must be 7-smooth)", n);
+  std::vector<double2> t64(n);
+  std::vector<float2> t32(n);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int t = 0; t < n; ++t) {
+    const long double ang = two_pi * (long double)t / (long double)n;
+    const double c = (double)cosl(ang), s = -(double)sinl(ang);
+    t64[t] = make_double2(c, s);
+    t32[t] = make_float2((float)c, (float)s);
+  }
+  HIPCHK(hipMalloc(&plan.tw64, sizeof(double2) * n));
+  HIPCHK(hipMalloc(&plan.tw32, sizeof(float2) * n));
+  HIPCHK(hipMemcpy(plan.tw64, t64.data(), sizeof(double2) * n, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(plan.tw32, t32.data(), sizeof(float2) * n, hipMemcpyHostToDevice));
+}
+
+void plan_destroy(FftPlan &plan) {
+  if (plan.tw64) (void)hipFree(plan.tw64);
+  if (plan.tw32) (void)hipFree(plan.tw32);
+  plan.tw64 = nullptr;
+  plan.tw32 = nullptr;
+}
+
+// ----------------------------------------------------------------------------- profiling
+
+int Profiler::kind_id(const char *name, double bytes) {
+  for (size_t i = 0; i < kinds.size(); ++i)
+    if (kinds[i].name == name) {
+      kinds[i].bytes = bytes;
+      return (int)i;
+    }
+  Kind k;
+  k.name = name;
+  k.bytes = bytes;
+  kinds.push_back(k);
+  return (int)kinds.size() - 1;
+}
+
+hipEvent_t Profiler::get_event() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
+void Profiler::collect() {
+  for (auto &pd : pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pd.a, pd.b) == hipSuccess) {
+      kinds[pd.kind].launches += 1;
+      kinds[pd.kind].total_ms += ms;
+    }
+    pool.push_back(pd.a);
+    pool.push_back(pd.b);
+  }
+  pending.clear();
+}
+
+void Profiler::reset() {
+  for (auto &k : kinds) {
+    k.launches = 0;
+    k.total_ms = 0.0;
+  }
+}
+
+void Profiler::destroy() {
+  for (auto &pd : pending) {
+    pool.push_back(pd.a);
+    pool.push_back(pd.b);
+  }
+  pending.clear();
+  for (auto e : pool) (void)hipEventDestroy(e);
+  pool.clear();
+}
+
+KTimer::KTimer(Profiler *p, hipStream_t s, const char *name, double bytes) : prof(p), st(s) {
+  if (!prof || !prof->on) {
+    prof = nullptr;
+    return;
+  }
+  const int kind = prof->kind_id(name, bytes);
+  a = prof->get_event();
+  b = prof->get_event();
+  HIPCHK(hipEventRecord(a, st));
+  prof->pending.push_back(Profiler::Pending{kind, a, b});
+}
+
+KTimer::~KTimer() {
+  if (prof) (void)hipEventRecord(b, st);
+}
+
+// ----------------------------------------------------------------------------- plain transforms
+
+void fft_rows_plain(dda_problem *p, const FftPlan &pl, double2 *data, long long rows, int inverse) {
+  RowArgs a{};
+  a.rows = rows;
+  a.n_in = pl.n;
+  a.n_out = pl.n;
+  a.in_stride = pl.n;
+  a.out_stride = pl.n;
+  a.sign = inverse ? 1 : -1;
+  launch_rows<double, ROW_PLAIN, double2, double2>(p, pl, data, data, a, "fft_rows_setup",
+                                                   32.0 * rows * pl.n);
+}
+
+void fft_strided_plain(dda_problem *p, const FftPlan &pl, double2 *data, long long batch,
+                       long long width, int inverse) {
+  launch_strided<double>(p, pl, data, data, batch, width, pl.n, pl.n, (long long)pl.n * width,
+                         (long long)pl.n * width, inverse ? 1 : -1, "fft_strided_setup",
+                         32.0 * batch * width * pl.n);
+}
+
+}  // namespace dda

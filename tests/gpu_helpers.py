@@ -1,0 +1,38 @@
+"""Shared helpers for GPU tests: build torch inputs from workloads, compare with the oracle."""
+
+import numpy as np
+
+import workloads as w
+
+
+def torch_inputs(s):
+    import torch
+    return torch.from_numpy(s.mask).cuda(), torch.from_numpy(s.eps).cuda()
+
+
+def make_problem(s, **kw):
+    from paper_1903_09802_amd.dda import Problem
+    m, e = torch_inputs(s)
+    return Problem(m, e, s.k, s.d, **kw)
+
+
+def rand_field(shape, nrhs, seed, mask=None):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(nrhs, 3) + shape) + 1j * rng.normal(size=(nrhs, 3) + shape)
+    if mask is not None:
+        x = x * mask[None, None]
+    return x
+
+
+def to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def rel_err(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def random_waves(n, seed):
+    rng = np.random.default_rng(seed)
+    return w.random_directions((n + 1) // 2, rng)

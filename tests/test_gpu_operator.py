@@ -1,0 +1,153 @@
+"""GPU parity of the FFT operator and of the 2-level preconditioner against the CPU oracle.
+
+Sizes span several FFT tiles with ragged tails, odd radices (3, 5, 7), degenerate
+dimensions (1 x 1 x n columns, a single voxel), several right-hand sides with different
+LDR factors S, and the full 128^3 benchmark grid via sampled rows.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as w
+from gpu_helpers import make_problem, rand_field, random_waves, rel_err, to_dev
+from oracle import circulant, fftmatvec, physics, rows, system
+
+pytestmark = pytest.mark.gpu
+
+OP_CASES = [
+    ((5, 6, 7), 0.7, 1),
+    ((9, 4, 12), 0.6, 2),
+    ((16, 16, 16), 0.65, 3),
+    ((3, 10, 14), 0.8, 4),
+    ((1, 1, 6), 1.0, 5),
+    ((1, 1, 1), 1.0, 6),
+    ((7, 5, 3), 0.5, 7),
+    ((12, 20, 9), 0.7, 8),
+]
+
+
+@pytest.mark.parametrize("shape,fill,seed", OP_CASES)
+def test_operator_fp64_vs_oracle(shape, fill, seed):
+    nz, ny, nx = shape
+    s = w.random_mask(nx, ny, nz, fill, seed, k=1.3, d=0.3, eps_jitter=0.05)
+    dirs, pols = random_waves(2, seed)
+    with make_problem(s, max_rhs=2, precond=0) as prob:
+        x = rand_field(shape, 2, seed)  # unmasked: air entries must pass through
+        y = prob.apply_operator(to_dev(x), dirs, pols).cpu().numpy()
+    for r in range(2):
+        S = physics.lattice_S(dirs[r], pols[r])
+        ref = fftmatvec.fft_matvec(x[r], s.mask, s.eps, s.k, s.d, S)
+        assert rel_err(y[r], ref) < 1e-10, (shape, r)
+
+
+@pytest.mark.parametrize("shape,fill,seed", [((4, 5, 6), 0.7, 11), ((6, 3, 5), 0.9, 12)])
+def test_operator_vs_dense_matrix(shape, fill, seed):
+    """Against the dense matrix assembled pair by pair (independent of any FFT)."""
+    nz, ny, nx = shape
+    s = w.random_mask(nx, ny, nz, fill, seed, k=2.1, d=0.25, eps_mean=3.1 + 0.2j, eps_jitter=0.1)
+    dirs, pols = random_waves(1, seed)
+    with make_problem(s, precond=0) as prob:
+        x = rand_field(shape, 1, seed, s.mask)
+        y = prob.apply_operator(to_dev(x), dirs[:1], pols[:1]).cpu().numpy()
+    S = physics.lattice_S(dirs[0], pols[0])
+    ref = system.box_operator_dense(s.mask, s.eps, s.k, s.d, S, x[0])
+    assert rel_err(y[0], ref) < 1e-10
+
+
+@pytest.mark.parametrize("shape,seed", [((5, 6, 7), 21), ((16, 16, 16), 22), ((12, 20, 9), 23)])
+def test_operator_fp32_vs_oracle(shape, seed):
+    nz, ny, nx = shape
+    s = w.random_mask(nx, ny, nz, 0.7, seed, k=1.3, d=0.3)
+    dirs, pols = random_waves(1, seed)
+    with make_problem(s, precond=0, precision=1) as prob:
+        x = rand_field(shape, 1, seed, s.mask)
+        y = prob.apply_operator(to_dev(x), dirs[:1], pols[:1], fp32=True).cpu().numpy()
+    ref = fftmatvec.fft_matvec(x[0], s.mask, s.eps, s.k, s.d, physics.lattice_S(dirs[0], pols[0]))
+    assert rel_err(y[0], ref) < 1e-5
+
+
+def _oracle_blocks(s, s_bar=0.0):
+    occ = s.mask.astype(bool)
+    ati = complex(physics.alpha_inv(s.eps[occ].mean(), s.k * s.d, s_bar))
+    return circulant.invert_blocks(circulant.two_level_blocks(s.shape, s.k, s.d, ati))
+
+
+PC_CASES = [((4, 5, 6), 31), ((5, 4, 3), 32), ((7, 6, 10), 33), ((1, 3, 4), 34),
+            ((16, 16, 16), 35), ((9, 8, 12), 36), ((3, 1, 1), 37), ((2, 7, 5), 38)]
+
+
+@pytest.mark.parametrize("shape,seed", PC_CASES)
+def test_preconditioner_fp64_vs_oracle(shape, seed):
+    nz, ny, nx = shape
+    s = w.random_mask(nx, ny, nz, 0.75, seed, k=1.1, d=0.35, eps_jitter=0.05)
+    with make_problem(s, precond=2, max_rhs=3) as prob:
+        prob.build_preconditioner(0.0)
+        x = rand_field(shape, 3, seed)
+        z = prob.apply_preconditioner(to_dev(x)).cpu().numpy()
+    Binv = _oracle_blocks(s)
+    for r in range(3):
+        ref = circulant.apply_blocks(x[r], s.mask, Binv)
+        assert rel_err(z[r], ref) < 1e-10, (shape, r)
+
+
+def test_preconditioner_brute_force_definition():
+    """Against P built by wrapped-diagonal averaging of the full-box BTTB matrix."""
+    shape = (4, 5, 6)
+    s = w.random_mask(6, 5, 4, 0.8, 41, k=1.6, d=0.3)
+    occ = s.mask.astype(bool)
+    ati = complex(physics.alpha_inv(s.eps[occ].mean(), s.k * s.d, 0.25))
+    P = circulant.two_level_dense(shape, s.k, s.d, ati)
+    with make_problem(s, precond=2) as prob:
+        prob.build_preconditioner(0.25)
+        x = rand_field(shape, 1, 41)
+        z = prob.apply_preconditioner(to_dev(x)).cpu().numpy()
+    ref = circulant.apply_dense(x[0], s.mask, P)
+    assert rel_err(z[0], ref) < 1e-10
+
+
+@pytest.mark.parametrize("shape,seed", [((5, 6, 7), 51), ((16, 16, 16), 52)])
+def test_preconditioner_fp32_vs_oracle(shape, seed):
+    nz, ny, nx = shape
+    s = w.random_mask(nx, ny, nz, 0.7, seed, k=1.3, d=0.3)
+    with make_problem(s, precond=2, precision=1) as prob:
+        prob.build_preconditioner(0.0)
+        x = rand_field(shape, 1, seed)
+        z = prob.apply_preconditioner(to_dev(x), fp32=True).cpu().numpy()
+    ref = circulant.apply_blocks(x[0], s.mask, _oracle_blocks(s))
+    assert rel_err(z[0], ref) < 1e-5
+
+
+def test_operator_full_size_sampled_rows():
+    """128^3 benchmark prism (padded 256^3), FP64: sampled rows by direct summation."""
+    cfg = w.config_c2()
+    s = cfg["scatterer"]
+    dirs, pols = cfg["dirs"], cfg["pols"]
+    with make_problem(s, precond=0, max_rhs=2) as prob:
+        x = rand_field(s.shape, 2, 61, s.mask)
+        y = prob.apply_operator(to_dev(x), dirs, pols).cpu().numpy()
+    occ = np.flatnonzero(s.mask.ravel())
+    rng = np.random.default_rng(61)
+    samples = np.concatenate([occ[[0, len(occ) // 2, -1]], rng.choice(occ, 3, replace=False)])
+    for r in range(2):
+        S = physics.lattice_S(dirs[r], pols[r])
+        ref = rows.operator_rows(samples, x[r], s.mask, s.eps, s.k, s.d, S)
+        got = np.stack([[y[r][a].ravel()[i] for a in range(3)] for i in samples])
+        assert np.abs(got - ref).max() < 1e-10 * np.abs(ref).max(), r
+
+
+def test_preconditioner_full_size_sampled_rows():
+    """128^3 homogeneous cuboid: z = P^{-1} v, checked by evaluating sampled rows of P z."""
+    n = 128
+    k, d = 20.0, 2.0 / n
+    s = w.cuboid_grid(n, n, n, k, d, 1.31)
+    ati = complex(physics.alpha_inv(1.31 ** 2, k * d, 0.0))
+    with make_problem(s, precond=2) as prob:
+        prob.build_preconditioner(0.0)
+        v = rand_field(s.shape, 1, 62)
+        z = prob.apply_preconditioner(to_dev(v)).cpu().numpy()
+    rng = np.random.default_rng(62)
+    samples = np.concatenate([[0, n ** 3 - 1], rng.choice(n ** 3, 3, replace=False)])
+    gen = circulant.two_level_generator(s.shape, k, d)
+    Pz = rows.precond_rows(samples, z[0], k, d, ati, generator=gen)
+    ref = np.stack([[v[0][a].ravel()[i] for a in range(3)] for i in samples])
+    assert np.abs(Pz - ref).max() < 1e-9 * np.abs(ref).max()
