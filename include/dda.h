@@ -192,9 +192,10 @@ void dda_destroy(dda_problem *p);
 /*
  * Per-kernel timing with HIP events recorded around every launch on the
  * handle's stream.  Enabling resets the counters.  dda_profile_get returns,
- * for kernel kind idx in [0, dda_profile_count()), its name (static storage),
- * the number of launches, their summed duration in ms, and the algorithmic
- * bytes one launch moves (read + write, per the traffic model of the kernel).
+ * for kernel kind idx in [0, dda_profile_count()), its name (valid until the
+ * handle is destroyed), the number of launches, their summed duration in ms,
+ * and the mean algorithmic bytes per launch (read + write, per the traffic
+ * model of the kernel; launches of one kind may differ in size).
  */
 dda_status dda_profile_enable(dda_problem *p, int on);
 int dda_profile_count(dda_problem *p);

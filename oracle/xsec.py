@@ -1,4 +1,4 @@
-"""Cross sections of the solved dipole array.  Test infrastructure only.
+r"""Cross sections of the solved dipole array.  Test infrastructure only.
 
 The paper reports no cross sections; these are the Draine-Flatau expressions
 (the DDA formulation the paper follows, Sec. 2.1) rewritten for its scaling, in

@@ -174,10 +174,10 @@ dda_status dda_solve(dda_problem *p, int nrhs, const double *dir_host, const dou
     const auto t0 = std::chrono::steady_clock::now();
     REQUIRE(p, DDA_EINVAL, "problem is NULL");
     REQUIRE(nrhs >= 1 && nrhs <= p->R, DDA_EINVAL, "nrhs must be in [1, max_rhs = %d]", p->R);
-    REQUIRE(p->opt.precond == 0 || p->prec_built, DDA_ESTATE,
-            "opt.precond = 2 but dda_build_preconditioner has not run");
     std::vector<double> S;
     check_waves(nrhs, dir_host, pol_host, S);
+    REQUIRE(p->opt.precond == 0 || p->prec_built, DDA_ESTATE,
+            "opt.precond = 2 but dda_build_preconditioner has not run");
     const long long n3 = 3 * p->N;
     setup_alpha(p, nrhs, S.data());
     setup_rhs(p, nrhs, dir_host, pol_host, p->bvec, 0);
@@ -327,7 +327,7 @@ dda_status dda_profile_get(dda_problem *p, int idx, const char **name, long long
     if (name) *name = k.name.c_str();
     if (launches) *launches = k.launches;
     if (total_ms) *total_ms = k.total_ms;
-    if (bytes_per_launch) *bytes_per_launch = k.bytes;
+    if (bytes_per_launch) *bytes_per_launch = k.launches ? k.total_bytes / k.launches : 0.0;
     return DDA_OK;
   });
 }

@@ -154,16 +154,17 @@ struct Profiler {
     std::string name;
     long long launches = 0;
     double total_ms = 0.0;
-    double bytes = 0.0;
+    double total_bytes = 0.0;  // algorithmic bytes summed over timed launches
   };
   std::vector<Kind> kinds;
   struct Pending {
     int kind;
+    double bytes;
     hipEvent_t a, b;
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
-  int kind_id(const char *name, double bytes);
+  int kind_id(const char *name);
   void begin(hipStream_t s, int kind, hipEvent_t *a, hipEvent_t *b);
   void collect();  // after a stream sync
   void reset();

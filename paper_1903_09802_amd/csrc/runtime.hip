@@ -68,15 +68,11 @@ void plan_destroy(FftPlan &plan) {
 
 // ----------------------------------------------------------------------------- profiling
 
-int Profiler::kind_id(const char *name, double bytes) {
+int Profiler::kind_id(const char *name) {
   for (size_t i = 0; i < kinds.size(); ++i)
-    if (kinds[i].name == name) {
-      kinds[i].bytes = bytes;
-      return (int)i;
-    }
+    if (kinds[i].name == name) return (int)i;
   Kind k;
   k.name = name;
-  k.bytes = bytes;
   kinds.push_back(k);
   return (int)kinds.size() - 1;
 }
@@ -98,6 +94,7 @@ void Profiler::collect() {
     if (hipEventElapsedTime(&ms, pd.a, pd.b) == hipSuccess) {
       kinds[pd.kind].launches += 1;
       kinds[pd.kind].total_ms += ms;
+      kinds[pd.kind].total_bytes += pd.bytes;
     }
     pool.push_back(pd.a);
     pool.push_back(pd.b);
@@ -109,6 +106,7 @@ void Profiler::reset() {
   for (auto &k : kinds) {
     k.launches = 0;
     k.total_ms = 0.0;
+    k.total_bytes = 0.0;
   }
 }
 
@@ -127,11 +125,11 @@ KTimer::KTimer(Profiler *p, hipStream_t s, const char *name, double bytes) : pro
     prof = nullptr;
     return;
   }
-  const int kind = prof->kind_id(name, bytes);
+  const int kind = prof->kind_id(name);
   a = prof->get_event();
   b = prof->get_event();
   HIPCHK(hipEventRecord(a, st));
-  prof->pending.push_back(Profiler::Pending{kind, a, b});
+  prof->pending.push_back(Profiler::Pending{kind, bytes, a, b});
 }
 
 KTimer::~KTimer() {
