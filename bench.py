@@ -122,6 +122,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -174,9 +176,12 @@ def main():
     agg = {}
     for pr in profs:
         for k in pr:
-            a = agg.setdefault(k["name"], dict(launches=0, total_ms=0.0, bytes=k["bytes_per_launch"]))
+            a = agg.setdefault(k["name"], dict(launches=0, total_ms=0.0, total_bytes=0.0))
             a["launches"] += k["launches"]
             a["total_ms"] += k["total_ms"]
+            a["total_bytes"] += k["bytes_per_launch"] * k["launches"]
+    for a in agg.values():
+        a["bytes"] = a["total_bytes"] / max(1, a["launches"])
     kernels = sorted(agg.items(), key=lambda kv: -kv[1]["total_ms"])
     hbm = [kv for kv in kernels if not kv[0].startswith(("pc_gj", "pc_assemble", "fft_rows_setup",
                                                          "fft_strided_setup"))]
@@ -226,6 +231,13 @@ def main():
                      cext=o["cext"].tolist())
         pp.close()
     prob.close()
+
+    if args.copy_probe:
+        src = torch.empty(1 << 26, dtype=torch.complex128, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -41,6 +41,20 @@ __host__ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 }
 template <typename V> __device__ __forceinline__ V ldc(const V *p) { return *p; }
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round robin.  A kernel that
+// launches xcd_grid(G) blocks and maps blockIdx through xcd_remap gets logically adjacent
+// work items (which share cache lines) on the same XCD; indices >= G exit at once.
+constexpr int kXcds = 8;
+// Largest Krylov basis (restart + 1 vectors); per-RHS arrays of small vectors use this stride.
+constexpr int kMaxM = 32;
+__host__ __device__ __forceinline__ long long xcd_grid(long long G) {
+  return ((G + kXcds - 1) / kXcds) * kXcds;
+}
+__device__ __forceinline__ long long xcd_remap(long long b, long long G) {
+  const long long per = (G + kXcds - 1) / kXcds;
+  return (b % kXcds) * per + b / kXcds;
+}
+
 __device__ __forceinline__ float2 to_c(double2 a, float2) { return make_float2((float)a.x, (float)a.y); }
 __device__ __forceinline__ double2 to_c(double2 a, double2) { return a; }
 __device__ __forceinline__ double2 to_d(float2 a) { return make_double2((double)a.x, (double)a.y); }
@@ -195,6 +209,7 @@ struct dda_problem {
   int R = 1;             // max right-hand sides
   size_t lds_max = 65536;      // device LDS per workgroup
   size_t lds_zpass = 98304;    // LDS budget of the fused z pass
+  int ztw[2] = {0, 0};         // z-pass columns per tile (FP64, FP32), chosen by autotune
 
   uint8_t *mask = nullptr;      // [N]
   double2 *eps = nullptr;       // [N]
@@ -231,7 +246,6 @@ struct dda_problem {
   double2 *work2 = nullptr;  // [R][3N]
   double2 *bvec = nullptr;   // [R][3N] right-hand side
   double2 *xvec = nullptr;   // [R][3N] iterate
-  double2 *rvec = nullptr;   // [R][3N] residual of the GMRES iterate
   double2 *xref = nullptr;   // [R][3N] refinement residual (right-hand side of the inner solve)
   double2 *rref = nullptr;   // [R][3N] refinement correction
   double2 *H = nullptr;      // [R][restart+1][restart]
@@ -240,9 +254,11 @@ struct dda_problem {
   double2 *hcol = nullptr;   // [R][restart+1] projections
   double2 *hcol2 = nullptr;  // [R][restart+1]
   double2 *ycoef = nullptr;  // [R][restart+1]
+  double2 *hnrm = nullptr;   // [R][kMaxM] squared norms before / after a projection
   double *partial = nullptr; // reduction partials
   size_t partial_elems = 0;
   double *dscal = nullptr;   // [R][16] device scalars
+  double *vsc = nullptr;     // [R][kMaxM] 1 / norm of each (unnormalised) basis vector
   double *hpin = nullptr;    // pinned host mirror [R][16]
   int *dflag = nullptr;      // device error flags [4]
 
@@ -263,7 +279,8 @@ void operator_setup(dda_problem *p);
 void setup_alpha(dda_problem *p, int nrhs, const double *S_host);
 void setup_rhs(dda_problem *p, int nrhs, const double *dir, const double *pol, double2 *b,
                int conjugate);
-// y = A x (FP64 in/out), prec: 0 FP64, 1 FP32 internal; kernel 0 = operator, 1 = Im-kernel conv
+// y = A (s x) with FP64 input and output (fp32: FP32 transforms inside).  xscale_dev: optional
+// per-RHS input scale s_r = xscale_dev[r * kMaxM] (used for unnormalised Krylov vectors).
 void apply_operator(dda_problem *p, int nrhs, const double2 *x, double2 *y, int fp32,
                     const double *xscale_dev);
 void apply_imag_conv(dda_problem *p, int nrhs, const double2 *x, double2 *y);

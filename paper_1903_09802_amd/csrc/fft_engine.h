@@ -1,14 +1,17 @@
 // LDS-resident mixed-radix FFT engine for CDNA (wave64) workgroups.
 //
-// A workgroup holds `ncols` independent sequences of length n in LDS, element
-// (i, c) at s[i * ld + c] (ld >= ncols).  Each radix pass is a Stockham
-// autosort step: butterfly j of a pass with radix R and accumulated span Ns
-// reads x[j + r n/R], twiddles by exp(sign 2 pi i r (j mod Ns) / (Ns R)),
-// applies the R-point DFT and writes x[(j / Ns) Ns R + (j mod Ns) + r Ns]; the
-// output is in natural order.  All reads of a pass finish (barrier) before any
-// write, so one LDS buffer suffices.  Threads are mapped column-fastest, so a
-// wave touches contiguous 128-byte LDS rows (no bank conflicts for complex
-// double / float).  Each thread holds at most EPT complex values per pass.
+// A workgroup holds `ncols` independent sequences of length n in LDS; element (i, c) sits at
+// s[lrow(i, ld) + c] with lrow(i) = i * ld + (i >> 3): rows are padded to ld >= ncols + 1 and
+// every eighth row is skewed by one more element, so the stride-R row accesses of a radix-R
+// pass spread over the LDS banks.  Each radix pass is a Stockham autosort step: butterfly j
+// of a pass with radix R and accumulated span Ns reads x[j + r n/R], twiddles by
+// exp(sign 2 pi i r (j mod Ns) / (Ns R)), applies the R-point DFT and writes
+// x[(j / Ns) Ns R + (j mod Ns) + r Ns]; the output is in natural order.  All reads of a
+// pass finish (barrier) before any write, so one LDS buffer suffices.
+//
+// Thread mapping: thread t owns column c = t % ncols and row slot jt = t / ncols (computed
+// once); with TPC threads per column it handles butterflies j = jt + q TPC.  When Ns is a
+// power of two the span arithmetic is shifts and masks.
 #pragma once
 
 #include "common.h"
@@ -18,6 +21,10 @@ namespace dda {
 template <typename V> struct RealOf;
 template <> struct RealOf<double2> { using type = double; };
 template <> struct RealOf<float2> { using type = float; };
+
+__host__ __device__ __forceinline__ int lrow(int i, int ld) { return i * ld + (i >> 3); }
+// LDS elements for n rows of stride ld
+__host__ __device__ __forceinline__ int lds_elems(int n, int ld) { return lrow(n, ld) + 1; }
 
 // R-point DFT in registers; sign = -1 forward, +1 inverse (unnormalised).
 template <int R, typename V>
@@ -109,25 +116,35 @@ __device__ __forceinline__ void dft(V *a, int sign) {
   }
 }
 
+// Per-thread placement inside a tile: column c, first butterfly row jt, TPC threads per column.
+struct Lane {
+  int c, jt, tpc, active;
+};
+
+__device__ __forceinline__ Lane make_lane(int ncols, int tpc) {
+  Lane L;
+  L.c = threadIdx.x % ncols;
+  L.jt = threadIdx.x / ncols;
+  L.tpc = tpc;
+  L.active = L.jt < tpc;
+  return L;
+}
+
 // One Stockham pass of radix R over all columns.
 template <int R, typename V, int EPT>
-__device__ __forceinline__ void fft_pass(V *s, int ld, int ncols, int n, int Ns,
-                                         const V *__restrict__ tw, int sign, int tid,
-                                         int nthreads) {
+__device__ __forceinline__ void fft_pass(V *s, int ld, const Lane &L, int n, int Ns, int nsh,
+                                         const V *__restrict__ tw, int sign) {
   constexpr int BPT = (EPT + R - 1) / R;
   V v[BPT][R];
   const int nb = n / R;
-  const int total = nb * ncols;
   const int twstep = n / (Ns * R);
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
-    const int b = tid + q * nthreads;
-    if (b < total) {
-      const int c = b % ncols;
-      const int j = b / ncols;
-      const int kk = j % Ns;
+    const int j = L.jt + q * L.tpc;
+    if (L.active && j < nb) {
+      const int kk = nsh >= 0 ? (j & (Ns - 1)) : (j % Ns);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = s[(j + r * nb) * ld + c];
+      for (int r = 0; r < R; ++r) v[q][r] = s[lrow(j + r * nb, ld) + L.c];
       if (kk != 0) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -142,43 +159,120 @@ __device__ __forceinline__ void fft_pass(V *s, int ld, int ncols, int n, int Ns,
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
-    const int b = tid + q * nthreads;
-    if (b < total) {
-      const int c = b % ncols;
-      const int j = b / ncols;
-      const int kk = j % Ns;
-      const int base = (j / Ns) * Ns * R + kk;
+    const int j = L.jt + q * L.tpc;
+    if (L.active && j < nb) {
+      int base;
+      if (nsh >= 0) base = ((j >> nsh) << nsh) * R + (j & (Ns - 1));
+      else base = (j / Ns) * Ns * R + (j % Ns);
 #pragma unroll
-      for (int r = 0; r < R; ++r) s[(base + r * Ns) * ld + c] = v[q][r];
+      for (int r = 0; r < R; ++r) s[lrow(base + r * Ns, ld) + L.c] = v[q][r];
     }
   }
   __syncthreads();
 }
 
-// Full transform of ncols columns (caller synchronises before the call).
+// Full transform of all columns (caller synchronises before the call).
 template <typename V, int EPT>
-__device__ __forceinline__ void lds_fft(V *s, int ld, int ncols, const FftDesc &pl,
-                                        const V *__restrict__ tw, int sign, int tid,
-                                        int nthreads) {
-  int Ns = 1;
+__device__ __forceinline__ void lds_fft(V *s, int ld, const Lane &L, const FftDesc &pl,
+                                        const V *__restrict__ tw, int sign) {
+  int Ns = 1, nsh = 0;
   for (int ps = 0; ps < pl.nrad; ++ps) {
     const int R = pl.rad[ps];
     switch (R) {
-      case 2: fft_pass<2, V, EPT>(s, ld, ncols, pl.n, Ns, tw, sign, tid, nthreads); break;
-      case 3: fft_pass<3, V, EPT>(s, ld, ncols, pl.n, Ns, tw, sign, tid, nthreads); break;
-      case 4: fft_pass<4, V, EPT>(s, ld, ncols, pl.n, Ns, tw, sign, tid, nthreads); break;
-      case 5: fft_pass<5, V, EPT>(s, ld, ncols, pl.n, Ns, tw, sign, tid, nthreads); break;
-      case 7: fft_pass<7, V, EPT>(s, ld, ncols, pl.n, Ns, tw, sign, tid, nthreads); break;
-      default: fft_pass<8, V, EPT>(s, ld, ncols, pl.n, Ns, tw, sign, tid, nthreads); break;
+      case 2: fft_pass<2, V, EPT>(s, ld, L, pl.n, Ns, nsh, tw, sign); break;
+      case 3: fft_pass<3, V, EPT>(s, ld, L, pl.n, Ns, nsh, tw, sign); break;
+      case 4: fft_pass<4, V, EPT>(s, ld, L, pl.n, Ns, nsh, tw, sign); break;
+      case 5: fft_pass<5, V, EPT>(s, ld, L, pl.n, Ns, nsh, tw, sign); break;
+      case 7: fft_pass<7, V, EPT>(s, ld, L, pl.n, Ns, nsh, tw, sign); break;
+      default: fft_pass<8, V, EPT>(s, ld, L, pl.n, Ns, nsh, tw, sign); break;
     }
     Ns *= R;
+    if (nsh >= 0) nsh = (R == 2) ? nsh + 1 : (R == 4) ? nsh + 2 : (R == 8) ? nsh + 3 : -1;
   }
 }
 
-// Elements per thread per pass: 8 complex doubles or 16 complex floats (32 KB tiles at 256 threads).
-template <typename T> struct EptOf;
-template <> struct EptOf<double> { static constexpr int value = 8; };
-template <> struct EptOf<float> { static constexpr int value = 16; };
+// Elements per thread per pass: 8 complex values (one radix-8 butterfly).
+constexpr int kEpt = 8;
+template <typename T> struct EptOf { static constexpr int value = kEpt; };
+
+// Threads per column for a length-n transform.
+__host__ __device__ __forceinline__ int tpc_of(int n) { return (n + kEpt - 1) / kEpt; }
+
+// ---------------------------------------------------------------------------- static plans
+// Power-of-two lengths with the radix plan fixed at compile time (8s, then a 4 or a 2): the
+// spans, strides and twiddle steps become constants.
+
+__host__ __device__ constexpr int p2_nrad(int n) {
+  int k = 0, m = n;
+  while (m % 8 == 0) { m /= 8; ++k; }
+  if (m % 4 == 0) { m /= 4; ++k; }
+  if (m % 2 == 0) { m /= 2; ++k; }
+  return k;
+}
+__host__ __device__ constexpr int p2_rad(int n, int p) {
+  int m = n, k = 0;
+  while (m % 8 == 0) { if (k == p) return 8; m /= 8; ++k; }
+  if (m % 4 == 0) { if (k == p) return 4; m /= 4; ++k; }
+  if (m % 2 == 0) { if (k == p) return 2; m /= 2; ++k; }
+  return 1;
+}
+
+template <int R, typename V, int N, int NS>
+__device__ __forceinline__ void fft_pass_s(V *s, int ld, const Lane &L, const V *__restrict__ tw,
+                                           int sign) {
+  constexpr int BPT = (kEpt + R - 1) / R;
+  constexpr int NB = N / R;
+  constexpr int TPC = (N + kEpt - 1) / kEpt;
+  constexpr int TWSTEP = N / (NS * R);
+  V v[BPT][R];
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int j = L.jt + q * TPC;
+    if (L.active && j < NB) {
+      const int kk = j & (NS - 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = s[lrow(j + r * NB, ld) + L.c];
+      if (NS > 1 && kk != 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          V w = tw[r * kk * TWSTEP];
+          if (sign > 0) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+      dft<R, V>(v[q], sign);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int j = L.jt + q * TPC;
+    if (L.active && j < NB) {
+      const int base = (j / NS) * (NS * R) + (j & (NS - 1));
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[lrow(base + r * NS, ld) + L.c] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename V, int N, int P = 0, int NS = 1>
+__device__ __forceinline__ void lds_fft_s(V *s, int ld, const Lane &L, const V *__restrict__ tw,
+                                          int sign) {
+  if constexpr (P < p2_nrad(N)) {
+    constexpr int R = p2_rad(N, P);
+    fft_pass_s<R, V, N, NS>(s, ld, L, tw, sign);
+    lds_fft_s<V, N, P + 1, NS * R>(s, ld, L, tw, sign);
+  }
+}
+
+// Transform with the static plan when NF > 0 (NF must equal pl.n), else the runtime plan.
+template <typename V, int EPT, int NF>
+__device__ __forceinline__ void lds_fft_any(V *s, int ld, const Lane &L, const FftDesc &pl,
+                                            const V *__restrict__ tw, int sign) {
+  if constexpr (NF > 0) lds_fft_s<V, NF>(s, ld, L, tw, sign);
+  else lds_fft<V, EPT>(s, ld, L, pl, tw, sign);
+}
 
 constexpr int kFftThreads = 256;
 

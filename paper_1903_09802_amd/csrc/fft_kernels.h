@@ -2,6 +2,9 @@
 // BTTB product.  Included by the translation units that launch them.
 #pragma once
 
+#include <algorithm>
+#include <type_traits>
+
 #include "fft_engine.h"
 
 namespace dda {
@@ -21,6 +24,7 @@ struct RowArgs {
   FftDesc pl;
   long long rows;      // number of rows transformed
   int tw;              // rows per workgroup (LDS columns)
+  int nsh;             // log2(n) when n is a power of two, else -1
   int n_in, n_out;     // valid input length (zero padded to n), output length written
   long long in_stride, out_stride;
   int sign;
@@ -31,11 +35,11 @@ struct RowArgs {
   long long N;
   const double2 *ainv; // [R][N]
   const double2 *xin;  // FP64 field rows for ROW_OP_INV
-  const double *xscale;// per-RHS input scale, or null
+  const double *xscale;// per-RHS input scale xscale[r * kMaxM], or null
   double scale;        // output scale of the transform
 };
 
-template <typename T, int MODE, typename TI, typename TO>
+template <typename T, int MODE, typename TI, typename TO, int NF>
 __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
                                                           const cplx<T> *__restrict__ tw,
                                                           RowArgs a) {
@@ -46,9 +50,10 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
   const int n = a.pl.n;
   const int ld = a.tw + 1;
   const long long row0 = (long long)blockIdx.x * a.tw;
+  // load: consecutive threads take consecutive elements of a row (global rows are contiguous)
   const int tot_in = a.tw * n;
   for (int e = tid; e < tot_in; e += nt) {
-    const int c = e / n;
+    const int c = a.nsh >= 0 ? (e >> a.nsh) : e / n;
     const int i = e - c * n;
     const long long row = row0 + c;
     V val = mk<T>((T)0, (T)0);
@@ -57,23 +62,24 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
         const long long vox = (row % a.vox_rows) * a.nx + i;
         double2 xv = in[row * a.in_stride + i];
         if (!a.mask[vox]) xv = make_double2(0.0, 0.0);
-        if (a.xscale) xv = cscale(xv, a.xscale[row / a.rhs_rows]);
+        if (a.xscale) xv = cscale(xv, a.xscale[(row / a.rhs_rows) * kMaxM]);
         val = to_c(xv, V{});
       } else {
         val = in[row * a.in_stride + i];
       }
     }
-    s[i * ld + c] = val;
+    s[lrow(i, ld) + c] = val;
   }
   __syncthreads();
-  lds_fft<V, EptOf<T>::value>(s, ld, a.tw, a.pl, tw, a.sign, tid, nt);
+  const Lane L = make_lane(a.tw, tpc_of(n));
+  lds_fft_any<V, EptOf<T>::value, NF>(s, ld, L, a.pl, tw, a.sign);
   const int tot_out = a.tw * a.n_out;
   for (int e = tid; e < tot_out; e += nt) {
     const int c = e / a.n_out;
     const int i = e - c * a.n_out;
     const long long row = row0 + c;
     if (row >= a.rows) continue;
-    const V v = s[i * ld + c];
+    const V v = s[lrow(i, ld) + c];
     if constexpr (MODE == ROW_PLAIN) {
       out[row * a.out_stride + i] = v;
     } else if constexpr (MODE == ROW_OP_INV || MODE == ROW_IMG_INV || MODE == ROW_PC_INV) {
@@ -83,7 +89,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
       if constexpr (MODE == ROW_OP_INV) {
         const long long r = row / a.rhs_rows;
         double2 xv = a.xin[row * a.out_stride + i];
-        if (a.xscale) xv = cscale(xv, a.xscale[r]);
+        if (a.xscale) xv = cscale(xv, a.xscale[r * kMaxM]);
         if (a.mask[vox]) y = csub(cmul(a.ainv[r * a.N + vox], xv), conv);
         else y = xv;
       } else {
@@ -110,36 +116,32 @@ struct StrArgs {
   int sign;
 };
 
-template <typename T>
+template <typename T, int NF>
 __global__ void __launch_bounds__(kFftThreads) k_fft_strided(const cplx<T> *in, cplx<T> *out,
                                                              const cplx<T> *__restrict__ tw,
                                                              StrArgs a) {
   using V = cplx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *s = reinterpret_cast<V *>(smem_raw);
-  const int tid = threadIdx.x, nt = blockDim.x;
   const int n = a.pl.n;
   const int ld = a.tw + 1;
   const long long b = blockIdx.x / a.ntiles;
   const long long c0 = (blockIdx.x - b * a.ntiles) * (long long)a.tw;
-  const V *src = in + b * a.in_bstride;
-  const int tot = a.tw * n;
-  for (int e = tid; e < tot; e += nt) {
-    const int i = e / a.tw;
-    const int c = e - i * a.tw;
-    V val = mk<T>((T)0, (T)0);
-    if (i < a.n_in && c0 + c < a.width) val = src[(long long)i * a.width + c0 + c];
-    s[i * ld + c] = val;
+  const Lane L = make_lane(a.tw, tpc_of(n));
+  const bool colok = L.active && (c0 + L.c < a.width);
+  const V *src = in + b * a.in_bstride + c0 + L.c;
+  if (L.active) {
+    for (int i = L.jt; i < n; i += L.tpc) {
+      V val = mk<T>((T)0, (T)0);
+      if (i < a.n_in && colok) val = src[(long long)i * a.width];
+      s[lrow(i, ld) + L.c] = val;
+    }
   }
   __syncthreads();
-  lds_fft<V, EptOf<T>::value>(s, ld, a.tw, a.pl, tw, a.sign, tid, nt);
-  V *dst = out + b * a.out_bstride;
-  const int toto = a.tw * a.n_out;
-  for (int e = tid; e < toto; e += nt) {
-    const int i = e / a.tw;
-    const int c = e - i * a.tw;
-    if (c0 + c < a.width) dst[(long long)i * a.width + c0 + c] = s[i * ld + c];
-  }
+  lds_fft_any<V, EptOf<T>::value, NF>(s, ld, L, a.pl, tw, a.sign);
+  V *dst = out + b * a.out_bstride + c0 + L.c;
+  if (colok)
+    for (int i = L.jt; i < a.n_out; i += L.tpc) dst[(long long)i * a.width] = s[lrow(i, ld) + L.c];
 }
 
 // ---------------------------------------------------------------------------- fused z pass
@@ -148,79 +150,85 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(const cplx<T> *in, 
 // tile of `tw` consecutive (ky, kx) columns of one right-hand side: zero-pad each of
 // the three components to 2nz along z, FFT, multiply by the 3x3 symmetric kernel
 // spectrum (six components, read from the stored octant with the per-axis parity
-// signs), inverse FFT, write the first nz entries back in place.
+// signs), inverse FFT, write the first nz entries back in place.  tw is a power of two.
 struct ZArgs {
   FftDesc pl;       // length 2nz
   int nz, ny, nx;
   long long plane;  // 4 nx ny
-  int tw;
+  int tw, twsh;     // columns per tile and log2(tw)
   long long ntiles;
+  long long nrhs;
 };
 
-template <typename T, int EPT>
+template <typename T, int EPT, int NF>
 __global__ void __launch_bounds__(768) k_zpass(cplx<T> *data, const cplx<T> *__restrict__ tw,
-                                                const cplx<T> *__restrict__ khat, ZArgs a) {
+                                               const cplx<T> *__restrict__ khat, ZArgs a) {
   using V = cplx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *s = reinterpret_cast<V *>(smem_raw);
-  const int tid = threadIdx.x, nt = blockDim.x;
   const int n = a.pl.n;
   const int ncols = 3 * a.tw;
   const int ld = ncols + 1;
-  const long long r = blockIdx.x / a.ntiles;
-  const long long c0 = (blockIdx.x - r * a.ntiles) * (long long)a.tw;
+  const long long blk = xcd_remap(blockIdx.x, a.ntiles * a.nrhs);
+  if (blk >= a.ntiles * a.nrhs) return;
+  const long long r = blk / a.ntiles;
+  const long long c0 = (blk - r * a.ntiles) * (long long)a.tw;
   V *base = data + r * 3LL * a.nz * a.plane;
-  const int tot = 3 * a.tw * n;
-  for (int e = tid; e < tot; e += nt) {
-    const int i = e / ncols;
-    const int cc = e - i * ncols;
-    const int comp = cc / a.tw;
-    const int c = cc - comp * a.tw;
-    V val = mk<T>((T)0, (T)0);
-    if (i < a.nz && c0 + c < a.plane) val = base[((long long)comp * a.nz + i) * a.plane + c0 + c];
-    s[i * ld + cc] = val;
-  }
-  __syncthreads();
-  lds_fft<V, EPT>(s, ld, ncols, a.pl, tw, -1, tid, nt);
-  // pointwise 3x3 multiply
-  const int L2x = 2 * a.nx;
-  const long long ox_n = a.nx + 1, oy_n = a.ny + 1;
-  const long long cstride = (long long)(a.nz + 1) * oy_n * ox_n;
-  for (int e = tid; e < a.tw * n; e += nt) {
-    const int i = e / a.tw;
-    const int c = e - i * a.tw;
-    const long long kyx = c0 + c;
-    if (kyx >= a.plane) continue;
-    const int ky = (int)(kyx / L2x);
-    const int kx = (int)(kyx - (long long)ky * L2x);
-    int mir = 0;
-    int ox = kx, oy = ky, oz = i;
-    if (kx > a.nx) { ox = L2x - kx; mir |= 1; }
-    if (ky > a.ny) { oy = 2 * a.ny - ky; mir |= 2; }
-    if (i > a.nz) { oz = n - i; mir |= 4; }
-    const long long o = ((long long)oz * oy_n + oy) * ox_n + ox;
-    V K[6];
-#pragma unroll
-    for (int cc = 0; cc < 6; ++cc) {
-      V kv = khat[cc * cstride + o];
-      if (__popc(comp_odd_mask(cc) & mir) & 1) { kv.x = -kv.x; kv.y = -kv.y; }
-      K[cc] = kv;
+  const Lane L = make_lane(ncols, tpc_of(n));
+  if (L.active) {
+    const int comp = L.c >> a.twsh, c = L.c & (a.tw - 1);
+    const bool ok = c0 + c < a.plane;
+    const V *src = base + (long long)comp * a.nz * a.plane + c0 + c;
+    for (int i = L.jt; i < n; i += L.tpc) {
+      V val = mk<T>((T)0, (T)0);
+      if (i < a.nz && ok) val = src[(long long)i * a.plane];
+      s[lrow(i, ld) + L.c] = val;
     }
-    V* row = s + i * ld;
-    const V x0 = row[c], x1 = row[a.tw + c], x2 = row[2 * a.tw + c];
-    row[c] = cadd(cadd(cmul(K[0], x0), cmul(K[1], x1)), cmul(K[2], x2));
-    row[a.tw + c] = cadd(cadd(cmul(K[1], x0), cmul(K[3], x1)), cmul(K[4], x2));
-    row[2 * a.tw + c] = cadd(cadd(cmul(K[2], x0), cmul(K[4], x1)), cmul(K[5], x2));
   }
   __syncthreads();
-  lds_fft<V, EPT>(s, ld, ncols, a.pl, tw, +1, tid, nt);
-  const int toto = 3 * a.tw * a.nz;
-  for (int e = tid; e < toto; e += nt) {
-    const int i = e / ncols;
-    const int cc = e - i * ncols;
-    const int comp = cc / a.tw;
-    const int c = cc - comp * a.tw;
-    if (c0 + c < a.plane) base[((long long)comp * a.nz + i) * a.plane + c0 + c] = s[i * ld + cc];
+  lds_fft_any<V, EPT, NF>(s, ld, L, a.pl, tw, -1);
+  // pointwise 3x3 multiply: thread -> column tid % tw, rows tid / tw + q (blockDim / tw)
+  {
+    const int L2x = 2 * a.nx;
+    const long long ox_n = a.nx + 1, oy_n = a.ny + 1;
+    const long long cstride = (long long)(a.nz + 1) * oy_n * ox_n;
+    const int c = threadIdx.x & (a.tw - 1);
+    const int rstep = blockDim.x >> a.twsh;
+    const long long kyx = c0 + c;
+    if (kyx < a.plane) {
+      const int ky = (int)(kyx / L2x);
+      const int kx = (int)(kyx - (long long)ky * L2x);
+      int mxy = 0;
+      int ox = kx, oy = ky;
+      if (kx > a.nx) { ox = L2x - kx; mxy |= 1; }
+      if (ky > a.ny) { oy = 2 * a.ny - ky; mxy |= 2; }
+      for (int i = threadIdx.x >> a.twsh; i < n; i += rstep) {
+        int mir = mxy, oz = i;
+        if (i > a.nz) { oz = n - i; mir |= 4; }
+        const long long o = ((long long)oz * oy_n + oy) * ox_n + ox;
+        V K[6];
+#pragma unroll
+        for (int cc = 0; cc < 6; ++cc) {
+          V kv = khat[cc * cstride + o];
+          if (__popc(comp_odd_mask(cc) & mir) & 1) { kv.x = -kv.x; kv.y = -kv.y; }
+          K[cc] = kv;
+        }
+        V *row = s + lrow(i, ld);
+        const V x0 = row[c], x1 = row[a.tw + c], x2 = row[2 * a.tw + c];
+        row[c] = cadd(cadd(cmul(K[0], x0), cmul(K[1], x1)), cmul(K[2], x2));
+        row[a.tw + c] = cadd(cadd(cmul(K[1], x0), cmul(K[3], x1)), cmul(K[4], x2));
+        row[2 * a.tw + c] = cadd(cadd(cmul(K[2], x0), cmul(K[4], x1)), cmul(K[5], x2));
+      }
+    }
+  }
+  __syncthreads();
+  lds_fft_any<V, EPT, NF>(s, ld, L, a.pl, tw, +1);
+  if (L.active) {
+    const int comp = L.c >> a.twsh, c = L.c & (a.tw - 1);
+    if (c0 + c < a.plane) {
+      V *dst = base + (long long)comp * a.nz * a.plane + c0 + c;
+      for (int i = L.jt; i < a.nz; i += L.tpc) dst[(long long)i * a.plane] = s[lrow(i, ld) + L.c];
+    }
   }
 }
 
@@ -234,31 +242,59 @@ template <typename T> inline const cplx<T> *tw_of(const FftPlan &p);
 template <> inline const double2 *tw_of<double>(const FftPlan &p) { return p.tw64; }
 template <> inline const float2 *tw_of<float>(const FftPlan &p) { return p.tw32; }
 
-// Columns per 32 KB tile for a transform of length n.
+// Call f(std::integral_constant<int, NF>) with NF = n for the power-of-two lengths that have
+// a compile-time plan, NF = 0 (runtime plan) otherwise.
+template <typename F> inline void with_static_n(int n, F &&f) {
+  switch (n) {
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    case 64: f(std::integral_constant<int, 64>{}); break;
+    case 128: f(std::integral_constant<int, 128>{}); break;
+    case 256: f(std::integral_constant<int, 256>{}); break;
+    case 512: f(std::integral_constant<int, 512>{}); break;
+    default: f(std::integral_constant<int, 0>{}); break;
+  }
+}
+
+inline int ilog2_exact(int n) {
+  if (n <= 0 || (n & (n - 1))) return -1;
+  int s = 0;
+  while ((1 << s) < n) ++s;
+  return s;
+}
+
+// Columns per tile for a length-n transform: fill 256 threads (tpc threads per column)
+// within a 40 KB LDS tile.
 template <typename T> inline int tile_cols(int n) {
-  const int elems = kFftThreads * EptOf<T>::value;
-  int t = elems / n;
-  return t < 1 ? 1 : t;
+  const int tpc = tpc_of(n);
+  int t = kFftThreads / tpc;
+  if (t < 1) t = 1;
+  while (t > 1 && (size_t)lds_elems(n, t + 1) * sizeof(cplx<T>) > 40 * 1024) --t;
+  return t;
 }
 
 template <typename T> inline size_t tile_lds(int n, int cols) {
-  return (size_t)n * (size_t)(cols + 1) * sizeof(cplx<T>);
+  return (size_t)lds_elems(n, cols + 1) * sizeof(cplx<T>);
 }
 
-// Launch a row transform.  `a` must have pl, rows, n_in, n_out, strides and sign set.
+// Launch a row transform.  `a` must have rows, n_in, n_out, strides and sign set.
 template <typename T, int MODE, typename TI, typename TO>
 inline void launch_rows(dda_problem *p, const FftPlan &pl, const TI *in, TO *out, RowArgs a,
                         const char *name, double bytes) {
   a.pl = desc(pl);
   a.tw = tile_cols<T>(pl.n);
   if (a.rows < a.tw) a.tw = (int)a.rows;
+  a.nsh = ilog2_exact(pl.n);
   const long long blocks = (a.rows + a.tw - 1) / a.tw;
   const size_t lds = tile_lds<T>(pl.n, a.tw);
-  auto fn = k_fft_rows<T, MODE, TI, TO>;
-  set_lds_limit((const void *)fn, lds);
+  const int threads = std::max(64, a.tw * tpc_of(pl.n));
   KTimer t(&p->prof, p->st, name, bytes);
-  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kFftThreads), lds, p->st, in, out,
-                     tw_of<T>(pl), a);
+  with_static_n(pl.n, [&](auto nf) {
+    auto fn = k_fft_rows<T, MODE, TI, TO, decltype(nf)::value>;
+    set_lds_limit((const void *)fn, lds);
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(threads), lds, p->st, in, out,
+                       tw_of<T>(pl), a);
+  });
   HIPCHK(hipGetLastError());
 }
 
@@ -280,11 +316,14 @@ inline void launch_strided(dda_problem *p, const FftPlan &pl, const cplx<T> *in,
   a.out_bstride = out_bstride;
   a.sign = sign;
   const size_t lds = tile_lds<T>(pl.n, a.tw);
-  auto fn = k_fft_strided<T>;
-  set_lds_limit((const void *)fn, lds);
+  const int threads = a.tw * tpc_of(pl.n);
   KTimer t(&p->prof, p->st, name, bytes);
-  hipLaunchKernelGGL(fn, dim3((unsigned)(a.ntiles * batch)), dim3(kFftThreads), lds, p->st, in,
-                     out, tw_of<T>(pl), a);
+  with_static_n(pl.n, [&](auto nf) {
+    auto fn = k_fft_strided<T, decltype(nf)::value>;
+    set_lds_limit((const void *)fn, lds);
+    hipLaunchKernelGGL(fn, dim3((unsigned)(a.ntiles * batch)), dim3(threads), lds, p->st, in,
+                       out, tw_of<T>(pl), a);
+  });
   HIPCHK(hipGetLastError());
 }
 

@@ -1,8 +1,16 @@
 // Restarted GMRES(m), right-preconditioned, FP64 Arnoldi with classical Gram-Schmidt
 // applied twice, per-RHS Hessenberg / Givens updates on the device, and the FP32-inner /
 // FP64-outer iterative refinement driver.  The paper runs GMRES to 1e-5 (Sec. 4); restarts
-// are the variant it recommends for memory (Sec. 4-5).  All reductions are fixed-order
-// (block partials, then one ordered pass), so results repeat bit for bit.
+// are the variant it recommends for memory (Sec. 4-5).
+//
+// Basis vectors are stored unnormalised: vsc[r][i] = 1 / ||v~_i|| scales them wherever they
+// are used (projection coefficients, the operator's input prologue, the solution update),
+// which saves one full pass per iteration.  Orthogonalisation is classical Gram-Schmidt
+// with selective reorthogonalisation: a second projection runs only when the first one
+// removed more than half of the vector's squared norm (||w'|| < ||w|| / sqrt 2, the
+// "twice is enough" criterion of Daniel, Gragg, Kaufman and Stewart), so most iterations
+// read the basis twice.  All reductions are fixed-order (per-block partials, then one
+// ordered pass), so results repeat bit for bit.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -13,22 +21,46 @@ namespace dda {
 
 constexpr int kRedThreads = 256;
 constexpr int kCH = 8;  // vectors per multi-dot sweep
-constexpr int kMaxM = 32;
 
 int reduce_blocks(long long n) {
   long long b = (n + 1023) / 1024;
   return (int)std::max<long long>(1, std::min<long long>(1024, b));
 }
 
-// partial[(r * kMaxM + i) * B + blk] = sum_{n in block} conj(V_i[n]) w[n], i in [0, nvec)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the block of NQ complex values per thread; results in sh[q] (all threads see them).
+template <int NQ>
+__device__ __forceinline__ void block_sum(double2 (&acc)[NQ], double2 *sh /* [4][NQ] */) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double re = wave_sum(acc[q].x), im = wave_sum(acc[q].y);
+    if (lane == 0) sh[wv * NQ + q] = make_double2(re, im);
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NQ) {
+    double2 t = make_double2(0.0, 0.0);
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = cadd(t, sh[w * NQ + threadIdx.x]);
+    sh[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// partial[(r * kMaxM + i) * B + blk] = sum_{n in block} conj(V_i[n]) w[n], i in [0, nvec);
+// with want_norm also the block's ||w||^2 in slot kMaxM - 1.
 __global__ void __launch_bounds__(kRedThreads) k_multidot(const double2 *V, long long vs_r,
                                                           long long vs_j, int nvec,
                                                           const double2 *w, long long ws_r,
                                                           long long n3, const int *active,
-                                                          double2 *partial, int B) {
+                                                          double2 *partial, int B, int want_norm) {
   const int r = blockIdx.y;
   if (!active[r]) return;
-  __shared__ double2 sh[kCH][kRedThreads];
+  __shared__ double2 sh[4 * kCH];
   const double2 *wr = w + r * ws_r;
   for (int i0 = 0; i0 < nvec; i0 += kCH) {
     double2 acc[kCH];
@@ -41,25 +73,30 @@ __global__ void __launch_bounds__(kRedThreads) k_multidot(const double2 *V, long
       for (int q = 0; q < kCH; ++q)
         if (i0 + q < nvec) acc[q] = cadd(acc[q], cmulcj(V[r * vs_r + (i0 + q) * vs_j + n], wv));
     }
-#pragma unroll
-    for (int q = 0; q < kCH; ++q) sh[q][threadIdx.x] = acc[q];
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s)
-#pragma unroll
-        for (int q = 0; q < kCH; ++q) sh[q][threadIdx.x] = cadd(sh[q][threadIdx.x], sh[q][threadIdx.x + s]);
-      __syncthreads();
-    }
+    block_sum<kCH>(acc, sh);
     if ((int)threadIdx.x < kCH && i0 + (int)threadIdx.x < nvec)
-      partial[((long long)r * kMaxM + i0 + threadIdx.x) * B + blockIdx.x] = sh[threadIdx.x][0];
+      partial[((long long)r * kMaxM + i0 + threadIdx.x) * B + blockIdx.x] = sh[threadIdx.x];
     __syncthreads();
+  }
+  if (want_norm) {  // ||w||^2 into slot kMaxM - 1
+    double2 acc[1] = {make_double2(0.0, 0.0)};
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
+         n += (long long)gridDim.x * blockDim.x) {
+      const double2 wv = wr[n];
+      acc[0].x += wv.x * wv.x + wv.y * wv.y;
+    }
+    block_sum<1>(acc, sh);
+    if (threadIdx.x == 0) partial[((long long)r * kMaxM + kMaxM - 1) * B + blockIdx.x] = sh[0];
   }
 }
 
-// out[r * kMaxM + i] (+)= sum_b partial[(r * kMaxM + i) * B + b]   (ordered tree)
-__global__ void k_finalize(const double2 *partial, int B, double2 *out, int accumulate,
-                           const int *active) {
-  const int i = blockIdx.x, r = blockIdx.y;
+// out[r * kMaxM + i] = s_i * sum_b partial[(r * kMaxM + i) * B + b] (ordered), and, if coef,
+// coef[r * kMaxM + i] = s_i * out[...]; s_i = vsc[r * kMaxM + i] (1 when vsc is null).
+// With islot >= 0 a single slot islot is reduced into out[r * kMaxM].
+__global__ void k_finalize(const double2 *partial, int B, double2 *out, double2 *coef,
+                           const double *vsc, const int *active, int islot) {
+  const int i = islot >= 0 ? islot : blockIdx.x, r = blockIdx.y;
+  const int io = islot >= 0 ? 0 : blockIdx.x;
   if (!active[r]) return;
   __shared__ double2 sh[kRedThreads];
   double2 acc = make_double2(0.0, 0.0);
@@ -72,8 +109,10 @@ __global__ void k_finalize(const double2 *partial, int B, double2 *out, int accu
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    if (accumulate) out[r * kMaxM + i] = cadd(out[r * kMaxM + i], sh[0]);
-    else out[r * kMaxM + i] = sh[0];
+    const double s = vsc ? vsc[r * kMaxM + i] : 1.0;
+    const double2 h = cscale(sh[0], s);
+    out[r * kMaxM + io] = h;
+    if (coef) coef[r * kMaxM + io] = cscale(h, s);
   }
 }
 
@@ -87,29 +126,26 @@ __global__ void __launch_bounds__(kRedThreads) k_multiaxpy(const double2 *V, lon
   const int r = blockIdx.y;
   if (!active[r]) return;
   __shared__ double2 c[kMaxM];
-  __shared__ double sh[kRedThreads];
+  __shared__ double2 sh[4];
   if ((int)threadIdx.x < nvec) c[threadIdx.x] = coef[r * kMaxM + threadIdx.x];
   __syncthreads();
   double2 *wr = w + r * ws_r;
-  double acc = 0.0;
+  const double2 *Vr = V + r * vs_r;
+  double2 acc[1] = {make_double2(0.0, 0.0)};
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
        n += (long long)gridDim.x * blockDim.x) {
     double2 v = wr[n];
-    for (int i = 0; i < nvec; ++i) v = csub(v, cmul(V[r * vs_r + i * vs_j + n], c[i]));
+#pragma unroll 4
+    for (int i = 0; i < nvec; ++i) v = csub(v, cmul(Vr[i * vs_j + n], c[i]));
     wr[n] = v;
-    acc += v.x * v.x + v.y * v.y;
+    acc[0].x += v.x * v.x + v.y * v.y;
   }
   if (!nrm_partial) return;
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) nrm_partial[((long long)r * kMaxM) * B + blockIdx.x] = make_double2(sh[0], 0.0);
+  block_sum<1>(acc, sh);
+  if (threadIdx.x == 0) nrm_partial[((long long)r * kMaxM) * B + blockIdx.x] = sh[0];
 }
 
-// out = sum_i V_i y_i  (y = coef[r * kMaxM + i]; zero coefficients beyond a RHS's cut)
+// out = sum_i V_i y_i  (y = coef[r * kMaxM + i], zero beyond a RHS's cut)
 __global__ void k_combine(const double2 *V, long long vs_r, long long vs_j, int nvec,
                           const double2 *coef, double2 *out, long long os_r, long long n3) {
   const int r = blockIdx.y;
@@ -131,23 +167,18 @@ __global__ void __launch_bounds__(kRedThreads) k_axpby(const double2 *a, const d
                                                        double2 *nrm_partial, int B) {
   const int r = blockIdx.y;
   if (active && !active[r]) return;
-  __shared__ double sh[kRedThreads];
-  double acc = 0.0;
+  __shared__ double2 sh[4];
+  double2 acc[1] = {make_double2(0.0, 0.0)};
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
        n += (long long)gridDim.x * blockDim.x) {
     const long long o = r * st_r + n;
     const double2 v = make_double2(a[o].x + s * b[o].x, a[o].y + s * b[o].y);
     out[o] = v;
-    acc += v.x * v.x + v.y * v.y;
+    acc[0].x += v.x * v.x + v.y * v.y;
   }
   if (!nrm_partial) return;
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int q = blockDim.x / 2; q > 0; q >>= 1) {
-    if ((int)threadIdx.x < q) sh[threadIdx.x] += sh[threadIdx.x + q];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) nrm_partial[((long long)r * kMaxM) * B + blockIdx.x] = make_double2(sh[0], 0.0);
+  block_sum<1>(acc, sh);
+  if (threadIdx.x == 0) nrm_partial[((long long)r * kMaxM) * B + blockIdx.x] = sh[0];
 }
 
 // partial ||a||^2
@@ -155,23 +186,18 @@ __global__ void __launch_bounds__(kRedThreads) k_norm2(const double2 *a, long lo
                                                        long long st_r, double2 *nrm_partial,
                                                        int B) {
   const int r = blockIdx.y;
-  __shared__ double sh[kRedThreads];
-  double acc = 0.0;
+  __shared__ double2 sh[4];
+  double2 acc[1] = {make_double2(0.0, 0.0)};
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
        n += (long long)gridDim.x * blockDim.x) {
     const double2 v = a[r * st_r + n];
-    acc += v.x * v.x + v.y * v.y;
+    acc[0].x += v.x * v.x + v.y * v.y;
   }
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int q = blockDim.x / 2; q > 0; q >>= 1) {
-    if ((int)threadIdx.x < q) sh[threadIdx.x] += sh[threadIdx.x + q];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) nrm_partial[((long long)r * kMaxM) * B + blockIdx.x] = make_double2(sh[0], 0.0);
+  block_sum<1>(acc, sh);
+  if (threadIdx.x == 0) nrm_partial[((long long)r * kMaxM) * B + blockIdx.x] = sh[0];
 }
 
-// out[n] = in[n] * scal[r]  (scal from the device scalars)
+// out[n] = in[n] * scal[r * sstride]
 __global__ void k_scale(const double2 *in, double2 *out, long long n3, long long ins_r,
                         long long outs_r, const double *scal, int sstride, const int *active) {
   const int r = blockIdx.y;
@@ -184,28 +210,31 @@ __global__ void k_scale(const double2 *in, double2 *out, long long n3, long long
   }
 }
 
-// Start of a cycle: g = (beta, 0, ...), scal = 1/beta with beta = sqrt(rn2)
-__global__ void k_cycle_init(const double2 *rn2, double2 *g, int m, double *dscal, const int *active,
+// Start of a cycle (basis vector 0 is the residual itself): g = (beta, 0, ...),
+// vsc[0] = 1 / beta with beta = sqrt(rn2).
+__global__ void k_cycle_init(const double2 *rn2, double2 *g, int m, double *vsc, const int *active,
                              int nrhs) {
   const int r = threadIdx.x;
   if (r >= nrhs || !active[r]) return;
   const double beta = sqrt(rn2[r * kMaxM].x);
   for (int i = 0; i <= m; ++i) g[r * (m + 1) + i] = make_double2(0.0, 0.0);
   g[r * (m + 1)] = make_double2(beta, 0.0);
-  dscal[r * 8 + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
+  vsc[r * kMaxM] = beta > 0.0 ? 1.0 / beta : 0.0;
 }
 
 // Column j of the Hessenberg matrix from the two projections and ||w||^2, previous
-// rotations, a new rotation, the updated residual estimate |g_{j+1}| and 1/h_{j+1,j}.
+// rotations, a new rotation, the updated residual estimate |g_{j+1}| (dscal[r*8]),
+// ||w|| (dscal[r*8+2]) and the scale 1/||w|| of the new basis vector (vsc[r][j+1]).
 __global__ void k_arnoldi(int j, int m, double2 *H, double2 *giv, double2 *g, const double2 *h1,
-                          const double2 *h2, const double2 *nrm2, double *dscal, const int *active,
-                          int nrhs) {
+                          const double2 *h2, int use_h2, const double2 *nrm2, double *dscal,
+                          double *vsc, const int *active, int nrhs) {
   const int r = threadIdx.x;
   if (r >= nrhs || !active[r]) return;
   double2 *Hr = H + (long long)r * (m + 1) * m;
   double2 *gr = g + r * (m + 1);
   double2 *cs = giv + (long long)r * m * 2;
-  for (int i = 0; i <= j; ++i) Hr[i * m + j] = cadd(h1[r * kMaxM + i], h2[r * kMaxM + i]);
+  for (int i = 0; i <= j; ++i)
+    Hr[i * m + j] = use_h2 ? cadd(h1[r * kMaxM + i], h2[r * kMaxM + i]) : h1[r * kMaxM + i];
   const double hn = sqrt(nrm2[r * kMaxM].x);
   Hr[(j + 1) * m + j] = make_double2(hn, 0.0);
   for (int i = 0; i < j; ++i) {
@@ -237,13 +266,14 @@ __global__ void k_arnoldi(int j, int m, double2 *H, double2 *giv, double2 *g, co
   gr[j] = cscale(gj, c);
   const double2 e = gr[j + 1];
   dscal[r * 8 + 0] = sqrt(e.x * e.x + e.y * e.y);
-  dscal[r * 8 + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
   dscal[r * 8 + 2] = hn;
+  if (j + 1 < kMaxM) vsc[r * kMaxM + j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
 }
 
-// y = H(0:jc, 0:jc)^{-1} g(0:jc) (upper triangular), zero beyond jc; ycoef[r * kMaxM + i]
+// y = H(0:jc, 0:jc)^{-1} g(0:jc) (upper triangular), zero beyond jc; stored as the
+// combination coefficients y_i * vsc_i of the unnormalised basis.
 __global__ void k_trisolve(const double2 *H, const double2 *g, int m, const int *jcut,
-                           double2 *y, int nrhs) {
+                           const double *vsc, double2 *y, int nrhs) {
   const int r = threadIdx.x;
   if (r >= nrhs) return;
   const double2 *Hr = H + (long long)r * (m + 1) * m;
@@ -255,6 +285,7 @@ __global__ void k_trisolve(const double2 *H, const double2 *g, int m, const int 
     for (int q = i + 1; q < jc; ++q) acc = csub(acc, cmul(Hr[i * m + q], y[r * kMaxM + q]));
     y[r * kMaxM + i] = cdiv(acc, Hr[i * m + i]);
   }
+  for (int i = 0; i < jc; ++i) y[r * kMaxM + i] = cscale(y[r * kMaxM + i], vsc[r * kMaxM + i]);
 }
 
 // ----------------------------------------------------------------------------- host side
@@ -274,17 +305,22 @@ static void sync_active(dda_problem *p, int *d, const std::vector<int> &h) {
   HIPCHK(hipMemcpyAsync(d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, p->st));
 }
 
-// ||a_r||^2 into hcol2[r * kMaxM] (device), for every RHS
-static void norm2_dev(Kry &K, const double2 *a, long long st_r, double2 *dst, const int *act) {
+static void finalize(Kry &K, int nvec, double2 *out, double2 *coef, const double *vsc,
+                     int islot = -1) {
+  hipLaunchKernelGGL(k_finalize, dim3(nvec, K.nrhs), dim3(kRedThreads), 0, K.p->st, K.partial, K.B,
+                     out, coef, vsc, K.d_active, islot);
+  HIPCHK(hipGetLastError());
+}
+
+// ||a_r||^2 into dst[r * kMaxM] (device), for every RHS
+static void norm2_dev(Kry &K, const double2 *a, long long st_r, double2 *dst) {
   dda_problem *p = K.p;
   {
     KTimer t(&p->prof, p->st, "kry_norm", 16.0 * K.n3 * K.nrhs);
     hipLaunchKernelGGL(k_norm2, grid_r(K.B, K.nrhs), dim3(kRedThreads), 0, p->st, a, K.n3, st_r,
                        K.partial, K.B);
   }
-  hipLaunchKernelGGL(k_finalize, dim3(1, K.nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B, dst,
-                     0, act);
-  HIPCHK(hipGetLastError());
+  finalize(K, 1, dst, nullptr, nullptr);
 }
 
 static void read_scalars(dda_problem *p, const double2 *src, int nrhs, std::vector<double> &out) {
@@ -295,6 +331,7 @@ static void read_scalars(dda_problem *p, const double2 *src, int nrhs, std::vect
   for (int r = 0; r < nrhs; ++r) out[r] = tmp[r * kMaxM].x;
 }
 
+// r = b - A x (FP64 operator) into r, relative norms ||r|| / ||b|| to the host.
 void residual(dda_problem *p, int nrhs, const double2 *b, const double2 *x, double2 *r,
               double *rel_host) {
   const long long n3 = 3 * p->N;
@@ -308,12 +345,10 @@ void residual(dda_problem *p, int nrhs, const double2 *b, const double2 *x, doub
     hipLaunchKernelGGL(k_axpby, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, b, p->work, -1.0, r,
                        n3, n3, nullptr, K.partial, K.B);
   }
-  hipLaunchKernelGGL(k_finalize, dim3(1, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
-                     p->hcol2, 0, K.d_active);
-  HIPCHK(hipGetLastError());
+  finalize(K, 1, p->hcol2, nullptr, nullptr);
   std::vector<double> rn2, bn2;
   read_scalars(p, p->hcol2, nrhs, rn2);
-  norm2_dev(K, b, n3, p->hcol2, K.d_active);
+  norm2_dev(K, b, n3, p->hcol2);
   read_scalars(p, p->hcol2, nrhs, bn2);
   for (int q = 0; q < nrhs; ++q) rel_host[q] = bn2[q] > 0 ? std::sqrt(rn2[q] / bn2[q]) : std::sqrt(rn2[q]);
 }
@@ -326,24 +361,22 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
         p->dflag + 4 + p->R};
   const long long vs_r = n3, vs_j = (long long)p->R * n3;  // V is [m+1][R][n3]
   const bool prec = p->opt.precond == 2;
+  double2 *rv = p->V;  // the residual is written straight into basis block 0
   std::vector<int> all(nrhs, 1), act(nrhs, 1), incyc(nrhs, 0), jcut(nrhs, 0), iters(nrhs, 0);
   std::vector<int> cycles(nrhs, 0), conv(nrhs, 0);
   std::vector<double> bn2, rn2, rel(nrhs, 0.0);
   sync_active(p, K.d_active, all);
-  norm2_dev(K, b, n3, p->hcol2, K.d_active);
+  norm2_dev(K, b, n3, p->hcol2);
   read_scalars(p, p->hcol2, nrhs, bn2);
-  // initial residual r = b - A x
   auto true_residual = [&](void) {
     sync_active(p, K.d_active, all);
     apply_operator(p, nrhs, x, p->work, fp32, nullptr);
     {
       KTimer t(&p->prof, p->st, "kry_residual", 48.0 * n3 * nrhs);
       hipLaunchKernelGGL(k_axpby, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, b, p->work, -1.0,
-                         p->rvec, n3, n3, nullptr, K.partial, K.B);
+                         rv, n3, n3, nullptr, K.partial, K.B);
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
-                       p->hcol2, 0, K.d_active);
-    HIPCHK(hipGetLastError());
+    finalize(K, 1, p->hcol2, nullptr, nullptr);
     read_scalars(p, p->hcol2, nrhs, rn2);
     for (int r = 0; r < nrhs; ++r) {
       rel[r] = bn2[r] > 0 ? std::sqrt(rn2[r] / bn2[r]) : 0.0;
@@ -364,52 +397,63 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
       if (incyc[r]) cycles[r] += 1;
     }
     sync_active(p, K.d_active, incyc);
-    // v0 = r / ||r||, g = beta e1
-    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, p->st, p->hcol2, p->gvec, m, p->dscal,
+    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, p->st, p->hcol2, p->gvec, m, p->vsc,
                        K.d_active, nrhs);
-    hipLaunchKernelGGL(k_scale, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->rvec, p->V, n3, n3,
-                       vs_r, p->dscal + 1, 8, K.d_active);
     HIPCHK(hipGetLastError());
-    int jused = 0;
     for (int j = 0; j < m; ++j) {
       double2 *vj = p->V + (long long)j * vs_j;
       double2 *w = p->V + (long long)(j + 1) * vs_j;
-      // basis block j is contiguous [nrhs][n3]: transform it in place of a copy
-      const double2 *z = vj;
+      // w = A P^{-1} (v~_j / ||v~_j||); block j is contiguous [nrhs][n3]
       if (prec) {
-        apply_precond(p, nrhs, vj, p->work2, fp32, nullptr);
-        z = p->work2;
+        apply_precond(p, nrhs, vj, p->work2, fp32, p->vsc + j);
+        apply_operator(p, nrhs, p->work2, w, fp32, nullptr);
+      } else {
+        apply_operator(p, nrhs, vj, w, fp32, p->vsc + j);
       }
-      apply_operator(p, nrhs, z, w, fp32, nullptr);
-      // CGS2
-      for (int pass = 0; pass < 2; ++pass) {
-        double2 *hdst = pass == 0 ? p->hcol : p->hcol2;
+      // CGS: h1 = V^H w (and ||w||^2), w -= V h1 (and ||w'||^2)
+      {
+        KTimer t(&p->prof, p->st, "kry_multidot", 16.0 * n3 * (j + 2) * nrhs);
+        hipLaunchKernelGGL(k_multidot, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r,
+                           vs_j, j + 1, w, vs_r, n3, K.d_active, K.partial, K.B, 1);
+      }
+      finalize(K, j + 1, p->hcol, p->ycoef, p->vsc);
+      finalize(K, 1, p->hnrm, nullptr, nullptr, kMaxM - 1);  // ||w||^2 -> hnrm[r][0]
+      {
+        KTimer t(&p->prof, p->st, "kry_multiaxpy", 16.0 * n3 * (j + 3) * nrhs);
+        hipLaunchKernelGGL(k_multiaxpy, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r,
+                           vs_j, j + 1, p->ycoef, w, vs_r, n3, K.d_active, K.partial, K.B);
+      }
+      finalize(K, 1, p->hnrm + 1, nullptr, nullptr, 0);  // ||w'||^2 -> hnrm[r][1]
+      // reorthogonalise (second CGS pass) where ||w'||^2 < ||w||^2 / 2
+      std::vector<double2> nr((size_t)kMaxM * nrhs);
+      HIPCHK(hipMemcpyAsync(nr.data(), p->hnrm, sizeof(double2) * kMaxM * nrhs,
+                            hipMemcpyDeviceToHost, p->st));
+      HIPCHK(hipStreamSynchronize(p->st));
+      bool reorth = false;
+      for (int r = 0; r < nrhs; ++r)
+        if (incyc[r] && nr[r * kMaxM + 1].x < 0.5 * nr[r * kMaxM].x) reorth = true;
+      const double2 *nrm2 = p->hnrm + 1;
+      if (reorth) {
         {
           KTimer t(&p->prof, p->st, "kry_multidot", 16.0 * n3 * (j + 2) * nrhs);
           hipLaunchKernelGGL(k_multidot, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r,
-                             vs_j, j + 1, w, vs_r, n3, K.d_active, K.partial, K.B);
+                             vs_j, j + 1, w, vs_r, n3, K.d_active, K.partial, K.B, 0);
         }
-        hipLaunchKernelGGL(k_finalize, dim3(j + 1, nrhs), dim3(kRedThreads), 0, p->st, K.partial,
-                           K.B, hdst, 0, K.d_active);
+        finalize(K, j + 1, p->hcol2, p->ycoef, p->vsc);
         {
           KTimer t(&p->prof, p->st, "kry_multiaxpy", 16.0 * n3 * (j + 3) * nrhs);
           hipLaunchKernelGGL(k_multiaxpy, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V,
-                             vs_r, vs_j, j + 1, hdst, w, vs_r, n3, K.d_active,
-                             pass == 1 ? K.partial : nullptr, K.B);
+                             vs_r, vs_j, j + 1, p->ycoef, w, vs_r, n3, K.d_active, K.partial, K.B);
         }
-        HIPCHK(hipGetLastError());
+        finalize(K, 1, p->ycoef, nullptr, nullptr, 0);
+        nrm2 = p->ycoef;
       }
-      hipLaunchKernelGGL(k_finalize, dim3(1, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
-                         p->ycoef, 0, K.d_active);
       hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, p->st, j, m, p->H, p->givens, p->gvec,
-                         p->hcol, p->hcol2, p->ycoef, p->dscal, K.d_active, nrhs);
-      hipLaunchKernelGGL(k_scale, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, w, w, n3, vs_r,
-                         vs_r, p->dscal + 1, 8, K.d_active);
+                         p->hcol, p->hcol2, reorth ? 1 : 0, nrm2, p->dscal, p->vsc, K.d_active, nrhs);
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(hp.data(), p->dscal, sizeof(double) * 8 * nrhs, hipMemcpyDeviceToHost,
                             p->st));
       HIPCHK(hipStreamSynchronize(p->st));
-      jused = j + 1;
       bool left = false;
       for (int r = 0; r < nrhs; ++r) {
         if (!incyc[r]) continue;
@@ -427,11 +471,10 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
       sync_active(p, K.d_active, incyc);
       if (!left) break;
     }
-    (void)jused;
     // x += P^{-1} (V y)
     HIPCHK(hipMemcpyAsync(K.d_jcut, jcut.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, p->st));
-    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, p->st, p->H, p->gvec, m, K.d_jcut, p->ycoef,
-                       nrhs);
+    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, p->st, p->H, p->gvec, m, K.d_jcut, p->vsc,
+                       p->ycoef, nrhs);
     int jmax = 0;
     for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jcut[r]);
     {
@@ -517,7 +560,6 @@ void krylov_alloc(dda_problem *p) {
   HIPCHK(hipMalloc(&p->work2, sizeof(double2) * (size_t)R * n3));
   HIPCHK(hipMalloc(&p->bvec, sizeof(double2) * (size_t)R * n3));
   HIPCHK(hipMalloc(&p->xvec, sizeof(double2) * (size_t)R * n3));
-  HIPCHK(hipMalloc(&p->rvec, sizeof(double2) * (size_t)R * n3));
   if (p->opt.precision == 1) {
     HIPCHK(hipMalloc(&p->xref, sizeof(double2) * (size_t)R * n3));
     HIPCHK(hipMalloc(&p->rref, sizeof(double2) * (size_t)R * n3));
@@ -528,13 +570,14 @@ void krylov_alloc(dda_problem *p) {
   HIPCHK(hipMalloc(&p->hcol, sizeof(double2) * (size_t)R * kMaxM));
   HIPCHK(hipMalloc(&p->hcol2, sizeof(double2) * (size_t)R * kMaxM));
   HIPCHK(hipMalloc(&p->ycoef, sizeof(double2) * (size_t)R * kMaxM));
+  HIPCHK(hipMalloc(&p->hnrm, sizeof(double2) * (size_t)R * kMaxM));
   const int B = reduce_blocks(n3);
   p->partial_elems = std::max<size_t>((size_t)R * kMaxM * B * 2, (size_t)R * 512 * 4);
   HIPCHK(hipMalloc(&p->partial, sizeof(double) * p->partial_elems));
   HIPCHK(hipMalloc(&p->dscal, sizeof(double) * 16 * R));
-  std::vector<double> init(16 * R, 0.0);
-  for (int r = 0; r < R; ++r) init[r * 8 + 7] = 1.0;  // unit scale slot
-  HIPCHK(hipMemcpy(p->dscal, init.data(), sizeof(double) * 16 * R, hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(p->dscal, 0, sizeof(double) * 16 * R));
+  HIPCHK(hipMalloc(&p->vsc, sizeof(double) * kMaxM * R));
+  HIPCHK(hipMemset(p->vsc, 0, sizeof(double) * kMaxM * R));
   HIPCHK(hipMalloc(&p->dflag, sizeof(int) * (4 + 2 * R)));
   HIPCHK(hipMemset(p->dflag, 0, sizeof(int) * (4 + 2 * R)));
 }

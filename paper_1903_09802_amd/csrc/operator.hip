@@ -1,5 +1,6 @@
 // The DDA operator: problem setup (polarisability, incident field), the Green-tensor
 // kernel spectrum, and the five-pass zero-padded FFT product (Sec. 1, 2.1-2.2).
+#include <algorithm>
 #include <cmath>
 
 #include "fft_kernels.h"
@@ -191,6 +192,8 @@ static void kernel_spectrum(dda_problem *p, int part) {
   HIPCHK(hipFree(tmp));
 }
 
+template <typename T> static void zpass_autotune(dda_problem *p, const cplx<T> *khat);
+
 void operator_setup(dda_problem *p) {
   // validation and mean permittivity
   const int nb = 1024;
@@ -222,6 +225,8 @@ void operator_setup(dda_problem *p) {
   HIPCHK(hipMalloc(&p->khat64, sizeof(double2) * oct));
   HIPCHK(hipMalloc(&p->khat32, sizeof(float2) * oct));
   kernel_spectrum(p, 0);
+  zpass_autotune<double>(p, p->khat64);
+  zpass_autotune<float>(p, p->khat32);
 }
 
 static void ensure_imag_spectrum(dda_problem *p) {
@@ -233,8 +238,10 @@ static void ensure_imag_spectrum(dda_problem *p) {
 
 // ----------------------------------------------------------------------------- the product
 
+// Launch the fused z pass with `tw` columns per tile (a power of two; 0: the autotuned choice).
 template <typename T>
-static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat) {
+static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, int tw = 0,
+                  bool timed = true) {
   const int n = p->pz.n;
   constexpr int EPT = EptOf<T>::value;
   ZArgs a;
@@ -243,28 +250,69 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat) {
   a.ny = p->ny;
   a.nx = p->nx;
   a.plane = 4LL * p->nx * p->ny;
-  // columns per tile: three components of tw columns in at most the LDS budget
-  const size_t budget = std::min<size_t>(p->lds_zpass, p->lds_max);
-  int tw = (int)(budget / (sizeof(cplx<T>) * (size_t)n * 3)) ;
-  while (tw > 1 && (size_t)n * (3 * tw + 1) * sizeof(cplx<T>) > budget) --tw;
-  if (tw < 1) tw = 1;
-  while (tw > 1 && ((3LL * tw * n + EPT - 1) / EPT) > 768) --tw;
-  if (tw > a.plane) tw = (int)a.plane;
+  if (tw <= 0) tw = p->ztw[sizeof(T) == 8 ? 0 : 1];
+  if (tw <= 0) tw = 1;
   a.tw = tw;
+  a.twsh = ilog2_exact(tw);
   a.ntiles = (a.plane + tw - 1) / tw;
-  int threads = (int)((3LL * tw * n + EPT - 1) / EPT);
-  threads = ((threads + 63) / 64) * 64;
-  if (threads > 768) threads = 768;
-  const size_t lds = (size_t)n * (3 * tw + 1) * sizeof(cplx<T>);
-  auto fn = k_zpass<T, EPT>;
-  set_lds_limit((const void *)fn, lds);
+  a.nrhs = nrhs;
+  const int threads = 3 * tw * tpc_of(n);
+  const size_t lds = (size_t)lds_elems(n, 3 * tw + 1) * sizeof(cplx<T>);
   const double sz = sizeof(cplx<T>);
   const double bytes = nrhs * (2.0 * 3.0 * a.plane * p->nz * sz) +
                        6.0 * (p->nx + 1) * (p->ny + 1) * (p->nz + 1) * sz;
-  KTimer t(&p->prof, p->st, sizeof(T) == 8 ? "zpass_f64" : "zpass_f32", bytes);
-  hipLaunchKernelGGL(fn, dim3((unsigned)(a.ntiles * nrhs)), dim3(threads), lds, p->st, w1,
-                     tw_of<T>(p->pz), khat, a);
+  KTimer t(timed ? &p->prof : nullptr, p->st, sizeof(T) == 8 ? "zpass_f64" : "zpass_f32", bytes);
+  with_static_n(n, [&](auto nf) {
+    auto fn = k_zpass<T, EPT, decltype(nf)::value>;
+    set_lds_limit((const void *)fn, lds);
+    hipLaunchKernelGGL(fn, dim3((unsigned)xcd_grid(a.ntiles * nrhs)), dim3(threads), lds, p->st,
+                       w1, tw_of<T>(p->pz), khat, a);
+  });
   HIPCHK(hipGetLastError());
+}
+
+// Largest power-of-two tile width that fits the LDS budget, 768 threads and the plane.
+template <typename T> static int zpass_max_tw(dda_problem *p) {
+  const int n = p->pz.n;
+  const size_t budget = std::min<size_t>(p->lds_zpass, p->lds_max);
+  int tw = 1;
+  while (true) {
+    const int t2 = tw * 2;
+    if ((size_t)lds_elems(n, 3 * t2 + 1) * sizeof(cplx<T>) > budget) break;
+    if (3 * t2 * tpc_of(n) > 768) break;
+    if (t2 > 4LL * p->nx * p->ny) break;
+    tw = t2;
+  }
+  return tw;
+}
+
+// Time each power-of-two tile width on the problem's own grid and keep the fastest.
+template <typename T> static void zpass_autotune(dda_problem *p, const cplx<T> *khat) {
+  const int tmax = zpass_max_tw<T>(p);
+  cplx<T> *w1 = reinterpret_cast<cplx<T> *>(p->w1);
+  HIPCHK(hipMemsetAsync(w1, 0, sizeof(cplx<T>) * 3 * 4LL * p->N, p->st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_tw = tmax;
+  for (int tw = tmax; tw >= 1; tw /= 2) {
+    zpass<T>(p, 1, w1, khat, tw, false);  // warm
+    HIPCHK(hipEventRecord(e0, p->st));
+    for (int rep = 0; rep < 3; ++rep) zpass<T>(p, 1, w1, khat, tw, false);
+    HIPCHK(hipEventRecord(e1, p->st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best * 0.97f) {
+      best = ms;
+      best_tw = tw;
+    }
+    if (tw <= 2) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->ztw[sizeof(T) == 8 ? 0 : 1] = best_tw;
 }
 
 // kind 0: DDA operator; kind 1: Im G convolution (scattering sum)

@@ -353,18 +353,21 @@ void precond_build(dda_problem *p, double s_bar) {
 // One workgroup per (unique mode, chunk of rc right-hand sides).  Gathers the
 // (+-wx, +-wy) mode vectors of each RHS, applies the Sx / Sy sign flips that map
 // them onto the stored mode, folds into the even / odd z halves, multiplies by
-// both stored inverse halves (read once for all vectors), unfolds, flips back and
-// writes in place.
-template <typename T>
+// both stored inverse halves (each matrix element read once for all NV vectors,
+// eight rows of both halves in flight per thread), unfolds, flips back and writes
+// in place.  Workgroups are XCD-remapped so neighbouring modes share an L2.
+template <typename T, int NV>
 __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__restrict__ binv,
                                                  int nx, int ny, int nz, int umx, int hh, int n2,
-                                                 int nrhs, int rc, long long nchunks) {
+                                                 int nrhs, int rc, long long nchunks, long long U) {
   using V = cplx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *Ub = reinterpret_cast<V *>(smem_raw);  // [2][nv][n2]
   const int tid = threadIdx.x, nt = blockDim.x;
-  const long long u = blockIdx.x / nchunks;
-  const int r0 = (int)(blockIdx.x - u * nchunks) * rc;
+  const long long blk = xcd_remap(blockIdx.x, U * nchunks);
+  if (blk >= U * nchunks) return;
+  const long long u = blk / nchunks;
+  const int r0 = (int)(blk - u * nchunks) * rc;
   const int nr = min(rc, nrhs - r0);
   const int uy = (int)(u / umx), ux = (int)(u % umx);
   const int mxs[2] = {ux, (nx - ux) % nx};
@@ -388,60 +391,65 @@ __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__re
     const long long cb = ((long long)r * 3 + a) * nz;
     const V v1 = W[(cb + iz) * plane + off];
     const V v2 = W[(cb + (nz - 1 - iz)) * plane + off];
-    const V vp = cscale(cadd(v1, cscale(v2, sa)), (T)0.5 * flip);
-    const V vm = cscale(csub(v1, cscale(v2, sa)), (T)0.5 * flip);
-    Ub[(0 * nv + vi) * n2 + a * hh + iz] = vp;
-    Ub[(1 * nv + vi) * n2 + a * hh + iz] = vm;
+    Ub[vi * n2 + a * hh + iz] = cscale(cadd(v1, cscale(v2, sa)), (T)0.5 * flip);
+    Ub[(nv + vi) * n2 + a * hh + iz] = cscale(csub(v1, cscale(v2, sa)), (T)0.5 * flip);
   }
   __syncthreads();
-  constexpr int MAXV = 16;
-  V acc[2][MAXV];
-  const int rows_per = (n2 + nt - 1) / nt;
-  for (int rp = 0; rp < rows_per; ++rp) {
-    const int i = tid + rp * nt;
+  constexpr int UNR = 8;
+  const V *M0 = binv + (u * 2 + 0) * (long long)n2 * n2;
+  const V *M1 = binv + (u * 2 + 1) * (long long)n2 * n2;
+  const V *U0 = Ub;
+  const V *U1 = Ub + (long long)nv * n2;
+  for (int i0 = 0; i0 < n2; i0 += nt) {
+    const int i = i0 + tid;
     const bool act = i < n2;
+    V a0[NV], a1[NV];
 #pragma unroll
-    for (int hf = 0; hf < 2; ++hf)
-#pragma unroll
-      for (int v = 0; v < MAXV; ++v) acc[hf][v] = mk<T>((T)0, (T)0);
+    for (int v = 0; v < NV; ++v) { a0[v] = mk<T>((T)0, (T)0); a1[v] = mk<T>((T)0, (T)0); }
     if (act) {
+      int j = 0;
+      for (; j + UNR <= n2; j += UNR) {
+        V m0[UNR], m1[UNR];
 #pragma unroll
-      for (int hf = 0; hf < 2; ++hf) {
-        const V *M = binv + ((u * 2 + hf) * (long long)n2) * n2;
-        const V *Uh = Ub + (long long)hf * nv * n2;
-        for (int j = 0; j < n2; ++j) {
-          const V m = M[(long long)j * n2 + i];
-#pragma unroll
-          for (int v = 0; v < MAXV; ++v)
-            if (v < nv) acc[hf][v] = cadd(acc[hf][v], cmul(m, Uh[v * n2 + j]));
+        for (int q = 0; q < UNR; ++q) {
+          m0[q] = M0[(long long)(j + q) * n2 + i];
+          m1[q] = M1[(long long)(j + q) * n2 + i];
         }
+#pragma unroll
+        for (int q = 0; q < UNR; ++q)
+#pragma unroll
+          for (int v = 0; v < NV; ++v)
+            if (v < nv) {
+              a0[v] = cadd(a0[v], cmul(m0[q], U0[v * n2 + j + q]));
+              a1[v] = cadd(a1[v], cmul(m1[q], U1[v * n2 + j + q]));
+            }
+      }
+      for (; j < n2; ++j) {
+        const V m0 = M0[(long long)j * n2 + i], m1 = M1[(long long)j * n2 + i];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          if (v < nv) {
+            a0[v] = cadd(a0[v], cmul(m0, U0[v * n2 + j]));
+            a1[v] = cadd(a1[v], cmul(m1, U1[v * n2 + j]));
+          }
       }
     }
-    __syncthreads();
+    // unfold + flip + scatter straight from registers: row i = (a, iz) of both halves
     if (act) {
+      const int a = i / hh, iz = i - a * hh;
+      const T sa = a == 2 ? (T)-1 : (T)1;
 #pragma unroll
-      for (int hf = 0; hf < 2; ++hf)
-#pragma unroll
-        for (int v = 0; v < MAXV; ++v)
-          if (v < nv) Ub[((long long)hf * nv + v) * n2 + i] = acc[hf][v];
+      for (int v = 0; v < NV; ++v) {
+        if (v >= nv) continue;
+        const int mode = v / nr, r = r0 + v % nr;
+        const int fx = mode % nmx, fy = mode / nmx;
+        const long long off = (long long)mys[fy] * nx + mxs[fx];
+        const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
+        const long long cb = ((long long)r * 3 + a) * nz;
+        W[(cb + iz) * plane + off] = cscale(cadd(a0[v], a1[v]), flip);
+        if (iz < h) W[(cb + (nz - 1 - iz)) * plane + off] = cscale(csub(a0[v], a1[v]), sa * flip);
+      }
     }
-    __syncthreads();
-  }
-  // unfold + flip + scatter
-  for (int e = tid; e < nv * 3 * hh; e += nt) {
-    const int vi = e / (3 * hh);
-    const int rem = e - vi * 3 * hh;
-    const int a = rem / hh, iz = rem - a * hh;
-    const int mode = vi / nr, r = r0 + vi % nr;
-    const int fx = mode % nmx, fy = mode / nmx;
-    const long long off = (long long)mys[fy] * nx + mxs[fx];
-    const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
-    const T sa = a == 2 ? (T)-1 : (T)1;
-    const long long cb = ((long long)r * 3 + a) * nz;
-    const V wp = Ub[(0 * nv + vi) * n2 + a * hh + iz];
-    const V wm = Ub[(1 * nv + vi) * n2 + a * hh + iz];
-    W[(cb + iz) * plane + off] = cscale(cadd(wp, wm), flip);
-    if (iz < h) W[(cb + (nz - 1 - iz)) * plane + off] = cscale(csub(wp, wm), sa * flip);
   }
 }
 
@@ -484,13 +492,27 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
     const size_t lds = (size_t)2 * 4 * rc * p->n2 * sizeof(cplx<T>);
     int threads = ((p->n2 + 63) / 64) * 64;
     threads = std::min(512, std::max(64, threads));
-    auto fn = k_pc_gemv<T>;
-    set_lds_limit((const void *)fn, lds);
     snprintf(nm, sizeof nm, "pc_gemv_%s", suf);
     const double bytes = (double)U * 2.0 * p->n2 * p->n2 * sz * nchunks + 2.0 * rows * nx * sz;
+    const int nvmax = 4 * rc;
+    const dim3 grid((unsigned)xcd_grid(U * nchunks));
     KTimer t(&p->prof, p->st, nm, bytes);
-    hipLaunchKernelGGL(fn, dim3((unsigned)(U * nchunks)), dim3(threads), lds, p->st, W, binv, nx, ny,
-                       nz, p->umx, p->hh, p->n2, nrhs, rc, nchunks);
+    if (nvmax <= 4) {
+      auto fn = k_pc_gemv<T, 4>;
+      set_lds_limit((const void *)fn, lds);
+      hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->umx, p->hh,
+                         p->n2, nrhs, rc, nchunks, U);
+    } else if (nvmax <= 8) {
+      auto fn = k_pc_gemv<T, 8>;
+      set_lds_limit((const void *)fn, lds);
+      hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->umx, p->hh,
+                         p->n2, nrhs, rc, nchunks, U);
+    } else {
+      auto fn = k_pc_gemv<T, 16>;
+      set_lds_limit((const void *)fn, lds);
+      hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->umx, p->hh,
+                         p->n2, nrhs, rc, nchunks, U);
+    }
     HIPCHK(hipGetLastError());
   }
   snprintf(nm, sizeof nm, "pc_y_inv_%s", suf);
