@@ -119,7 +119,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--c3-case", type=int, default=0, help="c3: 0 -> m = 1.31+0.001i, 1 -> m = 1.78")
+    ap.add_argument("--c4-prisms", type=int, default=16)
+    ap.add_argument("--c4-chunk", type=int, default=32, help="c4: right-hand sides per batched solve")
+    ap.add_argument("--c4-precision", type=int, default=0, help="c4: 0 FP64, 1 FP32 inside FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -137,6 +141,12 @@ def main():
     from paper_1903_09802_amd.dda import Problem, load
 
     load()
+    if args.workload == "c3":
+        return bench_c3(args)
+    if args.workload == "c4":
+        return bench_c4(args)
+    if args.workload == "c5":
+        return bench_c5(args)
     cfg, desc = workload(args.workload)
     s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
     nrhs = len(dirs)
@@ -256,6 +266,124 @@ def main():
         roofline=roofline, kernels=kernel_table, cpu_baseline=cpu,
     )
     print(json.dumps(line), flush=True)
+
+
+def _emit(line):
+    print(json.dumps(line), flush=True)
+
+
+def bench_c3(args):
+    """Precision: FP32 operator and preconditioner inside FP64 refinement vs all-FP64, 256^3."""
+    import numpy as np
+    import torch
+
+    import workloads as w
+    from paper_1903_09802_amd.dda import Problem
+
+    cfg = w.config_c3(args.c3_case)
+    s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
+    mask = torch.from_numpy(s.mask).cuda()
+    eps = torch.from_numpy(s.eps).cuda()
+    res = {}
+    for precision in (1, 0):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob = Problem(mask, eps, s.k, s.d, precond=2, tol=cfg["tol"], restart=30, precision=precision)
+        t1 = time.perf_counter()
+        prob.build_preconditioner(0.0)
+        t2 = time.perf_counter()
+        out = prob.solve(dirs, pols, return_c=False)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        prob.close()
+        del prob
+        torch.cuda.empty_cache()
+        st = out["stats"][0]
+        res[precision] = dict(setup_s=t1 - t0, build_s=t2 - t1, solve_s=t3 - t2, total_s=t3 - t0,
+                              iters=st["iters"], refinements=st["refinements"],
+                              rel_residual=st["rel_residual"], converged=st["converged"],
+                              cext=float(out["cext"][0]), cabs=float(out["cabs"][0]),
+                              csca=float(out["csca"][0]))
+    dev = {k: abs(res[1][k] - res[0][k]) / abs(res[0][k]) for k in ("cext", "csca")}
+    _emit(dict(metric=METRIC, workload="c3", unit="s", value=res[1]["total_s"], higher_is_better=False,
+               config=dict(workload=f"hex prism x=40 aspect 2, 256^3 grid (FFT 512^3), m="
+                           f"{'1.31+0.001i' if args.c3_case == 0 else '1.78'}, +z x-pol, tol 1e-5",
+                           grid=list(s.shape), n_occupied=int(s.n_occ)),
+               fp32_refined=res[1], fp64=res[0], speedup_fp32=res[0]["total_s"] / res[1]["total_s"],
+               xsec_rel_dev_fp32_vs_fp64=dev, dtype="f32 inner / f64 outer", data="synthetic"))
+
+
+def bench_c4(args):
+    """Batching: seeded prisms of uneven grids, 128 waves each, solved in RHS blocks."""
+    import numpy as np
+    import torch
+
+    import workloads as w
+    from paper_1903_09802_amd.dda import Problem
+
+    cfg = w.config_c4(n_prisms=args.c4_prisms)
+    lat, solved, iters = [], 0, []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for pr in cfg["prisms"]:
+        s, dirs, pols = pr["scatterer"], pr["dirs"], pr["pols"]
+        t0 = time.perf_counter()
+        mask = torch.from_numpy(s.mask).cuda()
+        eps = torch.from_numpy(s.eps).cuda()
+        S = np.sum((dirs * pols) ** 2, axis=1)
+        chunk = args.c4_chunk
+        prob = Problem(mask, eps, s.k, s.d, precond=2, tol=cfg["tol"], restart=30,
+                       precision=args.c4_precision, max_rhs=chunk)
+        prob.build_preconditioner(float(S.mean()))
+        for q0 in range(0, len(dirs), chunk):
+            out = prob.solve(dirs[q0:q0 + chunk], pols[q0:q0 + chunk], return_c=False)
+            solved += sum(st["converged"] for st in out["stats"])
+            iters += [st["iters"] for st in out["stats"]]
+        torch.cuda.synchronize()
+        prob.close()
+        lat.append(time.perf_counter() - t0)
+        print(f"c4 prism {len(lat)}/{len(cfg['prisms'])} grid {s.nx}^3: {lat[-1]:.3f} s", file=sys.stderr,
+              flush=True)
+    total = time.perf_counter() - t_all
+    n_rhs = sum(len(pr["dirs"]) for pr in cfg["prisms"])
+    _emit(dict(metric="RHS solves/s (batched, to rel. residual 1e-5)", workload="c4",
+               value=n_rhs / total, unit="solves/s", higher_is_better=True,
+               prisms_per_s=len(lat) / total, total_s=total, rhs_total=n_rhs, rhs_converged=solved,
+               latency_p50_s=float(np.percentile(lat, 50)), latency_p99_s=float(np.percentile(lat, 99)),
+               iters_mean=float(np.mean(iters)), iters_max=int(np.max(iters)),
+               grids=[pr["scatterer"].nx for pr in cfg["prisms"]], rhs_chunk=args.c4_chunk,
+               dtype="f64" if args.c4_precision == 0 else "f32 inner / f64 outer", data="synthetic"))
+
+
+def bench_c5(args):
+    """Differentiation: adjoint dC_ext/d eps on the 64^3 jittered prism vs a forward solve."""
+    import torch
+
+    import workloads as w
+    from paper_1903_09802_amd.dda import Problem
+
+    cfg = w.config_c5()
+    s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
+    mask = torch.from_numpy(s.mask).cuda()
+    eps = torch.from_numpy(s.eps).cuda()
+    prob = Problem(mask, eps, s.k, s.d, precond=2, tol=cfg["tol"], restart=30)
+    prob.build_preconditioner(0.0)
+    prob.solve(dirs, pols, return_c=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fwd = prob.solve(dirs, pols, return_c=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g, cext, stats, status = prob.grad_cext(dirs[0], pols[0])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    prob.close()
+    _emit(dict(metric="adjoint gradient s (forward + adjoint solve)", workload="c5",
+               value=t2 - t1, unit="s", higher_is_better=False, forward_s=t1 - t0,
+               grad_over_forward=(t2 - t1) / (t1 - t0), cext=cext, iters=[st["iters"] for st in stats],
+               grad_norm=float(torch.linalg.vector_norm(g).item()), dtype="f64", data="synthetic",
+               config=dict(workload="hex prism x=10 aspect 1, 64^3 grid, eps = 1.7161(1+U[-0.05,0.05])",
+                           grid=list(s.shape), n_occupied=int(s.n_occ))))
 
 
 if __name__ == "__main__":

@@ -69,17 +69,19 @@ typedef struct {
   int precond;      /* 0: none; 2: 2-level circulant preconditioner (Sec. 3); default 2 */
   int precision;    /* 0: everything in FP64;
                        1: operator and preconditioner applied in FP32 (complex64) inside
-                          FP64 iterative refinement; Krylov basis, Arnoldi and the refinement
-                          residual stay FP64.  default 0 */
-  double inner_tol; /* precision 1: relative tolerance of each inner solve; default 1e-4 */
-  int max_refine;   /* precision 1: cap on refinement steps; default 30 */
+                          FP64 iterative refinement: every restart cycle builds its Krylov
+                          space with the FP32 operator and preconditioner on an FP64 basis
+                          (FP64 Arnoldi), and every restart recomputes b - A x with the FP64
+                          operator, so each cycle is one refinement step.  default 0 */
+  double inner_tol; /* reserved (kept for layout stability); must lie in (0, 1); default 1e-4 */
+  int max_refine;   /* reserved (kept for layout stability); must be >= 1; default 30 */
   int max_rhs;      /* largest nrhs accepted by dda_solve / dda_apply_*; sizes the workspace; default 1 */
 } dda_options;
 
 typedef struct {
   int iters;           /* GMRES iterations (summed over refinement steps) */
   int cycles;          /* GMRES restart cycles */
-  int refinements;     /* outer refinement steps (precision 1), else 0 */
+  int refinements;     /* FP64 refinement steps = restart cycles (precision 1), else 0 */
   int converged;       /* 1 if rel_residual <= tol */
   double rel_residual; /* final true residual ||b - A x|| / ||b||, FP64 */
   double seconds;      /* wall-clock time of the call */
@@ -138,7 +140,7 @@ dda_status dda_build_preconditioner(dda_problem *p, double s_bar);
  *    (Draine-Flatau forms for this scaling; |E_0| = 1; area in length units^2).
  *  stats: optional host dda_stats [nrhs].
  * Returns OK when every right-hand side reached tol, NOT_CONVERGED (outputs
- * valid) when some hit max_iter / max_refine.  Errors: EINVAL (nrhs < 1 or
+ * valid) when some hit max_iter.  Errors: EINVAL (nrhs < 1 or
  * > max_rhs, bad vectors), ESTATE (opt.precond == 2 and no preconditioner
  * built), EDEVICE (non-finite residual, HIP failure).
  */

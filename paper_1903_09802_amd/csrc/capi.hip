@@ -31,7 +31,7 @@ void free_all(dda_problem *p) {
   };
   F(p->mask); F(p->eps); F(p->khat64); F(p->khat32); F(p->khatI64); F(p->w0); F(p->w1);
   F(p->ainv); F(p->Sdev); F(p->V); F(p->work); F(p->work2); F(p->bvec); F(p->xvec); F(p->vsc);
-  F(p->xref); F(p->rref); F(p->H); F(p->givens); F(p->gvec); F(p->hcol); F(p->hcol2);
+  F(p->H); F(p->givens); F(p->gvec); F(p->hcol); F(p->hcol2);
   F(p->ycoef); F(p->hnrm); F(p->partial); F(p->dscal); F(p->dflag);
   precond_free(p);
   plan_destroy(p->px); plan_destroy(p->py); plan_destroy(p->pz);
@@ -124,7 +124,6 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
       need += 8.0 * N * 6 * 16;                          // setup transient
       need += R * 3.0 * N * 2 * 16 + R * 3.0 * N * 4 * 16;  // w0 + w1
       need += R * (m + 1.0) * n3 * 16 + R * 5.0 * n3 * 16 + R * 16.0 * N;
-      if (o.precision == 1) need += 2.0 * R * n3 * 16;
       size_t freeb = 0, totb = 0;
       HIPCHK(hipMemGetInfo(&freeb, &totb));
       REQUIRE(need < 0.9 * (double)freeb, DDA_ENOMEM, "problem needs about %.2f GB, %.2f GB free",

@@ -246,8 +246,6 @@ struct dda_problem {
   double2 *work2 = nullptr;  // [R][3N]
   double2 *bvec = nullptr;   // [R][3N] right-hand side
   double2 *xvec = nullptr;   // [R][3N] iterate
-  double2 *xref = nullptr;   // [R][3N] refinement residual (right-hand side of the inner solve)
-  double2 *rref = nullptr;   // [R][3N] refinement correction
   double2 *H = nullptr;      // [R][restart+1][restart]
   double2 *givens = nullptr; // [R][restart][2] (c real in .x, s complex)
   double2 *gvec = nullptr;   // [R][restart+1]

@@ -414,3 +414,17 @@ def test_geometry_voxel_counts_match_tables_3_4():
             r = n / float(tot)
             best = r if best is None or abs(r - 1) < abs(best - 1) else best
         assert 0.95 <= best <= 1.05, (la, mu, x, tot, best)
+
+
+def test_torch_complex_gradient_convention():
+    """For a real loss L(z), torch stores dL/dRe z + i dL/dIm z in z.grad — the convention the
+    adjoint backward returns (pinned here on L = Im(a z) + |z|^2 by hand differentiation)."""
+    import torch
+    a = 0.7 - 1.3j
+    z = torch.tensor(0.4 + 0.9j, dtype=torch.complex128, requires_grad=True)
+    L = (a * z).imag + (z.abs() ** 2)
+    L.backward()
+    x, y = 0.4, 0.9
+    dLdx = a.imag + 2 * x   # Im(a z) = a_r y + a_i x
+    dLdy = a.real + 2 * y
+    assert abs(z.grad.item() - (dLdx + 1j * dLdy)) < 1e-14
