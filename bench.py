@@ -56,17 +56,61 @@ def operator_bytes(s, nrhs, elem=16):
     return nrhs * (p1 + p2 + p3 + p4 + p5) + e * 6 * (nx + 1) * (ny + 1) * (nz + 1)
 
 
-def cpu_baseline(cfg, gpu_iters):
-    """Oracle timed on a bounded sample of the same workload, extrapolated to one step."""
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_hex128_fp64.txt")
+
+
+def source_digest():
+    """Digest of the HIP sources; counter figures taken on other sources are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1903_09802_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a plain copy kernel), or
+    None when there is none for this kernel or it was taken on other sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest, rows = None, {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) >= 2 and f[0] == "source_digest:":
+                digest = f[1]
+            elif len(f) >= 6 and f[0] == "kernel" and f[2] == "fetch_bytes" and f[4] == "write_bytes":
+                rows[f[1]] = float(f[3]) + float(f[5])
+    if digest != source_digest():
+        return None
+    return rows.get(kernel)
+
+
+def cpu_baseline(cfg, gpu_iters, restart=30):
+    """The oracle timed on a bounded sample of the same workload and scaled to one step.
+
+    Timed oracle calls: the kernel spectrum (scipy FFTs of the padded Green tensor), one
+    FFT matvec, the Chan generator with its 2-D FFTs, the inversion and product of a sample
+    of mode blocks, and a few iterations of the oracle's own GMRES loop (modified
+    Gram-Schmidt) on vectors of the workload's length.  The step estimate is setup + build
+    (all modes) + the GPU's iteration count of matvec, block products and Gram-Schmidt work
+    (each Gram-Schmidt cost at its cycle position j).
+    """
     import numpy as np
     import scipy.fft as sfft
 
-    from oracle import circulant, fftmatvec, physics, system
+    from oracle import circulant, fftmatvec, gmres, physics, system
 
     cores = len(os.sched_getaffinity(0))
     s = cfg["scatterer"]
     dirs, pols = cfg["dirs"], cfg["pols"]
     nrhs = len(dirs)
+    nz, ny, nx = s.shape
     with sfft.set_workers(cores):
         t0 = time.perf_counter()
         Kh = fftmatvec.kernel_padded_fft(s.shape, s.k, s.d, workers=cores)
@@ -75,8 +119,7 @@ def cpu_baseline(cfg, gpu_iters):
         t0 = time.perf_counter()
         fftmatvec.fft_matvec(b, s.mask, s.eps, s.k, s.d, 0.0, Khat=Kh, workers=cores)
         t_mv = time.perf_counter() - t0
-        # preconditioner: generator + 2-D FFT for all modes, blocks inverted for a sample of modes
-        nz, ny, nx = s.shape
+        del Kh
         t0 = time.perf_counter()
         c2 = circulant.two_level_generator(s.shape, s.k, s.d)
         lam = np.fft.fft2(c2, axes=(2, 3))
@@ -85,33 +128,49 @@ def cpu_baseline(cfg, gpu_iters):
         iz = np.arange(nz)
         ds = (iz[:, None] - iz[None, :]) + nz - 1
         n_sample = 8
-        t0 = time.perf_counter()
+        v = np.ones((3 * nz, 4 * nrhs), dtype=np.complex128)
+        t_inv = t_gemv = 0.0
         for q in range(n_sample):
+            t0 = time.perf_counter()
             B = np.empty((3 * nz, 3 * nz), dtype=np.complex128)
             for a in range(3):
                 for bb in range(3):
                     B[a * nz:(a + 1) * nz, bb * nz:(bb + 1) * nz] = -lam[circulant.FULL[a, bb]][ds, q % ny, q % nx]
             B[np.arange(3 * nz), np.arange(3 * nz)] += ati
-            Bi = np.linalg.inv(B)
-            Bi @ np.ones(3 * nz, dtype=np.complex128)
-        t_inv = (time.perf_counter() - t0) / n_sample
+            Bi = circulant.invert_blocks(B[None, None])[0, 0]
+            t1 = time.perf_counter()
+            Bi @ v[:, :nrhs]
+            t_inv += t1 - t0
+            t_gemv += time.perf_counter() - t1
+        t_inv /= n_sample
+        t_gemv /= n_sample
+        del lam, c2
+        # Gram-Schmidt: the oracle's GMRES loop for k_it iterations with a diagonal operator
+        n3 = 3 * s.mask.size
+        rng = np.random.default_rng(0)
+        diag = 1.0 + 0.9 * np.exp(2j * np.pi * rng.random(n3))
+        rhs = rng.standard_normal(n3) + 0j
+        k_it = 6
         t0 = time.perf_counter()
-        for q in range(n_sample):
-            Bi @ np.ones((3 * nz, nrhs), dtype=np.complex128)
-        t_gemv = (time.perf_counter() - t0) / n_sample
+        for _ in range(k_it + 1):
+            diag * rhs
+        t_diag = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        gmres.gmres(lambda u: diag * u, rhs, restart=restart, tol=0.0, maxit=k_it)
+        t_gs = max(0.0, time.perf_counter() - t0 - t_diag)
+        per_pair = t_gs / (k_it * (k_it + 1) / 2)   # one projection (dot + update) per basis vector
     modes = nx * ny
     t_build = t_gen + modes * t_inv
-    t_pc = modes * t_gemv + 2 * t_mv / 3  # per-mode products + 2-D FFTs (about a third of a 3-D pair)
-    n3 = 3 * s.mask.size
-    t_arnoldi = 15 * 4 * n3 * 16 / 5e9  # CGS2 at j ~ 15, host memory bandwidth ~ 5 GB/s per pass
-    t_iter = nrhs * (t_mv + t_pc) + nrhs * t_arnoldi
-    est = t_setup + t_build + gpu_iters * t_iter
+    t_pc = modes * t_gemv + 2 * t_mv / 3          # per-mode products + 2-D FFTs (about a third of a 3-D pair)
+    pairs = sum((it % restart) + 1 for it in range(gpu_iters))
+    est = t_setup + t_build + nrhs * (gpu_iters * (t_mv + t_pc) + pairs * per_pair)
     sample = (f"oracle on {cores} host cores: kernel-spectrum setup, one FFT matvec, Chan generator "
-              f"+ 2-D FFTs, {n_sample} of {modes} mode-block inversions and products (scaled to all "
-              f"modes), extrapolated to {gpu_iters} preconditioned GMRES iterations x {nrhs} RHS")
+              f"+ 2-D FFTs, {n_sample} of {modes} mode blocks inverted and applied (scaled to all "
+              f"modes), {k_it} iterations of the oracle GMRES loop on {n3} unknowns (Gram-Schmidt "
+              f"cost per projection); extrapolated to {gpu_iters} preconditioned iterations x {nrhs} RHS")
     return dict(value=est, unit="s", cores=cores, kind="oracle", sample=sample,
                 parts=dict(setup_s=t_setup, matvec_s=t_mv, gen_s=t_gen, inv_per_mode_s=t_inv,
-                           apply_per_iter_s=t_pc))
+                           apply_per_iter_s=t_pc, gs_per_projection_s=per_pair))
 
 
 def main():
@@ -127,7 +186,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
+                    help="also run a plain 1 GiB elementwise copy kernel (calibrates HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -199,8 +258,8 @@ def main():
     avg_ms = dom["total_ms"] / max(1, dom["launches"])
     achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
     roofline = dict(bound="hbm", kernel=dom_name, achieved=achieved, peak=HBM_PEAK_GBPS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBPS, traffic=None, avg_launch_ms=avg_ms,
-                    bytes_per_launch=dom["bytes"])
+                    frac=achieved / HBM_PEAK_GBPS, traffic=measured_traffic(dom_name),
+                    avg_launch_ms=avg_ms, bytes_per_launch=dom["bytes"])
     kernel_table = {k: dict(launches=v["launches"], avg_ms=v["total_ms"] / max(1, v["launches"]),
                             share=v["total_ms"] / max(1e-12, sum(x["total_ms"] for x in agg.values())),
                             GBps=(v["bytes"] / (v["total_ms"] / max(1, v["launches"]) * 1e-3) / 1e9)
@@ -243,11 +302,13 @@ def main():
     prob.close()
 
     if args.copy_probe:
-        src = torch.empty(1 << 26, dtype=torch.complex128, device="cuda")
+        # an elementwise kernel that reads 1 GiB and writes 1 GiB: the scale for HBM byte counters
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

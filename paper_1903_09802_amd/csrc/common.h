@@ -252,7 +252,9 @@ struct dda_problem {
   double2 *hcol = nullptr;   // [R][restart+1] projections
   double2 *hcol2 = nullptr;  // [R][restart+1]
   double2 *ycoef = nullptr;  // [R][restart+1]
-  double2 *hnrm = nullptr;   // [R][kMaxM] squared norms before / after a projection
+  double2 *hnrm = nullptr;   // [R][kMaxM] squared norm after the projection
+  double2 *hraw = nullptr;   // [R][2 kMaxM] raw projections and Gram overlaps of one iteration
+  double2 *lmat = nullptr;   // [R][kMaxM][kMaxM] strictly lower triangle of the basis Gram matrix
   double *partial = nullptr; // reduction partials
   size_t partial_elems = 0;
   double *dscal = nullptr;   // [R][16] device scalars

@@ -1,17 +1,23 @@
-// Restarted GMRES(m), right-preconditioned, FP64 Arnoldi with classical Gram-Schmidt,
-// per-RHS Hessenberg / Givens updates on the device, and the mixed-precision mode in which
-// each restart cycle is one step of iterative refinement (FP32 operator and preconditioner
-// inside the cycle, FP64 residual at the restart).  The paper runs GMRES to 1e-5 (Sec. 4); restarts
-// are the variant it recommends for memory (Sec. 4-5).
+// Restarted GMRES(m), right-preconditioned, FP64 Arnoldi, per-RHS Hessenberg / Givens
+// updates on the device, and the mixed-precision mode in which each restart cycle is one step
+// of iterative refinement (FP32 operator and preconditioner inside the cycle, FP64 residual at
+// the restart).  The paper runs GMRES to 1e-5 (Sec. 4); restarts are the variant it recommends
+// for memory (Sec. 4-5).
 //
 // Basis vectors are stored unnormalised: vsc[r][i] = 1 / ||v~_i|| scales them wherever they
 // are used (projection coefficients, the operator's input prologue, the solution update),
-// which saves one full pass per iteration.  Orthogonalisation is classical Gram-Schmidt
-// with selective reorthogonalisation: a second projection runs only when the first one
-// removed more than half of the vector's squared norm (||w'|| < ||w|| / sqrt 2, the
-// "twice is enough" criterion of Daniel, Gragg, Kaufman and Stewart), so most iterations
-// read the basis twice.  All reductions are fixed-order (per-block partials, then one
-// ordered pass), so results repeat bit for bit.
+// which saves one full pass per iteration.
+//
+// Orthogonalisation is modified Gram-Schmidt written with one reduction per iteration (the
+// inverse compact WY form of Swirydowicz, Langou, Ananthan, Yang and Thomas): the MGS
+// sequence of projections (I - v_j v_j^H) ... (I - v_0 v_0^H) equals I - V T V^H with
+// T = (I + L)^{-1}, L the strictly lower triangle of V^H V.  One pass over the basis gives both
+// a = V^H w and the new row of L (the overlaps of v_j with v_0 .. v_{j-1}); a forward
+// substitution on the device gives the MGS coefficients c = T a; a second pass forms
+// w - V c and ||w - V c||^2.  Two reads of the basis per iteration, MGS's rounding behaviour
+// (loss of orthogonality of order eps * cond), no host decision inside an iteration.  All
+// reductions are fixed-order (per-block partials, then one ordered pass), so results repeat
+// bit for bit.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -31,7 +37,8 @@ static bool verbose() {
 }
 
 constexpr int kRedThreads = 256;
-constexpr int kCH = 8;  // vectors per multi-dot sweep
+constexpr int kCH = 8;             // vectors per multi-dot sweep
+constexpr int kSlots = 2 * kMaxM;  // reduction slots per RHS: projections, then Gram overlaps
 
 int reduce_blocks(long long n) {
   long long b = (n + 1023) / 1024;
@@ -62,46 +69,94 @@ __device__ __forceinline__ void block_sum(double2 (&acc)[NQ], double2 *sh /* [4]
   __syncthreads();
 }
 
-// partial[(r * kMaxM + i) * B + blk] = sum_{n in block} conj(V_i[n]) w[n], i in [0, nvec);
-// with want_norm also the block's ||w||^2 in slot kMaxM - 1.
-__global__ void __launch_bounds__(kRedThreads) k_multidot(const double2 *V, long long vs_r,
-                                                          long long vs_j, int nvec,
-                                                          const double2 *w, long long ws_r,
-                                                          long long n3, const int *active,
-                                                          double2 *partial, int B, int want_norm) {
+// One pass over basis blocks 0 .. j for every active RHS:
+//   partial slot i (i <= j):          sum_n conj(v~_i[n]) w[n]
+//   partial slot kMaxM + k (k < j):   sum_n conj(v~_k[n]) v~_j[n]
+// at partial[(r * kSlots + slot) * B + block].
+__global__ void __launch_bounds__(kRedThreads) k_gs_dots(const double2 *V, long long vs_r,
+                                                         long long vs_j, int j, const double2 *w,
+                                                         long long ws_r, long long n3,
+                                                         const int *active, double2 *partial,
+                                                         int B) {
   const int r = blockIdx.y;
   if (!active[r]) return;
-  __shared__ double2 sh[4 * kCH];
+  __shared__ double2 sh[4 * 2 * kCH];
   const double2 *wr = w + r * ws_r;
-  for (int i0 = 0; i0 < nvec; i0 += kCH) {
-    double2 acc[kCH];
+  const double2 *Vr = V + r * vs_r;
+  const double2 *vj = Vr + (long long)j * vs_j;
+  for (int i0 = 0; i0 <= j; i0 += kCH) {
+    double2 acc[2 * kCH];
 #pragma unroll
-    for (int q = 0; q < kCH; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (int q = 0; q < 2 * kCH; ++q) acc[q] = make_double2(0.0, 0.0);
+    const bool gram = i0 < j;
     for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
          n += (long long)gridDim.x * blockDim.x) {
       const double2 wv = wr[n];
+      const double2 jv = gram ? vj[n] : make_double2(0.0, 0.0);
 #pragma unroll
-      for (int q = 0; q < kCH; ++q)
-        if (i0 + q < nvec) acc[q] = cadd(acc[q], cmulcj(V[r * vs_r + (i0 + q) * vs_j + n], wv));
+      for (int q = 0; q < kCH; ++q) {
+        if (i0 + q <= j) {
+          const double2 v = Vr[(long long)(i0 + q) * vs_j + n];
+          acc[q] = cadd(acc[q], cmulcj(v, wv));
+          if (i0 + q < j) acc[kCH + q] = cadd(acc[kCH + q], cmulcj(v, jv));
+        }
+      }
     }
-    block_sum<kCH>(acc, sh);
-    if ((int)threadIdx.x < kCH && i0 + (int)threadIdx.x < nvec)
-      partial[((long long)r * kMaxM + i0 + threadIdx.x) * B + blockIdx.x] = sh[threadIdx.x];
+    block_sum<2 * kCH>(acc, sh);
+    const int t = threadIdx.x;
+    if (t < kCH && i0 + t <= j)
+      partial[((long long)r * kSlots + i0 + t) * B + blockIdx.x] = sh[t];
+    else if (t >= kCH && t < 2 * kCH && i0 + t - kCH < j)
+      partial[((long long)r * kSlots + kMaxM + i0 + t - kCH) * B + blockIdx.x] = sh[t];
     __syncthreads();
-  }
-  if (want_norm) {  // ||w||^2 into slot kMaxM - 1
-    double2 acc[1] = {make_double2(0.0, 0.0)};
-    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
-         n += (long long)gridDim.x * blockDim.x) {
-      const double2 wv = wr[n];
-      acc[0].x += wv.x * wv.x + wv.y * wv.y;
-    }
-    block_sum<1>(acc, sh);
-    if (threadIdx.x == 0) partial[((long long)r * kMaxM + kMaxM - 1) * B + blockIdx.x] = sh[0];
   }
 }
 
-// out[r * kMaxM + i] = s_i * sum_b partial[(r * kMaxM + i) * B + b] (ordered), and, if coef,
+// Ordered sum of one partial row over its B blocks; the result is valid in thread 0.
+__device__ __forceinline__ double2 ordered_sum(const double2 *row, int B, double2 *sh) {
+  double2 acc = make_double2(0.0, 0.0);
+  for (int b = threadIdx.x; b < B; b += blockDim.x) acc = cadd(acc, row[b]);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = cadd(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// Reduce the 2j + 1 slots k_gs_dots wrote: out[r * kSlots + slot] (raw, unscaled sums).
+__global__ void k_finalize_dots(const double2 *partial, int B, double2 *out, const int *active,
+                                int j) {
+  const int r = blockIdx.y, bx = blockIdx.x;
+  if (!active[r]) return;
+  const int slot = bx <= j ? bx : kMaxM + (bx - j - 1);
+  __shared__ double2 sh[kRedThreads];
+  const double2 v = ordered_sum(partial + ((long long)r * kSlots + slot) * B, B, sh);
+  if (threadIdx.x == 0) out[r * kSlots + slot] = v;
+}
+
+// MGS coefficients from one reduction (per RHS, one thread each): store row j of
+// L (L_jk = v_j^H v_k, k < j, with the basis scales applied), then c = (I + L)^{-1} a by
+// forward substitution, a_i = v_i^H w.  c goes to hcol (the Hessenberg column) and
+// c_i * vsc_i to ycoef (the coefficients of the unnormalised basis in the update).
+__global__ void k_mgs_coef(int j, const double2 *raw, double2 *L, const double *vsc, double2 *hcol,
+                           double2 *ycoef, const int *active, int nrhs) {
+  const int r = threadIdx.x;
+  if (r >= nrhs || !active[r]) return;
+  const double *sr = vsc + r * kMaxM;
+  double2 *Lr = L + (long long)r * kMaxM * kMaxM;
+  const double2 *rr = raw + r * kSlots;
+  for (int k = 0; k < j; ++k) Lr[j * kMaxM + k] = cconj(cscale(rr[kMaxM + k], sr[k] * sr[j]));
+  for (int i = 0; i <= j; ++i) {
+    double2 c = cscale(rr[i], sr[i]);
+    for (int k = 0; k < i; ++k) c = csub(c, cmul(Lr[i * kMaxM + k], hcol[r * kMaxM + k]));
+    hcol[r * kMaxM + i] = c;
+    ycoef[r * kMaxM + i] = cscale(c, sr[i]);
+  }
+}
+
+// out[r * kMaxM + i] = s_i * sum_b partial[(r * kSlots + i) * B + b] (ordered), and, if coef,
 // coef[r * kMaxM + i] = s_i * out[...]; s_i = vsc[r * kMaxM + i] (1 when vsc is null).
 // With islot >= 0 a single slot islot is reduced into out[r * kMaxM].
 __global__ void k_finalize(const double2 *partial, int B, double2 *out, double2 *coef,
@@ -110,18 +165,10 @@ __global__ void k_finalize(const double2 *partial, int B, double2 *out, double2 
   const int io = islot >= 0 ? 0 : blockIdx.x;
   if (!active[r]) return;
   __shared__ double2 sh[kRedThreads];
-  double2 acc = make_double2(0.0, 0.0);
-  for (int b = threadIdx.x; b < B; b += blockDim.x)
-    acc = cadd(acc, partial[((long long)r * kMaxM + i) * B + b]);
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] = cadd(sh[threadIdx.x], sh[threadIdx.x + s]);
-    __syncthreads();
-  }
+  const double2 sum = ordered_sum(partial + ((long long)r * kSlots + i) * B, B, sh);
   if (threadIdx.x == 0) {
     const double s = vsc ? vsc[r * kMaxM + i] : 1.0;
-    const double2 h = cscale(sh[0], s);
+    const double2 h = cscale(sum, s);
     out[r * kMaxM + io] = h;
     if (coef) coef[r * kMaxM + io] = cscale(h, s);
   }
@@ -153,7 +200,7 @@ __global__ void __launch_bounds__(kRedThreads) k_multiaxpy(const double2 *V, lon
   }
   if (!nrm_partial) return;
   block_sum<1>(acc, sh);
-  if (threadIdx.x == 0) nrm_partial[((long long)r * kMaxM) * B + blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) nrm_partial[((long long)r * kSlots) * B + blockIdx.x] = sh[0];
 }
 
 // out = sum_i V_i y_i  (y = coef[r * kMaxM + i], zero beyond a RHS's cut)
@@ -189,7 +236,7 @@ __global__ void __launch_bounds__(kRedThreads) k_axpby(const double2 *a, const d
   }
   if (!nrm_partial) return;
   block_sum<1>(acc, sh);
-  if (threadIdx.x == 0) nrm_partial[((long long)r * kMaxM) * B + blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) nrm_partial[((long long)r * kSlots) * B + blockIdx.x] = sh[0];
 }
 
 // partial ||a||^2
@@ -205,7 +252,7 @@ __global__ void __launch_bounds__(kRedThreads) k_norm2(const double2 *a, long lo
     acc[0].x += v.x * v.x + v.y * v.y;
   }
   block_sum<1>(acc, sh);
-  if (threadIdx.x == 0) nrm_partial[((long long)r * kMaxM) * B + blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) nrm_partial[((long long)r * kSlots) * B + blockIdx.x] = sh[0];
 }
 
 // out[n] = in[n] * scal[r * sstride]
@@ -423,46 +470,24 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
       } else {
         apply_operator(p, nrhs, vj, w, fp32, p->vsc + j);
       }
-      // CGS: h1 = V^H w (and ||w||^2), w -= V h1 (and ||w'||^2)
+      // MGS in one reduction: a = V^H w and row j of L, c = (I + L)^{-1} a, w -= V c
       {
-        KTimer t(&p->prof, p->st, "kry_multidot", 16.0 * n3 * (j + 2) * nrhs);
-        hipLaunchKernelGGL(k_multidot, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r,
-                           vs_j, j + 1, w, vs_r, n3, K.d_active, K.partial, K.B, 1);
+        KTimer t(&p->prof, p->st, "kry_gs_dots", 16.0 * n3 * (j + 2) * nrhs);
+        hipLaunchKernelGGL(k_gs_dots, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r,
+                           vs_j, j, w, vs_r, n3, K.d_active, K.partial, K.B);
       }
-      finalize(K, j + 1, p->hcol, p->ycoef, p->vsc);
-      finalize(K, 1, p->hnrm, nullptr, nullptr, kMaxM - 1);  // ||w||^2 -> hnrm[r][0]
+      hipLaunchKernelGGL(k_finalize_dots, dim3(2 * j + 1, nrhs), dim3(kRedThreads), 0, p->st,
+                         K.partial, K.B, p->hraw, K.d_active, j);
+      hipLaunchKernelGGL(k_mgs_coef, dim3(1), dim3(64), 0, p->st, j, p->hraw, p->lmat, p->vsc,
+                         p->hcol, p->ycoef, K.d_active, nrhs);
       {
         KTimer t(&p->prof, p->st, "kry_multiaxpy", 16.0 * n3 * (j + 3) * nrhs);
         hipLaunchKernelGGL(k_multiaxpy, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r,
                            vs_j, j + 1, p->ycoef, w, vs_r, n3, K.d_active, K.partial, K.B);
       }
-      finalize(K, 1, p->hnrm + 1, nullptr, nullptr, 0);  // ||w'||^2 -> hnrm[r][1]
-      // reorthogonalise (second CGS pass) where ||w'||^2 < ||w||^2 / 2
-      std::vector<double2> nr((size_t)kMaxM * nrhs);
-      HIPCHK(hipMemcpyAsync(nr.data(), p->hnrm, sizeof(double2) * kMaxM * nrhs,
-                            hipMemcpyDeviceToHost, p->st));
-      HIPCHK(hipStreamSynchronize(p->st));
-      bool reorth = false;
-      for (int r = 0; r < nrhs; ++r)
-        if (incyc[r] && nr[r * kMaxM + 1].x < 0.5 * nr[r * kMaxM].x) reorth = true;
-      const double2 *nrm2 = p->hnrm + 1;
-      if (reorth) {
-        {
-          KTimer t(&p->prof, p->st, "kry_multidot", 16.0 * n3 * (j + 2) * nrhs);
-          hipLaunchKernelGGL(k_multidot, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r,
-                             vs_j, j + 1, w, vs_r, n3, K.d_active, K.partial, K.B, 0);
-        }
-        finalize(K, j + 1, p->hcol2, p->ycoef, p->vsc);
-        {
-          KTimer t(&p->prof, p->st, "kry_multiaxpy", 16.0 * n3 * (j + 3) * nrhs);
-          hipLaunchKernelGGL(k_multiaxpy, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V,
-                             vs_r, vs_j, j + 1, p->ycoef, w, vs_r, n3, K.d_active, K.partial, K.B);
-        }
-        finalize(K, 1, p->ycoef, nullptr, nullptr, 0);
-        nrm2 = p->ycoef;
-      }
+      finalize(K, 1, p->hnrm, nullptr, nullptr, 0);  // ||w - V c||^2 -> hnrm[r][0]
       hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, p->st, j, m, p->H, p->givens, p->gvec,
-                         p->hcol, p->hcol2, reorth ? 1 : 0, nrm2, p->dscal, p->vsc, K.d_active, nrhs);
+                         p->hcol, p->hcol, 0, p->hnrm, p->dscal, p->vsc, K.d_active, nrhs);
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(hp.data(), p->dscal, sizeof(double) * 8 * nrhs, hipMemcpyDeviceToHost,
                             p->st));
@@ -549,8 +574,10 @@ void krylov_alloc(dda_problem *p) {
   HIPCHK(hipMalloc(&p->hcol2, sizeof(double2) * (size_t)R * kMaxM));
   HIPCHK(hipMalloc(&p->ycoef, sizeof(double2) * (size_t)R * kMaxM));
   HIPCHK(hipMalloc(&p->hnrm, sizeof(double2) * (size_t)R * kMaxM));
+  HIPCHK(hipMalloc(&p->hraw, sizeof(double2) * (size_t)R * kSlots));
+  HIPCHK(hipMalloc(&p->lmat, sizeof(double2) * (size_t)R * kMaxM * kMaxM));
   const int B = reduce_blocks(n3);
-  p->partial_elems = std::max<size_t>((size_t)R * kMaxM * B * 2, (size_t)R * 512 * 4);
+  p->partial_elems = std::max<size_t>((size_t)R * kSlots * B * 2, (size_t)R * 512 * 4);
   HIPCHK(hipMalloc(&p->partial, sizeof(double) * p->partial_elems));
   HIPCHK(hipMalloc(&p->dscal, sizeof(double) * 16 * R));
   HIPCHK(hipMemset(p->dscal, 0, sizeof(double) * 16 * R));
