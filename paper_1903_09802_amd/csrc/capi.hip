@@ -4,6 +4,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <cstdlib>
+
 #include "common.h"
 
 using namespace dda;
@@ -122,7 +124,7 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
       need += N * 17.0;                                  // mask + eps
       need += 6.0 * (nx + 1) * (ny + 1) * (nz + 1) * 24;  // khat64 + khat32
       need += 8.0 * N * 6 * 16;                          // setup transient
-      need += R * 3.0 * N * 2 * 16 + R * 3.0 * N * 4 * 16;  // w0 + w1
+      need += R * 3.0 * N * 2 * 16 + R * 3.0 * nz * (4.0 * nx * ny + 64) * 16;  // w0 + w1
       need += R * (m + 1.0) * n3 * 16 + R * 5.0 * n3 * 16 + R * 16.0 * N;
       size_t freeb = 0, totb = 0;
       HIPCHK(hipMemGetInfo(&freeb, &totb));
@@ -138,7 +140,10 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
       HIPCHK(hipMemcpyAsync(p->mask, mask_dev, N, hipMemcpyDeviceToDevice, p->st));
       HIPCHK(hipMemcpyAsync(p->eps, eps_dev, sizeof(double2) * N, hipMemcpyDeviceToDevice, p->st));
       p->w0_elems = (size_t)R * 3 * nz * ny * 2 * nx;
-      p->w1_elems = (size_t)R * 3 * nz * 2 * ny * 2 * nx;
+      // z rows of the z-pass work array are padded by 64 elements: with 4 nx ny a large power
+      // of two, unpadded rows alias the same HBM channels under the z-strided access
+      p->zplane = 4LL * nx * ny + 64;
+      p->w1_elems = (size_t)R * 3 * nz * p->zplane;
       HIPCHK(hipMalloc(&p->w0, sizeof(double2) * p->w0_elems));
       HIPCHK(hipMalloc(&p->w1, sizeof(double2) * p->w1_elems));
       HIPCHK(hipMalloc(&p->ainv, sizeof(double2) * R * N));

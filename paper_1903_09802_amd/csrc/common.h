@@ -91,13 +91,13 @@ __host__ __device__ __forceinline__ double2 ldr_dalpha_inv(double2 eps, double k
 // Parity bit mask per component: bit a set when the component is odd under
 // reflection of axis a (odd iff exactly one of its two indices is that axis).
 __host__ __device__ __forceinline__ int comp_odd_mask(int c) {
-  // xx:0, xy: x|y, xz: x|z, yy:0, yz: y|z, zz:0
-  const int m[6] = {0, 3, 5, 0, 6, 0};
-  return m[c];
+  // xx:0, xy: x|y, xz: x|z, yy:0, yz: y|z, zz:0 (4 bits per component, no memory table)
+  return (0x60530 >> (4 * c)) & 15;
 }
 __host__ __device__ __forceinline__ int comp_index(int a, int b) {
-  const int t[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
-  return t[a][b];
+  // (a, b) -> xx 0, xy 1, xz 2, yy 3, yz 4, zz 5
+  const int i = a < b ? a : b, j = a < b ? b : a;
+  return 3 * i - (i * (i - 1)) / 2 + (j - i);
 }
 
 // ----------------------------------------------------------------------------- error handling
@@ -210,6 +210,8 @@ struct dda_problem {
   size_t lds_max = 65536;      // device LDS per workgroup
   size_t lds_zpass = 98304;    // LDS budget of the fused z pass
   int ztw[2] = {0, 0};         // z-pass columns per tile (FP64, FP32), chosen by autotune
+  int zreg = 0;                // 1: register z pass (2 nz a power of two in [32, 256]); the
+                               // kernel spectra are then stored z-major, [oy][ox][oz][6]
 
   uint8_t *mask = nullptr;      // [N]
   double2 *eps = nullptr;       // [N]
@@ -227,6 +229,7 @@ struct dda_problem {
   void *w0 = nullptr;  // [R][3][nz][ny][2nx]
   void *w1 = nullptr;  // [R][3][nz][2ny][2nx]
   size_t w0_elems = 0, w1_elems = 0;
+  long long zplane = 0;  // z-row stride of the z-pass work array w1 (4 nx ny plus padding)
 
   double2 *ainv = nullptr;   // [R][N] per-RHS 1/alpha
   double *Sdev = nullptr;    // [R] lattice factor per RHS

@@ -146,7 +146,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(const cplx<T> *in, 
 
 // ---------------------------------------------------------------------------- fused z pass
 
-// Data [R][3][nz][plane] with plane = 2ny * 2nx (after the x and y transforms).  For a
+// Data [R][3][nz][zstride]: z rows of plane = 2ny * 2nx columns (after the x and y
+// transforms), zstride >= plane.  For a
 // tile of `tw` consecutive (ky, kx) columns of one right-hand side: zero-pad each of
 // the three components to 2nz along z, FFT, multiply by the 3x3 symmetric kernel
 // spectrum (six components, read from the stored octant with the per-axis parity
@@ -154,7 +155,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(const cplx<T> *in, 
 struct ZArgs {
   FftDesc pl;       // length 2nz
   int nz, ny, nx;
-  long long plane;  // 4 nx ny
+  long long plane;  // 4 nx ny columns
+  long long zstride;  // elements between z rows (>= plane)
   int tw, twsh;     // columns per tile and log2(tw)
   long long ntiles;
   long long nrhs;
@@ -173,15 +175,15 @@ __global__ void __launch_bounds__(768) k_zpass(cplx<T> *data, const cplx<T> *__r
   if (blk >= a.ntiles * a.nrhs) return;
   const long long r = blk / a.ntiles;
   const long long c0 = (blk - r * a.ntiles) * (long long)a.tw;
-  V *base = data + r * 3LL * a.nz * a.plane;
+  V *base = data + r * 3LL * a.nz * a.zstride;
   const Lane L = make_lane(ncols, tpc_of(n));
   if (L.active) {
     const int comp = L.c >> a.twsh, c = L.c & (a.tw - 1);
     const bool ok = c0 + c < a.plane;
-    const V *src = base + (long long)comp * a.nz * a.plane + c0 + c;
+    const V *src = base + (long long)comp * a.nz * a.zstride + c0 + c;
     for (int i = L.jt; i < n; i += L.tpc) {
       V val = mk<T>((T)0, (T)0);
-      if (i < a.nz && ok) val = src[(long long)i * a.plane];
+      if (i < a.nz && ok) val = src[(long long)i * a.zstride];
       s[lrow(i, ld) + L.c] = val;
     }
   }
@@ -226,8 +228,8 @@ __global__ void __launch_bounds__(768) k_zpass(cplx<T> *data, const cplx<T> *__r
   if (L.active) {
     const int comp = L.c >> a.twsh, c = L.c & (a.tw - 1);
     if (c0 + c < a.plane) {
-      V *dst = base + (long long)comp * a.nz * a.plane + c0 + c;
-      for (int i = L.jt; i < a.nz; i += L.tpc) dst[(long long)i * a.plane] = s[lrow(i, ld) + L.c];
+      V *dst = base + (long long)comp * a.nz * a.zstride + c0 + c;
+      for (int i = L.jt; i < a.nz; i += L.tpc) dst[(long long)i * a.zstride] = s[lrow(i, ld) + L.c];
     }
   }
 }

@@ -4,6 +4,7 @@
 #include <cmath>
 
 #include "fft_kernels.h"
+#include "zpass_reg.h"
 
 namespace dda {
 
@@ -58,20 +59,45 @@ __global__ void k_green_pad(double2 *out, int nx, int ny, int nz, double k, doub
   for (int c = 0; c < 6; ++c) out[c * tot + idx] = g[c];
 }
 
-template <typename TO>
+// One octant (non-negative offsets) of the padded spectrum: component-major
+// [6][nz+1][ny+1][nx+1], or z-major [ny+1][nx+1][nz+1][6] for the register z pass.
+template <typename TO, bool ZMAJOR>
 __global__ void k_extract_octant(const double2 *full, TO *oct, int nx, int ny, int nz) {
   const long long ox_n = nx + 1, oy_n = ny + 1, oz_n = nz + 1;
   const long long per = ox_n * oy_n * oz_n;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 6 * per) return;
-  const int c = (int)(idx / per);
-  const long long rem = idx - c * per;
-  const int ox = (int)(rem % ox_n);
-  const int oy = (int)((rem / ox_n) % oy_n);
-  const int oz = (int)(rem / (ox_n * oy_n));
+  int c, ox, oy, oz;
+  if (ZMAJOR) {
+    c = (int)(idx % 6);
+    const long long rem = idx / 6;
+    oz = (int)(rem % oz_n);
+    ox = (int)((rem / oz_n) % ox_n);
+    oy = (int)(rem / (oz_n * ox_n));
+  } else {
+    c = (int)(idx / per);
+    const long long rem = idx - c * per;
+    ox = (int)(rem % ox_n);
+    oy = (int)((rem / ox_n) % oy_n);
+    oz = (int)(rem / (ox_n * oy_n));
+  }
   const long long Lx = 2LL * nx, Ly = 2LL * ny, Lz = 2LL * nz;
   const double2 v = full[c * Lx * Ly * Lz + ((long long)oz * Ly + oy) * Lx + ox];
   oct[idx] = to_c(v, TO{});
+}
+
+static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <typename TO>
+static void extract_octant(dda_problem *p, const double2 *full, TO *oct) {
+  const long long n = 6LL * (p->nx + 1) * (p->ny + 1) * (p->nz + 1);
+  if (p->zreg)
+    hipLaunchKernelGGL((k_extract_octant<TO, true>), dim3(nblk(n, 256)), dim3(256), 0, p->st, full,
+                       oct, p->nx, p->ny, p->nz);
+  else
+    hipLaunchKernelGGL((k_extract_octant<TO, false>), dim3(nblk(n, 256)), dim3(256), 0, p->st, full,
+                       oct, p->nx, p->ny, p->nz);
+  HIPCHK(hipGetLastError());
 }
 
 // Occupancy, invalid permittivities and the occupied-permittivity sum, per block.
@@ -134,7 +160,6 @@ __global__ void k_incident(const uint8_t *mask, int nx, int ny, int nz, double k
   }
 }
 
-static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 void setup_alpha(dda_problem *p, int nrhs, const double *S_host) {
   HIPCHK(hipMemcpyAsync(p->Sdev, S_host, sizeof(double) * nrhs, hipMemcpyHostToDevice, p->st));
@@ -173,17 +198,12 @@ static void kernel_spectrum(dda_problem *p, int part) {
     fft_rows_plain(p, p->px, tmp, 6LL * (2 * nz) * (2 * ny), 0);
     fft_strided_plain(p, p->py, tmp, 6LL * (2 * nz), 2LL * nx, 0);
     fft_strided_plain(p, p->pz, tmp, 6LL, 4LL * nx * ny, 0);
-    const long long oct = 6LL * (nx + 1) * (ny + 1) * (nz + 1);
     if (part == 0) {
-      hipLaunchKernelGGL(k_extract_octant<double2>, dim3(nblk(oct, 256)), dim3(256), 0, p->st, tmp,
-                         p->khat64, nx, ny, nz);
-      hipLaunchKernelGGL(k_extract_octant<float2>, dim3(nblk(oct, 256)), dim3(256), 0, p->st, tmp,
-                         p->khat32, nx, ny, nz);
+      extract_octant(p, tmp, p->khat64);
+      extract_octant(p, tmp, p->khat32);
     } else {
-      hipLaunchKernelGGL(k_extract_octant<double2>, dim3(nblk(oct, 256)), dim3(256), 0, p->st, tmp,
-                         p->khatI64, nx, ny, nz);
+      extract_octant(p, tmp, p->khatI64);
     }
-    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(p->st));
   } catch (...) {
     (void)hipFree(tmp);
@@ -222,6 +242,8 @@ void operator_setup(dda_problem *p) {
   p->eps_mean = make_double2(sr / occ, si / occ);
 
   const long long oct = 6LL * (p->nx + 1) * (p->ny + 1) * (p->nz + 1);
+  const int nzz = 2 * p->nz;
+  p->zreg = (nzz >= 32 && nzz <= 256 && (nzz & (nzz - 1)) == 0) ? 1 : 0;
   HIPCHK(hipMalloc(&p->khat64, sizeof(double2) * oct));
   HIPCHK(hipMalloc(&p->khat32, sizeof(float2) * oct));
   kernel_spectrum(p, 0);
@@ -238,11 +260,54 @@ static void ensure_imag_spectrum(dda_problem *p) {
 
 // ----------------------------------------------------------------------------- the product
 
+// Register z pass for n = G P: (G, P) = (4, 8), (8, 8), (8, 16), (16, 16).
+template <typename T, typename F> static void with_gp(int n, F &&f) {
+  switch (n) {
+    case 32: f(std::integral_constant<int, 4>{}, std::integral_constant<int, 8>{}); break;
+    case 64: f(std::integral_constant<int, 8>{}, std::integral_constant<int, 8>{}); break;
+    case 128: f(std::integral_constant<int, 8>{}, std::integral_constant<int, 16>{}); break;
+    case 256: f(std::integral_constant<int, 16>{}, std::integral_constant<int, 16>{}); break;
+    default: REQUIRE(false, DDA_EUNSUPPORTED, "register z pass: length %d", n);
+  }
+}
+
+static int zreg_g(int n) { return n <= 32 ? 4 : n <= 128 ? 8 : 16; }
+
+// LDS bytes of one register z-pass workgroup with `tw` columns
+template <typename T> static size_t zreg_lds(int n, int tw) { return (size_t)(3 * tw + 1) * n * sizeof(cplx<T>); }
+
 // Launch the fused z pass with `tw` columns per tile (a power of two; 0: the autotuned choice).
 template <typename T>
 static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, int tw = 0,
                   bool timed = true) {
   const int n = p->pz.n;
+  const double sz = sizeof(cplx<T>);
+  const double bytes = nrhs * (2.0 * 3.0 * 4.0 * p->nx * p->ny * p->nz * sz) +
+                       6.0 * (p->nx + 1) * (p->ny + 1) * (p->nz + 1) * sz;
+  if (tw <= 0) tw = p->ztw[sizeof(T) == 8 ? 0 : 1];
+  if (tw <= 0) tw = 1;
+  KTimer t(timed ? &p->prof : nullptr, p->st, sizeof(T) == 8 ? "zpass_f64" : "zpass_f32", bytes);
+  if (p->zreg) {
+    ZRArgs a;
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.plane = p->zplane;
+    a.tw = tw;
+    a.tiles_x = (p->nx + 1 + tw - 1) / tw;
+    a.nrhs = nrhs;
+    a.nblk = (long long)a.tiles_x * (p->ny + 1) * 4 * nrhs;
+    const size_t lds = zreg_lds<T>(n, tw);
+    with_gp<T>(n, [&](auto G, auto P) {
+      auto fn = k_zpass_reg<T, decltype(G)::value, decltype(P)::value>;
+      set_lds_limit((const void *)fn, lds);
+      const int threads = 3 * tw * decltype(G)::value;
+      hipLaunchKernelGGL(fn, dim3((unsigned)xcd_grid(a.nblk)), dim3(threads), lds, p->st, w1,
+                         tw_of<T>(p->pz), khat, a);
+    });
+    HIPCHK(hipGetLastError());
+    return;
+  }
   constexpr int EPT = EptOf<T>::value;
   ZArgs a;
   a.pl = desc(p->pz);
@@ -250,18 +315,13 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, in
   a.ny = p->ny;
   a.nx = p->nx;
   a.plane = 4LL * p->nx * p->ny;
-  if (tw <= 0) tw = p->ztw[sizeof(T) == 8 ? 0 : 1];
-  if (tw <= 0) tw = 1;
+  a.zstride = p->zplane;
   a.tw = tw;
   a.twsh = ilog2_exact(tw);
   a.ntiles = (a.plane + tw - 1) / tw;
   a.nrhs = nrhs;
   const int threads = 3 * tw * tpc_of(n);
   const size_t lds = (size_t)lds_elems(n, 3 * tw + 1) * sizeof(cplx<T>);
-  const double sz = sizeof(cplx<T>);
-  const double bytes = nrhs * (2.0 * 3.0 * a.plane * p->nz * sz) +
-                       6.0 * (p->nx + 1) * (p->ny + 1) * (p->nz + 1) * sz;
-  KTimer t(timed ? &p->prof : nullptr, p->st, sizeof(T) == 8 ? "zpass_f64" : "zpass_f32", bytes);
   with_static_n(n, [&](auto nf) {
     auto fn = k_zpass<T, EPT, decltype(nf)::value>;
     set_lds_limit((const void *)fn, lds);
@@ -271,11 +331,20 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, in
   HIPCHK(hipGetLastError());
 }
 
-// Largest power-of-two tile width that fits the LDS budget, 768 threads and the plane.
+// Largest power-of-two tile width that fits the LDS budget, the thread limit and the plane.
 template <typename T> static int zpass_max_tw(dda_problem *p) {
   const int n = p->pz.n;
-  const size_t budget = std::min<size_t>(p->lds_zpass, p->lds_max);
   int tw = 1;
+  if (p->zreg) {
+    const int G = zreg_g(n);
+    while (true) {
+      const int t2 = tw * 2;
+      if (zreg_lds<T>(n, t2) > 64 * 1024 || 3 * t2 * G > 256 || t2 > p->nx + 1) break;
+      tw = t2;
+    }
+    return tw;
+  }
+  const size_t budget = std::min<size_t>(p->lds_zpass, p->lds_max);
   while (true) {
     const int t2 = tw * 2;
     if ((size_t)lds_elems(n, 3 * t2 + 1) * sizeof(cplx<T>) > budget) break;
@@ -290,7 +359,7 @@ template <typename T> static int zpass_max_tw(dda_problem *p) {
 template <typename T> static void zpass_autotune(dda_problem *p, const cplx<T> *khat) {
   const int tmax = zpass_max_tw<T>(p);
   cplx<T> *w1 = reinterpret_cast<cplx<T> *>(p->w1);
-  HIPCHK(hipMemsetAsync(w1, 0, sizeof(cplx<T>) * 3 * 4LL * p->N, p->st));
+  HIPCHK(hipMemsetAsync(w1, 0, sizeof(cplx<T>) * 3 * p->nz * p->zplane, p->st));
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -308,7 +377,7 @@ template <typename T> static void zpass_autotune(dda_problem *p, const cplx<T> *
       best = ms;
       best_tw = tw;
     }
-    if (tw <= 2) break;
+    if (tw <= (p->zreg ? 1 : 2)) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -347,14 +416,14 @@ static void op_passes(dda_problem *p, int nrhs, const double2 *x, double2 *y,
   }
   // P2: y transform, ny rows zero-padded to 2ny
   launch_strided<T>(p, p->py, w0, w1, (long long)nrhs * 3 * nz, 2LL * nx, ny, 2 * ny,
-                    (long long)ny * 2 * nx, 4LL * ny * nx, -1,
+                    (long long)ny * 2 * nx, p->zplane, -1,
                     sizeof(T) == 8 ? "op_y_fwd_f64" : "op_y_fwd_f32",
                     nrhs * 3.0 * nz * 2 * nx * (ny + 2.0 * ny) * sz);
   // P3: z transform, kernel multiply, inverse z transform (in place)
   zpass<T>(p, nrhs, w1, khat);
   // P4: inverse y transform, keep ny rows
   launch_strided<T>(p, p->py, w1, w0, (long long)nrhs * 3 * nz, 2LL * nx, 2 * ny, ny,
-                    4LL * ny * nx, (long long)ny * 2 * nx, +1,
+                    p->zplane, (long long)ny * 2 * nx, +1,
                     sizeof(T) == 8 ? "op_y_inv_f64" : "op_y_inv_f32",
                     nrhs * 3.0 * nz * 2 * nx * (2.0 * ny + ny) * sz);
   // P5: inverse x transform, keep nx, diagonal and mask epilogue

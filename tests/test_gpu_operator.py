@@ -23,6 +23,11 @@ OP_CASES = [
     ((1, 1, 1), 1.0, 6),
     ((7, 5, 3), 0.5, 7),
     ((12, 20, 9), 0.7, 8),
+    # z lengths 64, 128, 256: the register z pass, ragged tiles, a 1 x 1 column
+    ((32, 6, 9), 0.7, 9),
+    ((64, 5, 3), 0.6, 10),
+    ((128, 3, 4), 0.7, 11),
+    ((32, 1, 1), 1.0, 12),
 ]
 
 
@@ -54,7 +59,8 @@ def test_operator_vs_dense_matrix(shape, fill, seed):
     assert rel_err(y[0], ref) < 1e-10
 
 
-@pytest.mark.parametrize("shape,seed", [((5, 6, 7), 21), ((16, 16, 16), 22), ((12, 20, 9), 23)])
+@pytest.mark.parametrize("shape,seed", [((5, 6, 7), 21), ((16, 16, 16), 22), ((12, 20, 9), 23),
+                                        ((64, 6, 5), 24), ((128, 4, 3), 25)])
 def test_operator_fp32_vs_oracle(shape, seed):
     nz, ny, nx = shape
     s = w.random_mask(nx, ny, nz, 0.7, seed, k=1.3, d=0.3)
