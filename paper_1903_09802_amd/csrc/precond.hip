@@ -120,87 +120,165 @@ __global__ void k_assemble(const double2 *lam, double2 *out, long long m0, int n
   }
 }
 
-// Batched in-place inverse of row-major n x n complex matrices, one workgroup each:
-// Gauss-Jordan elimination with partial pivoting, blocked by NB columns.  For each panel
-// the NB pivot steps run in LDS on the n x NB panel (recording the multipliers F); the
-// other columns then receive the panel's row swaps, a short recurrence over the NB
-// pivot rows and a rank-NB update of the remaining rows.  Column interchanges are undone
-// at the end.  A zero pivot sets flag[0].
+// Gauss-Jordan step for one trailing column j and the panel [k0, k0 + kb): from the
+// column's (row-swapped) pivot-row entries, tv[kk] are the multiples of the panel's
+// eliminated columns it receives and aK its new pivot-row entries.
 template <int NB>
-__global__ void __launch_bounds__(256) k_gj_inverse(double2 *mats, int n, int *flag) {
+__device__ __forceinline__ void gj_pivot_rows(const double2 *A, int n, int j, int k0, int kb,
+                                              const double2 *F, const double2 *ipv,
+                                              double2 (&aK)[NB], double2 (&tv)[NB]) {
+#pragma unroll
+  for (int kk = 0; kk < NB; ++kk)
+    aK[kk] = kk < kb ? A[(long long)(k0 + kk) * n + j] : make_double2(0.0, 0.0);
+#pragma unroll
+  for (int kk = 0; kk < NB; ++kk) {
+    if (kk >= kb) { tv[kk] = make_double2(0.0, 0.0); continue; }
+    const double2 t = cmul(aK[kk], ipv[kk]);
+    tv[kk] = t;
+#pragma unroll
+    for (int k2 = 0; k2 < NB; ++k2)
+      if (k2 != kk && k2 < kb) aK[k2] = csub(aK[k2], cmul(F[(k0 + k2) * NB + kk], t));
+    aK[kk] = t;
+  }
+}
+
+constexpr int kGJMaxOrder = 768;  // the largest half-block order, 3 * 256
+constexpr int kGJThreads = 256;
+
+// Batched in-place inverse of row-major n x n complex matrices, one workgroup each:
+// Gauss-Jordan elimination with partial pivoting, blocked by NB columns.  For each panel of
+// NB columns the pivot steps run on rows held in registers (thread t owns rows t + r NT,
+// r < RPT); per step a wave-shuffle argmax picks the pivot, the pivot row and the old row k
+// pass through LDS, and the multipliers F (n x NB) are kept in LDS.  The other columns then
+// receive the panel's row swaps, a short recurrence over the NB pivot rows and a rank-NB
+// update of the remaining rows.  Column interchanges are undone at the end.  A zero pivot
+// sets flag[0].
+template <int NB, int NT, int RPT>
+__global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *flag) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double2 *P = reinterpret_cast<double2 *>(smem_raw);  // [n][NB]
-  double2 *F = P + (size_t)n * NB;                      // [n][NB]
+  double2 *F = reinterpret_cast<double2 *>(smem_raw);         // [n][NB]
   int *pivall = reinterpret_cast<int *>(F + (size_t)n * NB);  // [n]
-  __shared__ double2 ipv_s[NB];
-  __shared__ double red_v[256];
-  __shared__ int red_i[256];
-  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double2 ipv_s[NB], prow[NB], krow[NB];
+  __shared__ double red_v[NT / 64];
+  __shared__ int red_i[NT / 64];
+  const int tid = threadIdx.x;
   double2 *A = mats + (long long)blockIdx.x * n * n;
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int kb = min(NB, n - k0);
-    for (int e = tid; e < n * NB; e += nt) {
-      const int i = e / NB, c = e % NB;
-      P[e] = c < kb ? A[(long long)i * n + k0 + c] : make_double2(0.0, 0.0);
-      F[e] = make_double2(0.0, 0.0);
+    double2 rv[RPT][NB];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + r * NT;
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        rv[r][c] = (i < n && c < kb) ? A[(long long)i * n + k0 + c] : make_double2(0.0, 0.0);
     }
+    for (int e = tid; e < n * NB; e += NT) F[e] = make_double2(0.0, 0.0);
     __syncthreads();
     for (int kk = 0; kk < kb; ++kk) {
       const int k = k0 + kk;
-      // pivot: argmax |P[i][kk]| over i >= k (ties -> smallest i)
+      // pivot: argmax |row i, column kk| over rows i >= k, ties to the smallest row
       double bv = -1.0;
-      int bi = k;
-      for (int i = k + tid; i < n; i += nt) {
-        const double2 v = P[i * NB + kk];
+      int bi = n;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int i = tid + r * NT;
+        double2 v = rv[r][0];
+#pragma unroll
+        for (int c = 1; c < NB; ++c)
+          if (c == kk) v = rv[r][c];
         const double m2 = v.x * v.x + v.y * v.y;
-        if (m2 > bv) { bv = m2; bi = i; }
+        if (i < n && i >= k && m2 > bv) { bv = m2; bi = i; }
       }
-      red_v[tid] = bv;
-      red_i[tid] = bi;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if ((tid & 63) == 0) {
+        red_v[tid >> 6] = bv;
+        red_i[tid >> 6] = bi;
+      }
       __syncthreads();
-      for (int s = nt / 2; s > 0; s >>= 1) {
-        if (tid < s) {
-          const double ov = red_v[tid + s];
-          const int oi = red_i[tid + s];
-          if (ov > red_v[tid] || (ov == red_v[tid] && oi < red_i[tid])) {
-            red_v[tid] = ov;
-            red_i[tid] = oi;
-          }
-        }
-        __syncthreads();
+      bv = red_v[0];
+      int pr = red_i[0];
+#pragma unroll
+      for (int w = 1; w < NT / 64; ++w)
+        if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < pr)) { bv = red_v[w]; pr = red_i[w]; }
+      // publish the pivot row and the old row k; the multipliers of earlier panel columns
+      // follow the swap
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int i = tid + r * NT;
+        if (i == pr)
+#pragma unroll
+          for (int c = 0; c < NB; ++c) prow[c] = rv[r][c];
+        if (i == k)
+#pragma unroll
+          for (int c = 0; c < NB; ++c) krow[c] = rv[r][c];
       }
-      const int pr = red_i[0];
-      if (tid < NB && pr != k) {
-        double2 t = P[k * NB + tid]; P[k * NB + tid] = P[pr * NB + tid]; P[pr * NB + tid] = t;
-        t = F[k * NB + tid]; F[k * NB + tid] = F[pr * NB + tid]; F[pr * NB + tid] = t;
+      if (tid < kk && pr != k) {
+        const double2 t = F[k * NB + tid];
+        F[k * NB + tid] = F[pr * NB + tid];
+        F[pr * NB + tid] = t;
       }
-      if (tid == 0) pivall[k] = pr;
       __syncthreads();
-      const double2 pv = P[k * NB + kk];
+      double2 pv = prow[0];
+#pragma unroll
+      for (int c = 1; c < NB; ++c)
+        if (c == kk) pv = prow[c];
       const double pm = pv.x * pv.x + pv.y * pv.y;
-      double2 ipv = make_double2(0.0, 0.0);
-      if (pm > 0.0) ipv = make_double2(pv.x / pm, -pv.y / pm);
-      else if (tid == 0) atomicExch(flag, 1);
-      for (int i = tid; i < n; i += nt) F[i * NB + kk] = (i == k) ? make_double2(0.0, 0.0) : P[i * NB + kk];
-      if (tid == 0) ipv_s[kk] = ipv;
-      __syncthreads();
-      if (tid < kb) P[k * NB + tid] = (tid == kk) ? ipv : cmul(P[k * NB + tid], ipv);
-      __syncthreads();
-      for (int e = tid; e < n * kb; e += nt) {
-        const int i = e / kb, c = e % kb;
-        if (i == k) continue;
-        const double2 f = F[i * NB + kk];
-        if (c == kk) P[i * NB + c] = make_double2(-(f.x * ipv.x - f.y * ipv.y), -(f.x * ipv.y + f.y * ipv.x));
-        else P[i * NB + c] = csub(P[i * NB + c], cmul(f, P[k * NB + c]));
+      const double2 ipv = pm > 0.0 ? make_double2(pv.x / pm, -pv.y / pm) : make_double2(0.0, 0.0);
+      if (tid == 0) {
+        pivall[k] = pr;
+        ipv_s[kk] = ipv;
+        if (pm == 0.0) atomicExch(flag, 1);
       }
-      __syncthreads();
+      // swap rows k and pr, scale the pivot row, eliminate column kk from the other rows
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int i = tid + r * NT;
+        if (i >= n) continue;
+        if (i == k) {
+#pragma unroll
+          for (int c = 0; c < NB; ++c) rv[r][c] = (c == kk) ? ipv : cmul(prow[c], ipv);
+          F[k * NB + kk] = make_double2(0.0, 0.0);
+        } else {
+          if (i == pr)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) rv[r][c] = krow[c];
+          double2 f = rv[r][0];
+#pragma unroll
+          for (int c = 1; c < NB; ++c)
+            if (c == kk) f = rv[r][c];
+          F[i * NB + kk] = f;
+          const double2 fi = cmul(f, ipv);
+#pragma unroll
+          for (int c = 0; c < NB; ++c)
+            rv[r][c] = (c == kk) ? make_double2(-fi.x, -fi.y) : csub(rv[r][c], cmul(fi, prow[c]));
+        }
+      }
+      // the next step writes prow / krow only after its first barrier, which every thread
+      // reaches after finishing this step
     }
-    for (int e = tid; e < n * kb; e += nt) {
-      const int i = e / kb, c = e % kb;
-      A[(long long)i * n + k0 + c] = P[i * NB + c];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + r * NT;
+      if (i < n)
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (c < kb) A[(long long)i * n + k0 + c] = rv[r][c];
     }
-    // trailing columns: one thread per column
-    for (int jj = tid; jj < n - kb; jj += nt) {
+    // Trailing columns, in three barrier-separated phases so that no pivot-row value is read
+    // after it has been replaced: (A) the panel's row swaps, one thread per column; (B) kRG
+    // threads per column each form the NB pivot-row values (the short recurrence) and
+    // update their share of the other rows; (C) one thread per column forms them again and
+    // stores them in the pivot rows.
+    __syncthreads();
+    constexpr int kRG = 4;
+    const int ncol = n - kb;
+    for (int jj = tid; jj < ncol; jj += NT) {
       const int j = jj < k0 ? jj : jj + kb;
       for (int kk = 0; kk < kb; ++kk) {
         const int k = k0 + kk, pr = pivall[k];
@@ -210,24 +288,16 @@ __global__ void __launch_bounds__(256) k_gj_inverse(double2 *mats, int n, int *f
           A[(long long)pr * n + j] = t;
         }
       }
+    }
+    __syncthreads();
+    const int rows_per = (n + kRG - 1) / kRG;
+    for (int w = tid; w < kRG * ncol; w += NT) {
+      const int cgrp = w / ncol, jj = w - cgrp * ncol;
+      const int j = jj < k0 ? jj : jj + kb;
       double2 aK[NB], tv[NB];
-#pragma unroll
-      for (int kk = 0; kk < NB; ++kk)
-        aK[kk] = kk < kb ? A[(long long)(k0 + kk) * n + j] : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int kk = 0; kk < NB; ++kk) {
-        if (kk >= kb) { tv[kk] = make_double2(0.0, 0.0); continue; }
-        const double2 t = cmul(aK[kk], ipv_s[kk]);
-        tv[kk] = t;
-#pragma unroll
-        for (int k2 = 0; k2 < NB; ++k2)
-          if (k2 != kk && k2 < kb) aK[k2] = csub(aK[k2], cmul(F[(k0 + k2) * NB + kk], t));
-        aK[kk] = t;
-      }
-#pragma unroll
-      for (int kk = 0; kk < NB; ++kk)
-        if (kk < kb) A[(long long)(k0 + kk) * n + j] = aK[kk];
-      for (int i = 0; i < n; ++i) {
+      gj_pivot_rows<NB>(A, n, j, k0, kb, F, ipv_s, aK, tv);
+      const int i0 = cgrp * rows_per, i1 = min(n, i0 + rows_per);
+      for (int i = i0; i < i1; ++i) {
         if (i >= k0 && i < k0 + kb) continue;
         double2 acc = A[(long long)i * n + j];
 #pragma unroll
@@ -236,9 +306,18 @@ __global__ void __launch_bounds__(256) k_gj_inverse(double2 *mats, int n, int *f
       }
     }
     __syncthreads();
+    for (int jj = tid; jj < ncol; jj += NT) {
+      const int j = jj < k0 ? jj : jj + kb;
+      double2 aK[NB], tv[NB];
+      gj_pivot_rows<NB>(A, n, j, k0, kb, F, ipv_s, aK, tv);
+#pragma unroll
+      for (int kk = 0; kk < NB; ++kk)
+        if (kk < kb) A[(long long)(k0 + kk) * n + j] = aK[kk];
+    }
+    __syncthreads();
   }
   // undo the column interchanges, last first (each thread owns whole rows)
-  for (int i = tid; i < n; i += nt) {
+  for (int i = tid; i < n; i += NT) {
     for (int k = n - 1; k >= 0; --k) {
       const int pr = pivall[k];
       if (pr != k) {
@@ -248,6 +327,26 @@ __global__ void __launch_bounds__(256) k_gj_inverse(double2 *mats, int n, int *f
       }
     }
   }
+}
+
+// Launch k_gj_inverse with the panel width and rows per thread for order n: 16-column
+// panels up to n = 256 (multipliers 64 KB of LDS at most), 8 columns above.
+static size_t gj_lds(int n, int nb) { return sizeof(double2) * (size_t)n * nb + sizeof(int) * n; }
+static void gj_launch(dda_problem *p, double2 *mats, long long cnt, int n) {
+  if (n <= kGJThreads) {
+    auto fn = k_gj_inverse<16, kGJThreads, 1>;
+    set_lds_limit((const void *)fn, gj_lds(n, 16));
+    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(kGJThreads), gj_lds(n, 16), p->st, mats, n, p->dflag);
+  } else if (n <= 2 * kGJThreads) {
+    auto fn = k_gj_inverse<8, kGJThreads, 2>;
+    set_lds_limit((const void *)fn, gj_lds(n, 8));
+    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(kGJThreads), gj_lds(n, 8), p->st, mats, n, p->dflag);
+  } else {
+    auto fn = k_gj_inverse<8, kGJThreads, 3>;
+    set_lds_limit((const void *)fn, gj_lds(n, 8));
+    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(kGJThreads), gj_lds(n, 8), p->st, mats, n, p->dflag);
+  }
+  HIPCHK(hipGetLastError());
 }
 
 __global__ void k_to_f32(const double2 *in, float2 *out, long long n) {
@@ -305,9 +404,8 @@ void precond_build(dda_problem *p, double s_bar) {
     }
     const size_t lds_asm = sizeof(double2) * 6 * S;
     set_lds_limit((const void *)k_assemble, lds_asm);
-    constexpr int NB = 8;
-    const size_t lds_gj = sizeof(double2) * 2 * (size_t)p->n2 * NB + sizeof(int) * p->n2;
-    set_lds_limit((const void *)k_gj_inverse<NB>, lds_gj);
+    const size_t lds_gj = gj_lds(p->n2, p->n2 <= kGJThreads ? 16 : 8);
+    REQUIRE(p->n2 <= kGJMaxOrder, DDA_EUNSUPPORTED, "half-block order %d above %d", p->n2, kGJMaxOrder);
     REQUIRE(lds_gj <= p->lds_max && lds_asm <= p->lds_max, DDA_EUNSUPPORTED,
             "preconditioner blocks too large for LDS (nz = %d)", nz);
     HIPCHK(hipMemsetAsync(p->dflag, 0, sizeof(int) * 4, p->st));
@@ -322,8 +420,7 @@ void precond_build(dda_problem *p, double s_bar) {
       }
       {
         KTimer t(&p->prof, p->st, "pc_gj_inverse", 32.0 * cnt * msz);
-        hipLaunchKernelGGL(k_gj_inverse<NB>, dim3((unsigned)cnt), dim3(256), lds_gj, p->st, dst,
-                           p->n2, p->dflag);
+        gj_launch(p, dst, cnt, p->n2);
         HIPCHK(hipGetLastError());
       }
       if (fp32) {
