@@ -31,6 +31,14 @@ template <typename V> __host__ __device__ __forceinline__ V cmulcj(V a, V b) {
 }
 template <typename V, typename S> __host__ __device__ __forceinline__ V cscale(V a, S s) { V r; r.x = a.x * s; r.y = a.y * s; return r; }
 template <typename V> __host__ __device__ __forceinline__ V cconj(V a) { V r; r.x = a.x; r.y = -a.y; return r; }
+// acc + a b as four fused multiply-adds
+template <typename V> __host__ __device__ __forceinline__ V cmac(V acc, V a, V b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
 // multiply by -i (sign = -1) or +i (sign = +1)
 template <typename V> __host__ __device__ __forceinline__ V cmuli(V a, int sign) {
   V r; if (sign > 0) { r.x = -a.y; r.y = a.x; } else { r.x = a.y; r.y = -a.x; } return r;
@@ -240,7 +248,10 @@ struct dda_problem {
   double2 ati{0.0, 0.0};     // alpha~^{-1}
   int hh = 0, n2 = 0;        // ceil(nz/2), 3*hh
   int umx = 0, umy = 0;      // nx/2+1, ny/2+1
-  double2 *binv64 = nullptr; // [umy][umx][2][n2][n2], column-major inverse blocks
+  int psym = 0;              // 1 (even nz): packed symmetric tiles of (S B)^{-1}, see precond
+  int ntr = 0;               // tile rows per half, ceil(n2 / 16)
+  double2 *binv64 = nullptr; // psym 0: [umy][umx][2][n2][n2] column-major inverse halves;
+                             // psym 1: [umy][umx][2][ntr (ntr+1) / 2][256] packed tiles
   float2 *binv32 = nullptr;
 
   // Krylov state (FP64)

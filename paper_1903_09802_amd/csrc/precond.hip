@@ -12,8 +12,13 @@
 //   * B commutes with the z reflection (a, iz) -> s_a (a, nz-1-iz), s = (1, 1, -1), so
 //     each B splits into an even and an odd half of size 3 ceil(nz/2) (a padding entry is
 //     set to the identity when nz is odd).
-// The halves are inverted explicitly (Gauss-Jordan with partial pivoting, blocked) and
-// stored column-major so the application is a coalesced matrix-vector product.
+// The halves are inverted explicitly (Gauss-Jordan with partial pivoting, blocked).  For
+// even nz, S B_sigma is complex symmetric (S = diag(1, 1, -1) per component: the kernel
+// blocks are symmetric in (a, b) up to the x / y parities, and the z reflection maps xz and
+// yz onto their negatives), so its inverse Y = B_sigma^{-1} S is symmetric and only its lower
+// triangle is stored, as 16 x 16 tiles; the application is B_sigma^{-1} v = Y (S v).  For
+// odd nz the middle z plane breaks that symmetry and the full halves are stored
+// column-major.
 #include <algorithm>
 #include <cmath>
 
@@ -72,8 +77,9 @@ __global__ void k_chan_gen(double2 *gen, int nx, int ny, int nz, double k, doubl
 
 // Assemble the transposed half-blocks X = B_sigma^T (row-major) for matrices
 // [m0, m0 + count) of the list (mode u = m / 2, half = m % 2: 0 even, 1 odd).
+// With sym != 0 the block written is M = S B_sigma (symmetric) instead of B_sigma^T.
 __global__ void k_assemble(const double2 *lam, double2 *out, long long m0, int nx, int ny,
-                           int nz, int umx, int hh, int n2, double2 ati) {
+                           int nz, int umx, int hh, int n2, double2 ati, int sym) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double2 *L = reinterpret_cast<double2 *>(smem_raw);  // [6][2nz-1]
   const long long m = m0 + blockIdx.x;
@@ -94,8 +100,10 @@ __global__ void k_assemble(const double2 *lam, double2 *out, long long m0, int n
   for (long long e = threadIdx.x; e < (long long)n2 * n2; e += blockDim.x) {
     const int row = (int)(e / n2), col = (int)(e % n2);
     // X[row][col] = B_sigma[col][row]: B row index (a, iz) = col, column index (b, jz) = row
-    const int a = col / hh, iz = col % hh;
-    const int b = row / hh, jz = row % hh;
+    // transposed: B row index (a, iz) = col, column (b, jz) = row; sym: (a, iz) = row
+    const int br = sym ? row : col, bc = sym ? col : row;
+    const int a = br / hh, iz = br % hh;
+    const int b = bc / hh, jz = bc % hh;
     const double sa = a == 2 ? -1.0 : 1.0, sb = b == 2 ? -1.0 : 1.0;
     const bool vr = (iz < h) || (sig * sa > 0.0);
     const bool vc = (jz < h) || (sig * sb > 0.0);
@@ -115,6 +123,7 @@ __global__ void k_assemble(const double2 *lam, double2 *out, long long m0, int n
         if (a == b && iz == jm) v2 = cadd(v2, ati);
         val = cadd(val, cscale(v2, sig * sb));
       }
+      if (sym && a == 2) val = make_double2(-val.x, -val.y);
     }
     X[e] = val;
   }
@@ -356,6 +365,34 @@ __global__ void k_to_f32(const double2 *in, float2 *out, long long n) {
 
 static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Element (r, c) of a 16 x 16 tile sits at r + 16 (c / 4) + 64 (c % 4): lane l = r + 16 q of
+// a wave reads the tile with four 1 KB loads l + 64 k and receives row r, columns 4q .. 4q+3.
+__host__ __device__ __forceinline__ int tile_pos(int r, int c) { return r + 16 * (c >> 2) + 64 * (c & 3); }
+
+// Pack the lower-triangle tiles (I >= J, tile t = I (I + 1) / 2 + J) of `cnt` symmetric
+// row-major n2 x n2 matrices into out + m0 * tiles * 256; entries beyond n2 are zero.
+template <typename TO>
+__global__ void k_pack_sym(const double2 *Y, TO *out, long long m0, int n2, int ntr) {
+  const long long tiles = (long long)ntr * (ntr + 1) / 2;
+  const double2 *Ym = Y + (long long)blockIdx.x * n2 * n2;
+  TO *o = out + (m0 + blockIdx.x) * tiles * 256;
+  for (long long e = threadIdx.x; e < tiles * 256; e += blockDim.x) {
+    const long long t = e >> 8;
+    const int w = (int)(e & 255);
+    int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((long long)I * (I + 1) / 2 > t) --I;
+    while ((long long)(I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = (int)(t - (long long)I * (I + 1) / 2);
+    // invert tile_pos: w = r + 16 q + 64 k, column 4 q + k
+    const int r = w & 15, q = (w >> 4) & 3, k = w >> 6;
+    const int row = 16 * I + r, col = 16 * J + 4 * q + k;
+    const double2 v = (row < n2 && col < n2) ? Ym[(long long)row * n2 + col] : make_double2(0.0, 0.0);
+    o[t * 256 + tile_pos(r, 4 * q + k)] = to_c(v, TO{});
+  }
+}
+
+
+
 void precond_free(dda_problem *p) {
   if (p->binv64) (void)hipFree(p->binv64);
   if (p->binv32) (void)hipFree(p->binv32);
@@ -376,7 +413,10 @@ void precond_build(dda_problem *p, double s_bar) {
   const long long nmat = 2 * U;
   const long long msz = (long long)p->n2 * p->n2;
   const int fp32 = p->opt.precision == 1;
-  const size_t final_bytes = (size_t)nmat * msz * (fp32 ? sizeof(float2) : sizeof(double2));
+  p->psym = nz % 2 == 0 ? 1 : 0;
+  p->ntr = (p->n2 + 15) / 16;
+  const long long per = p->psym ? (long long)p->ntr * (p->ntr + 1) / 2 * 256 : msz;  // stored
+  const size_t final_bytes = (size_t)nmat * per * (fp32 ? sizeof(float2) : sizeof(double2));
   size_t freeb = 0, totb = 0;
   HIPCHK(hipMemGetInfo(&freeb, &totb));
   REQUIRE(final_bytes < (size_t)(0.85 * (double)freeb), DDA_ENOMEM,
@@ -397,7 +437,8 @@ void precond_build(dda_problem *p, double s_bar) {
     if (fp32) HIPCHK(hipMalloc(&p->binv32, final_bytes));
     else HIPCHK(hipMalloc(&p->binv64, final_bytes));
     long long chunk = nmat;
-    if (fp32) {
+    const bool staged = fp32 || p->psym;  // inverses formed in FP64 scratch, then converted
+    if (staged) {
       chunk = std::max<long long>(1, (long long)((1ULL << 31) / (msz * sizeof(double2))));
       chunk = std::min(chunk, nmat);
       HIPCHK(hipMalloc(&scratch, sizeof(double2) * chunk * msz));
@@ -411,11 +452,11 @@ void precond_build(dda_problem *p, double s_bar) {
     HIPCHK(hipMemsetAsync(p->dflag, 0, sizeof(int) * 4, p->st));
     for (long long m0 = 0; m0 < nmat; m0 += chunk) {
       const long long cnt = std::min(chunk, nmat - m0);
-      double2 *dst = fp32 ? scratch : p->binv64 + m0 * msz;
+      double2 *dst = staged ? scratch : p->binv64 + m0 * msz;
       {
         KTimer t(&p->prof, p->st, "pc_assemble", 16.0 * cnt * msz);
         hipLaunchKernelGGL(k_assemble, dim3((unsigned)cnt), dim3(256), lds_asm, p->st, gen, dst, m0,
-                           nx, ny, nz, p->umx, p->hh, p->n2, p->ati);
+                           nx, ny, nz, p->umx, p->hh, p->n2, p->ati, p->psym);
         HIPCHK(hipGetLastError());
       }
       {
@@ -423,7 +464,15 @@ void precond_build(dda_problem *p, double s_bar) {
         gj_launch(p, dst, cnt, p->n2);
         HIPCHK(hipGetLastError());
       }
-      if (fp32) {
+      if (p->psym) {
+        if (fp32)
+          hipLaunchKernelGGL(k_pack_sym<float2>, dim3((unsigned)cnt), dim3(256), 0, p->st, dst,
+                             p->binv32, m0, p->n2, p->ntr);
+        else
+          hipLaunchKernelGGL(k_pack_sym<double2>, dim3((unsigned)cnt), dim3(256), 0, p->st, dst,
+                             p->binv64, m0, p->n2, p->ntr);
+        HIPCHK(hipGetLastError());
+      } else if (fp32) {
         hipLaunchKernelGGL(k_to_f32, dim3(nblk(cnt * msz, 256)), dim3(256), 0, p->st, dst,
                            p->binv32 + m0 * msz, cnt * msz);
         HIPCHK(hipGetLastError());
@@ -517,8 +566,8 @@ __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__re
 #pragma unroll
           for (int v = 0; v < NV; ++v)
             if (v < nv) {
-              a0[v] = cadd(a0[v], cmul(m0[q], U0[v * n2 + j + q]));
-              a1[v] = cadd(a1[v], cmul(m1[q], U1[v * n2 + j + q]));
+              a0[v] = cmac(a0[v], m0[q], U0[v * n2 + j + q]);
+              a1[v] = cmac(a1[v], m1[q], U1[v * n2 + j + q]);
             }
       }
       for (; j < n2; ++j) {
@@ -526,8 +575,8 @@ __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__re
 #pragma unroll
         for (int v = 0; v < NV; ++v)
           if (v < nv) {
-            a0[v] = cadd(a0[v], cmul(m0, U0[v * n2 + j]));
-            a1[v] = cadd(a1[v], cmul(m1, U1[v * n2 + j]));
+            a0[v] = cmac(a0[v], m0, U0[v * n2 + j]);
+            a1[v] = cmac(a1[v], m1, U1[v * n2 + j]);
           }
       }
     }
@@ -545,6 +594,133 @@ __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__re
         const long long cb = ((long long)r * 3 + a) * nz;
         W[(cb + iz) * plane + off] = cscale(cadd(a0[v], a1[v]), flip);
         if (iz < h) W[(cb + (nz - 1 - iz)) * plane + off] = cscale(csub(a0[v], a1[v]), sa * flip);
+      }
+    }
+  }
+}
+
+// Symmetric variant (even nz): one workgroup per (unique mode, chunk of rc right-hand
+// sides).  Gather, sign flips and fold as above, with the z components negated (the S of
+// Y = B^{-1} S).  Wave w computes tile rows I = w, w + NW, ... of both halves at once: lane
+// l = r + 16 q accumulates row 16 I + r over columns 4q .. 4q+3 of every tile of the row,
+// reading the stored lower tiles (I, J <= I) directly and the tiles (J > I, I) transposed,
+// so each stored tile feeds two waves and no partial sums cross waves; JB tiles of each half
+// are loaded before they are used.  Two shuffles sum the four column quarters; the even- and
+// odd-half rows are unfolded and written from registers.
+template <typename T, int NV>
+__global__ void __launch_bounds__(512) k_pc_gemv_sym(cplx<T> *W, const cplx<T> *__restrict__ pk,
+                                                     int nx, int ny, int nz, int umx, int hh,
+                                                     int n2, int ntr, int nrhs, int rc,
+                                                     long long nchunks, long long U) {
+  using V = cplx<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V *Ub = reinterpret_cast<V *>(smem_raw);  // [2][nv][n2p]
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const long long blk = xcd_remap(blockIdx.x, U * nchunks);
+  if (blk >= U * nchunks) return;
+  const long long u = blk / nchunks;
+  const int r0 = (int)(blk - u * nchunks) * rc;
+  const int nr = min(rc, nrhs - r0);
+  const int uy = (int)(u / umx), ux = (int)(u % umx);
+  const int mxs[2] = {ux, (nx - ux) % nx};
+  const int mys[2] = {uy, (ny - uy) % ny};
+  const int nmx = (mxs[1] != mxs[0]) ? 2 : 1;
+  const int nmy = (mys[1] != mys[0]) ? 2 : 1;
+  const int nv = nmx * nmy * nr;
+  const int n2p = 16 * ntr;
+  const long long plane = (long long)nx * ny;
+  const int h = nz / 2;
+  // gather, flip, fold, S
+  for (int e = tid; e < nv * n2p; e += nt) {
+    const int vi = e / n2p;
+    const int row = e - vi * n2p;
+    V f0 = mk<T>((T)0, (T)0), f1 = f0;
+    if (row < n2) {
+      const int a = row / hh, iz = row - a * hh;
+      const int mode = vi / nr, r = r0 + vi % nr;
+      const int fx = mode % nmx, fy = mode / nmx;
+      const long long off = (long long)mys[fy] * nx + mxs[fx];
+      const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
+      const T sa = a == 2 ? (T)-1 : (T)1;
+      const long long cb = ((long long)r * 3 + a) * nz;
+      const V v1 = W[(cb + iz) * plane + off];
+      const V v2 = W[(cb + (nz - 1 - iz)) * plane + off];
+      f0 = cscale(cadd(v1, cscale(v2, sa)), (T)0.5 * flip * sa);
+      f1 = cscale(csub(v1, cscale(v2, sa)), (T)0.5 * flip * sa);
+    }
+    Ub[vi * n2p + row] = f0;
+    Ub[(nv + vi) * n2p + row] = f1;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const long long tiles = (long long)ntr * (ntr + 1) / 2;
+  const V *P0 = pk + (u * 2 + 0) * tiles * 256, *P1 = pk + (u * 2 + 1) * tiles * 256;
+  const V *U0 = Ub, *U1 = Ub + nv * n2p;
+  constexpr int JB = 1;  // tiles per half loaded ahead of their use (more waves pay better)
+  for (int I = wv; I < ntr; I += nw) {
+    V acc0[NV], acc1[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      acc0[v] = mk<T>((T)0, (T)0);
+      acc1[v] = mk<T>((T)0, (T)0);
+    }
+    for (int J0 = 0; J0 < ntr; J0 += JB) {
+      V x0[JB][4], x1[JB][4];
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        const int J = J0 + jb;
+        if (J >= ntr) continue;
+        // stored tile (I, J) read directly, or (J, I) read transposed: element (4q + k, r)
+        const long long t = J <= I ? (long long)I * (I + 1) / 2 + J : (long long)J * (J + 1) / 2 + I;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int e = J <= I ? lane + 64 * k : tile_pos(4 * q + k, r);
+          x0[jb][k] = P0[t * 256 + e];
+          x1[jb][k] = P1[t * 256 + e];
+        }
+      }
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        const int J = J0 + jb;
+        if (J >= ntr) continue;
+        const V *u0 = U0 + 16 * J + 4 * q, *u1 = U1 + 16 * J + 4 * q;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          if (v < nv)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              acc0[v] = cmac(acc0[v], x0[jb][k], u0[v * n2p + k]);
+              acc1[v] = cmac(acc1[v], x1[jb][k], u1[v * n2p + k]);
+            }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      acc0[v].x += __shfl_xor(acc0[v].x, 16, 64);
+      acc0[v].y += __shfl_xor(acc0[v].y, 16, 64);
+      acc0[v].x += __shfl_xor(acc0[v].x, 32, 64);
+      acc0[v].y += __shfl_xor(acc0[v].y, 32, 64);
+      acc1[v].x += __shfl_xor(acc1[v].x, 16, 64);
+      acc1[v].y += __shfl_xor(acc1[v].y, 16, 64);
+      acc1[v].x += __shfl_xor(acc1[v].x, 32, 64);
+      acc1[v].y += __shfl_xor(acc1[v].y, 32, 64);
+    }
+    // unfold + flip + scatter: row i = (a, iz); the four quarter lanes share the vectors
+    const int i = 16 * I + r;
+    if (i < n2) {
+      const int a = i / hh, iz = i - a * hh;
+      const T sa = a == 2 ? (T)-1 : (T)1;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if (v >= nv || (v & 3) != q) continue;
+        const int mode = v / nr, rr = r0 + v % nr;
+        const int fx = mode % nmx, fy = mode / nmx;
+        const long long off = (long long)mys[fy] * nx + mxs[fx];
+        const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
+        const long long cb = ((long long)rr * 3 + a) * nz;
+        W[(cb + iz) * plane + off] = cscale(cadd(acc0[v], acc1[v]), flip);
+        if (iz < h) W[(cb + (nz - 1 - iz)) * plane + off] = cscale(csub(acc0[v], acc1[v]), sa * flip);
       }
     }
   }
@@ -582,6 +758,31 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
                     (long long)ny * nx, -1, nm, 2.0 * rows * nx * sz);
   {
     const long long U = (long long)p->umx * p->umy;
+    snprintf(nm, sizeof nm, "pc_gemv_%s", suf);
+    if (p->psym) {
+      // right-hand sides per workgroup: 4 mode copies x rc vectors <= 8
+      const int rc = std::max(1, std::min(2, nrhs));
+      const long long nchunks = (nrhs + rc - 1) / rc;
+      const int n2p = 16 * p->ntr;
+      const size_t lds = (size_t)2 * 4 * rc * n2p * sizeof(cplx<T>);
+      const long long tiles = (long long)p->ntr * (p->ntr + 1) / 2;
+      const double bytes = (double)U * 2.0 * tiles * 256 * sz * nchunks + 2.0 * rows * nx * sz;
+      const int threads = 64 * std::min(8, p->ntr);
+      const dim3 grid((unsigned)xcd_grid(U * nchunks));
+      KTimer t(&p->prof, p->st, nm, bytes);
+      if (rc == 1) {
+        auto fn = k_pc_gemv_sym<T, 4>;
+        set_lds_limit((const void *)fn, lds);
+        hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->umx, p->hh,
+                           p->n2, p->ntr, nrhs, rc, nchunks, U);
+      } else {
+        auto fn = k_pc_gemv_sym<T, 8>;
+        set_lds_limit((const void *)fn, lds);
+        hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->umx, p->hh,
+                           p->n2, p->ntr, nrhs, rc, nchunks, U);
+      }
+      HIPCHK(hipGetLastError());
+    } else {
     // right-hand sides per workgroup: up to 4 mode copies x rc vectors <= 16, LDS <= 64 KB
     int rc = std::max(1, std::min(4, nrhs));
     while (rc > 1 && (size_t)2 * 4 * rc * p->n2 * sizeof(cplx<T>) > 65536) --rc;
@@ -589,7 +790,6 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
     const size_t lds = (size_t)2 * 4 * rc * p->n2 * sizeof(cplx<T>);
     int threads = ((p->n2 + 63) / 64) * 64;
     threads = std::min(512, std::max(64, threads));
-    snprintf(nm, sizeof nm, "pc_gemv_%s", suf);
     const double bytes = (double)U * 2.0 * p->n2 * p->n2 * sz * nchunks + 2.0 * rows * nx * sz;
     const int nvmax = 4 * rc;
     const dim3 grid((unsigned)xcd_grid(U * nchunks));
@@ -611,6 +811,7 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
                          p->n2, nrhs, rc, nchunks, U);
     }
     HIPCHK(hipGetLastError());
+    }
   }
   snprintf(nm, sizeof nm, "pc_y_inv_%s", suf);
   launch_strided<T>(p, p->uy, W, W, (long long)nrhs * 3 * nz, nx, ny, ny, (long long)ny * nx,

@@ -232,6 +232,38 @@ def test_two_level_block_symmetries():
             assert np.abs(Rm @ b - b @ Rm).max() < 1e-12
 
 
+def test_folded_halves_symmetric_for_even_nz():
+    """With v split into even / odd parts under the z reflection, each mode block restricted
+    to one half (planes iz < nz/2 with the mirror plane folded in with sign sigma s_b, plus
+    the middle plane for odd nz where sigma s_b = +1) satisfies (S B_sigma)^T = S B_sigma
+    with S = diag(1, 1, -1) per component when nz is even.  This is what allows storing half
+    of each inverse; with odd nz the middle plane enters without the fold's factor of two and
+    the symmetry is lost."""
+    for (nz, ny, nx), even in (((6, 4, 5), True), ((7, 3, 4), False)):
+        k, d = 1.3, 0.3
+        B = circulant.two_level_blocks((nz, ny, nx), k, d, 21.0 - 0.02j)
+        h = nz // 2
+        s = np.array([1.0, 1.0, -1.0])
+        worst = 0.0
+        for iy in range(ny):
+            for ix in range(nx):
+                b = B[iy, ix]
+                for sig in (1.0, -1.0):
+                    idx = [(a, iz) for a in range(3) for iz in range(h)]
+                    if nz % 2:
+                        idx += [(a, h) for a in range(3) if sig * s[a] > 0]
+                    half = np.empty((len(idx), len(idx)), dtype=complex)
+                    for p_, (a, iz) in enumerate(idx):
+                        for q_, (bb, jz) in enumerate(idx):
+                            v = b[a * nz + iz, bb * nz + jz]
+                            if jz < h:
+                                v += sig * s[bb] * b[a * nz + iz, bb * nz + nz - 1 - jz]
+                            half[p_, q_] = v
+                    M = np.array([s[a] for a, _ in idx])[:, None] * half
+                    worst = max(worst, np.abs(M - M.T).max() / np.abs(M).max())
+        assert (worst < 1e-13) if even else (worst > 1e-3), (nz, worst)
+
+
 def test_two_level_exact_for_single_column():
     """l = m = 1: both circulant levels are 1 x 1, so for a fully occupied homogeneous
     column P equals the system matrix and preconditioned GMRES converges in one step."""
