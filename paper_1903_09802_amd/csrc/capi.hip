@@ -31,7 +31,7 @@ void free_all(dda_problem *p) {
   auto F = [](void *ptr) {
     if (ptr) (void)hipFree(ptr);
   };
-  F(p->mask); F(p->eps); F(p->khat64); F(p->khat32); F(p->khatI64); F(p->w0); F(p->w1);
+  F(p->mask); F(p->eps); F(p->cidx); F(p->vox); F(p->khat64); F(p->khat32); F(p->khatI64); F(p->w0); F(p->w1);
   F(p->ainv); F(p->Sdev); F(p->V); F(p->work); F(p->work2); F(p->bvec); F(p->xvec); F(p->vsc);
   F(p->H); F(p->givens); F(p->gvec); F(p->hcol); F(p->hcol2);
   F(p->ycoef); F(p->hnrm); F(p->hraw); F(p->lmat); F(p->partial); F(p->dscal); F(p->dflag);
@@ -148,8 +148,9 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
       HIPCHK(hipMalloc(&p->w1, sizeof(double2) * p->w1_elems));
       HIPCHK(hipMalloc(&p->ainv, sizeof(double2) * R * N));
       HIPCHK(hipMalloc(&p->Sdev, sizeof(double) * R));
+      operator_setup(p);  // validation and the compact maps: the solver vectors are compact
       krylov_alloc(p);
-      operator_setup(p);
+      operator_spectrum_setup(p);
       HIPCHK(hipStreamSynchronize(p->st));
     } catch (...) {
       free_all(p);
@@ -182,17 +183,16 @@ dda_status dda_solve(dda_problem *p, int nrhs, const double *dir_host, const dou
     check_waves(nrhs, dir_host, pol_host, S);
     REQUIRE(p->opt.precond == 0 || p->prec_built, DDA_ESTATE,
             "opt.precond = 2 but dda_build_preconditioner has not run");
-    const long long n3 = 3 * p->N;
+    const long long n3 = 3 * p->nocc;
     setup_alpha(p, nrhs, S.data());
     setup_rhs(p, nrhs, dir_host, pol_host, p->bvec, 0);
     if (x0_dev)
-      HIPCHK(hipMemcpyAsync(p->xvec, x0_dev, sizeof(double2) * n3 * nrhs, hipMemcpyDeviceToDevice, p->st));
+      to_compact(p, nrhs, reinterpret_cast<const double2 *>(x0_dev), p->xvec);
     else
       HIPCHK(hipMemsetAsync(p->xvec, 0, sizeof(double2) * n3 * nrhs, p->st));
     std::vector<dda_stats> st(nrhs);
     dda_status res = solve_system(p, nrhs, p->bvec, p->xvec, st.data());
-    if (c_dev)
-      HIPCHK(hipMemcpyAsync(c_dev, p->xvec, sizeof(double2) * n3 * nrhs, hipMemcpyDeviceToDevice, p->st));
+    if (c_dev) to_box(p, nrhs, p->xvec, nullptr, reinterpret_cast<double2 *>(c_dev));
     if (cext || cabs || csca) cross_sections(p, nrhs, dir_host, pol_host, p->xvec, cext, cabs, csca);
     HIPCHK(hipStreamSynchronize(p->st));
     if (p->prof.on) p->prof.collect();
@@ -216,8 +216,11 @@ dda_status dda_apply_operator(dda_problem *p, int nrhs, const double *dir_host,
     std::vector<double> S;
     check_waves(nrhs, dir_host, pol_host, S);
     setup_alpha(p, nrhs, S.data());
-    apply_operator(p, nrhs, reinterpret_cast<const double2 *>(x_dev),
-                   reinterpret_cast<double2 *>(y_dev), fp32 ? 1 : 0, nullptr);
+    // box -> compact, A on the occupied voxels, and y = x in air
+    const double2 *xb = reinterpret_cast<const double2 *>(x_dev);
+    to_compact(p, nrhs, xb, p->work2);
+    apply_operator(p, nrhs, p->work2, p->work, fp32 ? 1 : 0, nullptr);
+    to_box(p, nrhs, p->work, xb, reinterpret_cast<double2 *>(y_dev));
     return DDA_OK;
   });
 }
@@ -228,8 +231,9 @@ dda_status dda_apply_preconditioner(dda_problem *p, int nrhs, const double *x_de
     REQUIRE(p, DDA_EINVAL, "problem is NULL");
     REQUIRE(nrhs >= 1 && nrhs <= p->R, DDA_EINVAL, "nrhs must be in [1, max_rhs = %d]", p->R);
     REQUIRE(x_dev && y_dev, DDA_EINVAL, "x_dev and y_dev are required");
-    apply_precond(p, nrhs, reinterpret_cast<const double2 *>(x_dev),
-                  reinterpret_cast<double2 *>(y_dev), fp32 ? 1 : 0, nullptr);
+    to_compact(p, nrhs, reinterpret_cast<const double2 *>(x_dev), p->work2);
+    apply_precond(p, nrhs, p->work2, p->work, fp32 ? 1 : 0, nullptr);
+    to_box(p, nrhs, p->work, nullptr, reinterpret_cast<double2 *>(y_dev));
     return DDA_OK;
   });
 }
@@ -244,8 +248,8 @@ dda_status dda_cross_sections(dda_problem *p, int nrhs, const double *dir_host,
     std::vector<double> S;
     check_waves(nrhs, dir_host, pol_host, S);
     setup_alpha(p, nrhs, S.data());
-    cross_sections(p, nrhs, dir_host, pol_host, reinterpret_cast<const double2 *>(c_dev), cext,
-                   cabs, csca);
+    to_compact(p, nrhs, reinterpret_cast<const double2 *>(c_dev), p->bvec);
+    cross_sections(p, nrhs, dir_host, pol_host, p->bvec, cext, cabs, csca);
     if (p->prof.on) p->prof.collect();
     return DDA_OK;
   });
@@ -261,7 +265,7 @@ dda_status dda_grad_cext(dda_problem *p, const double *dir_host, const double *p
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<double> S;
     check_waves(1, dir_host, pol_host, S);
-    const long long n3 = 3 * p->N;
+    const long long n3 = 3 * p->nocc;
     double2 *cfwd = nullptr;
     HIPCHK(hipMalloc(&cfwd, sizeof(double2) * n3));
     dda_status res = DDA_OK;

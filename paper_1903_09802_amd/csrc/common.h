@@ -223,6 +223,11 @@ struct dda_problem {
 
   uint8_t *mask = nullptr;      // [N]
   double2 *eps = nullptr;       // [N]
+  // Field vectors inside the solver are compact, [R][3][nocc]: one entry per occupied voxel,
+  // in voxel order.  cidx[v] is voxel v's entry (-1 in air), vox[c] the voxel of entry c.
+  long long nocc = 0;
+  int *cidx = nullptr;          // [N]
+  int *vox = nullptr;           // [nocc]
   double2 eps_mean{0.0, 0.0};   // mean permittivity over occupied voxels
 
   dda::FftPlan px, py, pz;   // padded lengths 2nx, 2ny, 2nz
@@ -289,11 +294,17 @@ void fft_strided_plain(dda_problem *p, const FftPlan &pl, double2 *data, long lo
                        long long width, int inverse);
 
 // operator.hip
+// Validation, mean permittivity, occupied count and the compact index maps.
 void operator_setup(dda_problem *p);
+// Kernel spectra and z-pass tuning (after the work buffers exist).
+void operator_spectrum_setup(dda_problem *p);
+// Box [nrhs][3][N] <-> compact [nrhs][3][nocc]; to_box fills air from `fill` (or zeros).
+void to_compact(dda_problem *p, int nrhs, const double2 *box, double2 *comp);
+void to_box(dda_problem *p, int nrhs, const double2 *comp, const double2 *fill, double2 *box);
 void setup_alpha(dda_problem *p, int nrhs, const double *S_host);
 void setup_rhs(dda_problem *p, int nrhs, const double *dir, const double *pol, double2 *b,
                int conjugate);
-// y = A (s x) with FP64 input and output (fp32: FP32 transforms inside).  xscale_dev: optional
+// y = A (s x) on compact FP64 vectors (fp32: FP32 transforms inside).  xscale_dev: optional
 // per-RHS input scale s_r = xscale_dev[r * kMaxM] (used for unnormalised Krylov vectors).
 void apply_operator(dda_problem *p, int nrhs, const double2 *x, double2 *y, int fp32,
                     const double *xscale_dev);
@@ -307,7 +318,7 @@ void precond_free(dda_problem *p);
 
 // krylov.hip
 void krylov_alloc(dda_problem *p);
-// Solve A x = b for nrhs RHS (b, x device [nrhs][3N]; x holds the initial guess).
+// Solve A x = b for nrhs RHS (b, x compact [nrhs][3 nocc]; x holds the initial guess).
 void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp32, double tol,
                  int maxit, dda_stats *st);
 // Full solve including refinement mode.

@@ -11,13 +11,15 @@ namespace dda {
 
 // ---------------------------------------------------------------------------- row (x-axis) FFT
 
+// Field vectors outside the transforms are compact: [R][3][nocc], one entry per occupied
+// voxel in voxel order; cidx[voxel] is the entry's index, -1 in air.
 enum RowMode {
   ROW_PLAIN = 0,  // in/out: T work rows (setup transforms)
-  ROW_OP_FWD,     // in: FP64 field rows (masked, optionally scaled), zero-padded; out: T rows
-  ROW_OP_INV,     // in: T rows; out: y = M (alpha^{-1} x - conv) + (1 - M) x, FP64
-  ROW_IMG_INV,    // in: T rows; out: y = M conv, FP64
-  ROW_PC_FWD,     // in: FP64 field rows, masked; out: T rows (unpadded)
-  ROW_PC_INV      // in: T rows; out: y = M * scale * v, FP64
+  ROW_OP_FWD,     // in: compact FP64 field (optionally scaled), zero in air and padding; out: T rows
+  ROW_OP_INV,     // in: T rows; out (compact): alpha^{-1} x - conv, FP64
+  ROW_IMG_INV,    // in: T rows; out (compact): conv, FP64
+  ROW_PC_FWD,     // in: compact FP64 field, zero in air; out: T rows (unpadded)
+  ROW_PC_INV      // in: T rows; out (compact): scale * v, FP64
 };
 
 struct RowArgs {
@@ -28,7 +30,8 @@ struct RowArgs {
   int n_in, n_out;     // valid input length (zero padded to n), output length written
   long long in_stride, out_stride;
   int sign;
-  const uint8_t *mask; // [N]
+  const int *cidx;     // [N] compact index of each voxel, -1 in air
+  long long nocc;      // occupied voxels (compact length per component)
   long long vox_rows;  // nz * ny: rows per component block
   long long rhs_rows;  // 3 * nz * ny: rows per right-hand side
   int nx;
@@ -60,10 +63,12 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
     if (row < a.rows && i < a.n_in) {
       if constexpr (MODE == ROW_OP_FWD || MODE == ROW_PC_FWD) {
         const long long vox = (row % a.vox_rows) * a.nx + i;
-        double2 xv = in[row * a.in_stride + i];
-        if (!a.mask[vox]) xv = make_double2(0.0, 0.0);
-        if (a.xscale) xv = cscale(xv, a.xscale[(row / a.rhs_rows) * kMaxM]);
-        val = to_c(xv, V{});
+        const int ci = a.cidx[vox];
+        if (ci >= 0) {
+          double2 xv = in[(row / a.vox_rows) * a.nocc + ci];
+          if (a.xscale) xv = cscale(xv, a.xscale[(row / a.rhs_rows) * kMaxM]);
+          val = to_c(xv, V{});
+        }
       } else {
         val = in[row * a.in_stride + i];
       }
@@ -84,18 +89,18 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
       out[row * a.out_stride + i] = v;
     } else if constexpr (MODE == ROW_OP_INV || MODE == ROW_IMG_INV || MODE == ROW_PC_INV) {
       const long long vox = (row % a.vox_rows) * a.nx + i;
+      const int ci = a.cidx[vox];
+      if (ci < 0) continue;
+      const long long o = (row / a.vox_rows) * a.nocc + ci;
       const double2 conv = cscale(to_d(v), a.scale);
-      double2 y = make_double2(0.0, 0.0);
+      double2 y = conv;
       if constexpr (MODE == ROW_OP_INV) {
         const long long r = row / a.rhs_rows;
-        double2 xv = a.xin[row * a.out_stride + i];
+        double2 xv = a.xin[o];
         if (a.xscale) xv = cscale(xv, a.xscale[r * kMaxM]);
-        if (a.mask[vox]) y = csub(cmul(a.ainv[r * a.N + vox], xv), conv);
-        else y = xv;
-      } else {
-        if (a.mask[vox]) y = conv;
+        y = csub(cmul(a.ainv[r * a.N + vox], xv), conv);
       }
-      out[row * a.out_stride + i] = y;
+      out[o] = y;
     } else {
       out[row * a.out_stride + i] = v;
     }

@@ -392,7 +392,7 @@ static void read_scalars(dda_problem *p, const double2 *src, int nrhs, std::vect
 // r = b - A x (FP64 operator) into r, relative norms ||r|| / ||b|| to the host.
 void residual(dda_problem *p, int nrhs, const double2 *b, const double2 *x, double2 *r,
               double *rel_host) {
-  const long long n3 = 3 * p->N;
+  const long long n3 = 3 * p->nocc;
   Kry K{p, nrhs, reduce_blocks(n3), p->opt.restart, n3, reinterpret_cast<double2 *>(p->partial),
         p->dflag + 4, p->dflag + 4 + p->R};
   std::vector<int> all(nrhs, 1);
@@ -414,7 +414,7 @@ void residual(dda_problem *p, int nrhs, const double2 *b, const double2 *x, doub
 void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp32, double tol,
                  int maxit, dda_stats *st) {
   const int m = p->opt.restart;
-  const long long n3 = 3 * p->N;
+  const long long n3 = 3 * p->nocc;
   Kry K{p, nrhs, reduce_blocks(n3), m, n3, reinterpret_cast<double2 *>(p->partial), p->dflag + 4,
         p->dflag + 4 + p->R};
   const long long vs_r = n3, vs_j = (long long)p->R * n3;  // V is [m+1][R][n3]
@@ -560,7 +560,7 @@ dda_status solve_system(dda_problem *p, int nrhs, const double2 *b, double2 *x, 
 void krylov_alloc(dda_problem *p) {
   const int m = p->opt.restart;
   const int R = p->R;
-  const long long n3 = 3 * p->N;
+  const long long n3 = 3 * p->nocc;
   HIPCHK(hipMalloc(&p->V, sizeof(double2) * (size_t)R * (m + 1) * n3));
   HIPCHK(hipMemsetAsync(p->V, 0, sizeof(double2) * (size_t)R * (m + 1) * n3, p->st));
   HIPCHK(hipMalloc(&p->work, sizeof(double2) * (size_t)R * n3));

@@ -2,6 +2,9 @@
 // kernel spectrum, and the five-pass zero-padded FFT product (Sec. 1, 2.1-2.2).
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "fft_kernels.h"
 #include "zpass_reg.h"
@@ -137,13 +140,13 @@ __global__ void k_alpha(const uint8_t *mask, const double2 *eps, long long N, do
   ainv[r * N + i] = mask[i] ? ldr_alpha_inv(eps[i], kd, S[r]) : make_double2(0.0, 0.0);
 }
 
-// b[r][a][v] = pol_a exp(+-i k dir . r_v) on occupied voxels, 0 in air.
-__global__ void k_incident(const uint8_t *mask, int nx, int ny, int nz, double k, double d,
-                           const double *dirpol, int conj, double2 *b) {
-  const long long N = (long long)nx * ny * nz;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// b[r][a][c] = pol_a exp(+-i k dir . r_v) for occupied voxel v = vox[c] (compact layout).
+__global__ void k_incident(const int *vox, long long nocc, int nx, int ny, int nz, double k,
+                           double d, const double *dirpol, int conj, double2 *b) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (i >= N) return;
+  if (c >= nocc) return;
+  const long long i = vox[c];
   const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long long)nx * ny));
   const double x = (ix - 0.5 * (nx - 1)) * d, y = (iy - 0.5 * (ny - 1)) * d,
                z = (iz - 0.5 * (nz - 1)) * d;
@@ -152,12 +155,113 @@ __global__ void k_incident(const uint8_t *mask, int nx, int ny, int nz, double k
   double sn, cs;
   sincos(ph, &sn, &cs);
   if (conj) sn = -sn;
-  double2 *br = b + (long long)r * 3 * N;
-  for (int a = 0; a < 3; ++a) {
-    double2 v = make_double2(0.0, 0.0);
-    if (mask[i]) v = make_double2(dp[3 + a] * cs, dp[3 + a] * sn);
-    br[a * N + i] = v;
+  double2 *br = b + (long long)r * 3 * nocc;
+  for (int a = 0; a < 3; ++a) br[a * nocc + c] = make_double2(dp[3 + a] * cs, dp[3 + a] * sn);
+}
+
+// Compact index map, pass 1: occupied voxels per block of kMapBlock voxels.
+constexpr int kMapBlock = 256;
+__global__ void k_map_count(const uint8_t *mask, long long N, int *count) {
+  __shared__ int sh[kMapBlock];
+  const long long v = (long long)blockIdx.x * kMapBlock + threadIdx.x;
+  sh[threadIdx.x] = (v < N && mask[v]) ? 1 : 0;
+  __syncthreads();
+  for (int s = kMapBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) count[blockIdx.x] = sh[0];
+}
+
+// Pass 2: with the exclusive prefix of the block counts, cidx[v] = compact index (or -1) and
+// vox[c] = voxel of compact entry c (a block-local inclusive scan gives the ranks).
+__global__ void k_map_fill(const uint8_t *mask, long long N, const long long *base, int *cidx,
+                           int *vox) {
+  __shared__ int sh[kMapBlock];
+  const long long v = (long long)blockIdx.x * kMapBlock + threadIdx.x;
+  const int occ = (v < N && mask[v]) ? 1 : 0;
+  sh[threadIdx.x] = occ;
+  __syncthreads();
+  for (int off = 1; off < kMapBlock; off <<= 1) {  // Hillis-Steele inclusive scan
+    const int t = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (v >= N) return;
+  if (occ) {
+    const long long c = base[blockIdx.x] + sh[threadIdx.x] - 1;
+    cidx[v] = (int)c;
+    vox[c] = (int)v;
+  } else {
+    cidx[v] = -1;
+  }
+}
+
+void build_compact_map(dda_problem *p) {
+  const long long nb = (p->N + kMapBlock - 1) / kMapBlock;
+  int *cnt = nullptr;
+  long long *base = nullptr;
+  HIPCHK(hipMalloc(&cnt, sizeof(int) * nb));
+  HIPCHK(hipMalloc(&base, sizeof(long long) * nb));
+  try {
+    hipLaunchKernelGGL(k_map_count, dim3((unsigned)nb), dim3(kMapBlock), 0, p->st, p->mask, p->N, cnt);
+    HIPCHK(hipGetLastError());
+    std::vector<int> hc(nb);
+    std::vector<long long> hb(nb);
+    HIPCHK(hipMemcpyAsync(hc.data(), cnt, sizeof(int) * nb, hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    long long acc = 0;
+    for (long long b = 0; b < nb; ++b) {
+      hb[b] = acc;
+      acc += hc[b];
+    }
+    REQUIRE(acc == p->nocc, DDA_EDEVICE, "occupied-voxel count mismatch (%lld vs %lld)", acc, p->nocc);
+    HIPCHK(hipMalloc(&p->cidx, sizeof(int) * p->N));
+    HIPCHK(hipMalloc(&p->vox, sizeof(int) * p->nocc));
+    HIPCHK(hipMemcpyAsync(base, hb.data(), sizeof(long long) * nb, hipMemcpyHostToDevice, p->st));
+    hipLaunchKernelGGL(k_map_fill, dim3((unsigned)nb), dim3(kMapBlock), 0, p->st, p->mask, p->N,
+                       base, p->cidx, p->vox);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(p->st));  // hb is host-local
+  } catch (...) {
+    (void)hipFree(cnt);
+    (void)hipFree(base);
+    throw;
+  }
+  HIPCHK(hipFree(cnt));
+  HIPCHK(hipFree(base));
+}
+
+// Box <-> compact: gather out[r][a][c] = in[r][a][vox[c]]; scatter out[r][a][v] =
+// in[r][a][cidx[v]] on occupied voxels and, in air, fill[r][a][v] (or 0 without fill).
+__global__ void k_gather(const double2 *in, const int *vox, long long N, long long nocc,
+                         double2 *out) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long ra = blockIdx.y;
+  if (c >= nocc) return;
+  out[ra * nocc + c] = in[ra * N + vox[c]];
+}
+
+__global__ void k_scatter(const double2 *in, const int *cidx, long long N, long long nocc,
+                          const double2 *fill, double2 *out) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long ra = blockIdx.y;
+  if (v >= N) return;
+  const int c = cidx[v];
+  out[ra * N + v] = c >= 0 ? in[ra * nocc + c] : (fill ? fill[ra * N + v] : make_double2(0.0, 0.0));
+}
+
+void to_compact(dda_problem *p, int nrhs, const double2 *box, double2 *comp) {
+  hipLaunchKernelGGL(k_gather, dim3(nblk(p->nocc, 256), 3 * nrhs), dim3(256), 0, p->st, box, p->vox,
+                     p->N, p->nocc, comp);
+  HIPCHK(hipGetLastError());
+}
+
+void to_box(dda_problem *p, int nrhs, const double2 *comp, const double2 *fill, double2 *box) {
+  hipLaunchKernelGGL(k_scatter, dim3(nblk(p->N, 256), 3 * nrhs), dim3(256), 0, p->st, comp, p->cidx,
+                     p->N, p->nocc, fill, box);
+  HIPCHK(hipGetLastError());
 }
 
 
@@ -179,9 +283,9 @@ void setup_rhs(dda_problem *p, int nrhs, const double *dir, const double *pol, d
     }
   double *dd = p->dscal + 8 * p->R;  // scratch area after the per-RHS scalars
   HIPCHK(hipMemcpyAsync(dd, dp.data(), sizeof(double) * 6 * nrhs, hipMemcpyHostToDevice, p->st));
-  KTimer t(&p->prof, p->st, "incident_field", 49.0 * p->N * nrhs);
-  hipLaunchKernelGGL(k_incident, dim3(nblk(p->N, 256), nrhs), dim3(256), 0, p->st, p->mask,
-                     p->nx, p->ny, p->nz, p->k, p->d, dd, conjugate, b);
+  KTimer t(&p->prof, p->st, "incident_field", 52.0 * p->nocc * nrhs);
+  hipLaunchKernelGGL(k_incident, dim3(nblk(p->nocc, 256), nrhs), dim3(256), 0, p->st, p->vox,
+                     p->nocc, p->nx, p->ny, p->nz, p->k, p->d, dd, conjugate, b);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(p->st));  // dp is host-local
 }
@@ -215,7 +319,7 @@ static void kernel_spectrum(dda_problem *p, int part) {
 template <typename T> static void zpass_autotune(dda_problem *p, const cplx<T> *khat);
 
 void operator_setup(dda_problem *p) {
-  // validation and mean permittivity
+  // validation, mean permittivity and the compact index map
   const int nb = 1024;
   double *part = nullptr;
   HIPCHK(hipMalloc(&part, sizeof(double) * 4 * nb));
@@ -239,8 +343,13 @@ void operator_setup(dda_problem *p) {
           "%.0f occupied voxel(s) have eps = 1, eps = -2 or a non-finite eps (polarisability undefined)",
           bad);
   p->n_occ = (long long)occ;
+  p->nocc = p->n_occ;
   p->eps_mean = make_double2(sr / occ, si / occ);
+  build_compact_map(p);
+}
 
+// Kernel spectra (FP64, FP32) and the z-pass tile widths.
+void operator_spectrum_setup(dda_problem *p) {
   const long long oct = 6LL * (p->nx + 1) * (p->ny + 1) * (p->nz + 1);
   const int nzz = 2 * p->nz;
   p->zreg = (nzz >= 32 && nzz <= 256 && (nzz & (nzz - 1)) == 0) ? 1 : 0;
@@ -356,7 +465,23 @@ template <typename T> static int zpass_max_tw(dda_problem *p) {
 }
 
 // Time each power-of-two tile width on the problem's own grid and keep the fastest.
+// Tile widths already measured in this process, per (device, grid, precision): problems of
+// a shape seen before skip the timing runs.
+static std::mutex g_ztw_mu;
+static std::map<std::tuple<int, int, int, int, int>, int> g_ztw;
+
 template <typename T> static void zpass_autotune(dda_problem *p, const cplx<T> *khat) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  const auto key = std::make_tuple(dev, p->nx, p->ny, p->nz, (int)sizeof(T));
+  {
+    std::lock_guard<std::mutex> lk(g_ztw_mu);
+    const auto it = g_ztw.find(key);
+    if (it != g_ztw.end()) {
+      p->ztw[sizeof(T) == 8 ? 0 : 1] = it->second;
+      return;
+    }
+  }
   const int tmax = zpass_max_tw<T>(p);
   cplx<T> *w1 = reinterpret_cast<cplx<T> *>(p->w1);
   HIPCHK(hipMemsetAsync(w1, 0, sizeof(cplx<T>) * 3 * p->nz * p->zplane, p->st));
@@ -382,6 +507,8 @@ template <typename T> static void zpass_autotune(dda_problem *p, const cplx<T> *
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   p->ztw[sizeof(T) == 8 ? 0 : 1] = best_tw;
+  std::lock_guard<std::mutex> lk(g_ztw_mu);
+  g_ztw[key] = best_tw;
 }
 
 // kind 0: DDA operator; kind 1: Im G convolution (scattering sum)
@@ -404,7 +531,8 @@ static void op_passes(dda_problem *p, int nrhs, const double2 *x, double2 *y,
     a.in_stride = nx;
     a.out_stride = 2 * nx;
     a.sign = -1;
-    a.mask = p->mask;
+    a.cidx = p->cidx;
+    a.nocc = p->nocc;
     a.vox_rows = (long long)nz * ny;
     a.rhs_rows = 3LL * nz * ny;
     a.nx = nx;
@@ -412,7 +540,7 @@ static void op_passes(dda_problem *p, int nrhs, const double2 *x, double2 *y,
     a.xscale = xscale;
     launch_rows<T, ROW_OP_FWD, double2, cplx<T>>(
         p, p->px, x, w0, a, sizeof(T) == 8 ? "op_x_fwd_f64" : "op_x_fwd_f32",
-        rows * (16.0 * nx + 1.0 * nx + sz * 2 * nx));
+        rows * (4.0 * nx + sz * 2 * nx) + nrhs * 48.0 * p->nocc);
   }
   // P2: y transform, ny rows zero-padded to 2ny
   launch_strided<T>(p, p->py, w0, w1, (long long)nrhs * 3 * nz, 2LL * nx, ny, 2 * ny,
@@ -435,7 +563,8 @@ static void op_passes(dda_problem *p, int nrhs, const double2 *x, double2 *y,
     a.in_stride = 2 * nx;
     a.out_stride = nx;
     a.sign = +1;
-    a.mask = p->mask;
+    a.cidx = p->cidx;
+    a.nocc = p->nocc;
     a.vox_rows = (long long)nz * ny;
     a.rhs_rows = 3LL * nz * ny;
     a.nx = nx;
@@ -447,10 +576,10 @@ static void op_passes(dda_problem *p, int nrhs, const double2 *x, double2 *y,
     if (kind == 0)
       launch_rows<T, ROW_OP_INV, cplx<T>, double2>(
           p, p->px, w0, y, a, sizeof(T) == 8 ? "op_x_inv_f64" : "op_x_inv_f32",
-          rows * (sz * 2 * nx + 16.0 * nx + 1.0 * nx + 16.0 * nx) + nrhs * 16.0 * p->N);
+          rows * (sz * 2 * nx + 4.0 * nx) + nrhs * (96.0 * p->nocc + 16.0 * p->N));
     else
       launch_rows<T, ROW_IMG_INV, cplx<T>, double2>(p, p->px, w0, y, a, "imag_x_inv",
-                                                    rows * (sz * 2 * nx + 1.0 * nx + 16.0 * nx));
+                                                    rows * (sz * 2 * nx + 4.0 * nx) + nrhs * 48.0 * p->nocc);
   }
 }
 

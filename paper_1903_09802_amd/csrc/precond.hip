@@ -743,7 +743,8 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
     a.in_stride = nx;
     a.out_stride = nx;
     a.sign = -1;
-    a.mask = p->mask;
+    a.cidx = p->cidx;
+    a.nocc = p->nocc;
     a.vox_rows = (long long)nz * ny;
     a.rhs_rows = 3LL * nz * ny;
     a.nx = nx;
@@ -751,7 +752,7 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
     a.xscale = xscale;
     snprintf(nm, sizeof nm, "pc_x_fwd_%s", suf);
     launch_rows<T, ROW_PC_FWD, double2, cplx<T>>(p, p->ux, x, W, a, nm,
-                                                 rows * (16.0 * nx + 1.0 * nx + sz * nx));
+                                                 rows * (4.0 * nx + sz * nx) + nrhs * 48.0 * p->nocc);
   }
   snprintf(nm, sizeof nm, "pc_y_fwd_%s", suf);
   launch_strided<T>(p, p->uy, W, W, (long long)nrhs * 3 * nz, nx, ny, ny, (long long)ny * nx,
@@ -824,7 +825,8 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
     a.in_stride = nx;
     a.out_stride = nx;
     a.sign = +1;
-    a.mask = p->mask;
+    a.cidx = p->cidx;
+    a.nocc = p->nocc;
     a.vox_rows = (long long)nz * ny;
     a.rhs_rows = 3LL * nz * ny;
     a.nx = nx;
@@ -832,7 +834,7 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
     a.scale = 1.0 / ((double)nx * ny);
     snprintf(nm, sizeof nm, "pc_x_inv_%s", suf);
     launch_rows<T, ROW_PC_INV, cplx<T>, double2>(p, p->ux, W, y, a, nm,
-                                                 rows * (sz * nx + 1.0 * nx + 16.0 * nx));
+                                                 rows * (sz * nx + 4.0 * nx) + nrhs * 48.0 * p->nocc);
   }
 }
 

@@ -1,4 +1,5 @@
-// Cross sections of a solved dipole array and the adjoint gradient of C_ext.
+// Cross sections of a solved dipole array and the adjoint gradient of C_ext (compact
+// field vectors, see the problem handle).
 //
 // With the paper's scaling (polarisation density c, voxel volume omitted from alpha,
 // Sec. 2.1) the Draine-Flatau expressions become, for |E_0| = 1,
@@ -14,21 +15,21 @@
 
 namespace dda {
 
-// partial[(r * B + blk) * 4 + q]: q = 0 ext, 1 abs weight sum, 2 Re(c^H u), 3 |c|^2
+// partial[(r * B + blk) * 4 + q]: q = 0 ext, 1 abs weight sum, 2 Re(c^H u), 3 |c|^2.
+// c, E, u compact [R][3][nocc]; ainv per voxel [R][N].
 __global__ void k_xsec_partial(const double2 *c, const double2 *E, const double2 *u,
-                               const double2 *ainv, const uint8_t *mask, long long N, double kd,
-                               double *partial, int B) {
+                               const double2 *ainv, const int *vox, long long N, long long nocc,
+                               double kd, double *partial, int B) {
   const int r = blockIdx.y;
   __shared__ double sh[4][256];
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
   const double rr = (2.0 / 3.0) * kd * kd * kd;
-  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < N;
-       v += (long long)gridDim.x * blockDim.x) {
-    if (!mask[v]) continue;
-    const double2 ai = ainv[r * N + v];
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < nocc;
+       q += (long long)gridDim.x * blockDim.x) {
+    const double2 ai = ainv[r * N + vox[q]];
     double c2 = 0;
     for (int a = 0; a < 3; ++a) {
-      const long long o = ((long long)r * 3 + a) * N + v;
+      const long long o = ((long long)r * 3 + a) * nocc + q;
       const double2 cv = c[o];
       const double2 ev = E[o];
       s0 += ev.x * cv.y - ev.y * cv.x;  // Im(conj(E) c)
@@ -68,9 +69,9 @@ void cross_sections(dda_problem *p, int nrhs, const double *dir, const double *p
   double *part = p->partial;  // [nrhs][B][4] fits the reduction buffer
   REQUIRE((size_t)nrhs * B * 4 <= p->partial_elems, DDA_EINVAL, "reduction buffer too small");
   {
-    KTimer t(&p->prof, p->st, "xsec_reduce", (double)nrhs * N * (16.0 * 9 + 17.0));
+    KTimer t(&p->prof, p->st, "xsec_reduce", (double)nrhs * p->nocc * (16.0 * 10 + 4.0));
     hipLaunchKernelGGL(k_xsec_partial, dim3(B, nrhs), dim3(256), 0, p->st, c, p->work2, u, p->ainv,
-                       p->mask, N, p->k * p->d, part, B);
+                       p->vox, N, p->nocc, p->k * p->d, part, B);
     HIPCHK(hipGetLastError());
   }
   std::vector<double> h((size_t)nrhs * B * 4);
@@ -88,17 +89,19 @@ void cross_sections(dda_problem *p, int nrhs, const double *dir, const double *p
   }
 }
 
-__global__ void k_grad(const double2 *c, const double2 *lam, const double2 *eps,
-                       const uint8_t *mask, long long N, double kd, double S, double pref,
+// c, lam compact [3][nocc]; grad per voxel [N], zero in air.
+__global__ void k_grad(const double2 *c, const double2 *lam, const double2 *eps, const int *cidx,
+                       long long N, long long nocc, double kd, double S, double pref,
                        double2 *grad) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
-  if (!mask[v]) {
+  const int q = cidx[v];
+  if (q < 0) {
     grad[v] = make_double2(0.0, 0.0);
     return;
   }
   double2 acc = make_double2(0.0, 0.0);
-  for (int a = 0; a < 3; ++a) acc = cadd(acc, cmul(lam[a * N + v], c[a * N + v]));
+  for (int a = 0; a < 3; ++a) acc = cadd(acc, cmul(lam[a * nocc + q], c[a * nocc + q]));
   const double2 da = ldr_dalpha_inv(eps[v], kd, S);
   const double2 hp = make_double2(-(da.x * acc.x - da.y * acc.y), -(da.x * acc.y + da.y * acc.x));
   // i * conj(h') = (Im h', Re h')
@@ -108,7 +111,7 @@ __global__ void k_grad(const double2 *c, const double2 *lam, const double2 *eps,
 void grad_kernel(dda_problem *p, const double2 *c, const double2 *lam, double S, double2 *grad) {
   KTimer t(&p->prof, p->st, "adjoint_grad", 113.0 * p->N);
   hipLaunchKernelGGL(k_grad, dim3((unsigned)((p->N + 255) / 256)), dim3(256), 0, p->st, c, lam,
-                     p->eps, p->mask, p->N, p->k * p->d, S,
+                     p->eps, p->cidx, p->N, p->nocc, p->k * p->d, S,
                      4.0 * DDA_PI * p->k * p->d * p->d * p->d, grad);
   HIPCHK(hipGetLastError());
 }
