@@ -608,7 +608,7 @@ __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__re
 // are loaded before they are used.  Two shuffles sum the four column quarters; the even- and
 // odd-half rows are unfolded and written from registers.
 template <typename T, int NV>
-__global__ void __launch_bounds__(512) k_pc_gemv_sym(cplx<T> *W, const cplx<T> *__restrict__ pk,
+__global__ void __launch_bounds__(768) k_pc_gemv_sym(cplx<T> *W, const cplx<T> *__restrict__ pk,
                                                      int nx, int ny, int nz, int umx, int hh,
                                                      int n2, int ntr, int nrhs, int rc,
                                                      long long nchunks, long long U) {
@@ -665,12 +665,14 @@ __global__ void __launch_bounds__(512) k_pc_gemv_sym(cplx<T> *W, const cplx<T> *
       acc0[v] = mk<T>((T)0, (T)0);
       acc1[v] = mk<T>((T)0, (T)0);
     }
+    // cyclic order J = (t - I) mod ntr: the waves of rows I and J read the shared tile in the
+    // same step t, so its second use hits in cache
     for (int J0 = 0; J0 < ntr; J0 += JB) {
       V x0[JB][4], x1[JB][4];
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb) {
-        const int J = J0 + jb;
-        if (J >= ntr) continue;
+        if (J0 + jb >= ntr) continue;
+        const int J = (J0 + jb + ntr - I % ntr) % ntr;
         // stored tile (I, J) read directly, or (J, I) read transposed: element (4q + k, r)
         const long long t = J <= I ? (long long)I * (I + 1) / 2 + J : (long long)J * (J + 1) / 2 + I;
 #pragma unroll
@@ -682,8 +684,8 @@ __global__ void __launch_bounds__(512) k_pc_gemv_sym(cplx<T> *W, const cplx<T> *
       }
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb) {
-        const int J = J0 + jb;
-        if (J >= ntr) continue;
+        if (J0 + jb >= ntr) continue;
+        const int J = (J0 + jb + ntr - I % ntr) % ntr;
         const V *u0 = U0 + 16 * J + 4 * q, *u1 = U1 + 16 * J + 4 * q;
 #pragma unroll
         for (int v = 0; v < NV; ++v)
@@ -768,7 +770,7 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
       const size_t lds = (size_t)2 * 4 * rc * n2p * sizeof(cplx<T>);
       const long long tiles = (long long)p->ntr * (p->ntr + 1) / 2;
       const double bytes = (double)U * 2.0 * tiles * 256 * sz * nchunks + 2.0 * rows * nx * sz;
-      const int threads = 64 * std::min(8, p->ntr);
+      const int threads = 64 * std::min(12, p->ntr);  // one wave per tile row up to 12 rows
       const dim3 grid((unsigned)xcd_grid(U * nchunks));
       KTimer t(&p->prof, p->st, nm, bytes);
       if (rc == 1) {
