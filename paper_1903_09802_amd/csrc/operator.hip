@@ -383,7 +383,12 @@ template <typename T, typename F> static void with_gp(int n, F &&f) {
 static int zreg_g(int n) { return n <= 32 ? 4 : n <= 128 ? 8 : 16; }
 
 // LDS bytes of one register z-pass workgroup with `tw` columns
-template <typename T> static size_t zreg_lds(int n, int tw) { return (size_t)(3 * tw + 1) * n * sizeof(cplx<T>); }
+// LDS bytes of one register z-pass workgroup with `tw` columns: exchange region, twiddles and
+// the kernel-spectrum slab
+template <typename T> static size_t zreg_lds(int n, int tw, int nz) {
+  return (size_t)3 * tw * n * sizeof(T) + (size_t)n * sizeof(cplx<T>) +
+         (size_t)tw * (nz + 1) * 6 * sizeof(cplx<T>);
+}
 
 // Launch the fused z pass with `tw` columns per tile (a power of two; 0: the autotuned choice).
 template <typename T>
@@ -406,7 +411,7 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, in
     a.tiles_x = (p->nx + 1 + tw - 1) / tw;
     a.nrhs = nrhs;
     a.nblk = (long long)a.tiles_x * (p->ny + 1) * 4 * nrhs;
-    const size_t lds = zreg_lds<T>(n, tw);
+    const size_t lds = zreg_lds<T>(n, tw, p->nz);
     with_gp<T>(n, [&](auto G, auto P) {
       auto fn = k_zpass_reg<T, decltype(G)::value, decltype(P)::value>;
       set_lds_limit((const void *)fn, lds);
@@ -448,7 +453,7 @@ template <typename T> static int zpass_max_tw(dda_problem *p) {
     const int G = zreg_g(n);
     while (true) {
       const int t2 = tw * 2;
-      if (zreg_lds<T>(n, t2) > 64 * 1024 || 3 * t2 * G > 256 || t2 > p->nx + 1) break;
+      if (zreg_lds<T>(n, t2, p->nz) > 80 * 1024 || 3 * t2 * G > 256 || t2 > p->nx + 1) break;
       tw = t2;
     }
     return tw;

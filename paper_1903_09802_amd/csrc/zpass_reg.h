@@ -11,14 +11,17 @@
 // three component groups of a column.  The inverse transform starts from exactly that
 // ownership (input index g + G b), so it needs one more exchange and no other permutation;
 // only the first nz outputs are formed and stored.  Three LDS exchanges in all, against two
-// per radix pass for a transform staged entirely in LDS.
+// per radix pass for a transform staged entirely in LDS.  Each exchange moves real and
+// imaginary parts (or two halves of the frequencies) in turn, which halves its LDS, and the
+// workgroup's slab of kernel spectrum is staged in LDS with coalesced loads issued together
+// with the field loads, so the 3x3 product never waits on global memory.
 //
 // Work assignment: a workgroup takes TW consecutive octant columns (ox, oy) of the kernel
 // spectrum in one of the four sign mirrors (kx = ox or 2 nx - ox, ky = oy or 2 ny - oy) for
 // one right-hand side, all three components.  The logical block index runs fastest over
 // RHS and mirrors, so the 4 R workgroups that read the same kernel-spectrum columns are
 // adjacent and, through the XCD remap, share one L2.  The kernel spectrum is stored z-major,
-// [oy][ox][oz][6], so a thread's frequencies read contiguous records.
+// [oy][ox][oz][6], so a workgroup's slab is one contiguous range.
 #pragma once
 
 #include "fft_engine.h"
@@ -137,92 +140,132 @@ __global__ void __launch_bounds__(256) k_zpass_reg(cplx<T> *data, const cplx<T> 
   const int kx = (mir & 1) ? 2 * a.nx - ox : ox;
   const int ky = (mir & 2) ? 2 * a.ny - oy : oy;
   V *cb = data + ((long long)r * 3 + comp) * a.nz * a.plane + (long long)ky * 2 * a.nx + kx;
-  V *sm = s + (comp * a.tw + col) * n;  // this (component, column)'s exchange tile
-  V *stw = s + 3 * a.tw * n;             // twiddles exp(-2 pi i t / n), t < n
+  // LDS: exchange region (3 tw tiles of n reals, or of G x P/2 complex), twiddles, and the
+  // kernel-spectrum slab of the workgroup's octant columns, [tw][nz+1][6]
+  T *exd = reinterpret_cast<T *>(s);
+  V *exc = s;
+  V *stw = reinterpret_cast<V *>(reinterpret_cast<unsigned char *>(s) + (size_t)3 * a.tw * n * sizeof(T));
+  V *kh = stw + n;
+  const int tile = comp * a.tw + col;
+  T *ed = exd + tile * n;
+  constexpr int PH = P / 2;
 
-  // forward: P-point DFTs over b of the non-zero half, twiddle, exchange
-  V X[P];
+  // issue the field loads first, then the spectrum slab (coalesced) and the twiddles
+  V x[HB];
+#pragma unroll
+  for (int b = 0; b < HB; ++b)
+    x[b] = ok ? cb[(long long)(g + G * b) * a.plane] : mk<T>((T)0, (T)0);
   {
-    V x[HB];
-#pragma unroll
-    for (int b = 0; b < HB; ++b)
-      x[b] = ok ? cb[(long long)(g + G * b) * a.plane] : mk<T>((T)0, (T)0);
-    for (int t = threadIdx.x; t < n; t += blockDim.x) stw[t] = tw[t];
-    __syncthreads();
-    rdft_half<P, -1, V>(x, X);
-  }
-#pragma unroll
-  for (int c = 1; c < P; ++c) X[c] = cmul(X[c], stw[g * c]);
-#pragma unroll
-  for (int c = 0; c < P; ++c) sm[zr_at<P>(g, c)] = X[c];
-  __syncthreads();
-  // G-point DFTs over the rows; frequency g + G b lands in X[b]
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-    const int c = g + G * j;
-    V y[G];
-#pragma unroll
-    for (int a_ = 0; a_ < G; ++a_) y[a_] = sm[zr_at<P>(a_, c)];
-    rdft<G, -1, V>(y);
-#pragma unroll
-    for (int d = 0; d < G; ++d) X[j + M * d] = y[d];
-  }
-  __syncthreads();
-  // 3x3 product with the kernel spectrum: publish this component, read the other two
-#pragma unroll
-  for (int b = 0; b < P; ++b) sm[zr_at<P>(g, b)] = X[b];
-  __syncthreads();
-  {
-    const int c1 = comp == 0 ? 1 : 0, c2 = comp == 2 ? 1 : 2;  // the other two components
-    const V *s1 = s + (c1 * a.tw + col) * n, *s2 = s + (c2 * a.tw + col) * n;
-    const int k_own = comp_index(comp, comp), k_1 = comp_index(comp, c1), k_2 = comp_index(comp, c2);
-    const long long rec0 = ((long long)oy * (a.nx + 1) + (ok ? ox : 0)) * (a.nz + 1);
-    constexpr int KB = 4;
-#pragma unroll
-    for (int b0 = 0; b0 < P; b0 += KB) {
-      V K0[KB], K1[KB], K2[KB];
+    const int nval = min(a.tw, a.nx + 1 - tx * a.tw);  // >= 1: tx * tw <= nx
+    const long long slab = (long long)nval * (a.nz + 1) * 6;
+    const V *src = khat + ((long long)oy * (a.nx + 1) + (long long)tx * a.tw) * (a.nz + 1) * 6;
+    constexpr int KB = 16;
+    for (long long e0 = threadIdx.x; e0 < slab; e0 += (long long)KB * blockDim.x) {
+      V t[KB];
 #pragma unroll
       for (int i = 0; i < KB; ++i) {
-        const int k = g + G * (b0 + i);
-        const int oz = k <= a.nz ? k : n - k;
-        const V *K = khat + (rec0 + oz) * 6;
-        K0[i] = K[k_own];
-        K1[i] = K[k_1];
-        K2[i] = K[k_2];
+        const long long e = e0 + (long long)i * blockDim.x;
+        t[i] = e < slab ? src[e] : mk<T>((T)0, (T)0);
       }
 #pragma unroll
       for (int i = 0; i < KB; ++i) {
-        const int b = b0 + i;
+        const long long e = e0 + (long long)i * blockDim.x;
+        if (e < slab) kh[e] = t[i];
+      }
+    }
+    for (int t = threadIdx.x; t < n; t += blockDim.x) stw[t] = tw[t];
+  }
+  __syncthreads();
+
+  // forward: P-point DFTs over b of the non-zero half, twiddle
+  V X[P];
+  rdft_half<P, -1, V>(x, X);
+#pragma unroll
+  for (int c = 1; c < P; ++c) X[c] = cmul(X[c], stw[g * c]);
+  // exchange (real parts, then imaginary parts) and G-point DFTs over the rows; frequency
+  // g + G b lands in X[b]
+  V Y[P];
+#pragma unroll
+  for (int c = 0; c < P; ++c) ed[zr_at<P>(g, c)] = X[c].x;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+#pragma unroll
+    for (int a_ = 0; a_ < G; ++a_) Y[j * G + a_].x = ed[zr_at<P>(a_, g + G * j)];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < P; ++c) ed[zr_at<P>(g, c)] = X[c].y;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+#pragma unroll
+    for (int a_ = 0; a_ < G; ++a_) Y[j * G + a_].y = ed[zr_at<P>(a_, g + G * j)];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    rdft<G, -1, V>(Y + j * G);
+#pragma unroll
+    for (int d = 0; d < G; ++d) X[j + M * d] = Y[j * G + d];
+  }
+
+  // 3x3 product with the kernel spectrum, in two halves of this thread's frequencies: publish
+  // this component's half, read the other two components' values and the spectrum from LDS
+  {
+    const int c1 = comp == 0 ? 1 : 0, c2 = comp == 2 ? 1 : 2;  // the other two components
+    const V *s1 = exc + (c1 * a.tw + col) * G * PH, *s2 = exc + (c2 * a.tw + col) * G * PH;
+    V *so = exc + tile * G * PH;
+    const int k_own = comp_index(comp, comp), k_1 = comp_index(comp, c1), k_2 = comp_index(comp, c2);
+    const V *kc = kh + (ok ? col : 0) * (a.nz + 1) * 6;
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < PH; ++i) so[g * PH + (i ^ (g & (PH - 1)))] = X[hf * PH + i];
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < PH; ++i) {
+        const int b = hf * PH + i;
         const int k = g + G * b;
+        const int oz = k <= a.nz ? k : n - k;
         const int mr = (mir & 3) | (k > a.nz ? 4 : 0);
-        V k0 = K0[i], k1 = K1[i], k2 = K2[i];
+        const V *K = kc + oz * 6;
+        V k0 = K[k_own], k1 = K[k_1], k2 = K[k_2];
         if (__popc(comp_odd_mask(k_own) & mr) & 1) k0 = mk<T>(-k0.x, -k0.y);
         if (__popc(comp_odd_mask(k_1) & mr) & 1) k1 = mk<T>(-k1.x, -k1.y);
         if (__popc(comp_odd_mask(k_2) & mr) & 1) k2 = mk<T>(-k2.x, -k2.y);
-        const V x1 = s1[zr_at<P>(g, b)], x2 = s2[zr_at<P>(g, b)];
-        X[b] = cadd(cadd(cmul(k0, X[b]), cmul(k1, x1)), cmul(k2, x2));
+        const int e = g * PH + (i ^ (g & (PH - 1)));
+        X[b] = cadd(cadd(cmul(k0, X[b]), cmul(k1, s1[e])), cmul(k2, s2[e]));
       }
     }
   }
-  // inverse: P-point DFTs over b (input index g + G b), twiddle, exchange
+
+  // inverse: P-point DFTs over b (input index g + G b), twiddle, exchange as above
   rdft<P, +1, V>(X);
 #pragma unroll
   for (int c = 1; c < P; ++c) X[c] = cmulcj(stw[g * c], X[c]);
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < P; ++c) sm[zr_at<P>(g, c)] = X[c];
+  for (int c = 0; c < P; ++c) ed[zr_at<P>(g, c)] = X[c].x;
   __syncthreads();
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+#pragma unroll
+    for (int a_ = 0; a_ < G; ++a_) Y[j * G + a_].x = ed[zr_at<P>(a_, g + G * j)];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < P; ++c) ed[zr_at<P>(g, c)] = X[c].y;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+#pragma unroll
+    for (int a_ = 0; a_ < G; ++a_) Y[j * G + a_].y = ed[zr_at<P>(a_, g + G * j)];
   // G-point DFTs over the rows, first half of the outputs only (rows c + P d < nz)
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     const int c = g + G * j;
-    V y[G];
-#pragma unroll
-    for (int a_ = 0; a_ < G; ++a_) y[a_] = sm[zr_at<P>(a_, c)];
-    rdft<G, +1, V>(y);
+    rdft<G, +1, V>(Y + j * G);
     if (ok) {
 #pragma unroll
-      for (int d = 0; d < G / 2; ++d) cb[(long long)(c + P * d) * a.plane] = y[d];
+      for (int d = 0; d < G / 2; ++d) cb[(long long)(c + P * d) * a.plane] = Y[j * G + d];
     }
   }
 }
