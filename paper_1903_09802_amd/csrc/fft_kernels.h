@@ -42,6 +42,8 @@ struct RowArgs {
   double scale;        // output scale of the transform
 };
 
+constexpr int kRowEpt = 8;  // elements per thread of a row tile: tw n <= 8 (tw tpc) threads
+
 template <typename T, int MODE, typename TI, typename TO, int NF>
 __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
                                                           const cplx<T> *__restrict__ tw,
@@ -55,25 +57,42 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
   const long long row0 = (long long)blockIdx.x * a.tw;
   // load: consecutive threads take consecutive elements of a row (global rows are contiguous)
   const int tot_in = a.tw * n;
-  for (int e = tid; e < tot_in; e += nt) {
-    const int c = a.nsh >= 0 ? (e >> a.nsh) : e / n;
-    const int i = e - c * n;
-    const long long row = row0 + c;
-    V val = mk<T>((T)0, (T)0);
-    if (row < a.rows && i < a.n_in) {
-      if constexpr (MODE == ROW_OP_FWD || MODE == ROW_PC_FWD) {
-        const long long vox = (row % a.vox_rows) * a.nx + i;
-        const int ci = a.cidx[vox];
-        if (ci >= 0) {
-          double2 xv = in[(row / a.vox_rows) * a.nocc + ci];
-          if (a.xscale) xv = cscale(xv, a.xscale[(row / a.rhs_rows) * kMaxM]);
-          val = to_c(xv, V{});
-        }
-      } else {
-        val = in[row * a.in_stride + i];
-      }
+  if constexpr (MODE == ROW_OP_FWD || MODE == ROW_PC_FWD) {
+    // compact input: all index-map loads of the thread first, then the value loads (at most
+    // kRowEpt elements per thread, checked at launch)
+    int cis[kRowEpt];
+#pragma unroll
+    for (int q = 0; q < kRowEpt; ++q) {
+      const int e = tid + q * nt;
+      const int c = a.nsh >= 0 ? (e >> a.nsh) : e / n;
+      const int i = e - c * n;
+      const long long row = row0 + c;
+      cis[q] = (e < tot_in && row < a.rows && i < a.n_in) ? a.cidx[(row % a.vox_rows) * a.nx + i] : -1;
     }
-    s[lrow(i, ld) + c] = val;
+#pragma unroll
+    for (int q = 0; q < kRowEpt; ++q) {
+      const int e = tid + q * nt;
+      if (e >= tot_in) continue;
+      const int c = a.nsh >= 0 ? (e >> a.nsh) : e / n;
+      const int i = e - c * n;
+      const long long row = row0 + c;
+      V val = mk<T>((T)0, (T)0);
+      if (cis[q] >= 0) {
+        double2 xv = in[(row / a.vox_rows) * a.nocc + cis[q]];
+        if (a.xscale) xv = cscale(xv, a.xscale[(row / a.rhs_rows) * kMaxM]);
+        val = to_c(xv, V{});
+      }
+      s[lrow(i, ld) + c] = val;
+    }
+  } else {
+    for (int e = tid; e < tot_in; e += nt) {
+      const int c = a.nsh >= 0 ? (e >> a.nsh) : e / n;
+      const int i = e - c * n;
+      const long long row = row0 + c;
+      V val = mk<T>((T)0, (T)0);
+      if (row < a.rows && i < a.n_in) val = in[row * a.in_stride + i];
+      s[lrow(i, ld) + c] = val;
+    }
   }
   __syncthreads();
   const Lane L = make_lane(a.tw, tpc_of(n));
@@ -295,6 +314,8 @@ inline void launch_rows(dda_problem *p, const FftPlan &pl, const TI *in, TO *out
   const long long blocks = (a.rows + a.tw - 1) / a.tw;
   const size_t lds = tile_lds<T>(pl.n, a.tw);
   const int threads = std::max(64, a.tw * tpc_of(pl.n));
+  REQUIRE((long long)a.tw * pl.n <= (long long)kRowEpt * threads, DDA_EUNSUPPORTED,
+          "row tile of %d x %d exceeds %d elements per thread", a.tw, pl.n, kRowEpt);
   KTimer t(&p->prof, p->st, name, bytes);
   with_static_n(pl.n, [&](auto nf) {
     auto fn = k_fft_rows<T, MODE, TI, TO, decltype(nf)::value>;

@@ -282,8 +282,8 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *fl
     // Trailing columns, in three barrier-separated phases so that no pivot-row value is read
     // after it has been replaced: (A) the panel's row swaps, one thread per column; (B) kRG
     // threads per column each form the NB pivot-row values (the short recurrence) and
-    // update their share of the other rows; (C) one thread per column forms them again and
-    // stores them in the pivot rows.
+    // update their share of the other rows, eight rows of loads in flight; (C) one thread
+    // per column forms them again and stores them in the pivot rows.
     __syncthreads();
     constexpr int kRG = 4;
     const int ncol = n - kb;
@@ -306,12 +306,20 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *fl
       double2 aK[NB], tv[NB];
       gj_pivot_rows<NB>(A, n, j, k0, kb, F, ipv_s, aK, tv);
       const int i0 = cgrp * rows_per, i1 = min(n, i0 + rows_per);
-      for (int i = i0; i < i1; ++i) {
-        if (i >= k0 && i < k0 + kb) continue;
-        double2 acc = A[(long long)i * n + j];
+      for (int ib = i0; ib < i1; ib += 8) {
+        double2 av[8];
 #pragma unroll
-        for (int kk = 0; kk < NB; ++kk) acc = csub(acc, cmul(F[i * NB + kk], tv[kk]));
-        A[(long long)i * n + j] = acc;
+        for (int u = 0; u < 8; ++u)
+          av[u] = ib + u < i1 ? A[(long long)(ib + u) * n + j] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = ib + u;
+          if (i >= i1 || (i >= k0 && i < k0 + kb)) continue;
+          double2 acc = av[u];
+#pragma unroll
+          for (int kk = 0; kk < NB; ++kk) acc = csub(acc, cmul(F[i * NB + kk], tv[kk]));
+          A[(long long)i * n + j] = acc;
+        }
       }
     }
     __syncthreads();
