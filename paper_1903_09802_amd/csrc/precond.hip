@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *fl
     // Trailing columns, in three barrier-separated phases so that no pivot-row value is read
     // after it has been replaced: (A) the panel's row swaps, one thread per column; (B) kRG
     // threads per column each form the NB pivot-row values (the short recurrence) and
-    // update their share of the other rows, eight rows of loads in flight; (C) one thread
+    // update their share of the other rows, sixteen rows of loads in flight; (C) one thread
     // per column forms them again and stores them in the pivot rows.
     __syncthreads();
     constexpr int kRG = 4;
@@ -306,13 +306,13 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *fl
       double2 aK[NB], tv[NB];
       gj_pivot_rows<NB>(A, n, j, k0, kb, F, ipv_s, aK, tv);
       const int i0 = cgrp * rows_per, i1 = min(n, i0 + rows_per);
-      for (int ib = i0; ib < i1; ib += 8) {
-        double2 av[8];
+      for (int ib = i0; ib < i1; ib += 16) {
+        double2 av[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < 16; ++u)
           av[u] = ib + u < i1 ? A[(long long)(ib + u) * n + j] : make_double2(0.0, 0.0);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 16; ++u) {
           const int i = ib + u;
           if (i >= i1 || (i >= k0 && i < k0 + kb)) continue;
           double2 acc = av[u];

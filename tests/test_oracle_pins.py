@@ -460,3 +460,31 @@ def test_torch_complex_gradient_convention():
     dLdx = a.imag + 2 * x   # Im(a z) = a_r y + a_i x
     dLdy = a.real + 2 * y
     assert abs(z.grad.item() - (dLdx + 1j * dLdy)) < 1e-14
+
+
+def test_bicgstab_matches_lu_and_is_exact_for_scaled_identity():
+    """BiCGStab (Sec. 4's second solver) against LU on a small DDA system, with and without
+    the 2-level preconditioner, and its one-step exactness for A = c I."""
+    from oracle import bicgstab
+    s = w.hex_prism_grid(1.0, 1.0, 6, 1.31)
+    A = system.dense_matrix(s.mask, s.eps, s.k, s.d, 0.0)
+    b = system.incident_field(s.mask, s.k, s.d, (0, 0, 1), (1, 0, 0))
+    occ = s.mask.astype(bool)
+    x_lu = np.linalg.solve(A, system.box_to_compact(b, s.mask))
+    mv = lambda x: fftmatvec.fft_matvec(x, s.mask, s.eps, s.k, s.d, 0.0)
+    ati = complex(physics.alpha_inv(1.31 ** 2, s.k * s.d, 0.0))
+    Bi = circulant.invert_blocks(circulant.two_level_blocks(s.shape, s.k, s.d, ati))
+    pc = lambda v: circulant.apply_blocks(v, s.mask, Bi)
+    its = {}
+    for name, P in (("plain", None), ("precond", pc)):
+        x, info = bicgstab.bicgstab(mv, b, precond=P, tol=1e-12, maxit=500)
+        assert info["converged"] and info["rel_residual"] <= 1e-12
+        xc = system.box_to_compact(x, s.mask)
+        assert np.abs(xc - x_lu).max() < 1e-9 * np.abs(x_lu).max()
+        assert np.all(x[:, ~occ] == 0)
+        its[name] = info["iters"]
+    assert its["precond"] < its["plain"]
+    c = 3.0 - 0.5j
+    rhs = np.arange(12, dtype=complex).reshape(3, 2, 2) + 1j
+    x, info = bicgstab.bicgstab(lambda v: c * v, rhs, tol=1e-14)
+    assert info["iters"] == 1 and np.abs(x - rhs / c).max() < 1e-14
