@@ -185,6 +185,8 @@ def main():
     ap.add_argument("--c4-precision", type=int, default=0, help="c4: 0 FP64, 1 FP32 inside FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-bicgstab", action="store_true",
+                    help="skip the preconditioned BiCGStab solve reported beside the GMRES step")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB elementwise copy kernel (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -299,6 +301,22 @@ def main():
                      converged=all(st["converged"] for st in o["stats"]),
                      cext=o["cext"].tolist())
         pp.close()
+    # preconditioned BiCGStab on the same problem (the paper's second solver, cap 4000)
+    bicg = None
+    if not args.no_bicgstab:
+        pb = Problem(mask, eps, s.k, s.d, precond=2, tol=tol, restart=30, max_rhs=nrhs,
+                     max_iter=4000, solver="bicgstab")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pb.build_preconditioner(0.0)
+        o = pb.solve(dirs, pols, return_c=False, xsec=True)
+        torch.cuda.synchronize()
+        bicg = dict(step_s=time.perf_counter() - t0, iters=[st["iters"] for st in o["stats"]],
+                    restarts=[max(0, st["cycles"] - 1) for st in o["stats"]],
+                    converged=all(st["converged"] for st in o["stats"]),
+                    rel_residual=[st["rel_residual"] for st in o["stats"]],
+                    cext=o["cext"].tolist())
+        pb.close()
     prob.close()
 
     if args.copy_probe:
@@ -322,7 +340,7 @@ def main():
                     size_parameter=s.meta.get("x"), restart=30, tol=tol),
         precond_iters=p_iters, precond_rel_residual=p_res, converged=converged,
         cext=last["cext"].tolist(), cabs=last["cabs"].tolist(), csca=last["csca"].tolist(),
-        plain=plain, matvec_ms=1000 * t_mv, matvec_GBps=matvec_gbps,
+        plain=plain, bicgstab=bicg, matvec_ms=1000 * t_mv, matvec_GBps=matvec_gbps,
         matvec_frac_hbm=matvec_gbps / HBM_PEAK_GBPS, precond_apply_ms=1000 * t_pc,
         roofline=roofline, kernels=kernel_table, cpu_baseline=cpu,
     )

@@ -76,11 +76,16 @@ typedef struct {
   double inner_tol; /* reserved (kept for layout stability); must lie in (0, 1); default 1e-4 */
   int max_refine;   /* reserved (kept for layout stability); must be >= 1; default 30 */
   int max_rhs;      /* largest nrhs accepted by dda_solve / dda_apply_*; sizes the workspace; default 1 */
+  int solver;       /* 0: restarted GMRES(restart); 1: BiCGStab (Sec. 4's second solver), right-
+                       preconditioned, restarted from the true residual when the updated one
+                       has drifted or broken down; needs precision 0 and restart >= 7 (its eight
+                       work vectors use the basis storage).  default 0 */
 } dda_options;
 
 typedef struct {
-  int iters;           /* GMRES iterations (summed over refinement steps) */
-  int cycles;          /* GMRES restart cycles */
+  int iters;           /* solver iterations: GMRES steps (summed over refinement steps), or
+                          BiCGStab iterations of two operator and two preconditioner applications */
+  int cycles;          /* GMRES restart cycles, or BiCGStab runs from a true residual */
   int refinements;     /* FP64 refinement steps = restart cycles (precision 1), else 0 */
   int converged;       /* 1 if rel_residual <= tol */
   double rel_residual; /* final true residual ||b - A x|| / ||b||, FP64 */

@@ -71,6 +71,7 @@ void dda_default_options(dda_options *opt) {
   opt->inner_tol = 1e-4;
   opt->max_refine = 30;
   opt->max_rhs = 1;
+  opt->solver = 0;
 }
 
 const char *dda_last_error(void) { return get_error(); }
@@ -99,6 +100,9 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
     REQUIRE(o.max_rhs >= 1 && o.max_rhs <= 64, DDA_EINVAL, "max_rhs must be in [1, 64]");
     REQUIRE(o.inner_tol > 0.0 && o.inner_tol < 1.0, DDA_EINVAL, "inner_tol must be in (0, 1)");
     REQUIRE(o.max_refine >= 1, DDA_EINVAL, "max_refine must be >= 1");
+    REQUIRE(o.solver == 0 || o.solver == 1, DDA_EINVAL, "solver must be 0 (GMRES) or 1 (BiCGStab)");
+    REQUIRE(o.solver == 0 || o.precision == 0, DDA_EUNSUPPORTED, "BiCGStab runs in FP64 only (precision 0)");
+    REQUIRE(o.solver == 0 || o.restart >= 7, DDA_EINVAL, "BiCGStab needs restart >= 7 (work vectors)");
     {
       FftPlan t;
       REQUIRE(factor_7smooth(nx, t) && factor_7smooth(ny, t) && factor_7smooth(nz, t),

@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <vector>
 
 #include "common.h"
 
@@ -544,12 +545,298 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
   }
 }
 
+// ----------------------------------------------------------------------------- BiCGStab
+
+// BiCGStab (the paper's second solver, Sec. 4), right-preconditioned, van der Vorst's
+// recurrence with conjugated inner products.  Per-RHS scalars live on the device in
+// bc[r * kMaxM + q]: q = 0 alpha, 1 omega, 2 beta, 3 rho, 4 breakdown flag; the dot products
+// come reduced into hraw[r * kSlots + slot].  After a breakdown (a zero denominator) the
+// rest of the iteration runs with alpha = omega = 0, which leaves x and r unchanged.
+
+// partial slots 0, 1: sum conj(a_q) b_q over n for q < nq (b1 may equal a1 for a norm)
+__global__ void __launch_bounds__(kRedThreads) k_dots2(const double2 *a0, const double2 *b0,
+                                                       const double2 *a1, const double2 *b1,
+                                                       int nq, long long n3, const int *active,
+                                                       double2 *partial, int B) {
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  __shared__ double2 sh[4 * 2];
+  double2 acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+  const long long o = (long long)r * n3;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
+       n += (long long)gridDim.x * blockDim.x) {
+    acc[0] = cadd(acc[0], cmulcj(a0[o + n], b0[o + n]));
+    if (nq > 1) acc[1] = cadd(acc[1], cmulcj(a1[o + n], b1[o + n]));
+  }
+  block_sum<2>(acc, sh);
+  if ((int)threadIdx.x < nq) partial[((long long)r * kSlots + threadIdx.x) * B + blockIdx.x] = sh[threadIdx.x];
+}
+
+// Reduce slots [0, nq) into hraw[r * kSlots + slot].
+__global__ void k_finalize_n(const double2 *partial, int B, double2 *out, const int *active) {
+  const int r = blockIdx.y, slot = blockIdx.x;
+  if (!active[r]) return;
+  __shared__ double2 sh[kRedThreads];
+  const double2 v = ordered_sum(partial + ((long long)r * kSlots + slot) * B, B, sh);
+  if (threadIdx.x == 0) out[r * kSlots + slot] = v;
+}
+
+// Scalar updates, one thread per RHS.  stage 0: beta from rho_new = (rhat, r) (hraw slot 1);
+// stage 1: alpha = rho / (rhat, v) (slot 0); stage 2: omega = (t, s) / (t, t) (slots 0, 1).
+__global__ void k_bcg_scalars(int stage, const double2 *hraw, double2 *bc, const int *active,
+                              int nrhs) {
+  const int r = threadIdx.x;
+  if (r >= nrhs || !active[r]) return;
+  double2 *c = bc + r * kMaxM;
+  const double2 *h = hraw + r * kSlots;
+  const double2 zero = make_double2(0.0, 0.0);
+  if (stage > 0 && c[4].x != 0.0) {  // broken down earlier in this iteration
+    c[stage == 1 ? 0 : 1] = zero;
+    return;
+  }
+  if (stage == 0) {
+    const double2 rho_new = h[1];
+    if (rho_new.x == 0.0 && rho_new.y == 0.0) {
+      c[4] = make_double2(1.0, 0.0);
+      c[2] = zero;
+      return;
+    }
+    c[2] = cmul(cdiv(rho_new, c[3]), cdiv(c[0], c[1]));
+    c[3] = rho_new;
+  } else if (stage == 1) {
+    const double2 den = h[0];
+    if (den.x == 0.0 && den.y == 0.0) {
+      c[4] = make_double2(1.0, 0.0);
+      c[0] = zero;
+      return;
+    }
+    c[0] = cdiv(c[3], den);
+  } else {
+    const double2 ts = h[0], tt = h[1];
+    c[1] = (tt.x == 0.0 && tt.y == 0.0) ? zero : cdiv(ts, tt);
+  }
+}
+
+// p = r + beta (p - omega v)
+__global__ void k_bcg_p(const double2 *rr, double2 *pp, const double2 *v, const double2 *bc,
+                        long long n3, const int *active) {
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  const double2 beta = bc[r * kMaxM + 2], omega = bc[r * kMaxM + 1];
+  const long long o = (long long)r * n3;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
+       n += (long long)gridDim.x * blockDim.x)
+    pp[o + n] = cadd(rr[o + n], cmul(beta, csub(pp[o + n], cmul(omega, v[o + n]))));
+}
+
+// s = r - alpha v
+__global__ void k_bcg_s(const double2 *rr, const double2 *v, double2 *s, const double2 *bc,
+                        long long n3, const int *active) {
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  const double2 alpha = bc[r * kMaxM + 0];
+  const long long o = (long long)r * n3;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
+       n += (long long)gridDim.x * blockDim.x)
+    s[o + n] = csub(rr[o + n], cmul(alpha, v[o + n]));
+}
+
+// x += alpha ph + omega sh; r = s - omega t; partial slot 0: ||r||^2, slot 1: (rhat, r)
+__global__ void __launch_bounds__(kRedThreads) k_bcg_xr(double2 *x, const double2 *ph,
+                                                        const double2 *shv, const double2 *s,
+                                                        const double2 *t, double2 *rr,
+                                                        const double2 *rh, const double2 *bc,
+                                                        long long n3, const int *active,
+                                                        double2 *partial, int B) {
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  __shared__ double2 sh[4 * 2];
+  const double2 alpha = bc[r * kMaxM + 0], omega = bc[r * kMaxM + 1];
+  const long long o = (long long)r * n3;
+  double2 acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
+       n += (long long)gridDim.x * blockDim.x) {
+    x[o + n] = cadd(x[o + n], cadd(cmul(alpha, ph[o + n]), cmul(omega, shv[o + n])));
+    const double2 rn = csub(s[o + n], cmul(omega, t[o + n]));
+    rr[o + n] = rn;
+    acc[0].x += rn.x * rn.x + rn.y * rn.y;
+    acc[1] = cadd(acc[1], cmulcj(rh[o + n], rn));
+  }
+  block_sum<2>(acc, sh);
+  if ((int)threadIdx.x < 2) partial[((long long)r * kSlots + threadIdx.x) * B + blockIdx.x] = sh[threadIdx.x];
+}
+
+// Start of a BiCGStab run: rhat = r, p = v = 0, alpha = omega = rho = 1, hraw slot 1 = ||r||^2
+// (= (rhat, r)), breakdown flag cleared.
+__global__ void k_bcg_init(const double2 *rr, double2 *rh, double2 *pp, double2 *v, long long n3,
+                           const int *active) {
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  const long long o = (long long)r * n3;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
+       n += (long long)gridDim.x * blockDim.x) {
+    rh[o + n] = rr[o + n];
+    pp[o + n] = make_double2(0.0, 0.0);
+    v[o + n] = make_double2(0.0, 0.0);
+  }
+}
+
+__global__ void k_bcg_init_scalars(double2 *hraw, double2 *bc, const int *active, int nrhs) {
+  const int r = threadIdx.x;
+  if (r >= nrhs || !active[r]) return;
+  hraw[r * kSlots + 1] = hraw[r * kSlots + 0];
+  double2 *c = bc + r * kMaxM;
+  c[0] = c[1] = c[3] = make_double2(1.0, 0.0);
+  c[2] = make_double2(0.0, 0.0);
+  c[4] = make_double2(0.0, 0.0);
+}
+
+void bicgstab_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, double tol, int maxit,
+                    dda_stats *st) {
+  const long long n3 = 3 * p->nocc;
+  REQUIRE(p->opt.restart >= 7, DDA_EINVAL, "BiCGStab needs restart >= 7 (work vectors)");
+  Kry K{p, nrhs, reduce_blocks(n3), p->opt.restart, n3, reinterpret_cast<double2 *>(p->partial),
+        p->dflag + 4, p->dflag + 4 + p->R};
+  const bool prec = p->opt.precond == 2;
+  const long long blk = (long long)p->R * n3;  // one basis block holds [R][n3]
+  double2 *rr = p->V, *rh = p->V + blk, *pp = p->V + 2 * blk, *v = p->V + 3 * blk;
+  double2 *s = p->V + 4 * blk, *t = p->V + 5 * blk, *ph = p->V + 6 * blk, *shv = p->V + 7 * blk;
+  double2 *bc = p->ycoef;  // [R][kMaxM] complex: the first 5 per RHS hold the scalars
+  const dim3 grid = grid_r(K.B, nrhs);
+  std::vector<int> all(nrhs, 1), act(nrhs, 0), conv(nrhs, 0), iters(nrhs, 0), runs(nrhs, 0);
+  std::vector<int> stuck(nrhs, 0);  // a run broke down before its first step: give up
+  std::vector<double> bn2, rn2, rel(nrhs, 0.0);
+  sync_active(p, K.d_active, all);
+  norm2_dev(K, b, n3, p->hcol2);
+  read_scalars(p, p->hcol2, nrhs, bn2);
+  std::vector<double2> hb((size_t)nrhs * kSlots), cb((size_t)nrhs * kMaxM);
+  while (true) {
+    // true residual r = b - A x for every RHS (FP64)
+    sync_active(p, K.d_active, all);
+    apply_operator(p, nrhs, x, p->work, 0, nullptr);
+    {
+      KTimer tm(&p->prof, p->st, "kry_residual", 48.0 * n3 * nrhs);
+      hipLaunchKernelGGL(k_axpby, grid, dim3(kRedThreads), 0, p->st, b, p->work, -1.0, rr, n3, n3,
+                         nullptr, K.partial, K.B);
+    }
+    finalize(K, 1, p->hcol2, nullptr, nullptr);
+    read_scalars(p, p->hcol2, nrhs, rn2);
+    bool any = false;
+    for (int r = 0; r < nrhs; ++r) {
+      rel[r] = bn2[r] > 0 ? std::sqrt(rn2[r] / bn2[r]) : 0.0;
+      REQUIRE(std::isfinite(rel[r]), DDA_EDEVICE, "non-finite residual for right-hand side %d", r);
+      conv[r] = rel[r] <= tol || bn2[r] == 0.0;
+      act[r] = !conv[r] && iters[r] < maxit && !stuck[r];
+      if (act[r]) { ++runs[r]; any = true; }
+    }
+    if (verbose())
+      for (int r = 0; r < nrhs; ++r)
+        fprintf(stderr, "[dda] bicgstab rhs %d run %d iters %d true rel residual %.3e (tol %.1e)\n",
+                r, runs[r], iters[r], rel[r], tol);
+    if (!any) break;
+    sync_active(p, K.d_active, act);
+    // hraw slot 0 = ||r||^2 for the active RHS, then rhat = r, p = v = 0, scalars
+    {
+      KTimer tm(&p->prof, p->st, "kry_norm", 16.0 * n3 * nrhs);
+      hipLaunchKernelGGL(k_dots2, grid, dim3(kRedThreads), 0, p->st, rr, rr, rr, rr, 1, n3,
+                         K.d_active, K.partial, K.B);
+    }
+    hipLaunchKernelGGL(k_finalize_n, dim3(1, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
+                       p->hraw, K.d_active);
+    hipLaunchKernelGGL(k_bcg_init, grid, dim3(kRedThreads), 0, p->st, rr, rh, pp, v, n3, K.d_active);
+    hipLaunchKernelGGL(k_bcg_init_scalars, dim3(1), dim3(64), 0, p->st, p->hraw, bc, K.d_active, nrhs);
+    HIPCHK(hipGetLastError());
+    const std::vector<int> run_start(iters), in_run(act);
+    while (true) {
+      bool left = false;
+      for (int r = 0; r < nrhs; ++r) left = left || act[r];
+      if (!left) break;
+      hipLaunchKernelGGL(k_bcg_scalars, dim3(1), dim3(64), 0, p->st, 0, p->hraw, bc, K.d_active, nrhs);
+      {
+        KTimer tm(&p->prof, p->st, "bcg_p", 16.0 * n3 * 4 * nrhs);
+        hipLaunchKernelGGL(k_bcg_p, grid, dim3(kRedThreads), 0, p->st, rr, pp, v, bc, n3, K.d_active);
+      }
+      if (prec) {
+        apply_precond(p, nrhs, pp, ph, 0, nullptr);
+        apply_operator(p, nrhs, ph, v, 0, nullptr);
+      } else {
+        apply_operator(p, nrhs, pp, v, 0, nullptr);
+      }
+      {
+        KTimer tm(&p->prof, p->st, "bcg_dots", 16.0 * n3 * 2 * nrhs);
+        hipLaunchKernelGGL(k_dots2, grid, dim3(kRedThreads), 0, p->st, rh, v, rh, v, 1, n3,
+                           K.d_active, K.partial, K.B);
+      }
+      hipLaunchKernelGGL(k_finalize_n, dim3(1, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
+                         p->hraw, K.d_active);
+      hipLaunchKernelGGL(k_bcg_scalars, dim3(1), dim3(64), 0, p->st, 1, p->hraw, bc, K.d_active, nrhs);
+      {
+        KTimer tm(&p->prof, p->st, "bcg_s", 16.0 * n3 * 3 * nrhs);
+        hipLaunchKernelGGL(k_bcg_s, grid, dim3(kRedThreads), 0, p->st, rr, v, s, bc, n3, K.d_active);
+      }
+      if (prec) {
+        apply_precond(p, nrhs, s, shv, 0, nullptr);
+        apply_operator(p, nrhs, shv, t, 0, nullptr);
+      } else {
+        apply_operator(p, nrhs, s, t, 0, nullptr);
+      }
+      {
+        KTimer tm(&p->prof, p->st, "bcg_dots", 16.0 * n3 * 2 * nrhs);
+        hipLaunchKernelGGL(k_dots2, grid, dim3(kRedThreads), 0, p->st, t, s, t, t, 2, n3,
+                           K.d_active, K.partial, K.B);
+      }
+      hipLaunchKernelGGL(k_finalize_n, dim3(2, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
+                         p->hraw, K.d_active);
+      hipLaunchKernelGGL(k_bcg_scalars, dim3(1), dim3(64), 0, p->st, 2, p->hraw, bc, K.d_active, nrhs);
+      {
+        KTimer tm(&p->prof, p->st, "bcg_xr", 16.0 * n3 * 8 * nrhs);
+        hipLaunchKernelGGL(k_bcg_xr, grid, dim3(kRedThreads), 0, p->st, x, prec ? ph : pp,
+                           prec ? shv : s, s, t, rr, rh, bc, n3, K.d_active, K.partial, K.B);
+      }
+      hipLaunchKernelGGL(k_finalize_n, dim3(2, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
+                         p->hraw, K.d_active);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(hb.data(), p->hraw, sizeof(double2) * kSlots * nrhs, hipMemcpyDeviceToHost,
+                            p->st));
+      HIPCHK(hipMemcpyAsync(cb.data(), bc, sizeof(double2) * kMaxM * nrhs, hipMemcpyDeviceToHost, p->st));
+      HIPCHK(hipStreamSynchronize(p->st));
+      for (int r = 0; r < nrhs; ++r) {
+        if (!act[r]) continue;
+        // a breakdown left x and r unchanged: it ends the run and is not counted as a step
+        const bool brk = cb[r * kMaxM + 4].x != 0.0;
+        if (brk) {
+          act[r] = 0;
+          continue;
+        }
+        iters[r] += 1;
+        const double est = bn2[r] > 0 ? std::sqrt(hb[r * kSlots].x / bn2[r]) : 0.0;
+        REQUIRE(std::isfinite(est), DDA_EDEVICE, "non-finite residual estimate (RHS %d)", r);
+        const double2 om = cb[r * kMaxM + 1];
+        // stop this run at the updated tolerance, omega = 0 or the cap
+        if (est <= tol || (om.x == 0.0 && om.y == 0.0) || iters[r] >= maxit) act[r] = 0;
+      }
+      sync_active(p, K.d_active, act);
+    }
+    for (int r = 0; r < nrhs; ++r)
+      if (in_run[r] && iters[r] == run_start[r]) stuck[r] = 1;
+  }
+  for (int r = 0; r < nrhs; ++r) {
+    st[r].iters += iters[r];
+    st[r].cycles += runs[r];
+    st[r].rel_residual = rel[r];
+    st[r].converged = conv[r];
+  }
+}
+
 dda_status solve_system(dda_problem *p, int nrhs, const double2 *b, double2 *x, dda_stats *st) {
   for (int r = 0; r < nrhs; ++r) st[r] = dda_stats{0, 0, 0, 0, 0.0, 0.0};
   // precision 1: each GMRES(m) cycle applies the operator and the preconditioner in FP32 to an
   // FP64 basis, and each restart recomputes b - A x in FP64 (one refinement step per cycle)
   const int fp32 = p->opt.precision == 1 ? 1 : 0;
-  gmres_solve(p, nrhs, b, x, fp32, p->opt.tol, p->opt.max_iter, st);
+  if (p->opt.solver == 1)
+    bicgstab_solve(p, nrhs, b, x, p->opt.tol, p->opt.max_iter, st);
+  else
+    gmres_solve(p, nrhs, b, x, fp32, p->opt.tol, p->opt.max_iter, st);
   if (fp32)
     for (int r = 0; r < nrhs; ++r) st[r].refinements = st[r].cycles;
   bool ok = true;

@@ -36,7 +36,7 @@ class Options(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
-                ("max_rhs", ctypes.c_int)]
+                ("max_rhs", ctypes.c_int), ("solver", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -128,7 +128,8 @@ class Problem:
     """One voxelised scatterer on the GPU (handle of ``dda_create``)."""
 
     def __init__(self, mask, eps, k: float, d: float, *, restart=30, max_iter=2000, tol=1e-5,
-                 precond=2, precision=0, inner_tol=1e-4, max_refine=30, max_rhs=1, stream=None):
+                 precond=2, precision=0, inner_tol=1e-4, max_refine=30, max_rhs=1, solver="gmres",
+                 stream=None):
         import torch
         L = load()
         self.mask = mask.to(device="cuda", dtype=torch.uint8).contiguous()
@@ -140,6 +141,10 @@ class Problem:
         o.restart, o.max_iter, o.tol = restart, max_iter, tol
         o.precond, o.precision, o.inner_tol = precond, precision, inner_tol
         o.max_refine, o.max_rhs = max_refine, max_rhs
+        solvers = {"gmres": 0, "bicgstab": 1}
+        if solver not in solvers:
+            raise ValueError(f"solver must be one of {sorted(solvers)}")
+        o.solver = solvers[solver]
         self.opts = o
         self.stream = torch.cuda.current_stream() if stream is None else stream
         h = ctypes.c_void_p()

@@ -39,6 +39,23 @@ def test_default_options(lib):
     o = dda.default_options()
     assert (o.restart, o.max_iter, o.tol, o.precond, o.precision, o.max_rhs) == (30, 2000, 1e-5, 2, 0, 1)
     assert abs(o.inner_tol - 1e-4) < 1e-18 and o.max_refine == 30
+    assert o.solver == 0
+
+
+@pytest.mark.parametrize("solver,precision,restart,status", [
+    (2, 0, 30, -1),   # unknown solver
+    (1, 1, 30, -5),   # BiCGStab has no FP32 mode
+    (1, 0, 5, -1),    # BiCGStab's work vectors need restart >= 7
+])
+def test_create_rejects_bad_solver_options(lib, solver, precision, restart, status):
+    from paper_1903_09802_amd import dda
+    o = dda.default_options()
+    o.solver, o.precision, o.restart = solver, precision, restart
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: option validation fails first
+    st = lib.dda_create(4, 4, 4, dummy, dummy, 1.0, 0.1, ctypes.byref(o), None, ctypes.byref(h))
+    assert st == status
+    assert h.value is None
 
 
 @pytest.mark.parametrize("dims,k,d,status", [
