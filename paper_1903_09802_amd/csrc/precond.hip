@@ -16,9 +16,10 @@
 // even nz, S B_sigma is complex symmetric (S = diag(1, 1, -1) per component: the kernel
 // blocks are symmetric in (a, b) up to the x / y parities, and the z reflection maps xz and
 // yz onto their negatives), so its inverse Y = B_sigma^{-1} S is symmetric and only its lower
-// triangle is stored, as 16 x 16 tiles; the application is B_sigma^{-1} v = Y (S v).  For
-// odd nz the middle z plane breaks that symmetry and the full halves are stored
-// column-major.
+// triangle is stored, as 16 x 16 tiles; the application is B_sigma^{-1} v = Y (S v), a dense
+// product of Y with the 8 complex columns of a mode (its up to 4 sign copies x 2 right-hand
+// sides), run on the matrix cores.  For odd nz the middle z plane breaks that symmetry and
+// the full halves are stored column-major.
 #include <algorithm>
 #include <cmath>
 
@@ -373,9 +374,10 @@ __global__ void k_to_f32(const double2 *in, float2 *out, long long n) {
 
 static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// Element (r, c) of a 16 x 16 tile sits at r + 16 (c / 4) + 64 (c % 4): lane l = r + 16 q of
-// a wave reads the tile with four 1 KB loads l + 64 k and receives row r, columns 4q .. 4q+3.
-__host__ __device__ __forceinline__ int tile_pos(int r, int c) { return r + 16 * (c >> 2) + 64 * (c & 3); }
+// Element (r, c) of a 16 x 16 tile sits at r + 16 (c % 4) + 64 (c / 4): lane l = r + 16 q of
+// a wave reads the tile with four 1 KB loads l + 64 k and receives row r, column 4 k + q, which
+// is the A operand of the k-th 16 x 16 x 4 matrix instruction over the tile's columns.
+__host__ __device__ __forceinline__ int tile_pos(int r, int c) { return r + 16 * (c & 3) + 64 * (c >> 2); }
 
 // Pack the lower-triangle tiles (I >= J, tile t = I (I + 1) / 2 + J) of `cnt` symmetric
 // row-major n2 x n2 matrices into out + m0 * tiles * 256; entries beyond n2 are zero.
@@ -391,11 +393,11 @@ __global__ void k_pack_sym(const double2 *Y, TO *out, long long m0, int n2, int 
     while ((long long)I * (I + 1) / 2 > t) --I;
     while ((long long)(I + 1) * (I + 2) / 2 <= t) ++I;
     const int J = (int)(t - (long long)I * (I + 1) / 2);
-    // invert tile_pos: w = r + 16 q + 64 k, column 4 q + k
-    const int r = w & 15, q = (w >> 4) & 3, k = w >> 6;
-    const int row = 16 * I + r, col = 16 * J + 4 * q + k;
+    // invert tile_pos: w = r + 16 (c % 4) + 64 (c / 4)
+    const int r = w & 15, c = 4 * (w >> 6) + ((w >> 4) & 3);
+    const int row = 16 * I + r, col = 16 * J + c;
     const double2 v = (row < n2 && col < n2) ? Ym[(long long)row * n2 + col] : make_double2(0.0, 0.0);
-    o[t * 256 + tile_pos(r, 4 * q + k)] = to_c(v, TO{});
+    o[t * 256 + w] = to_c(v, TO{});
   }
 }
 
@@ -607,22 +609,40 @@ __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__re
   }
 }
 
-// Symmetric variant (even nz): one workgroup per (unique mode, chunk of rc right-hand
-// sides).  Gather, sign flips and fold as above, with the z components negated (the S of
-// Y = B^{-1} S).  Wave w computes tile rows I = w, w + NW, ... of both halves at once: lane
-// l = r + 16 q accumulates row 16 I + r over columns 4q .. 4q+3 of every tile of the row,
-// reading the stored lower tiles (I, J <= I) directly and the tiles (J > I, I) transposed,
-// so each stored tile feeds two waves and no partial sums cross waves; JB tiles of each half
-// are loaded before they are used.  Two shuffles sum the four column quarters; the even- and
-// odd-half rows are unfolded and written from registers.
-template <typename T, int NV>
-__global__ void __launch_bounds__(768) k_pc_gemv_sym(cplx<T> *W, const cplx<T> *__restrict__ pk,
-                                                     int nx, int ny, int nz, int umx, int hh,
-                                                     int n2, int ntr, int nrhs, int rc,
-                                                     long long nchunks, long long U) {
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of D held in item m of a lane of k-slot q (column = lane % 16)
+  static __device__ __forceinline__ int row(int q, int m) { return q + 4 * m; }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int m) { return 4 * q + m; }
+};
+
+// Symmetric block product on the matrix cores (even nz).  One workgroup per (unique mode,
+// chunk of rc <= 2 right-hand sides): the up to 4 mode copies x rc vectors form an n2 x 8
+// complex block U per half, and Y U is computed as the real product [Re Y | Im Y] x
+// [[Re U, Im U], [-Im U, Re U]] (n2 x 2 n2 times 2 n2 x 16), with 16 x 16 x 4 MFMAs.  Wave w
+// computes tile rows I = w, w + NW, ...; step s pairs row I with J = (s - I) mod ntr, taking the
+// stored tile (I, J) directly or (J, I) transposed, so the two rows that share a stored tile
+// read it in the same step.  Tiles are fetched three steps ahead of their use.
+template <typename T, int NWMAX>
+__global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const cplx<T> *__restrict__ pk,
+                                                             int nx, int ny, int nz, int umx, int hh,
+                                                             int n2, int ntr, int nrhs, int rc,
+                                                             long long nchunks, long long U) {
   using V = cplx<T>;
+  using v4 = typename Mfma<T>::v4;
+  constexpr int NV = 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  V *Ub = reinterpret_cast<V *>(smem_raw);  // [2][nv][n2p]
+  V *Ub = reinterpret_cast<V *>(smem_raw);  // [2][NV][n2p], zero beyond nv and n2
   const int tid = threadIdx.x, nt = blockDim.x;
   const long long blk = xcd_remap(blockIdx.x, U * nchunks);
   if (blk >= U * nchunks) return;
@@ -638,100 +658,101 @@ __global__ void __launch_bounds__(768) k_pc_gemv_sym(cplx<T> *W, const cplx<T> *
   const int n2p = 16 * ntr;
   const long long plane = (long long)nx * ny;
   const int h = nz / 2;
-  // gather, flip, fold, S
-  for (int e = tid; e < nv * n2p; e += nt) {
-    const int vi = e / n2p;
-    const int row = e - vi * n2p;
-    V f0 = mk<T>((T)0, (T)0), f1 = f0;
-    if (row < n2) {
-      const int a = row / hh, iz = row - a * hh;
-      const int mode = vi / nr, r = r0 + vi % nr;
+  // gather, flip, fold, S; GB elements per thread are loaded before any is stored
+  constexpr int GB = 4;
+  const int ne = NV * n2p;
+  for (int e0 = 0; e0 < ne; e0 += GB * nt) {
+    V v1[GB], v2[GB];
+#pragma unroll
+    for (int g = 0; g < GB; ++g) {
+      const int e = e0 + g * nt + tid;
+      const int vi = e / n2p, row = e - (e / n2p) * n2p;
+      v1[g] = v2[g] = mk<T>((T)0, (T)0);
+      if (e < ne && row < n2 && vi < nv) {
+        const int a = row / hh, iz = row - a * hh;
+        const int mode = vi / nr, r = r0 + vi % nr;
+        const int fx = mode % nmx, fy = mode / nmx;
+        const long long off = (long long)mys[fy] * nx + mxs[fx];
+        const long long cb = ((long long)r * 3 + a) * nz;
+        v1[g] = W[(cb + iz) * plane + off];
+        v2[g] = W[(cb + (nz - 1 - iz)) * plane + off];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < GB; ++g) {
+      const int e = e0 + g * nt + tid;
+      if (e >= ne) continue;
+      const int vi = e / n2p, row = e - (e / n2p) * n2p;
+      const int a = row < n2 ? row / hh : 0;
+      const int mode = vi / nr;
       const int fx = mode % nmx, fy = mode / nmx;
-      const long long off = (long long)mys[fy] * nx + mxs[fx];
       const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
       const T sa = a == 2 ? (T)-1 : (T)1;
-      const long long cb = ((long long)r * 3 + a) * nz;
-      const V v1 = W[(cb + iz) * plane + off];
-      const V v2 = W[(cb + (nz - 1 - iz)) * plane + off];
-      f0 = cscale(cadd(v1, cscale(v2, sa)), (T)0.5 * flip * sa);
-      f1 = cscale(csub(v1, cscale(v2, sa)), (T)0.5 * flip * sa);
+      Ub[vi * n2p + row] = cscale(cadd(v1[g], cscale(v2[g], sa)), (T)0.5 * flip * sa);
+      Ub[(NV + vi) * n2p + row] = cscale(csub(v1[g], cscale(v2[g], sa)), (T)0.5 * flip * sa);
     }
-    Ub[vi * n2p + row] = f0;
-    Ub[(nv + vi) * n2p + row] = f1;
   }
   __syncthreads();
   const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-  const int r = lane & 15, q = lane >> 4;
+  const int r = lane & 15, q = lane >> 4;  // A: row r, k-slot q; B and D: column r
+  const int vj = r & 7;
+  const bool im = r >= 8;
   const long long tiles = (long long)ntr * (ntr + 1) / 2;
-  const V *P0 = pk + (u * 2 + 0) * tiles * 256, *P1 = pk + (u * 2 + 1) * tiles * 256;
-  const V *U0 = Ub, *U1 = Ub + nv * n2p;
-  constexpr int JB = 1;  // tiles per half loaded ahead of their use (more waves pay better)
   for (int I = wv; I < ntr; I += nw) {
-    V acc0[NV], acc1[NV];
+    v4 c[2];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      acc0[v] = mk<T>((T)0, (T)0);
-      acc1[v] = mk<T>((T)0, (T)0);
-    }
-    // cyclic order J = (t - I) mod ntr: the waves of rows I and J read the shared tile in the
-    // same step t, so its second use hits in cache
-    for (int J0 = 0; J0 < ntr; J0 += JB) {
-      V x0[JB][4], x1[JB][4];
-#pragma unroll
-      for (int jb = 0; jb < JB; ++jb) {
-        if (J0 + jb >= ntr) continue;
-        const int J = (J0 + jb + ntr - I % ntr) % ntr;
-        // stored tile (I, J) read directly, or (J, I) read transposed: element (4q + k, r)
+    for (int hf = 0; hf < 2; ++hf) {
+      const V *P = pk + (u * 2 + hf) * tiles * 256;
+      const V *Uh = Ub + (hf * NV + vj) * n2p + q;
+      v4 acc = {0, 0, 0, 0};
+      auto fetch = [&](int s, V (&a)[4]) {
+        const int J = (s + ntr - I) % ntr;
         const long long t = J <= I ? (long long)I * (I + 1) / 2 + J : (long long)J * (J + 1) / 2 + I;
 #pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] = P[t * 256 + (J <= I ? lane + 64 * k : tile_pos(4 * k + q, r))];
+      };
+      auto mac = [&](int s, const V (&a)[4]) {
+        const int J = (s + ntr - I) % ntr;
+        V x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = Uh[16 * J + 4 * k];
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const int e = J <= I ? lane + 64 * k : tile_pos(4 * q + k, r);
-          x0[jb][k] = P0[t * 256 + e];
-          x1[jb][k] = P1[t * 256 + e];
+          acc = Mfma<T>::mma(a[k].x, im ? x[k].y : x[k].x, acc);
+          acc = Mfma<T>::mma(a[k].y, im ? x[k].x : -x[k].y, acc);
+        }
+      };
+      V buf[4][4];
+      fetch(0, buf[0]);
+      if (1 < ntr) fetch(1, buf[1]);
+      if (2 < ntr) fetch(2, buf[2]);
+      for (int s = 0; s < ntr; s += 4) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if (s + b + 3 < ntr) fetch(s + b + 3, buf[(b + 3) & 3]);
+          if (s + b < ntr) mac(s + b, buf[b]);
         }
       }
-#pragma unroll
-      for (int jb = 0; jb < JB; ++jb) {
-        if (J0 + jb >= ntr) continue;
-        const int J = (J0 + jb + ntr - I % ntr) % ntr;
-        const V *u0 = U0 + 16 * J + 4 * q, *u1 = U1 + 16 * J + 4 * q;
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-          if (v < nv)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              acc0[v] = cmac(acc0[v], x0[jb][k], u0[v * n2p + k]);
-              acc1[v] = cmac(acc1[v], x1[jb][k], u1[v * n2p + k]);
-            }
-      }
+      c[hf] = acc;
     }
+    // D[i][j] sits in column lane j, item m, row Mfma<T>::row(q, m): lane j < 8 holds Re of
+    // vector j, lane j + 8 its Im.  Unfold the halves, flip, scatter.
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      acc0[v].x += __shfl_xor(acc0[v].x, 16, 64);
-      acc0[v].y += __shfl_xor(acc0[v].y, 16, 64);
-      acc0[v].x += __shfl_xor(acc0[v].x, 32, 64);
-      acc0[v].y += __shfl_xor(acc0[v].y, 32, 64);
-      acc1[v].x += __shfl_xor(acc1[v].x, 16, 64);
-      acc1[v].y += __shfl_xor(acc1[v].y, 16, 64);
-      acc1[v].x += __shfl_xor(acc1[v].x, 32, 64);
-      acc1[v].y += __shfl_xor(acc1[v].y, 32, 64);
-    }
-    // unfold + flip + scatter: row i = (a, iz); the four quarter lanes share the vectors
-    const int i = 16 * I + r;
-    if (i < n2) {
+    for (int m = 0; m < 4; ++m) {
+      const T e0 = c[0][m], e1 = c[1][m];
+      const T o0 = __shfl_xor(e0, 8, 64), o1 = __shfl_xor(e1, 8, 64);
+      const int i = 16 * I + Mfma<T>::row(q, m);
+      if (im || vj >= nv || i >= n2) continue;
+      const V y0 = mk<T>(e0, o0), y1 = mk<T>(e1, o1);
       const int a = i / hh, iz = i - a * hh;
       const T sa = a == 2 ? (T)-1 : (T)1;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        if (v >= nv || (v & 3) != q) continue;
-        const int mode = v / nr, rr = r0 + v % nr;
-        const int fx = mode % nmx, fy = mode / nmx;
-        const long long off = (long long)mys[fy] * nx + mxs[fx];
-        const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
-        const long long cb = ((long long)rr * 3 + a) * nz;
-        W[(cb + iz) * plane + off] = cscale(cadd(acc0[v], acc1[v]), flip);
-        if (iz < h) W[(cb + (nz - 1 - iz)) * plane + off] = cscale(csub(acc0[v], acc1[v]), sa * flip);
-      }
+      const int mode = vj / nr, rr = r0 + vj % nr;
+      const int fx = mode % nmx, fy = mode / nmx;
+      const long long off = (long long)mys[fy] * nx + mxs[fx];
+      const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
+      const long long cb = ((long long)rr * 3 + a) * nz;
+      W[(cb + iz) * plane + off] = cscale(cadd(y0, y1), flip);
+      if (iz < h) W[(cb + (nz - 1 - iz)) * plane + off] = cscale(csub(y0, y1), sa * flip);
     }
   }
 }
@@ -771,27 +792,20 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
     const long long U = (long long)p->umx * p->umy;
     snprintf(nm, sizeof nm, "pc_gemv_%s", suf);
     if (p->psym) {
-      // right-hand sides per workgroup: 4 mode copies x rc vectors <= 8
+      // right-hand sides per workgroup: 4 mode copies x rc vectors <= 8 columns of U
       const int rc = std::max(1, std::min(2, nrhs));
       const long long nchunks = (nrhs + rc - 1) / rc;
       const int n2p = 16 * p->ntr;
-      const size_t lds = (size_t)2 * 4 * rc * n2p * sizeof(cplx<T>);
+      const size_t lds = (size_t)2 * 8 * n2p * sizeof(cplx<T>);
       const long long tiles = (long long)p->ntr * (p->ntr + 1) / 2;
       const double bytes = (double)U * 2.0 * tiles * 256 * sz * nchunks + 2.0 * rows * nx * sz;
       const int threads = 64 * std::min(12, p->ntr);  // one wave per tile row up to 12 rows
       const dim3 grid((unsigned)xcd_grid(U * nchunks));
       KTimer t(&p->prof, p->st, nm, bytes);
-      if (rc == 1) {
-        auto fn = k_pc_gemv_sym<T, 4>;
-        set_lds_limit((const void *)fn, lds);
-        hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->umx, p->hh,
-                           p->n2, p->ntr, nrhs, rc, nchunks, U);
-      } else {
-        auto fn = k_pc_gemv_sym<T, 8>;
-        set_lds_limit((const void *)fn, lds);
-        hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->umx, p->hh,
-                           p->n2, p->ntr, nrhs, rc, nchunks, U);
-      }
+      auto fn = k_pc_gemv_mfma<T, 12>;
+      set_lds_limit((const void *)fn, lds);
+      hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->umx, p->hh,
+                         p->n2, p->ntr, nrhs, rc, nchunks, U);
       HIPCHK(hipGetLastError());
     } else {
     // right-hand sides per workgroup: up to 4 mode copies x rc vectors <= 16, LDS <= 64 KB
