@@ -178,11 +178,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "plates"])
     ap.add_argument("--c3-case", type=int, default=0, help="c3: 0 -> m = 1.31+0.001i, 1 -> m = 1.78")
     ap.add_argument("--c4-prisms", type=int, default=16)
     ap.add_argument("--c4-chunk", type=int, default=32, help="c4: right-hand sides per batched solve")
     ap.add_argument("--c4-precision", type=int, default=0, help="c4: 0 FP64, 1 FP32 inside FP64 refinement")
+    ap.add_argument("--plates", default="0.1:1.2",
+                    help="plates: 'all', or L/a[:mu[:x,x,...]] (e.g. 0.1, 0.2:1.4, 0.1:2.0:10,20)")
+    ap.add_argument("--plates-plain", action="store_true",
+                    help="plates: also run the unpreconditioned solvers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-bicgstab", action="store_true",
@@ -208,6 +212,8 @@ def main():
         return bench_c4(args)
     if args.workload == "c5":
         return bench_c5(args)
+    if args.workload == "plates":
+        return bench_plates(args)
     cfg, desc = workload(args.workload)
     s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
     nrhs = len(dirs)
@@ -463,6 +469,91 @@ def bench_c5(args):
                grad_norm=float(torch.linalg.vector_norm(g).item()), dtype="f64", data="synthetic",
                config=dict(workload="hex prism x=10 aspect 1, 64^3 grid, eps = 1.7161(1+U[-0.05,0.05])",
                            grid=list(s.shape), n_occupied=int(s.n_occ))))
+
+
+PAPER_TABLES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                            "paper_tables_3_4.txt")
+
+
+def paper_tables():
+    """{(l_over_a, mu, x): row} from the transcription of the paper's Tables 3 and 4."""
+    keys = ("total", "plain_gmres_its", "plain_gmres_s", "plain_bicg_its", "plain_bicg_s",
+            "build_s", "prec_gmres_its", "prec_gmres_s", "prec_bicg_its", "prec_bicg_s")
+    out = {}
+    for ln in open(PAPER_TABLES):
+        f = ln.split()
+        if not f or f[0].startswith("#"):
+            continue
+        vals = [v if v in ("nc", "oom") else float(v) for v in f[3:13]]
+        out[(float(f[0]), float(f[1]), int(f[2]))] = dict(zip(keys, vals), table=f[13])
+    return out
+
+
+def _plate_cases(spec):
+    import workloads as w
+    tab = paper_tables()
+    if spec == "all":
+        return sorted(tab)
+    parts = spec.split(":")
+    la = float(parts[0])
+    mus = [float(parts[1])] if len(parts) > 1 else list(w.PLATE_MU)
+    xs = [int(v) for v in parts[2].split(",")] if len(parts) > 2 else list(w.PLATE_X)
+    return [(la, mu, x) for mu in mus for x in xs if (la, mu, x) in tab]
+
+
+def bench_plates(args):
+    """The paper's Sec. 4 plate sweep: preconditioned (and optionally plain) GMRES(30) and
+    BiCGStab to 1e-5 per case, one JSON line each, beside the paper's Tables 3-4 entries."""
+    import torch
+
+    import workloads as w
+    from paper_1903_09802_amd.dda import DDAError, Problem
+
+    tab = paper_tables()
+    for la, mu, x in _plate_cases(args.plates):
+        cfg = w.plate_case(la, mu, x)
+        s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
+        line = dict(workload="plates", l_over_a=la, mu=mu, x=x, grid=list(s.shape),
+                    fit_grid=list(s.meta["fit_shape"]), total_voxels=int(s.meta["fit_total"]),
+                    n_occupied=int(s.n_occ), paper=tab[(la, mu, x)])
+        if max(s.shape) > 512:
+            line["skipped"] = "grid dimension above 512"
+            _emit(line)
+            continue
+        mask = torch.from_numpy(s.mask).cuda()
+        eps = torch.from_numpy(s.eps).cuda()
+        runs = [("prec", 2)] + ([("plain", 0)] if args.plates_plain else [])
+        try:
+            for tag, pc in runs:
+                res = {}
+                for solver, cap in (("gmres", 2000), ("bicgstab", 4000)):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    prob = Problem(mask, eps, s.k, s.d, precond=pc, tol=cfg["tol"], restart=30,
+                                   max_iter=cap, solver=solver)
+                    try:
+                        torch.cuda.synchronize()
+                        t1 = time.perf_counter()
+                        if pc:
+                            prob.build_preconditioner(0.0)
+                        torch.cuda.synchronize()
+                        t2 = time.perf_counter()
+                        o = prob.solve(dirs, pols, return_c=False, xsec=True)
+                        torch.cuda.synchronize()
+                        t3 = time.perf_counter()
+                    finally:
+                        prob.close()
+                    st = o["stats"][0]
+                    res[solver] = dict(its=st["iters"], converged=bool(st["converged"]),
+                                       rel_residual=st["rel_residual"], setup_s=t1 - t0,
+                                       build_s=(t2 - t1) if pc else None, solve_s=t3 - t2,
+                                       cext=float(o["cext"][0]))
+                line[tag] = res
+        except DDAError as e:
+            line["error"] = str(e)
+        del mask, eps
+        torch.cuda.empty_cache()
+        _emit(line)
 
 
 if __name__ == "__main__":

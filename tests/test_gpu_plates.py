@@ -1,0 +1,54 @@
+"""The paper's Sec. 4 plate on the GPU: a thin, non-cubic grid (nz = 2) solved by both
+Krylov methods, against dense LU, with iteration counts beside Table 3's."""
+
+import os
+
+import numpy as np
+import pytest
+
+import workloads as w
+from gpu_helpers import make_problem, rel_err
+from oracle import physics, system
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _paper_row(la, mu, x):
+    for ln in open(os.path.join(GOLDEN, "paper_tables_3_4.txt")):
+        f = ln.split()
+        if f and not f[0].startswith("#") and (float(f[0]), float(f[1]), int(f[2])) == (la, mu, x):
+            return f
+    raise KeyError((la, mu, x))
+
+
+def test_plate_x10_both_solvers_vs_dense_lu():
+    c = w.plate_case(0.1, 1.2, 10)
+    s, dirs, pols = c["scatterer"], c["dirs"], c["pols"]
+    A = system.dense_matrix(s.mask, s.eps, s.k, s.d, physics.lattice_S(dirs[0], pols[0]))
+    b = system.incident_field(s.mask, s.k, s.d, dirs[0], pols[0])
+    cref = system.compact_to_box(np.linalg.solve(A, system.box_to_compact(b, s.mask)), s.mask)
+    row = _paper_row(0.1, 1.2, 10)
+    paper = {("gmres", 0): int(row[4]), ("bicgstab", 0): int(row[6]),
+             ("gmres", 2): int(row[9]), ("bicgstab", 2): int(row[11])}
+    its = {}
+    for solver in ("gmres", "bicgstab"):
+        for precond in (0, 2):
+            with make_problem(s, precond=precond, tol=1e-10, solver=solver, max_iter=4000) as prob:
+                if precond:
+                    prob.build_preconditioner(0.0)
+                out = prob.solve(dirs, pols)
+            assert out["stats"][0]["converged"] == 1
+            assert rel_err(out["c"][0].cpu().numpy(), cref) < 1e-8, (solver, precond)
+            with make_problem(s, precond=precond, tol=1e-5, solver=solver, max_iter=4000) as prob:
+                if precond:
+                    prob.build_preconditioner(0.0)
+                st = prob.solve(dirs, pols, return_c=False)["stats"][0]
+            assert st["converged"] == 1 and st["rel_residual"] <= 1e-5
+            its[(solver, precond)] = st["iters"]
+    print("iterations (ours, paper):", {k: (its[k], paper[k]) for k in its})
+    # same order of magnitude as the paper's (left-preconditioned, full GMRES) counts
+    for k in its:
+        assert its[k] <= 2 * paper[k] + 2, (k, its[k], paper[k])
+    assert its[("gmres", 2)] <= its[("gmres", 0)]

@@ -1,0 +1,55 @@
+"""The paper's Sec. 4 plate workload: geometry padding and the transcription of Tables 3-4."""
+
+import os
+
+import numpy as np
+import pytest
+
+import workloads as w
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    return [ln.split() for ln in open(os.path.join(GOLDEN, name)) if ln.strip() and not ln.startswith("#")]
+
+
+def test_tables_transcription_consistent_with_voxel_counts():
+    """Every row of Tables 3-4 is present once, with the same total voxel count as the
+    separate voxel-count fixture, and the markers are only nc / oom."""
+    counts = {(r[0], r[1], r[2]): r[3] for r in _rows("paper_voxel_counts.txt")}
+    tab = _rows("paper_tables_3_4.txt")
+    keys = [(r[0], r[1], r[2]) for r in tab]
+    assert len(keys) == len(set(keys)) == len(counts)
+    for r in tab:
+        assert len(r) == 14
+        assert counts[(r[0], r[1], r[2])] == r[3]
+        for v in r[4:13]:
+            assert v in ("nc", "oom") or float(v) > 0
+        assert r[13] == ("T3" if r[0] == "0.1" else "T4")
+        # the preconditioned GMRES never needs more iterations than the plain one
+        if r[4] not in ("nc", "oom") and r[9] not in ("nc", "oom"):
+            assert float(r[9]) <= float(r[4])
+
+
+def test_smooth7():
+    assert [w.smooth7(n) for n in (1, 11, 13, 17, 19, 23, 331, 382, 509, 512)] == \
+        [1, 12, 14, 18, 20, 24, 336, 384, 512, 512]
+
+
+@pytest.mark.parametrize("la,mu,x", [(0.1, 1.2, 10), (0.1, 2.0, 20), (0.2, 1.4, 10), (0.2, 1.8, 20)])
+def test_plate_case_pads_with_air_only(la, mu, x):
+    c = w.plate_case(la, mu, x)
+    s = c["scatterer"]
+    f = w.hex_prism_fit(float(x), la, mu)
+    nz, ny, nx = f.mask.shape
+    assert s.meta["fit_shape"] == (nz, ny, nx)
+    for n_fit, n in zip((nz, ny, nx), s.shape):
+        assert n == w.smooth7(n_fit) and n_fit <= n < 1.1 * n_fit + 2
+    assert np.array_equal(s.mask[:nz, :ny, :nx], f.mask)
+    assert s.mask.sum() == f.mask.sum()
+    pad = np.ones(s.shape, dtype=bool)
+    pad[:nz, :ny, :nx] = False
+    assert not s.mask[pad].any() and np.all(s.eps[pad] == 1.0)
+    assert np.allclose(s.eps[s.mask.astype(bool)], mu * mu)
+    assert s.k == x and np.allclose(c["dirs"], [[1, 0, 0]]) and np.allclose(c["pols"], [[0, 0, 1]])

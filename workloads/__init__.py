@@ -28,4 +28,8 @@ from .configs import (  # noqa: F401
     config_c4,
     config_c5,
     config_c5_dense,
+    plate_case,
+    smooth7,
+    PLATE_MU,
+    PLATE_X,
 )

@@ -12,13 +12,17 @@ extent spans it).  Refractive index 1.31 is ice in the visible; eps = m^2.
 * c5: x = 10, aspect 1, 64^3, eps_j = 1.7161 (1 + delta_j), delta_j ~ U[-0.05, 0.05]
   from ``default_rng(9802)`` over occupied voxels in C order; dense check grid
   12^3 at the same k d (x = 1.875).
+* plates: the paper's Sec. 4 experiment, hexagonal plates L/a = 0.1, 0.2 with
+  mu = 1.2 ... 2 and x = 10 ... 100 at lambda / (mu d) = 10, lit by (0, 0, 1) e^{ikx};
+  each box is the fitted grid grown at its high ends to the next 2-3-5-7-smooth size
+  (air voxels only), since the FFT lengths are 2 n per axis.
 """
 
 from __future__ import annotations
 
 import numpy as np
 
-from .geometry import hex_prism_grid
+from .geometry import Scatterer, hex_prism_fit, hex_prism_grid
 from .incidence import plane_wave_z, random_directions
 
 C4_GRIDS = (32, 40, 48, 56, 64, 72, 80, 96)
@@ -85,3 +89,37 @@ def config_c5_dense():
     s = _jitter_eps(hex_prism_grid(1.875, 1.0, 12, 1.31, name="c5_hex12"), 9802)
     dirs, pols = plane_wave_z(("x",))
     return dict(name="c5_dense", scatterer=s, dirs=dirs, pols=pols, tol=1e-10, restart=30)
+
+
+PLATE_MU = (1.2, 1.4, 1.6, 1.8, 2.0)
+PLATE_X = (10, 20, 30, 40, 60, 80, 100)
+
+
+def smooth7(n: int) -> int:
+    """Smallest m >= n whose only prime factors are 2, 3, 5 and 7."""
+    m = max(1, int(n))
+    while True:
+        k = m
+        for f in (2, 3, 5, 7):
+            while k % f == 0:
+                k //= f
+        if k == 1:
+            return m
+        m += 1
+
+
+def plate_case(l_over_a: float, mu: float, x: float):
+    """One plate of the Sec. 4 sweep: the fitted voxelisation, zero-padded (air) at the high
+    end of each axis to 7-smooth dimensions, and the incident wave (0, 0, 1) e^{ikx}."""
+    f = hex_prism_fit(float(x), float(l_over_a), float(mu))
+    nz, ny, nx = f.mask.shape
+    pz, py, px = smooth7(nz), smooth7(ny), smooth7(nx)
+    mask = np.zeros((pz, py, px), dtype=np.uint8)
+    eps = np.ones((pz, py, px), dtype=np.complex128)
+    mask[:nz, :ny, :nx] = f.mask
+    eps[:nz, :ny, :nx] = f.eps
+    meta = dict(f.meta, fit_shape=(nz, ny, nx), fit_total=nz * ny * nx)
+    s = Scatterer(f"plate_la{l_over_a}_mu{mu}_x{x}", mask, eps, k=f.k, d=f.d, meta=meta)
+    dirs = np.array([[1.0, 0.0, 0.0]])
+    pols = np.array([[0.0, 0.0, 1.0]])
+    return dict(name="plate", scatterer=s, dirs=dirs, pols=pols, tol=1e-5, restart=30)
