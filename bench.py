@@ -187,6 +187,11 @@ def main():
                     help="plates: 'all', or L/a[:mu[:x,x,...]] (e.g. 0.1, 0.2:1.4, 0.1:2.0:10,20)")
     ap.add_argument("--plates-plain", action="store_true",
                     help="plates: also run the unpreconditioned solvers")
+    ap.add_argument("--plates-plain-max-x", type=float, default=1e9,
+                    help="plates: run the unpreconditioned solvers only up to this size parameter")
+    ap.add_argument("--plates-restart", type=int, default=255,
+                    help="plates: GMRES restart length (255 keeps the whole Krylov space up to 255 "
+                         "iterations, the paper's unrestarted GMRES)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-bicgstab", action="store_true",
@@ -502,7 +507,7 @@ def _plate_cases(spec):
 
 
 def bench_plates(args):
-    """The paper's Sec. 4 plate sweep: preconditioned (and optionally plain) GMRES(30) and
+    """The paper's Sec. 4 plate sweep: preconditioned (and optionally plain) GMRES(m) and
     BiCGStab to 1e-5 per case, one JSON line each, beside the paper's Tables 3-4 entries."""
     import torch
 
@@ -513,7 +518,8 @@ def bench_plates(args):
     for la, mu, x in _plate_cases(args.plates):
         cfg = w.plate_case(la, mu, x)
         s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
-        line = dict(workload="plates", l_over_a=la, mu=mu, x=x, grid=list(s.shape),
+        line = dict(workload="plates", l_over_a=la, mu=mu, x=x, restart=args.plates_restart,
+                    grid=list(s.shape),
                     fit_grid=list(s.meta["fit_shape"]), total_voxels=int(s.meta["fit_total"]),
                     n_occupied=int(s.n_occ), paper=tab[(la, mu, x)])
         if max(s.shape) > 512:
@@ -522,14 +528,16 @@ def bench_plates(args):
             continue
         mask = torch.from_numpy(s.mask).cuda()
         eps = torch.from_numpy(s.eps).cuda()
-        runs = [("prec", 2)] + ([("plain", 0)] if args.plates_plain else [])
+        plain = args.plates_plain and x <= args.plates_plain_max_x
+        runs = [("prec", 2)] + ([("plain", 0)] if plain else [])
         try:
             for tag, pc in runs:
                 res = {}
                 for solver, cap in (("gmres", 2000), ("bicgstab", 4000)):
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
-                    prob = Problem(mask, eps, s.k, s.d, precond=pc, tol=cfg["tol"], restart=30,
+                    prob = Problem(mask, eps, s.k, s.d, precond=pc, tol=cfg["tol"],
+                                   restart=args.plates_restart if solver == "gmres" else 30,
                                    max_iter=cap, solver=solver)
                     try:
                         torch.cuda.synchronize()

@@ -161,3 +161,28 @@ def apply_dense(vbox, mask, P):
     m = mask.astype(np.float64)[None]
     z = np.linalg.solve(P, (vbox * m).ravel()).reshape(vbox.shape)
     return m * z
+
+
+def occupied_layers(mask):
+    """(z0, z1): the first and one-past-last z layer holding an occupied voxel.
+
+    The paper's grid is the smallest box around the body (Sec. 4), so its dense (z) level
+    spans exactly these layers; a box with extra air layers keeps that preconditioner."""
+    zs = np.flatnonzero(np.asarray(mask).reshape(mask.shape[0], -1).any(axis=1))
+    return int(zs[0]), int(zs[-1]) + 1
+
+
+def blocks_for_mask(mask, k: float, d: float, alpha_tilde_inv: complex):
+    """(z0, inverse blocks) of the 2-level preconditioner on the occupied layers of ``mask``."""
+    z0, z1 = occupied_layers(mask)
+    shape = (z1 - z0,) + tuple(mask.shape[1:])
+    return z0, invert_blocks(two_level_blocks(shape, k, d, alpha_tilde_inv))
+
+
+def apply_blocks_layers(vbox, mask, Binv, z0: int):
+    """z = M P^{-1} (M v) with P built on layers z0 .. z0 + bz - 1 (bz = Binv's z extent); the
+    layers outside hold only air, so they come out zero."""
+    bz = Binv.shape[-1] // 3
+    out = np.zeros_like(vbox, dtype=np.complex128)
+    out[:, z0:z0 + bz] = apply_blocks(vbox[:, z0:z0 + bz], mask[z0:z0 + bz], Binv)
+    return out

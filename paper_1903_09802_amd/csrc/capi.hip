@@ -92,7 +92,7 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
     dda_options o;
     dda_default_options(&o);
     if (opt) o = *opt;
-    REQUIRE(o.restart >= 1 && o.restart <= 31, DDA_EINVAL, "restart must be in [1, 31]");
+    REQUIRE(o.restart >= 1 && o.restart < kMaxM, DDA_EINVAL, "restart must be in [1, %d]", kMaxM - 1);
     REQUIRE(o.max_iter >= 1, DDA_EINVAL, "max_iter must be >= 1");
     REQUIRE(o.tol > 0.0, DDA_EINVAL, "tol must be > 0");
     REQUIRE(o.precond == 0 || o.precond == 2, DDA_EINVAL, "precond must be 0 or 2");

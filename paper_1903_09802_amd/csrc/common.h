@@ -54,7 +54,9 @@ template <typename V> __device__ __forceinline__ V ldc(const V *p) { return *p; 
 // work items (which share cache lines) on the same XCD; indices >= G exit at once.
 constexpr int kXcds = 8;
 // Largest Krylov basis (restart + 1 vectors); per-RHS arrays of small vectors use this stride.
-constexpr int kMaxM = 32;
+// 256 lets GMRES keep the whole Krylov space for the few hundred iterations the paper's
+// hardest converging cases need (Sec. 4), the basis being sized by the actual restart.
+constexpr int kMaxM = 256;
 __host__ __device__ __forceinline__ long long xcd_grid(long long G) {
   return ((G + kXcds - 1) / kXcds) * kXcds;
 }
@@ -251,9 +253,10 @@ struct dda_problem {
   int prec_built = 0;
   int prec_fp32 = 0;
   double2 ati{0.0, 0.0};     // alpha~^{-1}
-  int hh = 0, n2 = 0;        // ceil(nz/2), 3*hh
+  int pz0 = 0, pbz = 0;      // occupied z layers [pz0, pz0 + pbz): the dense level's extent
+  int hh = 0, n2 = 0;        // ceil(pbz/2), 3*hh
   int umx = 0, umy = 0;      // nx/2+1, ny/2+1
-  int psym = 0;              // 1 (even nz): packed symmetric tiles of (S B)^{-1}, see precond
+  int psym = 0;              // 1 (even pbz): packed symmetric tiles of (S B)^{-1}, see precond
   int ntr = 0;               // tile rows per half, ceil(n2 / 16)
   double2 *binv64 = nullptr; // psym 0: [umy][umx][2][n2][n2] column-major inverse halves;
                              // psym 1: [umy][umx][2][ntr (ntr+1) / 2][256] packed tiles

@@ -137,23 +137,39 @@ __global__ void k_finalize_dots(const double2 *partial, int B, double2 *out, con
   if (threadIdx.x == 0) out[r * kSlots + slot] = v;
 }
 
-// MGS coefficients from one reduction (per RHS, one thread each): store row j of
+// MGS coefficients from one reduction (one 64-lane block per RHS): store row j of
 // L (L_jk = v_j^H v_k, k < j, with the basis scales applied), then c = (I + L)^{-1} a by
-// forward substitution, a_i = v_i^H w.  c goes to hcol (the Hessenberg column) and
-// c_i * vsc_i to ycoef (the coefficients of the unnormalised basis in the update).
-__global__ void k_mgs_coef(int j, const double2 *raw, double2 *L, const double *vsc, double2 *hcol,
-                           double2 *ycoef, const int *active, int nrhs) {
-  const int r = threadIdx.x;
+// forward substitution, a_i = v_i^H w, each step's dot product split over the lanes.  c goes
+// to hcol (the Hessenberg column) and c_i * vsc_i to ycoef (the coefficients of the
+// unnormalised basis in the update).
+__global__ void __launch_bounds__(64) k_mgs_coef(int j, const double2 *raw, double2 *L,
+                                                 const double *vsc, double2 *hcol, double2 *ycoef,
+                                                 const int *active, int nrhs) {
+  const int r = blockIdx.x, lane = threadIdx.x;
   if (r >= nrhs || !active[r]) return;
+  __shared__ double2 c[kMaxM];
   const double *sr = vsc + r * kMaxM;
   double2 *Lr = L + (long long)r * kMaxM * kMaxM;
   const double2 *rr = raw + r * kSlots;
-  for (int k = 0; k < j; ++k) Lr[j * kMaxM + k] = cconj(cscale(rr[kMaxM + k], sr[k] * sr[j]));
+  for (int k = lane; k < j; k += 64) Lr[j * kMaxM + k] = cconj(cscale(rr[kMaxM + k], sr[k] * sr[j]));
+  __syncthreads();
   for (int i = 0; i <= j; ++i) {
-    double2 c = cscale(rr[i], sr[i]);
-    for (int k = 0; k < i; ++k) c = csub(c, cmul(Lr[i * kMaxM + k], hcol[r * kMaxM + k]));
-    hcol[r * kMaxM + i] = c;
-    ycoef[r * kMaxM + i] = cscale(c, sr[i]);
+    double re = 0.0, im = 0.0;
+    for (int k = lane; k < i; k += 64) {
+      const double2 t = cmul(Lr[i * kMaxM + k], c[k]);
+      re += t.x;
+      im += t.y;
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) {
+      const double2 a = cscale(rr[i], sr[i]);
+      const double2 ci = make_double2(a.x - re, a.y - im);
+      c[i] = ci;
+      hcol[r * kMaxM + i] = ci;
+      ycoef[r * kMaxM + i] = cscale(ci, sr[i]);
+    }
+    __syncthreads();
   }
 }
 
@@ -479,7 +495,7 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
       }
       hipLaunchKernelGGL(k_finalize_dots, dim3(2 * j + 1, nrhs), dim3(kRedThreads), 0, p->st,
                          K.partial, K.B, p->hraw, K.d_active, j);
-      hipLaunchKernelGGL(k_mgs_coef, dim3(1), dim3(64), 0, p->st, j, p->hraw, p->lmat, p->vsc,
+      hipLaunchKernelGGL(k_mgs_coef, dim3(nrhs), dim3(64), 0, p->st, j, p->hraw, p->lmat, p->vsc,
                          p->hcol, p->ycoef, K.d_active, nrhs);
       {
         KTimer t(&p->prof, p->st, "kry_multiaxpy", 16.0 * n3 * (j + 3) * nrhs);

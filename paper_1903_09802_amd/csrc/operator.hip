@@ -223,7 +223,14 @@ void build_compact_map(dda_problem *p) {
     hipLaunchKernelGGL(k_map_fill, dim3((unsigned)nb), dim3(kMapBlock), 0, p->st, p->mask, p->N,
                        base, p->cidx, p->vox);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(p->st));  // hb is host-local
+    // the first and last entries (voxel order, z slowest) bound the occupied z layers
+    int ends[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&ends[0], p->vox, sizeof(int), hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipMemcpyAsync(&ends[1], p->vox + (p->nocc - 1), sizeof(int), hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));  // hb and ends are host-local
+    const long long plane = (long long)p->nx * p->ny;
+    p->pz0 = (int)(ends[0] / plane);
+    p->pbz = (int)(ends[1] / plane) - p->pz0 + 1;
   } catch (...) {
     (void)hipFree(cnt);
     (void)hipFree(base);

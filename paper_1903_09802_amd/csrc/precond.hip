@@ -1,5 +1,9 @@
 // The 2-level circulant preconditioner (Sec. 3, 3.1): setup and application.
 //
+// The dense (z) level spans the occupied layers [pz0, pz0 + pbz) of the box, as the paper's
+// box is the smallest one around the body; below, nz stands for that extent pbz.  Layers
+// outside it hold only air, which M P^{-1} M never reads or keeps.
+//
 // Setup.  eq. Chan along x then y on the signed-offset kernel K(p, q, s) = d^3 G(p d,
 // q d, s d) gives the generator c2_ab(pbar, qbar, s) (pbar < nx, qbar < ny, |s| < nz);
 // its 2-D DFT over (pbar, qbar) gives lambda_ab(wx, wy, s).  For every Fourier mode the
@@ -413,7 +417,7 @@ void precond_free(dda_problem *p) {
 
 void precond_build(dda_problem *p, double s_bar) {
   precond_free(p);
-  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const int nx = p->nx, ny = p->ny, nz = p->pbz;  // the dense level's extent
   p->ati = ldr_alpha_inv(p->eps_mean, p->k * p->d, s_bar);
   p->hh = (nz + 1) / 2;
   p->n2 = 3 * p->hh;
@@ -514,7 +518,8 @@ void precond_build(dda_problem *p, double s_bar) {
 // in place.  Workgroups are XCD-remapped so neighbouring modes share an L2.
 template <typename T, int NV>
 __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__restrict__ binv,
-                                                 int nx, int ny, int nz, int umx, int hh, int n2,
+                                                 int nx, int ny, int nzw, int z0, int nz, int umx,
+                                                 int hh, int n2,
                                                  int nrhs, int rc, long long nchunks, long long U) {
   using V = cplx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -544,7 +549,7 @@ __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__re
     const long long off = (long long)mys[fy] * nx + mxs[fx];
     const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
     const T sa = a == 2 ? (T)-1 : (T)1;
-    const long long cb = ((long long)r * 3 + a) * nz;
+    const long long cb = ((long long)r * 3 + a) * nzw + z0;
     const V v1 = W[(cb + iz) * plane + off];
     const V v2 = W[(cb + (nz - 1 - iz)) * plane + off];
     Ub[vi * n2 + a * hh + iz] = cscale(cadd(v1, cscale(v2, sa)), (T)0.5 * flip);
@@ -601,7 +606,7 @@ __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__re
         const int fx = mode % nmx, fy = mode / nmx;
         const long long off = (long long)mys[fy] * nx + mxs[fx];
         const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
-        const long long cb = ((long long)r * 3 + a) * nz;
+        const long long cb = ((long long)r * 3 + a) * nzw + z0;
         W[(cb + iz) * plane + off] = cscale(cadd(a0[v], a1[v]), flip);
         if (iz < h) W[(cb + (nz - 1 - iz)) * plane + off] = cscale(csub(a0[v], a1[v]), sa * flip);
       }
@@ -635,7 +640,8 @@ template <> struct Mfma<float> {
 // read it in the same step.  Tiles are fetched three steps ahead of their use.
 template <typename T, int NWMAX>
 __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const cplx<T> *__restrict__ pk,
-                                                             int nx, int ny, int nz, int umx, int hh,
+                                                             int nx, int ny, int nzw, int z0, int nz,
+                                                             int umx, int hh,
                                                              int n2, int ntr, int nrhs, int rc,
                                                              long long nchunks, long long U) {
   using V = cplx<T>;
@@ -673,7 +679,7 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
         const int mode = vi / nr, r = r0 + vi % nr;
         const int fx = mode % nmx, fy = mode / nmx;
         const long long off = (long long)mys[fy] * nx + mxs[fx];
-        const long long cb = ((long long)r * 3 + a) * nz;
+        const long long cb = ((long long)r * 3 + a) * nzw + z0;
         v1[g] = W[(cb + iz) * plane + off];
         v2[g] = W[(cb + (nz - 1 - iz)) * plane + off];
       }
@@ -750,7 +756,7 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
       const int fx = mode % nmx, fy = mode / nmx;
       const long long off = (long long)mys[fy] * nx + mxs[fx];
       const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
-      const long long cb = ((long long)rr * 3 + a) * nz;
+      const long long cb = ((long long)rr * 3 + a) * nzw + z0;
       W[(cb + iz) * plane + off] = cscale(cadd(y0, y1), flip);
       if (iz < h) W[(cb + (nz - 1 - iz)) * plane + off] = cscale(csub(y0, y1), sa * flip);
     }
@@ -804,8 +810,8 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
       KTimer t(&p->prof, p->st, nm, bytes);
       auto fn = k_pc_gemv_mfma<T, 12>;
       set_lds_limit((const void *)fn, lds);
-      hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->umx, p->hh,
-                         p->n2, p->ntr, nrhs, rc, nchunks, U);
+      hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
+                         p->umx, p->hh, p->n2, p->ntr, nrhs, rc, nchunks, U);
       HIPCHK(hipGetLastError());
     } else {
     // right-hand sides per workgroup: up to 4 mode copies x rc vectors <= 16, LDS <= 64 KB
@@ -822,18 +828,18 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
     if (nvmax <= 4) {
       auto fn = k_pc_gemv<T, 4>;
       set_lds_limit((const void *)fn, lds);
-      hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->umx, p->hh,
-                         p->n2, nrhs, rc, nchunks, U);
+      hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
+                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U);
     } else if (nvmax <= 8) {
       auto fn = k_pc_gemv<T, 8>;
       set_lds_limit((const void *)fn, lds);
-      hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->umx, p->hh,
-                         p->n2, nrhs, rc, nchunks, U);
+      hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
+                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U);
     } else {
       auto fn = k_pc_gemv<T, 16>;
       set_lds_limit((const void *)fn, lds);
-      hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->umx, p->hh,
-                         p->n2, nrhs, rc, nchunks, U);
+      hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
+                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U);
     }
     HIPCHK(hipGetLastError());
     }

@@ -4,8 +4,8 @@ import numpy as np
 import pytest
 
 import workloads as w
-from gpu_helpers import make_problem, rel_err, random_waves
-from oracle import bicgstab, circulant, fftmatvec, physics, system, xsec
+from gpu_helpers import make_problem, oracle_precond, rel_err, random_waves
+from oracle import bicgstab, fftmatvec, physics, system, xsec
 
 pytestmark = pytest.mark.gpu
 
@@ -17,12 +17,7 @@ def _oracle_bicgstab(s, dvec, pvec, precond, tol):
     b = system.incident_field(s.mask, s.k, s.d, dvec, pvec)
     Kh = fftmatvec.kernel_padded_fft(s.shape, s.k, s.d)
     mv = lambda x: fftmatvec.fft_matvec(x, s.mask, s.eps, s.k, s.d, S, Khat=Kh)
-    pc = None
-    if precond:
-        occ = s.mask.astype(bool)
-        ati = complex(physics.alpha_inv(s.eps[occ].mean(), s.k * s.d, 0.0))
-        Bi = circulant.invert_blocks(circulant.two_level_blocks(s.shape, s.k, s.d, ati))
-        pc = lambda v: circulant.apply_blocks(v, s.mask, Bi)
+    pc = oracle_precond(s) if precond else None
     return bicgstab.bicgstab(mv, b, precond=pc, tol=tol, maxit=4000)
 
 

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import workloads as w
-from gpu_helpers import make_problem, rand_field, random_waves, rel_err, to_dev
+from gpu_helpers import make_problem, oracle_precond, rand_field, random_waves, rel_err, to_dev
 from oracle import circulant, fftmatvec, physics, rows, system
 
 pytestmark = pytest.mark.gpu
@@ -72,12 +72,6 @@ def test_operator_fp32_vs_oracle(shape, seed):
     assert rel_err(y[0], ref) < 1e-5
 
 
-def _oracle_blocks(s, s_bar=0.0):
-    occ = s.mask.astype(bool)
-    ati = complex(physics.alpha_inv(s.eps[occ].mean(), s.k * s.d, s_bar))
-    return circulant.invert_blocks(circulant.two_level_blocks(s.shape, s.k, s.d, ati))
-
-
 PC_CASES = [((4, 5, 6), 31), ((5, 4, 3), 32), ((7, 6, 10), 33), ((1, 3, 4), 34),
             ((16, 16, 16), 35), ((9, 8, 12), 36), ((3, 1, 1), 37), ((2, 7, 5), 38)]
 
@@ -90,16 +84,40 @@ def test_preconditioner_fp64_vs_oracle(shape, seed):
         prob.build_preconditioner(0.0)
         x = rand_field(shape, 3, seed)
         z = prob.apply_preconditioner(to_dev(x)).cpu().numpy()
-    Binv = _oracle_blocks(s)
+    pc = oracle_precond(s)
     for r in range(3):
-        ref = circulant.apply_blocks(x[r], s.mask, Binv)
+        ref = pc(x[r])
         assert rel_err(z[r], ref) < 1e-10, (shape, r)
+
+
+@pytest.mark.parametrize("shape,z0,z1,seed", [((10, 8, 12), 2, 7, 61), ((9, 6, 10), 1, 7, 62),
+                                               ((12, 16, 16), 3, 11, 63), ((7, 5, 6), 0, 5, 64)])
+def test_preconditioner_spans_occupied_layers(shape, z0, z1, seed):
+    """A box with air layers above and below the body: the dense level spans the occupied
+    layers only (even and odd extents), as for the paper's smallest box around the body."""
+    nz, ny, nx = shape
+    s = w.random_mask(nx, ny, nz, 0.7, seed, k=1.3, d=0.3, eps_jitter=0.05)
+    air = np.ones(nz, dtype=bool)
+    air[z0:z1] = False
+    s.mask[air] = 0
+    s.eps[air] = 1.0
+    assert s.mask[z0].any() and s.mask[z1 - 1].any()
+    assert circulant.occupied_layers(s.mask) == (z0, z1)
+    with make_problem(s, precond=2, max_rhs=2) as prob:
+        prob.build_preconditioner(0.0)
+        x = rand_field(shape, 2, seed)
+        z = prob.apply_preconditioner(to_dev(x)).cpu().numpy()
+    pc = oracle_precond(s)
+    for r in range(2):
+        assert rel_err(z[r], pc(x[r])) < 1e-10, (shape, r)
+        assert np.all(z[r][:, air] == 0)
 
 
 def test_preconditioner_brute_force_definition():
     """Against P built by wrapped-diagonal averaging of the full-box BTTB matrix."""
     shape = (4, 5, 6)
     s = w.random_mask(6, 5, 4, 0.8, 41, k=1.6, d=0.3)
+    assert circulant.occupied_layers(s.mask) == (0, 4)  # the dense level spans the box
     occ = s.mask.astype(bool)
     ati = complex(physics.alpha_inv(s.eps[occ].mean(), s.k * s.d, 0.25))
     P = circulant.two_level_dense(shape, s.k, s.d, ati)
@@ -119,7 +137,7 @@ def test_preconditioner_fp32_vs_oracle(shape, seed):
         prob.build_preconditioner(0.0)
         x = rand_field(shape, 1, seed)
         z = prob.apply_preconditioner(to_dev(x), fp32=True).cpu().numpy()
-    ref = circulant.apply_blocks(x[0], s.mask, _oracle_blocks(s))
+    ref = oracle_precond(s)(x[0])
     assert rel_err(z[0], ref) < 1e-5
 
 

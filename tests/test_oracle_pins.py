@@ -210,6 +210,33 @@ def test_two_level_brute_force_equals_formula(shape):
     assert np.abs(z1 - z2).max() < 1e-12 * np.abs(z1).max()
 
 
+def test_occupied_layers_preconditioner_is_the_smallest_box_one():
+    """The dense level spans the occupied z layers: for a body with air layers above and
+    below, M P^{-1} M equals the brute-force P of the smallest box around it (the paper's
+    grid), embedded with zeros; on a box the body fills, it is the plain full-box P."""
+    k, d = 1.3, 0.3
+    ati = complex(physics.alpha_inv(1.7161, k * d, 0.0))
+    rng = np.random.default_rng(11)
+    mask = np.zeros((7, 4, 5), dtype=np.uint8)
+    mask[2:5] = rng.random((3, 4, 5)) < 0.8
+    mask[2, 0, 0] = mask[4, 3, 4] = 1
+    assert circulant.occupied_layers(mask) == (2, 5)
+    v = rng.normal(size=(3, 7, 4, 5)) + 1j * rng.normal(size=(3, 7, 4, 5))
+    z0, Binv = circulant.blocks_for_mask(mask, k, d, ati)
+    z = circulant.apply_blocks_layers(v, mask, Binv, z0)
+    P = circulant.two_level_dense((3, 4, 5), k, d, ati)
+    ref = np.zeros_like(z)
+    ref[:, 2:5] = circulant.apply_dense(v[:, 2:5], mask[2:5], P)
+    assert np.abs(z - ref).max() < 1e-12 * np.abs(ref).max()
+    full = np.ones((3, 4, 5), dtype=np.uint8)
+    z0, Binv = circulant.blocks_for_mask(full, k, d, ati)
+    assert z0 == 0
+    assert np.abs(circulant.apply_blocks_layers(v[:, :3], full, Binv, 0)
+                  - circulant.apply_dense(v[:, :3], full, P)).max() < 1e-12 * np.abs(v).max()
+    plate = w.plate_case(0.1, 1.6, 40)["scatterer"]  # fitted nz = 11, box grown to 12
+    assert circulant.occupied_layers(plate.mask) == (0, plate.meta["fit_shape"][0]) == (0, 11)
+
+
 def test_two_level_block_symmetries():
     """B(-wx, wy) = Sx B Sx (and likewise for y), B(w)^T = B(-w), and B commutes
     with the z-reflection R = J_n (x) diag(1, 1, -1)."""
