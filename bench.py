@@ -189,9 +189,9 @@ def main():
                     help="plates: also run the unpreconditioned solvers")
     ap.add_argument("--plates-plain-max-x", type=float, default=1e9,
                     help="plates: run the unpreconditioned solvers only up to this size parameter")
-    ap.add_argument("--plates-restart", type=int, default=255,
-                    help="plates: GMRES restart length (255 keeps the whole Krylov space up to 255 "
-                         "iterations, the paper's unrestarted GMRES)")
+    ap.add_argument("--plates-restart", type=int, default=500,
+                    help="plates: GMRES restart length (500 keeps the whole Krylov space for every "
+                         "case the paper's unrestarted GMRES solved)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-bicgstab", action="store_true",

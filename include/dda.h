@@ -63,7 +63,7 @@ typedef enum {
 } dda_status;
 
 typedef struct {
-  int restart;      /* GMRES restart length m of GMRES(m), 1 .. 255; default 30 */
+  int restart;      /* GMRES restart length m of GMRES(m), 1 .. 1023; default 30 */
   int max_iter;     /* cap on total GMRES iterations (inner ones in refinement mode); default 2000 */
   double tol;       /* stop when ||b - A x||_2 / ||b||_2 <= tol (true residual, FP64); default 1e-5 */
   int precond;      /* 0: none; 2: 2-level circulant preconditioner (Sec. 3); default 2 */

@@ -130,6 +130,7 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
       need += 8.0 * N * 6 * 16;                          // setup transient
       need += R * 3.0 * N * 2 * 16 + R * 3.0 * nz * (4.0 * nx * ny + 64) * 16;  // w0 + w1
       need += R * (m + 1.0) * n3 * 16 + R * 5.0 * n3 * 16 + R * 16.0 * N;
+      need += R * 2.0 * kMaxM * 1024 * 16 + R * (m + 1.0) * (m + 1.0) * 16;  // reductions, Gram
       size_t freeb = 0, totb = 0;
       HIPCHK(hipMemGetInfo(&freeb, &totb));
       REQUIRE(need < 0.9 * (double)freeb, DDA_ENOMEM, "problem needs about %.2f GB, %.2f GB free",

@@ -54,9 +54,10 @@ template <typename V> __device__ __forceinline__ V ldc(const V *p) { return *p; 
 // work items (which share cache lines) on the same XCD; indices >= G exit at once.
 constexpr int kXcds = 8;
 // Largest Krylov basis (restart + 1 vectors); per-RHS arrays of small vectors use this stride.
-// 256 lets GMRES keep the whole Krylov space for the few hundred iterations the paper's
-// hardest converging cases need (Sec. 4), the basis being sized by the actual restart.
-constexpr int kMaxM = 256;
+// 1024 lets GMRES keep the whole Krylov space for the few hundred iterations the paper's
+// hardest converging cases need (Sec. 4); the basis and the Gram matrix are sized by the
+// actual restart.
+constexpr int kMaxM = 1024;
 __host__ __device__ __forceinline__ long long xcd_grid(long long G) {
   return ((G + kXcds - 1) / kXcds) * kXcds;
 }
@@ -276,7 +277,7 @@ struct dda_problem {
   double2 *ycoef = nullptr;  // [R][restart+1]
   double2 *hnrm = nullptr;   // [R][kMaxM] squared norm after the projection
   double2 *hraw = nullptr;   // [R][2 kMaxM] raw projections and Gram overlaps of one iteration
-  double2 *lmat = nullptr;   // [R][kMaxM][kMaxM] strictly lower triangle of the basis Gram matrix
+  double2 *lmat = nullptr;   // [R][m+1][m+1] strictly lower triangle of the basis Gram matrix
   double *partial = nullptr; // reduction partials
   size_t partial_elems = 0;
   double *dscal = nullptr;   // [R][16] device scalars

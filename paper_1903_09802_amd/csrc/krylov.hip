@@ -142,21 +142,21 @@ __global__ void k_finalize_dots(const double2 *partial, int B, double2 *out, con
 // forward substitution, a_i = v_i^H w, each step's dot product split over the lanes.  c goes
 // to hcol (the Hessenberg column) and c_i * vsc_i to ycoef (the coefficients of the
 // unnormalised basis in the update).
-__global__ void __launch_bounds__(64) k_mgs_coef(int j, const double2 *raw, double2 *L,
+__global__ void __launch_bounds__(64) k_mgs_coef(int j, const double2 *raw, double2 *L, int lm,
                                                  const double *vsc, double2 *hcol, double2 *ycoef,
                                                  const int *active, int nrhs) {
   const int r = blockIdx.x, lane = threadIdx.x;
   if (r >= nrhs || !active[r]) return;
   __shared__ double2 c[kMaxM];
   const double *sr = vsc + r * kMaxM;
-  double2 *Lr = L + (long long)r * kMaxM * kMaxM;
+  double2 *Lr = L + (long long)r * lm * lm;  // [lm][lm], lm = restart + 1
   const double2 *rr = raw + r * kSlots;
-  for (int k = lane; k < j; k += 64) Lr[j * kMaxM + k] = cconj(cscale(rr[kMaxM + k], sr[k] * sr[j]));
+  for (int k = lane; k < j; k += 64) Lr[j * lm + k] = cconj(cscale(rr[kMaxM + k], sr[k] * sr[j]));
   __syncthreads();
   for (int i = 0; i <= j; ++i) {
     double re = 0.0, im = 0.0;
     for (int k = lane; k < i; k += 64) {
-      const double2 t = cmul(Lr[i * kMaxM + k], c[k]);
+      const double2 t = cmul(Lr[i * lm + k], c[k]);
       re += t.x;
       im += t.y;
     }
@@ -202,7 +202,7 @@ __global__ void __launch_bounds__(kRedThreads) k_multiaxpy(const double2 *V, lon
   if (!active[r]) return;
   __shared__ double2 c[kMaxM];
   __shared__ double2 sh[4];
-  if ((int)threadIdx.x < nvec) c[threadIdx.x] = coef[r * kMaxM + threadIdx.x];
+  for (int i = threadIdx.x; i < nvec; i += blockDim.x) c[i] = coef[r * kMaxM + i];
   __syncthreads();
   double2 *wr = w + r * ws_r;
   const double2 *Vr = V + r * vs_r;
@@ -225,7 +225,7 @@ __global__ void k_combine(const double2 *V, long long vs_r, long long vs_j, int 
                           const double2 *coef, double2 *out, long long os_r, long long n3) {
   const int r = blockIdx.y;
   __shared__ double2 c[kMaxM];
-  if ((int)threadIdx.x < nvec) c[threadIdx.x] = coef[r * kMaxM + threadIdx.x];
+  for (int i = threadIdx.x; i < nvec; i += blockDim.x) c[i] = coef[r * kMaxM + i];
   __syncthreads();
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
        n += (long long)gridDim.x * blockDim.x) {
@@ -495,7 +495,7 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
       }
       hipLaunchKernelGGL(k_finalize_dots, dim3(2 * j + 1, nrhs), dim3(kRedThreads), 0, p->st,
                          K.partial, K.B, p->hraw, K.d_active, j);
-      hipLaunchKernelGGL(k_mgs_coef, dim3(nrhs), dim3(64), 0, p->st, j, p->hraw, p->lmat, p->vsc,
+      hipLaunchKernelGGL(k_mgs_coef, dim3(nrhs), dim3(64), 0, p->st, j, p->hraw, p->lmat, m + 1, p->vsc,
                          p->hcol, p->ycoef, K.d_active, nrhs);
       {
         KTimer t(&p->prof, p->st, "kry_multiaxpy", 16.0 * n3 * (j + 3) * nrhs);
@@ -725,7 +725,7 @@ void bicgstab_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, doub
   sync_active(p, K.d_active, all);
   norm2_dev(K, b, n3, p->hcol2);
   read_scalars(p, p->hcol2, nrhs, bn2);
-  std::vector<double2> hb((size_t)nrhs * kSlots), cb((size_t)nrhs * kMaxM);
+  std::vector<double2> hb((size_t)nrhs), cb((size_t)nrhs * 5);  // ||r||^2 and the 5 scalars
   while (true) {
     // true residual r = b - A x for every RHS (FP64)
     sync_active(p, K.d_active, all);
@@ -812,22 +812,23 @@ void bicgstab_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, doub
       hipLaunchKernelGGL(k_finalize_n, dim3(2, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
                          p->hraw, K.d_active);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(hb.data(), p->hraw, sizeof(double2) * kSlots * nrhs, hipMemcpyDeviceToHost,
-                            p->st));
-      HIPCHK(hipMemcpyAsync(cb.data(), bc, sizeof(double2) * kMaxM * nrhs, hipMemcpyDeviceToHost, p->st));
+      HIPCHK(hipMemcpy2DAsync(hb.data(), sizeof(double2), p->hraw, sizeof(double2) * kSlots,
+                              sizeof(double2), nrhs, hipMemcpyDeviceToHost, p->st));
+      HIPCHK(hipMemcpy2DAsync(cb.data(), sizeof(double2) * 5, bc, sizeof(double2) * kMaxM,
+                              sizeof(double2) * 5, nrhs, hipMemcpyDeviceToHost, p->st));
       HIPCHK(hipStreamSynchronize(p->st));
       for (int r = 0; r < nrhs; ++r) {
         if (!act[r]) continue;
         // a breakdown left x and r unchanged: it ends the run and is not counted as a step
-        const bool brk = cb[r * kMaxM + 4].x != 0.0;
+        const bool brk = cb[r * 5 + 4].x != 0.0;
         if (brk) {
           act[r] = 0;
           continue;
         }
         iters[r] += 1;
-        const double est = bn2[r] > 0 ? std::sqrt(hb[r * kSlots].x / bn2[r]) : 0.0;
+        const double est = bn2[r] > 0 ? std::sqrt(hb[r].x / bn2[r]) : 0.0;
         REQUIRE(std::isfinite(est), DDA_EDEVICE, "non-finite residual estimate (RHS %d)", r);
-        const double2 om = cb[r * kMaxM + 1];
+        const double2 om = cb[r * 5 + 1];
         // stop this run at the updated tolerance, omega = 0 or the cap
         if (est <= tol || (om.x == 0.0 && om.y == 0.0) || iters[r] >= maxit) act[r] = 0;
       }
@@ -878,7 +879,7 @@ void krylov_alloc(dda_problem *p) {
   HIPCHK(hipMalloc(&p->ycoef, sizeof(double2) * (size_t)R * kMaxM));
   HIPCHK(hipMalloc(&p->hnrm, sizeof(double2) * (size_t)R * kMaxM));
   HIPCHK(hipMalloc(&p->hraw, sizeof(double2) * (size_t)R * kSlots));
-  HIPCHK(hipMalloc(&p->lmat, sizeof(double2) * (size_t)R * kMaxM * kMaxM));
+  HIPCHK(hipMalloc(&p->lmat, sizeof(double2) * (size_t)R * (m + 1) * (m + 1)));
   const int B = reduce_blocks(n3);
   p->partial_elems = std::max<size_t>((size_t)R * kSlots * B * 2, (size_t)R * 512 * 4);
   HIPCHK(hipMalloc(&p->partial, sizeof(double) * p->partial_elems));

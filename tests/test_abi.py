@@ -47,7 +47,7 @@ def test_default_options(lib):
     (1, 1, 30, -5),   # BiCGStab has no FP32 mode
     (1, 0, 5, -1),    # BiCGStab's work vectors need restart >= 7
     (0, 0, 0, -1),    # GMRES(m) needs m >= 1
-    (0, 0, 256, -1),  # and at most 255 basis vectors beyond the first
+    (0, 0, 1024, -1),  # and at most 1023 basis vectors beyond the first
 ])
 def test_create_rejects_bad_solver_options(lib, solver, precision, restart, status):
     from paper_1903_09802_amd import dda
