@@ -516,9 +516,11 @@ def bench_plates(args):
 
     tab = paper_tables()
     for la, mu, x in _plate_cases(args.plates):
-        cfg = w.plate_case(la, mu, x)
+        rounding = w.plate_fit_rounding(la, mu, x, tab[(la, mu, x)]["total"])
+        cfg = w.plate_case(la, mu, x, rounding=rounding)
         s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
         line = dict(workload="plates", l_over_a=la, mu=mu, x=x, restart=args.plates_restart,
+                    rounding=rounding,
                     grid=list(s.shape),
                     fit_grid=list(s.meta["fit_shape"]), total_voxels=int(s.meta["fit_total"]),
                     n_occupied=int(s.n_occ), paper=tab[(la, mu, x)])

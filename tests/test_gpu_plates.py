@@ -24,12 +24,12 @@ def _paper_row(la, mu, x):
 
 
 def test_plate_x10_both_solvers_vs_dense_lu():
-    c = w.plate_case(0.1, 1.2, 10)
+    row = _paper_row(0.1, 1.2, 10)
+    c = w.plate_case(0.1, 1.2, 10, rounding=w.plate_fit_rounding(0.1, 1.2, 10, float(row[3])))
     s, dirs, pols = c["scatterer"], c["dirs"], c["pols"]
     A = system.dense_matrix(s.mask, s.eps, s.k, s.d, physics.lattice_S(dirs[0], pols[0]))
     b = system.incident_field(s.mask, s.k, s.d, dirs[0], pols[0])
     cref = system.compact_to_box(np.linalg.solve(A, system.box_to_compact(b, s.mask)), s.mask)
-    row = _paper_row(0.1, 1.2, 10)
     paper = {("gmres", 0): int(row[4]), ("bicgstab", 0): int(row[6]),
              ("gmres", 2): int(row[9]), ("bicgstab", 2): int(row[11])}
     its = {}

@@ -53,3 +53,20 @@ def test_plate_case_pads_with_air_only(la, mu, x):
     assert not s.mask[pad].any() and np.all(s.eps[pad] == 1.0)
     assert np.allclose(s.eps[s.mask.astype(bool)], mu * mu)
     assert s.k == x and np.allclose(c["dirs"], [[1, 0, 0]]) and np.allclose(c["pols"], [[0, 0, 1]])
+
+
+def test_plate_rounding_picks_the_paper_total():
+    """Of the two box roundings, the one closer to the printed total is used; it lands within
+    5 % of the printed total for every row of Tables 3-4."""
+    import math
+    for r in _rows("paper_tables_3_4.txt"):
+        la, mu, x, tot = float(r[0]), float(r[1]), float(r[2]), float(r[3])
+        rnd = w.plate_fit_rounding(la, mu, x, tot)
+        d = 2 * math.pi / x / (10 * mu)
+        f = math.ceil if rnd == "ceil" else (lambda v: max(1, round(v)))
+        n = 1
+        for e in (2.0, math.sqrt(3.0), la):
+            n *= max(1, f(e / d - 1e-12))
+        assert abs(n / tot - 1) <= 0.05, (r, rnd, n)
+    assert w.plate_fit_rounding(0.1, 1.6, 20, 4.5e4) == "round"
+    assert w.plate_fit_rounding(0.1, 1.2, 30, 6.9e4) == "ceil"

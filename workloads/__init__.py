@@ -29,6 +29,7 @@ from .configs import (  # noqa: F401
     config_c5,
     config_c5_dense,
     plate_case,
+    plate_fit_rounding,
     smooth7,
     PLATE_MU,
     PLATE_X,

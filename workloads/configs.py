@@ -22,7 +22,9 @@ from __future__ import annotations
 
 import numpy as np
 
-from .geometry import Scatterer, hex_prism_fit, hex_prism_grid
+import math
+
+from .geometry import SQRT3, Scatterer, hex_prism_fit, hex_prism_grid
 from .incidence import plane_wave_z, random_directions
 
 C4_GRIDS = (32, 40, 48, 56, 64, 72, 80, 96)
@@ -108,10 +110,26 @@ def smooth7(n: int) -> int:
         m += 1
 
 
-def plate_case(l_over_a: float, mu: float, x: float):
+def plate_fit_rounding(l_over_a: float, mu: float, x: float, total: float) -> str:
+    """The box rounding ("ceil" or "round") whose voxel total is closer to ``total`` (the
+    paper prints its totals to two digits and neither rule reproduces all of them)."""
+    d = 2.0 * math.pi / float(x) / (10.0 * float(mu))
+    best = None
+    for rnd in ("ceil", "round"):
+        f = math.ceil if rnd == "ceil" else (lambda v: max(1, int(round(v))))
+        n = 1
+        for e in (2.0, SQRT3, float(l_over_a)):
+            n *= max(1, f(e / d - 1e-12))
+        err = abs(n / float(total) - 1.0)
+        if best is None or err < best[0]:
+            best = (err, rnd)
+    return best[1]
+
+
+def plate_case(l_over_a: float, mu: float, x: float, rounding: str = "ceil"):
     """One plate of the Sec. 4 sweep: the fitted voxelisation, zero-padded (air) at the high
     end of each axis to 7-smooth dimensions, and the incident wave (0, 0, 1) e^{ikx}."""
-    f = hex_prism_fit(float(x), float(l_over_a), float(mu))
+    f = hex_prism_fit(float(x), float(l_over_a), float(mu), rounding=rounding)
     nz, ny, nx = f.mask.shape
     pz, py, px = smooth7(nz), smooth7(ny), smooth7(nx)
     mask = np.zeros((pz, py, px), dtype=np.uint8)
