@@ -80,6 +80,13 @@ typedef struct {
                        preconditioned, restarted from the true residual when the updated one
                        has drifted or broken down; needs precision 0 and restart >= 7 (its eight
                        work vectors use the basis storage).  default 0 */
+  int dense_axis;   /* axis (0 x, 1 y, 2 z) along which the 2-level preconditioner keeps dense
+                       blocks; the other two axes are the circulant levels.  The paper makes x
+                       and y circulant for plates and suggests the long axis of an elongated
+                       prism as a circulant level instead (Sec. 5).  The library then works in
+                       the cyclically rotated frame whose z axis is dense_axis; every buffer at
+                       this interface stays in the caller's [.][3][nz][ny][nx] layout and
+                       frame.  default 2 */
 } dda_options;
 
 typedef struct {

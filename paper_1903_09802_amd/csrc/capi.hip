@@ -57,6 +57,14 @@ void check_waves(int nrhs, const double *dir, const double *pol, std::vector<dou
   }
 }
 
+// Wave vectors (3 per wave) in the library's rotated frame.
+std::vector<double> in_frame(const dda_problem *p, int nrhs, const double *v) {
+  std::vector<double> out(3 * (size_t)nrhs);
+  for (int r = 0; r < nrhs; ++r)
+    for (int a = 0; a < 3; ++a) out[3 * r + a] = v[3 * r + p->fr.comp_ext(a)];
+  return out;
+}
+
 }  // namespace
 
 extern "C" {
@@ -72,6 +80,7 @@ void dda_default_options(dda_options *opt) {
   opt->max_refine = 30;
   opt->max_rhs = 1;
   opt->solver = 0;
+  opt->dense_axis = 2;
 }
 
 const char *dda_last_error(void) { return get_error(); }
@@ -103,6 +112,7 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
     REQUIRE(o.solver == 0 || o.solver == 1, DDA_EINVAL, "solver must be 0 (GMRES) or 1 (BiCGStab)");
     REQUIRE(o.solver == 0 || o.precision == 0, DDA_EUNSUPPORTED, "BiCGStab runs in FP64 only (precision 0)");
     REQUIRE(o.solver == 0 || o.restart >= 7, DDA_EINVAL, "BiCGStab needs restart >= 7 (work vectors)");
+    REQUIRE(o.dense_axis >= 0 && o.dense_axis <= 2, DDA_EINVAL, "dense_axis must be 0, 1 or 2");
     {
       FftPlan t;
       REQUIRE(factor_7smooth(nx, t) && factor_7smooth(ny, t) && factor_7smooth(nz, t),
@@ -111,6 +121,13 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
     }
     dda_problem *p = new dda_problem();
     try {
+      // internal frame: the cyclic rotation of the axes that puts the dense axis last
+      const int ax0 = (o.dense_axis + 1) % 3, ax1 = (o.dense_axis + 2) % 3, ax2 = o.dense_axis;
+      const int ext[3] = {nx, ny, nz};
+      p->fr = Frame{ext[ax0], ext[ax1], ext[ax2], nx, ny, ax0, ax1, ax2};
+      nx = ext[ax0];
+      ny = ext[ax1];
+      nz = ext[ax2];
       p->nx = nx; p->ny = ny; p->nz = nz;
       p->N = (long long)nx * ny * nz;
       p->k = k; p->d = d;
@@ -142,8 +159,7 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
       plan_create(p->uy, ny);
       HIPCHK(hipMalloc(&p->mask, N));
       HIPCHK(hipMalloc(&p->eps, sizeof(double2) * N));
-      HIPCHK(hipMemcpyAsync(p->mask, mask_dev, N, hipMemcpyDeviceToDevice, p->st));
-      HIPCHK(hipMemcpyAsync(p->eps, eps_dev, sizeof(double2) * N, hipMemcpyDeviceToDevice, p->st));
+      copy_to_frame(p, mask_dev, reinterpret_cast<const double2 *>(eps_dev));
       p->w0_elems = (size_t)R * 3 * nz * ny * 2 * nx;
       // z rows of the z-pass work array are padded by 64 elements: with 4 nx ny a large power
       // of two, unpadded rows alias the same HBM channels under the z-strided access
@@ -186,6 +202,9 @@ dda_status dda_solve(dda_problem *p, int nrhs, const double *dir_host, const dou
     REQUIRE(nrhs >= 1 && nrhs <= p->R, DDA_EINVAL, "nrhs must be in [1, max_rhs = %d]", p->R);
     std::vector<double> S;
     check_waves(nrhs, dir_host, pol_host, S);
+    const std::vector<double> dirs = in_frame(p, nrhs, dir_host), pols = in_frame(p, nrhs, pol_host);
+    dir_host = dirs.data();
+    pol_host = pols.data();
     REQUIRE(p->opt.precond == 0 || p->prec_built, DDA_ESTATE,
             "opt.precond = 2 but dda_build_preconditioner has not run");
     const long long n3 = 3 * p->nocc;
@@ -220,6 +239,9 @@ dda_status dda_apply_operator(dda_problem *p, int nrhs, const double *dir_host,
     REQUIRE(x_dev && y_dev && x_dev != y_dev, DDA_EINVAL, "x_dev and y_dev must be distinct buffers");
     std::vector<double> S;
     check_waves(nrhs, dir_host, pol_host, S);
+    const std::vector<double> dirs = in_frame(p, nrhs, dir_host), pols = in_frame(p, nrhs, pol_host);
+    dir_host = dirs.data();
+    pol_host = pols.data();
     setup_alpha(p, nrhs, S.data());
     // box -> compact, A on the occupied voxels, and y = x in air
     const double2 *xb = reinterpret_cast<const double2 *>(x_dev);
@@ -252,6 +274,9 @@ dda_status dda_cross_sections(dda_problem *p, int nrhs, const double *dir_host,
     REQUIRE(c_dev, DDA_EINVAL, "c_dev is required");
     std::vector<double> S;
     check_waves(nrhs, dir_host, pol_host, S);
+    const std::vector<double> dirs = in_frame(p, nrhs, dir_host), pols = in_frame(p, nrhs, pol_host);
+    dir_host = dirs.data();
+    pol_host = pols.data();
     setup_alpha(p, nrhs, S.data());
     to_compact(p, nrhs, reinterpret_cast<const double2 *>(c_dev), p->bvec);
     cross_sections(p, nrhs, dir_host, pol_host, p->bvec, cext, cabs, csca);
@@ -270,6 +295,9 @@ dda_status dda_grad_cext(dda_problem *p, const double *dir_host, const double *p
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<double> S;
     check_waves(1, dir_host, pol_host, S);
+    const std::vector<double> dirs = in_frame(p, 1, dir_host), pols = in_frame(p, 1, pol_host);
+    dir_host = dirs.data();
+    pol_host = pols.data();
     const long long n3 = 3 * p->nocc;
     double2 *cfwd = nullptr;
     HIPCHK(hipMalloc(&cfwd, sizeof(double2) * n3));

@@ -210,8 +210,38 @@ struct KTimer {
 
 // ----------------------------------------------------------------------------- problem handle
 
+// The library's frame: internal axis k (0 x', 1 y', 2 z') is the caller's axis ax[k], a
+// cyclic rotation that puts the preconditioner's dense axis last; vector components rotate
+// with the axes (internal component a is the caller's component ax[a]).  e* are the caller's
+// dimensions, n* the internal ones (n_k = e_{ax[k]}).
+struct Frame {
+  int nx, ny, nz;
+  int ex, ey;
+  int ax0, ax1, ax2;
+  // caller's voxel index of internal voxel v
+  __host__ __device__ __forceinline__ long long to_ext(long long v) const {
+    const long long i0 = v % nx, i1 = (v / nx) % ny, i2 = v / ((long long)nx * ny);
+    const long long e0 = ax0 == 0 ? i0 : ax1 == 0 ? i1 : i2;
+    const long long e1 = ax0 == 1 ? i0 : ax1 == 1 ? i1 : i2;
+    const long long e2 = ax0 == 2 ? i0 : ax1 == 2 ? i1 : i2;
+    return e0 + ex * (e1 + (long long)ey * e2);
+  }
+  // internal voxel index of the caller's voxel e
+  __host__ __device__ __forceinline__ long long to_int(long long e) const {
+    const long long e0 = e % ex, e1 = (e / ex) % ey, e2 = e / ((long long)ex * ey);
+    const long long i0 = ax0 == 0 ? e0 : ax0 == 1 ? e1 : e2;
+    const long long i1 = ax1 == 0 ? e0 : ax1 == 1 ? e1 : e2;
+    const long long i2 = ax2 == 0 ? e0 : ax2 == 1 ? e1 : e2;
+    return i0 + nx * (i1 + (long long)ny * i2);
+  }
+  // caller's component of internal component a, and the inverse
+  __host__ __device__ __forceinline__ int comp_ext(int a) const { return a == 0 ? ax0 : a == 1 ? ax1 : ax2; }
+  __host__ __device__ __forceinline__ int comp_int(int e) const { return ax0 == e ? 0 : ax1 == e ? 1 : 2; }
+};
+
 struct dda_problem {
   int nx = 0, ny = 0, nz = 0;
+  Frame fr{};            // internal <-> caller's frame (identity for dense_axis 2)
   long long N = 0;       // voxels in the box
   long long n_occ = 0;   // occupied voxels
   double k = 0.0, d = 0.0;
@@ -305,6 +335,7 @@ void operator_spectrum_setup(dda_problem *p);
 // Box [nrhs][3][N] <-> compact [nrhs][3][nocc]; to_box fills air from `fill` (or zeros).
 void to_compact(dda_problem *p, int nrhs, const double2 *box, double2 *comp);
 void to_box(dda_problem *p, int nrhs, const double2 *comp, const double2 *fill, double2 *box);
+void copy_to_frame(dda_problem *p, const uint8_t *mask, const double2 *eps);
 void setup_alpha(dda_problem *p, int nrhs, const double *S_host);
 void setup_rhs(dda_problem *p, int nrhs, const double *dir, const double *pol, double2 *b,
                int conjugate);

@@ -240,34 +240,54 @@ void build_compact_map(dda_problem *p) {
   HIPCHK(hipFree(base));
 }
 
-// Box <-> compact: gather out[r][a][c] = in[r][a][vox[c]]; scatter out[r][a][v] =
-// in[r][a][cidx[v]] on occupied voxels and, in air, fill[r][a][v] (or 0 without fill).
-__global__ void k_gather(const double2 *in, const int *vox, long long N, long long nocc,
+// Caller's box <-> compact, through the frame rotation: gather out[r][a][c] =
+// in[r][a'][vox'[c]] (a' the caller's component of a, vox' the caller's voxel of entry c);
+// scatter, over the caller's voxels e, out[r][a][e] = in[r][a_int][cidx[v(e)]] on occupied
+// voxels and, in air, fill[r][a][e] (or 0 without fill).
+__global__ void k_gather(const double2 *in, const int *vox, long long N, long long nocc, Frame fr,
                          double2 *out) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long ra = blockIdx.y;
+  const int r = blockIdx.y / 3, a = blockIdx.y % 3;
   if (c >= nocc) return;
-  out[ra * nocc + c] = in[ra * N + vox[c]];
+  out[(long long)blockIdx.y * nocc + c] = in[((long long)r * 3 + fr.comp_ext(a)) * N + fr.to_ext(vox[c])];
 }
 
-__global__ void k_scatter(const double2 *in, const int *cidx, long long N, long long nocc,
+__global__ void k_scatter(const double2 *in, const int *cidx, long long N, long long nocc, Frame fr,
                           const double2 *fill, double2 *out) {
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long ra = blockIdx.y;
-  if (v >= N) return;
-  const int c = cidx[v];
-  out[ra * N + v] = c >= 0 ? in[ra * nocc + c] : (fill ? fill[ra * N + v] : make_double2(0.0, 0.0));
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y / 3, a = blockIdx.y % 3;
+  if (e >= N) return;
+  const int c = cidx[fr.to_int(e)];
+  const long long o = (long long)blockIdx.y * N + e;
+  out[o] = c >= 0 ? in[((long long)r * 3 + fr.comp_int(a)) * nocc + c]
+                  : (fill ? fill[o] : make_double2(0.0, 0.0));
 }
 
 void to_compact(dda_problem *p, int nrhs, const double2 *box, double2 *comp) {
   hipLaunchKernelGGL(k_gather, dim3(nblk(p->nocc, 256), 3 * nrhs), dim3(256), 0, p->st, box, p->vox,
-                     p->N, p->nocc, comp);
+                     p->N, p->nocc, p->fr, comp);
   HIPCHK(hipGetLastError());
 }
 
 void to_box(dda_problem *p, int nrhs, const double2 *comp, const double2 *fill, double2 *box) {
   hipLaunchKernelGGL(k_scatter, dim3(nblk(p->N, 256), 3 * nrhs), dim3(256), 0, p->st, comp, p->cidx,
-                     p->N, p->nocc, fill, box);
+                     p->N, p->nocc, p->fr, fill, box);
+  HIPCHK(hipGetLastError());
+}
+
+// Internal copies of the caller's mask and permittivity in the rotated frame.
+__global__ void k_to_frame(const uint8_t *mask, const double2 *eps, long long N, Frame fr,
+                           uint8_t *mask_out, double2 *eps_out) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const long long e = fr.to_ext(v);
+  mask_out[v] = mask[e];
+  eps_out[v] = eps[e];
+}
+
+void copy_to_frame(dda_problem *p, const uint8_t *mask, const double2 *eps) {
+  hipLaunchKernelGGL(k_to_frame, dim3(nblk(p->N, 256)), dim3(256), 0, p->st, mask, eps, p->N, p->fr,
+                     p->mask, p->eps);
   HIPCHK(hipGetLastError());
 }
 

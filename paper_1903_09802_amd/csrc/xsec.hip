@@ -89,15 +89,16 @@ void cross_sections(dda_problem *p, int nrhs, const double *dir, const double *p
   }
 }
 
-// c, lam compact [3][nocc]; grad per voxel [N], zero in air.
+// c, lam compact [3][nocc]; grad per voxel [N] in the caller's layout, zero in air.
 __global__ void k_grad(const double2 *c, const double2 *lam, const double2 *eps, const int *cidx,
-                       long long N, long long nocc, double kd, double S, double pref,
+                       long long N, long long nocc, Frame fr, double kd, double S, double pref,
                        double2 *grad) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   const int q = cidx[v];
+  const long long ve = fr.to_ext(v);
   if (q < 0) {
-    grad[v] = make_double2(0.0, 0.0);
+    grad[ve] = make_double2(0.0, 0.0);
     return;
   }
   double2 acc = make_double2(0.0, 0.0);
@@ -105,13 +106,13 @@ __global__ void k_grad(const double2 *c, const double2 *lam, const double2 *eps,
   const double2 da = ldr_dalpha_inv(eps[v], kd, S);
   const double2 hp = make_double2(-(da.x * acc.x - da.y * acc.y), -(da.x * acc.y + da.y * acc.x));
   // i * conj(h') = (Im h', Re h')
-  grad[v] = make_double2(pref * hp.y, pref * hp.x);
+  grad[ve] = make_double2(pref * hp.y, pref * hp.x);
 }
 
 void grad_kernel(dda_problem *p, const double2 *c, const double2 *lam, double S, double2 *grad) {
   KTimer t(&p->prof, p->st, "adjoint_grad", 113.0 * p->N);
   hipLaunchKernelGGL(k_grad, dim3((unsigned)((p->N + 255) / 256)), dim3(256), 0, p->st, c, lam,
-                     p->eps, p->cidx, p->N, p->nocc, p->k * p->d, S,
+                     p->eps, p->cidx, p->N, p->nocc, p->fr, p->k * p->d, S,
                      4.0 * DDA_PI * p->k * p->d * p->d * p->d, grad);
   HIPCHK(hipGetLastError());
 }

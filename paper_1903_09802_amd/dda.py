@@ -36,7 +36,7 @@ class Options(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
-                ("max_rhs", ctypes.c_int), ("solver", ctypes.c_int)]
+                ("max_rhs", ctypes.c_int), ("solver", ctypes.c_int), ("dense_axis", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -129,7 +129,7 @@ class Problem:
 
     def __init__(self, mask, eps, k: float, d: float, *, restart=30, max_iter=2000, tol=1e-5,
                  precond=2, precision=0, inner_tol=1e-4, max_refine=30, max_rhs=1, solver="gmres",
-                 stream=None):
+                 dense_axis=2, stream=None):
         import torch
         L = load()
         self.mask = mask.to(device="cuda", dtype=torch.uint8).contiguous()
@@ -145,6 +145,7 @@ class Problem:
         if solver not in solvers:
             raise ValueError(f"solver must be one of {sorted(solvers)}")
         o.solver = solvers[solver]
+        o.dense_axis = int(dense_axis)
         self.opts = o
         self.stream = torch.cuda.current_stream() if stream is None else stream
         h = ctypes.c_void_p()
