@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "plates"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "plates", "axes"])
     ap.add_argument("--c3-case", type=int, default=0, help="c3: 0 -> m = 1.31+0.001i, 1 -> m = 1.78")
     ap.add_argument("--c4-prisms", type=int, default=16)
     ap.add_argument("--c4-chunk", type=int, default=32, help="c4: right-hand sides per batched solve")
@@ -219,6 +219,8 @@ def main():
         return bench_c5(args)
     if args.workload == "plates":
         return bench_plates(args)
+    if args.workload == "axes":
+        return bench_axes(args)
     cfg, desc = workload(args.workload)
     s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
     nrhs = len(dirs)
@@ -564,6 +566,46 @@ def bench_plates(args):
         del mask, eps
         torch.cuda.empty_cache()
         _emit(line)
+
+
+def bench_axes(args):
+    """Choice of circulant axes (option dense_axis) on elongated prisms (axis along z): the
+    paper's layout keeps the long axis dense; the alternative makes it a circulant level."""
+    import torch
+
+    import workloads as w
+    from paper_1903_09802_amd.dda import Problem
+
+    cases = [("prism x=20 aspect 2, 128^3, m=1.31", w.hex_prism_grid(20.0, 2.0, 128, 1.31)),
+             ("prism x=20 aspect 4, 128^3, m=1.31", w.hex_prism_grid(20.0, 4.0, 128, 1.31)),
+             ("prism x=20 aspect 2, 128^3, m=1.78", w.hex_prism_grid(20.0, 2.0, 128, 1.78))]
+    dirs, pols = w.plane_wave_z(("x",))
+    for desc, s in cases:
+        mask = torch.from_numpy(s.mask).cuda()
+        eps = torch.from_numpy(s.eps).cuda()
+        for axis in (2, 0):
+            line = dict(workload="axes", case=desc, grid=list(s.shape), n_occupied=int(s.n_occ),
+                        dense_axis=axis)
+            for solver, cap in (("gmres", 2000), ("bicgstab", 4000)):
+                prob = Problem(mask, eps, s.k, s.d, precond=2, tol=1e-5, restart=30, max_iter=cap,
+                               solver=solver, dense_axis=axis)
+                try:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    prob.build_preconditioner(0.0)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    o = prob.solve(dirs, pols, return_c=False, xsec=True)
+                    torch.cuda.synchronize()
+                    t2 = time.perf_counter()
+                finally:
+                    prob.close()
+                st = o["stats"][0]
+                line[solver] = dict(its=st["iters"], converged=bool(st["converged"]),
+                                    build_s=t1 - t0, solve_s=t2 - t1, cext=float(o["cext"][0]))
+            _emit(line)
+        del mask, eps
+        torch.cuda.empty_cache()
 
 
 if __name__ == "__main__":

@@ -409,7 +409,6 @@ template <typename T, typename F> static void with_gp(int n, F &&f) {
 
 static int zreg_g(int n) { return n <= 32 ? 4 : n <= 128 ? 8 : 16; }
 
-// LDS bytes of one register z-pass workgroup with `tw` columns
 // LDS bytes of one register z-pass workgroup with `tw` columns: exchange region, twiddles and
 // the kernel-spectrum slab
 template <typename T> static size_t zreg_lds(int n, int tw, int nz) {
