@@ -632,13 +632,14 @@ template <> struct Mfma<float> {
 };
 
 // Symmetric block product on the matrix cores (even nz).  One workgroup per (unique mode,
-// chunk of rc <= 2 right-hand sides): the up to 4 mode copies x rc vectors form an n2 x 8
-// complex block U per half, and Y U is computed as the real product [Re Y | Im Y] x
-// [[Re U, Im U], [-Im U, Re U]] (n2 x 2 n2 times 2 n2 x 16), with 16 x 16 x 4 MFMAs.  Wave w
+// chunk of rc <= 2 NCB right-hand sides): the up to 4 mode copies x rc vectors form an
+// n2 x 8 NCB complex block U per half, and Y U is computed as the real product
+// [Re Y | Im Y] x [[Re U, Im U], [-Im U, Re U]] in NCB column blocks of 16 (n2 x 2 n2 times
+// 2 n2 x 16 each), with 16 x 16 x 4 MFMAs; each tile fragment feeds all NCB blocks.  Wave w
 // computes tile rows I = w, w + NW, ...; step s pairs row I with J = (s - I) mod ntr, taking the
 // stored tile (I, J) directly or (J, I) transposed, so the two rows that share a stored tile
 // read it in the same step.  Tiles are fetched three steps ahead of their use.
-template <typename T, int NWMAX>
+template <typename T, int NWMAX, int NCB>
 __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const cplx<T> *__restrict__ pk,
                                                              int nx, int ny, int nzw, int z0, int nz,
                                                              int umx, int hh,
@@ -646,7 +647,7 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
                                                              long long nchunks, long long U) {
   using V = cplx<T>;
   using v4 = typename Mfma<T>::v4;
-  constexpr int NV = 8;
+  constexpr int NV = 8 * NCB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *Ub = reinterpret_cast<V *>(smem_raw);  // [2][NV][n2p], zero beyond nv and n2
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -705,12 +706,14 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
   const bool im = r >= 8;
   const long long tiles = (long long)ntr * (ntr + 1) / 2;
   for (int I = wv; I < ntr; I += nw) {
-    v4 c[2];
+    v4 c[2][NCB];
 #pragma unroll
     for (int hf = 0; hf < 2; ++hf) {
       const V *P = pk + (u * 2 + hf) * tiles * 256;
-      const V *Uh = Ub + (hf * NV + vj) * n2p + q;
-      v4 acc = {0, 0, 0, 0};
+      const V *Uh = Ub + (hf * NV + vj) * n2p + q;  // column block cb adds 8 cb n2p
+      v4 acc[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[cb] = v4{0, 0, 0, 0};
       auto fetch = [&](int s, V (&a)[4]) {
         const int J = (s + ntr - I) % ntr;
         const long long t = J <= I ? (long long)I * (I + 1) / 2 + J : (long long)J * (J + 1) / 2 + I;
@@ -719,13 +722,16 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
       };
       auto mac = [&](int s, const V (&a)[4]) {
         const int J = (s + ntr - I) % ntr;
-        V x[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) x[k] = Uh[16 * J + 4 * k];
+        for (int cb = 0; cb < NCB; ++cb) {
+          V x[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          acc = Mfma<T>::mma(a[k].x, im ? x[k].y : x[k].x, acc);
-          acc = Mfma<T>::mma(a[k].y, im ? x[k].x : -x[k].y, acc);
+          for (int k = 0; k < 4; ++k) x[k] = Uh[8 * cb * n2p + 16 * J + 4 * k];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            acc[cb] = Mfma<T>::mma(a[k].x, im ? x[k].y : x[k].x, acc[cb]);
+            acc[cb] = Mfma<T>::mma(a[k].y, im ? x[k].x : -x[k].y, acc[cb]);
+          }
         }
       };
       V buf[4][4];
@@ -739,20 +745,24 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
           if (s + b < ntr) mac(s + b, buf[b]);
         }
       }
-      c[hf] = acc;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) c[hf][cb] = acc[cb];
     }
     // D[i][j] sits in column lane j, item m, row Mfma<T>::row(q, m): lane j < 8 holds Re of
     // vector j, lane j + 8 its Im.  Unfold the halves, flip, scatter.
 #pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const T e0 = c[0][m], e1 = c[1][m];
+      const T e0 = c[0][cb][m], e1 = c[1][cb][m];
       const T o0 = __shfl_xor(e0, 8, 64), o1 = __shfl_xor(e1, 8, 64);
       const int i = 16 * I + Mfma<T>::row(q, m);
-      if (im || vj >= nv || i >= n2) continue;
+      const int v = 8 * cb + vj;
+      if (im || v >= nv || i >= n2) continue;
       const V y0 = mk<T>(e0, o0), y1 = mk<T>(e1, o1);
       const int a = i / hh, iz = i - a * hh;
       const T sa = a == 2 ? (T)-1 : (T)1;
-      const int mode = vj / nr, rr = r0 + vj % nr;
+      const int mode = v / nr, rr = r0 + v % nr;
       const int fx = mode % nmx, fy = mode / nmx;
       const long long off = (long long)mys[fy] * nx + mxs[fx];
       const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
@@ -762,6 +772,8 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
     }
   }
 }
+
+constexpr size_t kLdsMax = 160 * 1024;  // LDS of one gfx950 CU, the most one workgroup can take
 
 template <typename T>
 static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, const cplx<T> *binv,
@@ -798,17 +810,23 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
     const long long U = (long long)p->umx * p->umy;
     snprintf(nm, sizeof nm, "pc_gemv_%s", suf);
     if (p->psym) {
-      // right-hand sides per workgroup: 4 mode copies x rc vectors <= 8 columns of U
-      const int rc = std::max(1, std::min(2, nrhs));
-      const long long nchunks = (nrhs + rc - 1) / rc;
+      // right-hand sides per workgroup: 4 mode copies x rc vectors <= 8 NCB columns of U; more
+      // column blocks stream each tile once for more right-hand sides, as LDS allows
       const int n2p = 16 * p->ntr;
-      const size_t lds = (size_t)2 * 8 * n2p * sizeof(cplx<T>);
+      auto lds_of = [&](int ncb) { return (size_t)2 * 8 * ncb * n2p * sizeof(cplx<T>); };
+      int ncb = nrhs <= 2 ? 1 : (nrhs <= 4 || sizeof(T) == 8) ? 2 : 4;  // FP64: 4 would spill
+      while (ncb > 1 && lds_of(ncb) > kLdsMax) ncb /= 2;
+      const int rc = std::max(1, std::min(2 * ncb, nrhs));
+      const long long nchunks = (nrhs + rc - 1) / rc;
+      const size_t lds = lds_of(ncb);
       const long long tiles = (long long)p->ntr * (p->ntr + 1) / 2;
       const double bytes = (double)U * 2.0 * tiles * 256 * sz * nchunks + 2.0 * rows * nx * sz;
       const int threads = 64 * std::min(12, p->ntr);  // one wave per tile row up to 12 rows
       const dim3 grid((unsigned)xcd_grid(U * nchunks));
       KTimer t(&p->prof, p->st, nm, bytes);
-      auto fn = k_pc_gemv_mfma<T, 12>;
+      auto fn = ncb == 1   ? k_pc_gemv_mfma<T, 12, 1>
+                : ncb == 2 ? k_pc_gemv_mfma<T, 12, 2>
+                           : k_pc_gemv_mfma<T, 12, sizeof(T) == 8 ? 2 : 4>;
       set_lds_limit((const void *)fn, lds);
       hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
                          p->umx, p->hh, p->n2, p->ntr, nrhs, rc, nchunks, U);

@@ -90,6 +90,22 @@ def test_preconditioner_fp64_vs_oracle(shape, seed):
         assert rel_err(z[r], ref) < 1e-10, (shape, r)
 
 
+@pytest.mark.parametrize("fp32,nrhs,shape,seed", [(0, 6, (6, 8, 10), 81), (1, 6, (6, 8, 10), 82),
+                                                  (1, 9, (8, 6, 5), 83), (0, 5, (16, 12, 10), 84)])
+def test_preconditioner_many_rhs_vs_oracle(fp32, nrhs, shape, seed):
+    """More right-hand sides than one column block: the block product streams each tile for
+    2 (FP64) or 4 (FP32) blocks of 8 columns, over several chunks with a ragged last one."""
+    nz, ny, nx = shape
+    s = w.random_mask(nx, ny, nz, 0.75, seed, k=1.2, d=0.3, eps_jitter=0.05)
+    with make_problem(s, precond=2, max_rhs=nrhs, precision=fp32) as prob:
+        prob.build_preconditioner(0.0)
+        x = rand_field(shape, nrhs, seed)
+        z = prob.apply_preconditioner(to_dev(x), fp32=bool(fp32)).cpu().numpy()
+    pc = oracle_precond(s)
+    for r in range(nrhs):
+        assert rel_err(z[r], pc(x[r])) < (1e-5 if fp32 else 1e-10), (shape, r)
+
+
 @pytest.mark.parametrize("shape,z0,z1,seed", [((10, 8, 12), 2, 7, 61), ((9, 6, 10), 1, 7, 62),
                                                ((12, 16, 16), 3, 11, 63), ((7, 5, 6), 0, 5, 64)])
 def test_preconditioner_spans_occupied_layers(shape, z0, z1, seed):
