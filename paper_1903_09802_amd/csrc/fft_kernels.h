@@ -197,8 +197,10 @@ __global__ void __launch_bounds__(768) k_zpass(cplx<T> *data, const cplx<T> *__r
   const int ld = ncols + 1;
   const long long blk = xcd_remap(blockIdx.x, a.ntiles * a.nrhs);
   if (blk >= a.ntiles * a.nrhs) return;
-  const long long r = blk / a.ntiles;
-  const long long c0 = (blk - r * a.ntiles) * (long long)a.tw;
+  // right-hand sides fastest: the workgroups that read the same kernel-spectrum columns are
+  // adjacent and, through the XCD remap, share one L2
+  const long long r = blk % a.nrhs;
+  const long long c0 = (blk / a.nrhs) * (long long)a.tw;
   V *base = data + r * 3LL * a.nz * a.zstride;
   const Lane L = make_lane(ncols, tpc_of(n));
   if (L.active) {
