@@ -104,6 +104,50 @@ def two_level_dense(shape, k: float, d: float, alpha_tilde_inv: complex):
     return P
 
 
+def one_level_dense(shape, k: float, d: float, alpha_tilde_inv: complex):
+    """Brute-force 1-level P = alpha~^{-1} I - C1(d^3 G): only the x-level Toeplitz blocks are
+    replaced by their Frobenius-nearest circulants (Sec. 3, C_B); (3N x 3N), box order."""
+    nz, ny, nx = shape
+    C1 = average_wrapped(bttb_full(shape, k, d), 3, 7)
+    n3 = 3 * nz * ny * nx
+    P = -C1.reshape(n3, n3)
+    P[np.arange(n3), np.arange(n3)] += alpha_tilde_inv
+    return P
+
+
+def one_level_blocks(shape, k: float, d: float, alpha_tilde_inv: complex):
+    """Per-mode blocks of the 1-level preconditioner: eq. Chan along x of the signed kernel, a
+    DFT over x, and for each of the nx modes the dense (3 nz ny) x (3 nz ny) block
+    D(wx)[(a, iz, iy), (b, jz, jy)] = alpha~^{-1} delta - lambda_ab(wx; iz - jz, iy - jy)
+    (block-Toeplitz-Toeplitz-block in z and y): [nx][3 nz ny][3 nz ny]."""
+    nz, ny, nx = shape
+    c1 = chan_column(kernel_signed(shape, k, d))  # [6][2nz-1][2ny-1][nx]
+    lam = np.fft.fft(c1, axis=3)
+    iz, iy = np.arange(nz), np.arange(ny)
+    dz = (iz[:, None] - iz[None, :]) + nz - 1
+    dy = (iy[:, None] - iy[None, :]) + ny - 1
+    m = nz * ny
+    D = np.empty((nx, 3 * m, 3 * m), dtype=np.complex128)
+    for a in range(3):
+        for b in range(3):
+            L = lam[FULL[a, b]][dz[:, None, :, None], dy[None, :, None, :]]  # [nz][ny][nz][ny][nx]
+            D[:, a * m:(a + 1) * m, b * m:(b + 1) * m] = -np.moveaxis(L, 4, 0).reshape(nx, m, m)
+    idx = np.arange(3 * m)
+    D[:, idx, idx] += alpha_tilde_inv
+    return D
+
+
+def apply_one_level(vbox, mask, Dinv):
+    """z = M P^{-1} (M v) for the 1-level preconditioner given by its per-mode inverse blocks."""
+    m = mask.astype(np.float64)[None]
+    nx = vbox.shape[3]
+    V = np.fft.fft(vbox * m, axis=3)  # [3][nz][ny][nx]
+    Vm = np.moveaxis(V, 3, 0).reshape(nx, -1)  # unknown order (a, iz, iy) per mode
+    Z = np.einsum("xij,xj->xi", Dinv, Vm)
+    Z = np.moveaxis(Z.reshape((nx,) + V.shape[:3]), 0, 3)
+    return m * np.fft.ifft(Z, axis=3)
+
+
 def two_level_generator(shape, k: float, d: float):
     """c2_c(qbar, pbar, s): eq. Chan along x then y of the signed kernel.
 

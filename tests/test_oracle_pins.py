@@ -210,6 +210,29 @@ def test_two_level_brute_force_equals_formula(shape):
     assert np.abs(z1 - z2).max() < 1e-12 * np.abs(z1).max()
 
 
+@pytest.mark.parametrize("shape", [(3, 2, 5), (2, 3, 4), (1, 2, 6), (3, 2, 1)])
+def test_one_level_brute_force_equals_formula(shape):
+    """The 1-level preconditioner C_B of Sec. 3: wrapped-diagonal averaging of the x-level
+    Toeplitz blocks of the full-box matrix equals the per-mode dense blocks from eq. Chan
+    along x and a DFT over x; it is complex symmetric, and for nx = 1 it is the matrix
+    itself (nothing to average)."""
+    k, d = 1.3, 0.3
+    ati = complex(physics.alpha_inv(1.7161, k * d, 0.0))
+    P = circulant.one_level_dense(shape, k, d, ati)
+    assert np.abs(P - P.T).max() < 1e-14
+    D = circulant.one_level_blocks(shape, k, d, ati)
+    rng = np.random.default_rng(6)
+    v = rng.normal(size=(3,) + shape) + 1j * rng.normal(size=(3,) + shape)
+    ones = np.ones(shape, dtype=np.uint8)
+    Dinv = np.linalg.inv(D)
+    z1 = circulant.apply_dense(v, ones, P)
+    z2 = circulant.apply_one_level(v, ones, Dinv)
+    assert np.abs(z1 - z2).max() < 1e-12 * np.abs(z1).max()
+    if shape[2] == 1:
+        A = system.dense_matrix(ones, np.full(shape, 1.7161, dtype=complex), k, d, 0.0)
+        assert np.abs(P - A).max() < 1e-12 * np.abs(A).max()
+
+
 def test_occupied_layers_preconditioner_is_the_smallest_box_one():
     """The dense level spans the occupied z layers: for a body with air layers above and
     below, M P^{-1} M equals the brute-force P of the smallest box around it (the paper's
