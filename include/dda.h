@@ -66,7 +66,9 @@ typedef struct {
   int restart;      /* GMRES restart length m of GMRES(m), 1 .. 1023; default 30 */
   int max_iter;     /* cap on total GMRES iterations (inner ones in refinement mode); default 2000 */
   double tol;       /* stop when ||b - A x||_2 / ||b||_2 <= tol (true residual, FP64); default 1e-5 */
-  int precond;      /* 0: none; 2: 2-level circulant preconditioner (Sec. 3); default 2 */
+  int precond;      /* 0: none; 1: 1-level circulant preconditioner (Sec. 3, C_B: circulant along
+                       x, a dense 3 nz ny block per x mode, 3 nz ny <= 768); 2: 2-level circulant
+                       preconditioner (Sec. 3.1, circulant along x and y); default 2 */
   int precision;    /* 0: everything in FP64;
                        1: operator and preconditioner applied in FP32 (complex64) inside
                           FP64 iterative refinement: every restart cycle builds its Krylov
@@ -131,9 +133,14 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
  * LDR polarisability of the mean occupied permittivity (the "ice" value for a
  * homogeneous body, Sec. 3.1) with lattice factor S = s_bar.  Only the
  * (nx/2+1)(ny/2+1) modes with non-negative frequencies are inverted; the
- * block symmetries under x, y and z reflections supply the rest exactly.
+ * block symmetries under x, y and z reflections supply the rest exactly.  The
+ * dense z level spans the box's occupied z layers.
+ * With opt.precond = 1 it builds instead the 1-level preconditioner C_B of Sec. 3:
+ * eq. Chan along x only, an FFT along x, and one dense (3 nz ny)^2 block per x mode
+ * (nx/2+1 inverted, the x reflection supplies the rest).
  * Stored in FP64 (precision 0) or FP32 (precision 1).
- * Errors: EINVAL (s_bar outside [0,1]); ENOMEM; EDEVICE (a singular block).
+ * Errors: EINVAL (s_bar outside [0,1]); ENOMEM; EDEVICE (a singular block);
+ * EUNSUPPORTED (1-level blocks of order 3 nz ny above 768).
  */
 dda_status dda_build_preconditioner(dda_problem *p, double s_bar);
 

@@ -104,7 +104,7 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
     REQUIRE(o.restart >= 1 && o.restart < kMaxM, DDA_EINVAL, "restart must be in [1, %d]", kMaxM - 1);
     REQUIRE(o.max_iter >= 1, DDA_EINVAL, "max_iter must be >= 1");
     REQUIRE(o.tol > 0.0, DDA_EINVAL, "tol must be > 0");
-    REQUIRE(o.precond == 0 || o.precond == 2, DDA_EINVAL, "precond must be 0 or 2");
+    REQUIRE(o.precond >= 0 && o.precond <= 2, DDA_EINVAL, "precond must be 0, 1 or 2");
     REQUIRE(o.precision == 0 || o.precision == 1, DDA_EINVAL, "precision must be 0 or 1");
     REQUIRE(o.max_rhs >= 1 && o.max_rhs <= 64, DDA_EINVAL, "max_rhs must be in [1, 64]");
     REQUIRE(o.inner_tol > 0.0 && o.inner_tol < 1.0, DDA_EINVAL, "inner_tol must be in (0, 1)");
@@ -206,7 +206,7 @@ dda_status dda_solve(dda_problem *p, int nrhs, const double *dir_host, const dou
     dir_host = dirs.data();
     pol_host = pols.data();
     REQUIRE(p->opt.precond == 0 || p->prec_built, DDA_ESTATE,
-            "opt.precond = 2 but dda_build_preconditioner has not run");
+            "opt.precond != 0 but dda_build_preconditioner has not run");
     const long long n3 = 3 * p->nocc;
     setup_alpha(p, nrhs, S.data());
     setup_rhs(p, nrhs, dir_host, pol_host, p->bvec, 0);
@@ -291,7 +291,7 @@ dda_status dda_grad_cext(dda_problem *p, const double *dir_host, const double *p
     REQUIRE(p, DDA_EINVAL, "problem is NULL");
     REQUIRE(grad_dev, DDA_EINVAL, "grad_dev is required");
     REQUIRE(p->opt.precond == 0 || p->prec_built, DDA_ESTATE,
-            "opt.precond = 2 but dda_build_preconditioner has not run");
+            "opt.precond != 0 but dda_build_preconditioner has not run");
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<double> S;
     check_waves(1, dir_host, pol_host, S);

@@ -435,7 +435,7 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
   Kry K{p, nrhs, reduce_blocks(n3), m, n3, reinterpret_cast<double2 *>(p->partial), p->dflag + 4,
         p->dflag + 4 + p->R};
   const long long vs_r = n3, vs_j = (long long)p->R * n3;  // V is [m+1][R][n3]
-  const bool prec = p->opt.precond == 2;
+  const bool prec = p->opt.precond != 0;
   double2 *rv = p->V;  // the residual is written straight into basis block 0
   std::vector<int> all(nrhs, 1), act(nrhs, 1), incyc(nrhs, 0), jcut(nrhs, 0), iters(nrhs, 0);
   std::vector<int> cycles(nrhs, 0), conv(nrhs, 0);
@@ -713,7 +713,7 @@ void bicgstab_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, doub
   REQUIRE(p->opt.restart >= 7, DDA_EINVAL, "BiCGStab needs restart >= 7 (work vectors)");
   Kry K{p, nrhs, reduce_blocks(n3), p->opt.restart, n3, reinterpret_cast<double2 *>(p->partial),
         p->dflag + 4, p->dflag + 4 + p->R};
-  const bool prec = p->opt.precond == 2;
+  const bool prec = p->opt.precond != 0;
   const long long blk = (long long)p->R * n3;  // one basis block holds [R][n3]
   double2 *rr = p->V, *rh = p->V + blk, *pp = p->V + 2 * blk, *v = p->V + 3 * blk;
   double2 *s = p->V + 4 * blk, *t = p->V + 5 * blk, *ph = p->V + 6 * blk, *shv = p->V + 7 * blk;

@@ -157,6 +157,7 @@ __device__ __forceinline__ void gj_pivot_rows(const double2 *A, int n, int j, in
 }
 
 constexpr int kGJMaxOrder = 768;  // the largest half-block order, 3 * 256
+constexpr size_t kLdsMax = 160 * 1024;  // LDS of one gfx950 CU, the most one workgroup can take
 constexpr int kGJThreads = 256;
 
 // Batched in-place inverse of row-major n x n complex matrices, one workgroup each:
@@ -415,8 +416,15 @@ void precond_free(dda_problem *p) {
   p->prec_built = 0;
 }
 
+static void precond1_build(dda_problem *p);
+
 void precond_build(dda_problem *p, double s_bar) {
   precond_free(p);
+  if (p->opt.precond == 1) {
+    p->ati = ldr_alpha_inv(p->eps_mean, p->k * p->d, s_bar);
+    precond1_build(p);
+    return;
+  }
   const int nx = p->nx, ny = p->ny, nz = p->pbz;  // the dense level's extent
   p->ati = ldr_alpha_inv(p->eps_mean, p->k * p->d, s_bar);
   p->hh = (nz + 1) / 2;
@@ -487,6 +495,120 @@ void precond_build(dda_problem *p, double s_bar) {
                              p->binv64, m0, p->n2, p->ntr);
         HIPCHK(hipGetLastError());
       } else if (fp32) {
+        hipLaunchKernelGGL(k_to_f32, dim3(nblk(cnt * msz, 256)), dim3(256), 0, p->st, dst,
+                           p->binv32 + m0 * msz, cnt * msz);
+        HIPCHK(hipGetLastError());
+      }
+    }
+    int hflag[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(hflag, p->dflag, sizeof(int) * 4, hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    REQUIRE(hflag[0] == 0, DDA_EDEVICE, "a preconditioner block is singular");
+  } catch (...) {
+    if (gen) (void)hipFree(gen);
+    if (scratch) (void)hipFree(scratch);
+    precond_free(p);
+    throw;
+  }
+  HIPCHK(hipFree(gen));
+  if (scratch) HIPCHK(hipFree(scratch));
+  p->prec_built = 1;
+  p->prec_fp32 = fp32;
+}
+
+// ----------------------------------------------------------------------------- 1-level
+
+// The 1-level preconditioner C_B of Sec. 3: eq. Chan along x only, so each x mode keeps a
+// dense (3 nz ny)^2 block, block-Toeplitz-Toeplitz-block in z and y.
+// gen1[c][sz + nz - 1][sy + ny - 1][pbar] = sum over p in {pbar, pbar - nx} of wx(p) K_c(p, sy, sz).
+__global__ void k_chan_gen1(double2 *gen, int nx, int ny, int nz, double k, double d) {
+  const long long SY = 2LL * ny - 1, SZ = 2LL * nz - 1;
+  const long long tot = SZ * SY * nx;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  const int pb = (int)(idx % nx);
+  const int sy = (int)((idx / nx) % SY) - (ny - 1);
+  const int sz = (int)(idx / ((long long)nx * SY)) - (nz - 1);
+  double2 acc[6];
+  for (int c = 0; c < 6; ++c) acc[c] = make_double2(0.0, 0.0);
+  const double d3 = d * d * d;
+  const int ps[2] = {pb, pb - nx};
+  const double wxs[2] = {(double)(nx - pb) / nx, (double)pb / nx};
+  for (int u = 0; u < 2; ++u)
+    if (wxs[u] != 0.0) green6_chan(ps[u] * d, sy * d, sz * d, k, d3, wxs[u], acc);
+  for (int c = 0; c < 6; ++c) gen[c * tot + idx] = acc[c];
+}
+
+// X = D(u)^T, row-major, for the unique x modes u in [m0, m0 + count):
+// D[(a, iz, iy), (b, jz, jy)] = ati delta - lambda_ab(u; iz - jz, iy - jy), unknown index
+// a nz ny + iz ny + iy.
+__global__ void k_assemble1(const double2 *lam, double2 *out, long long m0, int nx, int ny, int nz,
+                            double2 ati) {
+  const long long u = m0 + blockIdx.x;
+  const int m = nz * ny, n1 = 3 * m;
+  const long long SY = 2LL * ny - 1, SZ = 2LL * nz - 1, tot = SZ * SY * nx;
+  double2 *X = out + (long long)blockIdx.x * n1 * n1;
+  for (long long e = threadIdx.x; e < (long long)n1 * n1; e += blockDim.x) {
+    const int br = (int)(e % n1), bc = (int)(e / n1);  // X[bc][br] = D[br][bc]
+    const int a = br / m, rz = (br % m) / ny, ry = br % ny;
+    const int b = bc / m, cz = (bc % m) / ny, cy = bc % ny;
+    const double2 t = lam[comp_index(a, b) * tot + ((long long)(rz - cz + nz - 1) * SY + (ry - cy + ny - 1)) * nx + u];
+    double2 val = make_double2(-t.x, -t.y);
+    if (br == bc) val = cadd(val, ati);
+    X[e] = val;
+  }
+}
+
+static void precond1_build(dda_problem *p) {
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const int n1 = 3 * nz * ny;
+  REQUIRE(n1 <= kGJMaxOrder, DDA_EUNSUPPORTED,
+          "1-level blocks of order 3 nz ny = %d above %d (use the 2-level preconditioner)", n1,
+          kGJMaxOrder);
+  p->n2 = n1;
+  p->umx = nx / 2 + 1;
+  p->umy = 1;
+  p->psym = 0;
+  const long long nmat = p->umx, msz = (long long)n1 * n1;
+  const int fp32 = p->opt.precision == 1;
+  const size_t final_bytes = (size_t)nmat * msz * (fp32 ? sizeof(float2) : sizeof(double2));
+  size_t freeb = 0, totb = 0;
+  HIPCHK(hipMemGetInfo(&freeb, &totb));
+  REQUIRE(final_bytes < (size_t)(0.85 * (double)freeb), DDA_ENOMEM,
+          "preconditioner blocks need %.2f GB, %.2f GB free", final_bytes / 1e9, freeb / 1e9);
+  const long long rows = 6LL * (2 * nz - 1) * (2 * ny - 1);
+  double2 *gen = nullptr, *scratch = nullptr;
+  HIPCHK(hipMalloc(&gen, sizeof(double2) * rows * nx));
+  try {
+    hipLaunchKernelGGL(k_chan_gen1, dim3(nblk(rows / 6 * nx, 256)), dim3(256), 0, p->st, gen, nx, ny,
+                       nz, p->k, p->d);
+    HIPCHK(hipGetLastError());
+    fft_rows_plain(p, p->ux, gen, rows, 0);
+    if (fp32) HIPCHK(hipMalloc(&p->binv32, final_bytes));
+    else HIPCHK(hipMalloc(&p->binv64, final_bytes));
+    long long chunk = nmat;
+    if (fp32) {
+      chunk = std::max<long long>(1, (long long)((1ULL << 31) / (msz * sizeof(double2))));
+      chunk = std::min(chunk, nmat);
+      HIPCHK(hipMalloc(&scratch, sizeof(double2) * chunk * msz));
+    }
+    REQUIRE(gj_lds(n1, n1 <= kGJThreads ? 16 : 8) <= std::max(p->lds_max, kLdsMax), DDA_EUNSUPPORTED,
+            "1-level blocks too large for LDS (order %d)", n1);
+    HIPCHK(hipMemsetAsync(p->dflag, 0, sizeof(int) * 4, p->st));
+    for (long long m0 = 0; m0 < nmat; m0 += chunk) {
+      const long long cnt = std::min(chunk, nmat - m0);
+      double2 *dst = fp32 ? scratch : p->binv64 + m0 * msz;
+      {
+        KTimer t(&p->prof, p->st, "pc_assemble", 16.0 * cnt * msz);
+        hipLaunchKernelGGL(k_assemble1, dim3((unsigned)cnt), dim3(256), 0, p->st, gen, dst, m0, nx, ny,
+                           nz, p->ati);
+        HIPCHK(hipGetLastError());
+      }
+      {
+        KTimer t(&p->prof, p->st, "pc_gj_inverse", 32.0 * cnt * msz);
+        gj_launch(p, dst, cnt, n1);
+      }
+      if (fp32) {
         hipLaunchKernelGGL(k_to_f32, dim3(nblk(cnt * msz, 256)), dim3(256), 0, p->st, dst,
                            p->binv32 + m0 * msz, cnt * msz);
         HIPCHK(hipGetLastError());
@@ -773,8 +895,6 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
   }
 }
 
-constexpr size_t kLdsMax = 160 * 1024;  // LDS of one gfx950 CU, the most one workgroup can take
-
 template <typename T>
 static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, const cplx<T> *binv,
                      const double *xscale) {
@@ -886,15 +1006,140 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
   }
 }
 
+// 1-level application: one workgroup per (unique x mode u, chunk of rc right-hand sides).
+// Gathers the mode copies kx = u and nx - u of each RHS (the x component negated on the copy,
+// D(-w) = Sx D(w) Sx), multiplies by the stored inverse (column-major, each element read
+// once for all NV vectors) and writes back in place.
+template <typename T, int NV>
+__global__ void __launch_bounds__(256) k_pc1_gemv(cplx<T> *W, const cplx<T> *__restrict__ binv,
+                                                  int nx, int ny, int nz, int umx, int n1, int nrhs,
+                                                  int rc, long long nchunks) {
+  using V = cplx<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V *Ub = reinterpret_cast<V *>(smem_raw);  // [nv][n1]
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const long long blk = xcd_remap(blockIdx.x, umx * nchunks);
+  if (blk >= umx * nchunks) return;
+  const int u = (int)(blk / nchunks);
+  const int r0 = (int)(blk - (long long)u * nchunks) * rc;
+  const int nr = min(rc, nrhs - r0);
+  const int kxs[2] = {u, (nx - u) % nx};
+  const int nmode = kxs[1] != kxs[0] ? 2 : 1;
+  const int nv = nmode * nr;
+  const int m = nz * ny;
+  for (int e = tid; e < nv * n1; e += nt) {
+    const int vi = e / n1, i = e - vi * n1;
+    const int mode = vi / nr, r = r0 + vi % nr;
+    const int a = i / m, yz = i - a * m;
+    V v = W[(((long long)r * 3 + a) * m + yz) * nx + kxs[mode]];
+    if (mode == 1 && a == 0) v = mk<T>(-v.x, -v.y);
+    Ub[e] = v;
+  }
+  __syncthreads();
+  const V *M = binv + (long long)u * n1 * n1;
+  constexpr int UNR = 4;
+  for (int i = tid; i < n1; i += nt) {
+    V acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = mk<T>((T)0, (T)0);
+    int j = 0;
+    for (; j + UNR <= n1; j += UNR) {
+      V mv[UNR];
+#pragma unroll
+      for (int q = 0; q < UNR; ++q) mv[q] = M[(long long)(j + q) * n1 + i];
+#pragma unroll
+      for (int q = 0; q < UNR; ++q)
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          if (v < nv) acc[v] = cmac(acc[v], mv[q], Ub[v * n1 + j + q]);
+    }
+    for (; j < n1; ++j) {
+      const V mv = M[(long long)j * n1 + i];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (v < nv) acc[v] = cmac(acc[v], mv, Ub[v * n1 + j]);
+    }
+    const int a = i / m, yz = i - a * m;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (v >= nv) continue;
+      const int mode = v / nr, r = r0 + v % nr;
+      V y = acc[v];
+      if (mode == 1 && a == 0) y = mk<T>(-y.x, -y.y);
+      W[(((long long)r * 3 + a) * m + yz) * nx + kxs[mode]] = y;
+    }
+  }
+}
+
+template <typename T>
+static void pc_apply1(dda_problem *p, int nrhs, const double2 *x, double2 *y, const cplx<T> *binv,
+                      const double *xscale) {
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const double sz = sizeof(cplx<T>);
+  cplx<T> *W = reinterpret_cast<cplx<T> *>(p->w0);
+  const long long rows = (long long)nrhs * 3 * nz * ny;
+  const char *suf = sizeof(T) == 8 ? "f64" : "f32";
+  char nm[64];
+  RowArgs a{};
+  a.rows = rows;
+  a.n_in = nx;
+  a.n_out = nx;
+  a.in_stride = nx;
+  a.out_stride = nx;
+  a.cidx = p->cidx;
+  a.nocc = p->nocc;
+  a.vox_rows = (long long)nz * ny;
+  a.rhs_rows = 3LL * nz * ny;
+  a.nx = nx;
+  a.N = p->N;
+  {
+    RowArgs f = a;
+    f.sign = -1;
+    f.xscale = xscale;
+    snprintf(nm, sizeof nm, "pc_x_fwd_%s", suf);
+    launch_rows<T, ROW_PC_FWD, double2, cplx<T>>(p, p->ux, x, W, f, nm,
+                                                 rows * (4.0 * nx + sz * nx) + nrhs * 48.0 * p->nocc);
+  }
+  {
+    const int n1 = p->n2;
+    const int rc = std::max(1, std::min(2, nrhs));
+    const long long nchunks = (nrhs + rc - 1) / rc;
+    const size_t lds = (size_t)2 * rc * n1 * sizeof(cplx<T>);
+    const int threads = std::min(256, ((n1 + 63) / 64) * 64);
+    const double bytes = (double)p->umx * n1 * n1 * sz * nchunks + 2.0 * rows * nx * sz;
+    snprintf(nm, sizeof nm, "pc1_gemv_%s", suf);
+    KTimer t(&p->prof, p->st, nm, bytes);
+    auto fn = k_pc1_gemv<T, 4>;
+    set_lds_limit((const void *)fn, lds);
+    hipLaunchKernelGGL(fn, dim3((unsigned)xcd_grid((long long)p->umx * nchunks)), dim3(threads), lds,
+                       p->st, W, binv, nx, ny, nz, p->umx, n1, nrhs, rc, nchunks);
+    HIPCHK(hipGetLastError());
+  }
+  {
+    RowArgs b = a;
+    b.sign = +1;
+    b.scale = 1.0 / (double)nx;
+    snprintf(nm, sizeof nm, "pc_x_inv_%s", suf);
+    launch_rows<T, ROW_PC_INV, cplx<T>, double2>(p, p->ux, W, y, b, nm,
+                                                 rows * (sz * nx + 4.0 * nx) + nrhs * 48.0 * p->nocc);
+  }
+}
+
 void apply_precond(dda_problem *p, int nrhs, const double2 *x, double2 *y, int fp32,
                    const double *xscale) {
   REQUIRE(p->prec_built, DDA_ESTATE, "preconditioner not built");
   REQUIRE(fp32 == p->prec_fp32, DDA_ESTATE, "preconditioner was built in %s",
           p->prec_fp32 ? "FP32" : "FP64");
-  if (fp32)
+  if (p->opt.precond == 1) {
+    if (fp32)
+      pc_apply1<float>(p, nrhs, x, y, p->binv32, xscale);
+    else
+      pc_apply1<double>(p, nrhs, x, y, p->binv64, xscale);
+  } else if (fp32) {
     pc_apply<float>(p, nrhs, x, y, p->binv32, xscale);
-  else
+  } else {
     pc_apply<double>(p, nrhs, x, y, p->binv64, xscale);
+  }
 }
 
 }  // namespace dda

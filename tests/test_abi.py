@@ -42,6 +42,17 @@ def test_default_options(lib):
     assert o.solver == 0 and o.dense_axis == 2
 
 
+@pytest.mark.parametrize("precond", [-1, 3])
+def test_create_rejects_bad_precond(lib, precond):
+    from paper_1903_09802_amd import dda
+    o = dda.default_options()
+    o.precond = precond
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: option validation fails first
+    st = lib.dda_create(4, 4, 4, dummy, dummy, 1.0, 0.1, ctypes.byref(o), None, ctypes.byref(h))
+    assert st == -1 and h.value is None
+
+
 @pytest.mark.parametrize("axis", [-1, 3])
 def test_create_rejects_bad_dense_axis(lib, axis):
     from paper_1903_09802_amd import dda

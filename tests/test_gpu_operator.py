@@ -129,6 +129,58 @@ def test_preconditioner_spans_occupied_layers(shape, z0, z1, seed):
         assert np.all(z[r][:, air] == 0)
 
 
+ONE_LEVEL_CASES = [((4, 5, 12), 0, 1, 91), ((3, 2, 16), 0, 3, 92), ((6, 4, 9), 1, 1, 93),
+                   ((2, 3, 7), 0, 2, 94), ((1, 1, 8), 0, 1, 95), ((16, 16, 6), 0, 2, 96),
+                   ((5, 6, 10), 1, 3, 97)]
+
+
+@pytest.mark.parametrize("shape,fp32,nrhs,seed", ONE_LEVEL_CASES)
+def test_one_level_preconditioner_vs_oracle(shape, fp32, nrhs, seed):
+    """The 1-level preconditioner (precond = 1, Sec. 3 C_B): x-mode blocks of order 3 nz ny,
+    odd and even nx, one and several right-hand sides, FP64 and FP32."""
+    from oracle import circulant
+    nz, ny, nx = shape
+    s = w.random_mask(nx, ny, nz, 0.75, seed, k=1.2, d=0.3, eps_jitter=0.05)
+    with make_problem(s, precond=1, max_rhs=nrhs, precision=fp32) as prob:
+        prob.build_preconditioner(0.0)
+        x = rand_field(shape, nrhs, seed)
+        z = prob.apply_preconditioner(to_dev(x), fp32=bool(fp32)).cpu().numpy()
+    occ = s.mask.astype(bool)
+    ati = complex(physics.alpha_inv(s.eps[occ].mean(), s.k * s.d, 0.0))
+    Dinv = np.linalg.inv(circulant.one_level_blocks(shape, s.k, s.d, ati))
+    for r in range(nrhs):
+        ref = circulant.apply_one_level(x[r], s.mask, Dinv)
+        assert rel_err(z[r], ref) < (1e-5 if fp32 else 1e-10), (shape, r)
+
+
+def test_one_level_solve_and_limits():
+    """GMRES with the 1-level preconditioner reaches the dense-LU solution on a cuboid
+    elongated along x, and blocks above order 768 are refused."""
+    from paper_1903_09802_amd.dda import DDAError
+    from oracle import system
+    s = w.cuboid_grid(24, 4, 4, 1.5, 0.25, 1.31)
+    dirs, pols = random_waves(1, 98)
+    dirs, pols = dirs[:1], pols[:1]
+    A = system.dense_matrix(s.mask, s.eps, s.k, s.d, physics.lattice_S(dirs[0], pols[0]))
+    b = system.incident_field(s.mask, s.k, s.d, dirs[0], pols[0])
+    cref = system.compact_to_box(np.linalg.solve(A, system.box_to_compact(b, s.mask)), s.mask)
+    its = {}
+    for precond in (0, 1, 2):
+        with make_problem(s, precond=precond, tol=1e-11) as prob:
+            if precond:
+                prob.build_preconditioner(0.0)
+            out = prob.solve(dirs, pols)
+        assert out["stats"][0]["converged"] == 1
+        assert rel_err(out["c"][0].cpu().numpy(), cref) < 1e-9, precond
+        its[precond] = out["stats"][0]["iters"]
+    assert its[1] < its[0], its
+    s = w.cuboid_grid(4, 16, 18, 1.0, 0.3, 1.31)  # 3 nz ny = 864
+    with make_problem(s, precond=1) as prob:
+        with pytest.raises(DDAError) as ei:
+            prob.build_preconditioner(0.0)
+        assert ei.value.status == -5
+
+
 def test_preconditioner_brute_force_definition():
     """Against P built by wrapped-diagonal averaging of the full-box BTTB matrix."""
     shape = (4, 5, 6)
