@@ -178,7 +178,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "plates", "axes"])
+    ap.add_argument("--workload", default="c2",
+                    choices=["c1", "c2", "c3", "c4", "c5", "plates", "axes", "levels"])
     ap.add_argument("--c3-case", type=int, default=0, help="c3: 0 -> m = 1.31+0.001i, 1 -> m = 1.78")
     ap.add_argument("--c4-prisms", type=int, default=16)
     ap.add_argument("--c4-chunk", type=int, default=32, help="c4: right-hand sides per batched solve")
@@ -221,6 +222,8 @@ def main():
         return bench_plates(args)
     if args.workload == "axes":
         return bench_axes(args)
+    if args.workload == "levels":
+        return bench_levels(args)
     cfg, desc = workload(args.workload)
     s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
     nrhs = len(dirs)
@@ -603,6 +606,48 @@ def bench_axes(args):
                 st = o["stats"][0]
                 line[solver] = dict(its=st["iters"], converged=bool(st["converged"]),
                                     build_s=t1 - t0, solve_s=t2 - t1, cext=float(o["cext"][0]))
+            _emit(line)
+        del mask, eps
+        torch.cuda.empty_cache()
+
+
+def bench_levels(args):
+    """1-level vs 2-level circulant preconditioner on needles (long axis z): the 1-level one
+    is circulant along the needle (dense_axis = 1 puts z on the circulant x level) with dense
+    (3 nx ny)^2 blocks; the 2-level one keeps z dense."""
+    import numpy as np
+    import torch
+
+    import workloads as w
+    from paper_1903_09802_amd.dda import Problem
+
+    cases = [("needle 12x12x256, m=1.31", w.cuboid_grid(12, 12, 256, 2.0, 0.25, 1.31)),
+             ("needle 16x16x256, m=1.31", w.cuboid_grid(16, 16, 256, 2.0, 0.25, 1.31)),
+             ("needle 12x12x256, m=1.78", w.cuboid_grid(12, 12, 256, 2.0, 0.25, 1.78))]
+    dirs, pols = np.array([[1.0, 0.0, 0.0]]), np.array([[0.0, 0.0, 1.0]])
+    for desc, s in cases:
+        mask = torch.from_numpy(s.mask).cuda()
+        eps = torch.from_numpy(s.eps).cuda()
+        for precond, axis in ((0, 2), (2, 2), (1, 1)):
+            line = dict(workload="levels", case=desc, grid=list(s.shape), precond=precond,
+                        dense_axis=axis)
+            prob = Problem(mask, eps, s.k, s.d, precond=precond, tol=1e-5, restart=30,
+                           max_iter=2000, dense_axis=axis)
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if precond:
+                    prob.build_preconditioner(0.0)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                o = prob.solve(dirs, pols, return_c=False, xsec=True)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+            finally:
+                prob.close()
+            st = o["stats"][0]
+            line.update(its=st["iters"], converged=bool(st["converged"]), build_s=t1 - t0,
+                        solve_s=t2 - t1, cext=float(o["cext"][0]))
             _emit(line)
         del mask, eps
         torch.cuda.empty_cache()
