@@ -352,8 +352,10 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *fl
   }
 }
 
-// Launch k_gj_inverse with the panel width and rows per thread for order n: 16-column
-// panels up to n = 256 (multipliers 64 KB of LDS at most), 8 columns above.
+// Launch k_gj_inverse with the panel width and rows per thread for order n: 16-column panels
+// up to n = 512 (256 threads, or 512 above n = 256, one row each), 8 columns above (three rows
+// per thread).  Wider panels mean fewer passes over the matrix, which bound the kernel.
+static int gj_nb(int n) { return n <= 2 * kGJThreads ? 16 : 8; }
 static size_t gj_lds(int n, int nb) { return sizeof(double2) * (size_t)n * nb + sizeof(int) * n; }
 static void gj_launch(dda_problem *p, double2 *mats, long long cnt, int n) {
   if (n <= kGJThreads) {
@@ -361,9 +363,10 @@ static void gj_launch(dda_problem *p, double2 *mats, long long cnt, int n) {
     set_lds_limit((const void *)fn, gj_lds(n, 16));
     hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(kGJThreads), gj_lds(n, 16), p->st, mats, n, p->dflag);
   } else if (n <= 2 * kGJThreads) {
-    auto fn = k_gj_inverse<8, kGJThreads, 2>;
-    set_lds_limit((const void *)fn, gj_lds(n, 8));
-    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(kGJThreads), gj_lds(n, 8), p->st, mats, n, p->dflag);
+    auto fn = k_gj_inverse<16, 2 * kGJThreads, 1>;
+    set_lds_limit((const void *)fn, gj_lds(n, 16));
+    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(2 * kGJThreads), gj_lds(n, 16), p->st, mats, n,
+                       p->dflag);
   } else {
     auto fn = k_gj_inverse<8, kGJThreads, 3>;
     set_lds_limit((const void *)fn, gj_lds(n, 8));
@@ -467,9 +470,10 @@ void precond_build(dda_problem *p, double s_bar) {
     }
     const size_t lds_asm = sizeof(double2) * 6 * S;
     set_lds_limit((const void *)k_assemble, lds_asm);
-    const size_t lds_gj = gj_lds(p->n2, p->n2 <= kGJThreads ? 16 : 8);
+    const size_t lds_gj = gj_lds(p->n2, gj_nb(p->n2));
     REQUIRE(p->n2 <= kGJMaxOrder, DDA_EUNSUPPORTED, "half-block order %d above %d", p->n2, kGJMaxOrder);
-    REQUIRE(lds_gj <= p->lds_max && lds_asm <= p->lds_max, DDA_EUNSUPPORTED,
+    const size_t lds_cap = std::max(p->lds_max, kLdsMax);
+    REQUIRE(lds_gj <= lds_cap && lds_asm <= lds_cap, DDA_EUNSUPPORTED,
             "preconditioner blocks too large for LDS (nz = %d)", nz);
     HIPCHK(hipMemsetAsync(p->dflag, 0, sizeof(int) * 4, p->st));
     for (long long m0 = 0; m0 < nmat; m0 += chunk) {
@@ -592,7 +596,7 @@ static void precond1_build(dda_problem *p) {
       chunk = std::min(chunk, nmat);
       HIPCHK(hipMalloc(&scratch, sizeof(double2) * chunk * msz));
     }
-    REQUIRE(gj_lds(n1, n1 <= kGJThreads ? 16 : 8) <= std::max(p->lds_max, kLdsMax), DDA_EUNSUPPORTED,
+    REQUIRE(gj_lds(n1, gj_nb(n1)) <= std::max(p->lds_max, kLdsMax), DDA_EUNSUPPORTED,
             "1-level blocks too large for LDS (order %d)", n1);
     HIPCHK(hipMemsetAsync(p->dflag, 0, sizeof(int) * 4, p->st));
     for (long long m0 = 0; m0 < nmat; m0 += chunk) {
