@@ -14,7 +14,10 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "dda")
 LIB = os.path.join(HERE, "lib", "libdda.so")
 
-SOURCES = ["runtime.hip", "operator.hip", "precond.hip", "krylov.hip", "xsec.hip", "capi.hip"]
+SOURCES = [
+    "runtime.hip", "operator.hip", "zpass_mr.hip", "precond.hip", "krylov.hip", "xsec.hip",
+    "capi.hip",
+]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("DDA_OFFLOAD_ARCH", "gfx950")
@@ -48,7 +51,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = True) -> str:
     os.makedirs(OBJ, exist_ok=True)
     os.makedirs(os.path.dirname(LIB), exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(len(SOURCES), 6)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), 7)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -7,6 +7,7 @@
 #include <tuple>
 
 #include "fft_kernels.h"
+#include "zpass_mr.h"
 #include "zpass_reg.h"
 
 namespace dda {
@@ -379,7 +380,8 @@ void operator_setup(dda_problem *p) {
 void operator_spectrum_setup(dda_problem *p) {
   const long long oct = 6LL * (p->nx + 1) * (p->ny + 1) * (p->nz + 1);
   const int nzz = 2 * p->nz;
-  p->zreg = (nzz >= 32 && nzz <= 256 && (nzz & (nzz - 1)) == 0) ? 1 : 0;
+  int G = 0, P = 0;
+  p->zreg = (nzz >= 32 && nzz <= 256 && (nzz & (nzz - 1)) == 0) ? 1 : zmr_split(nzz, &G, &P) ? 2 : 0;
   HIPCHK(hipMalloc(&p->khat64, sizeof(double2) * oct));
   HIPCHK(hipMalloc(&p->khat32, sizeof(float2) * oct));
   kernel_spectrum(p, 0);
@@ -437,6 +439,14 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, in
     a.tiles_x = (p->nx + 1 + tw - 1) / tw;
     a.nrhs = nrhs;
     a.nblk = (long long)a.tiles_x * (p->ny + 1) * 4 * nrhs;
+    if (p->zreg == 2) {
+      int G = 0, P = 0;
+      zmr_split(n, &G, &P);
+      zmr_launch<T>(n, (unsigned)xcd_grid(a.nblk), 3 * tw * zmr_tpc(G, P), zmr_lds<T>(G, P, tw, p->nz),
+                    p->st, w1, tw_of<T>(p->pz), khat, a);
+      HIPCHK(hipGetLastError());
+      return;
+    }
     const size_t lds = zreg_lds<T>(n, tw, p->nz);
     with_gp<T>(n, [&](auto G, auto P) {
       auto fn = k_zpass_reg<T, decltype(G)::value, decltype(P)::value>;
@@ -475,6 +485,17 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, in
 template <typename T> static int zpass_max_tw(dda_problem *p) {
   const int n = p->pz.n;
   int tw = 1;
+  if (p->zreg == 2) {
+    int G = 0, P = 0;
+    zmr_split(n, &G, &P);
+    while (true) {
+      const int t2 = tw * 2;
+      if (zmr_lds<T>(G, P, t2, p->nz) > 80 * 1024 || 3 * t2 * zmr_tpc(G, P) > 256 || t2 > p->nx + 1)
+        break;
+      tw = t2;
+    }
+    return tw;
+  }
   if (p->zreg) {
     const int G = zreg_g(n);
     while (true) {

@@ -28,6 +28,20 @@ OP_CASES = [
     ((64, 5, 3), 0.6, 10),
     ((128, 3, 4), 0.7, 11),
     ((32, 1, 1), 1.0, 12),
+    # z lengths 36 .. 224 that are not powers of two: the mixed-radix register z pass, one
+    # case per (G, P) split shape, ragged tiles and a 1 x 1 column
+    ((18, 5, 7), 0.7, 13),
+    ((20, 3, 9), 0.6, 14),
+    ((24, 7, 5), 0.7, 15),
+    ((40, 4, 6), 0.7, 16),
+    ((48, 3, 5), 0.8, 17),
+    ((56, 2, 3), 0.7, 18),
+    ((72, 3, 2), 0.7, 19),
+    ((80, 2, 3), 0.6, 20),
+    ((96, 3, 3), 0.7, 21),
+    ((98, 2, 2), 0.7, 22),
+    ((112, 2, 2), 0.7, 23),
+    ((48, 1, 1), 1.0, 24),
 ]
 
 
@@ -60,7 +74,8 @@ def test_operator_vs_dense_matrix(shape, fill, seed):
 
 
 @pytest.mark.parametrize("shape,seed", [((5, 6, 7), 21), ((16, 16, 16), 22), ((12, 20, 9), 23),
-                                        ((64, 6, 5), 24), ((128, 4, 3), 25)])
+                                        ((64, 6, 5), 24), ((128, 4, 3), 25), ((40, 5, 6), 26),
+                                        ((96, 4, 3), 27), ((72, 3, 4), 28)])
 def test_operator_fp32_vs_oracle(shape, seed):
     nz, ny, nx = shape
     s = w.random_mask(nx, ny, nz, 0.7, seed, k=1.3, d=0.3)
@@ -225,6 +240,25 @@ def test_operator_full_size_sampled_rows():
         ref = rows.operator_rows(samples, x[r], s.mask, s.eps, s.k, s.d, S)
         got = np.stack([[y[r][a].ravel()[i] for a in range(3)] for i in samples])
         assert np.abs(got - ref).max() < 1e-10 * np.abs(ref).max(), r
+
+
+def test_operator_96_prism_sampled_rows():
+    """The largest prism grid of the batch workload, 96^3 (z length 192 = 16 x 12, the
+    mixed-radix register z pass), FP64 and FP32: sampled rows by direct summation."""
+    s = w.hex_prism_grid(19.0, 1.0, 96, 1.31)
+    dirs, pols = random_waves(2, 63)
+    occ = np.flatnonzero(s.mask.ravel())
+    rng = np.random.default_rng(63)
+    samples = np.concatenate([occ[[0, len(occ) // 2, -1]], rng.choice(occ, 3, replace=False)])
+    x = rand_field(s.shape, 2, 63, s.mask)
+    with make_problem(s, precond=0, max_rhs=2) as prob:
+        for fp32, tol in ((0, 1e-10), (1, 2e-5)):
+            y = prob.apply_operator(to_dev(x), dirs, pols, fp32=fp32).cpu().numpy()
+            for r in range(2):
+                S = physics.lattice_S(dirs[r], pols[r])
+                ref = rows.operator_rows(samples, x[r], s.mask, s.eps, s.k, s.d, S)
+                got = np.stack([[y[r][a].ravel()[i] for a in range(3)] for i in samples])
+                assert np.abs(got - ref).max() < tol * np.abs(ref).max(), (fp32, r)
 
 
 def test_preconditioner_full_size_sampled_rows():
