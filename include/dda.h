@@ -117,9 +117,14 @@ const char *dda_last_error(void);
  * six components (the per-level parities of Table 1 give the rest).
  *  k > 0: wavenumber; d > 0: voxel edge; opt may be NULL (defaults);
  *  stream: a hipStream_t (NULL = default stream).
+ * Creation also times the fused z-FFT pass's launch shapes on this grid (once
+ * per grid shape and process); the environment variable DDA_ZPASS_FORCE="tw,ipw"
+ * replaces that choice by tw octant columns per tile and ipw items per
+ * workgroup (for tests and benchmarks of that pass).
  * Errors: EINVAL (sizes < 1, k or d <= 0, no occupied voxel, an occupied voxel
- * with eps == 1 or eps == -2 where the polarisability is undefined);
- * EUNSUPPORTED (a dimension not 7-smooth or > 512); ENOMEM; EDEVICE.
+ * with eps == 1 or eps == -2 where the polarisability is undefined, a malformed
+ * or out-of-range DDA_ZPASS_FORCE); EUNSUPPORTED (a dimension not 7-smooth or
+ * > 512); ENOMEM; EDEVICE.
  */
 dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const double *eps_dev,
                       double k, double d, const dda_options *opt, void *stream,

@@ -251,9 +251,9 @@ struct dda_problem {
   size_t lds_max = 65536;      // device LDS per workgroup
   size_t lds_zpass = 98304;    // LDS budget of the fused z pass
   int ztw[2] = {0, 0};         // z-pass columns per tile (FP64, FP32), chosen by autotune
-  int zreg = 0;                // 1: register z pass (2 nz a power of two in [32, 256]); 2: its
-                               // mixed-radix form (2 nz = G P in the supported list); either
-                               // way the kernel spectra are stored z-major, [oy][ox][oz][6]
+  int zipw[2] = {1, 1};        // register z pass: items per workgroup (FP64, FP32), autotuned
+  int zreg = 0;                // 1: register z pass (2 nz = G P in its list of lengths); the
+                               // kernel spectra are then stored z-major, [oy][ox][oz][6]
 
   uint8_t *mask = nullptr;      // [N]
   double2 *eps = nullptr;       // [N]

@@ -1,6 +1,7 @@
 // The DDA operator: problem setup (polarisability, incident field), the Green-tensor
 // kernel spectrum, and the five-pass zero-padded FFT product (Sec. 1, 2.1-2.2).
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -8,7 +9,6 @@
 
 #include "fft_kernels.h"
 #include "zpass_mr.h"
-#include "zpass_reg.h"
 
 namespace dda {
 
@@ -381,7 +381,7 @@ void operator_spectrum_setup(dda_problem *p) {
   const long long oct = 6LL * (p->nx + 1) * (p->ny + 1) * (p->nz + 1);
   const int nzz = 2 * p->nz;
   int G = 0, P = 0;
-  p->zreg = (nzz >= 32 && nzz <= 256 && (nzz & (nzz - 1)) == 0) ? 1 : zmr_split(nzz, &G, &P) ? 2 : 0;
+  p->zreg = zmr_split(nzz, &G, &P) ? 1 : 0;
   HIPCHK(hipMalloc(&p->khat64, sizeof(double2) * oct));
   HIPCHK(hipMalloc(&p->khat32, sizeof(float2) * oct));
   kernel_spectrum(p, 0);
@@ -398,36 +398,19 @@ static void ensure_imag_spectrum(dda_problem *p) {
 
 // ----------------------------------------------------------------------------- the product
 
-// Register z pass for n = G P: (G, P) = (4, 8), (8, 8), (8, 16), (16, 16).
-template <typename T, typename F> static void with_gp(int n, F &&f) {
-  switch (n) {
-    case 32: f(std::integral_constant<int, 4>{}, std::integral_constant<int, 8>{}); break;
-    case 64: f(std::integral_constant<int, 8>{}, std::integral_constant<int, 8>{}); break;
-    case 128: f(std::integral_constant<int, 8>{}, std::integral_constant<int, 16>{}); break;
-    case 256: f(std::integral_constant<int, 16>{}, std::integral_constant<int, 16>{}); break;
-    default: REQUIRE(false, DDA_EUNSUPPORTED, "register z pass: length %d", n);
-  }
-}
-
-static int zreg_g(int n) { return n <= 32 ? 4 : n <= 128 ? 8 : 16; }
-
-// LDS bytes of one register z-pass workgroup with `tw` columns: exchange region, twiddles and
-// the kernel-spectrum slab
-template <typename T> static size_t zreg_lds(int n, int tw, int nz) {
-  return (size_t)3 * tw * n * sizeof(T) + (size_t)n * sizeof(cplx<T>) +
-         (size_t)tw * (nz + 1) * 6 * sizeof(cplx<T>);
-}
-
-// Launch the fused z pass with `tw` columns per tile (a power of two; 0: the autotuned choice).
+// Launch the fused z pass with `tw` columns per tile (a power of two) and, for the register
+// z pass, `ipw` items per workgroup; 0: the autotuned choice.
 template <typename T>
 static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, int tw = 0,
-                  bool timed = true) {
+                  bool timed = true, int ipw = 0) {
   const int n = p->pz.n;
   const double sz = sizeof(cplx<T>);
   const double bytes = nrhs * (2.0 * 3.0 * 4.0 * p->nx * p->ny * p->nz * sz) +
                        6.0 * (p->nx + 1) * (p->ny + 1) * (p->nz + 1) * sz;
   if (tw <= 0) tw = p->ztw[sizeof(T) == 8 ? 0 : 1];
   if (tw <= 0) tw = 1;
+  if (ipw <= 0) ipw = p->zipw[sizeof(T) == 8 ? 0 : 1];
+  if (ipw <= 0) ipw = 1;
   KTimer t(timed ? &p->prof : nullptr, p->st, sizeof(T) == 8 ? "zpass_f64" : "zpass_f32", bytes);
   if (p->zreg) {
     ZRArgs a;
@@ -438,23 +421,13 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, in
     a.tw = tw;
     a.tiles_x = (p->nx + 1 + tw - 1) / tw;
     a.nrhs = nrhs;
-    a.nblk = (long long)a.tiles_x * (p->ny + 1) * 4 * nrhs;
-    if (p->zreg == 2) {
-      int G = 0, P = 0;
-      zmr_split(n, &G, &P);
-      zmr_launch<T>(n, (unsigned)xcd_grid(a.nblk), 3 * tw * zmr_tpc(G, P), zmr_lds<T>(G, P, tw, p->nz),
-                    p->st, w1, tw_of<T>(p->pz), khat, a);
-      HIPCHK(hipGetLastError());
-      return;
-    }
-    const size_t lds = zreg_lds<T>(n, tw, p->nz);
-    with_gp<T>(n, [&](auto G, auto P) {
-      auto fn = k_zpass_reg<T, decltype(G)::value, decltype(P)::value>;
-      set_lds_limit((const void *)fn, lds);
-      const int threads = 3 * tw * decltype(G)::value;
-      hipLaunchKernelGGL(fn, dim3((unsigned)xcd_grid(a.nblk)), dim3(threads), lds, p->st, w1,
-                         tw_of<T>(p->pz), khat, a);
-    });
+    a.ipw = std::min(ipw, 4 * nrhs);
+    a.nch = (4 * nrhs + a.ipw - 1) / a.ipw;
+    a.nblk = (long long)a.tiles_x * (p->ny + 1) * a.nch;
+    int G = 0, P = 0;
+    zmr_split(n, &G, &P);
+    zmr_launch<T>(n, (unsigned)xcd_grid(a.nblk), 3 * tw * zmr_tpc(G, P), zmr_lds<T>(G, P, tw, p->nz),
+                  p->st, w1, tw_of<T>(p->pz), khat, a);
     HIPCHK(hipGetLastError());
     return;
   }
@@ -485,22 +458,13 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, in
 template <typename T> static int zpass_max_tw(dda_problem *p) {
   const int n = p->pz.n;
   int tw = 1;
-  if (p->zreg == 2) {
+  if (p->zreg) {
     int G = 0, P = 0;
     zmr_split(n, &G, &P);
     while (true) {
       const int t2 = tw * 2;
       if (zmr_lds<T>(G, P, t2, p->nz) > 80 * 1024 || 3 * t2 * zmr_tpc(G, P) > 256 || t2 > p->nx + 1)
         break;
-      tw = t2;
-    }
-    return tw;
-  }
-  if (p->zreg) {
-    const int G = zreg_g(n);
-    while (true) {
-      const int t2 = tw * 2;
-      if (zreg_lds<T>(n, t2, p->nz) > 80 * 1024 || 3 * t2 * G > 256 || t2 > p->nx + 1) break;
       tw = t2;
     }
     return tw;
@@ -516,51 +480,73 @@ template <typename T> static int zpass_max_tw(dda_problem *p) {
   return tw;
 }
 
-// Time each power-of-two tile width on the problem's own grid and keep the fastest.
-// Tile widths already measured in this process, per (device, grid, precision): problems of
-// a shape seen before skip the timing runs.
+// Time each power-of-two tile width (and, for the register z pass, each count of items per
+// workgroup) on the problem's own grid at min(max_rhs, 2) right-hand sides and keep the
+// fastest.  Choices already measured in this process, per (device, grid, max_rhs bucket,
+// precision), are reused: problems of a shape seen before skip the timing runs.  The
+// environment variable DDA_ZPASS_FORCE="tw,ipw" overrides the choice (for tests and
+// benchmarks of the z pass itself).
 static std::mutex g_ztw_mu;
-static std::map<std::tuple<int, int, int, int, int>, int> g_ztw;
+static std::map<std::tuple<int, int, int, int, int, int>, std::pair<int, int>> g_ztw;
 
 template <typename T> static void zpass_autotune(dda_problem *p, const cplx<T> *khat) {
+  const int pi = sizeof(T) == 8 ? 0 : 1;
+  const int nt = std::min(p->R, 2);
+  const int tmax = zpass_max_tw<T>(p);
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
-  const auto key = std::make_tuple(dev, p->nx, p->ny, p->nz, (int)sizeof(T));
+  const auto key = std::make_tuple(dev, p->nx, p->ny, p->nz, nt, (int)sizeof(T));
+  bool cached = false;
   {
     std::lock_guard<std::mutex> lk(g_ztw_mu);
     const auto it = g_ztw.find(key);
     if (it != g_ztw.end()) {
-      p->ztw[sizeof(T) == 8 ? 0 : 1] = it->second;
-      return;
+      p->ztw[pi] = it->second.first;
+      p->zipw[pi] = it->second.second;
+      cached = true;
     }
   }
-  const int tmax = zpass_max_tw<T>(p);
-  cplx<T> *w1 = reinterpret_cast<cplx<T> *>(p->w1);
-  HIPCHK(hipMemsetAsync(w1, 0, sizeof(cplx<T>) * 3 * p->nz * p->zplane, p->st));
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  float best = 1e30f;
-  int best_tw = tmax;
-  for (int tw = tmax; tw >= 1; tw /= 2) {
-    zpass<T>(p, 1, w1, khat, tw, false);  // warm
-    HIPCHK(hipEventRecord(e0, p->st));
-    for (int rep = 0; rep < 3; ++rep) zpass<T>(p, 1, w1, khat, tw, false);
-    HIPCHK(hipEventRecord(e1, p->st));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best * 0.97f) {
-      best = ms;
-      best_tw = tw;
+  if (!cached) {
+    cplx<T> *w1 = reinterpret_cast<cplx<T> *>(p->w1);
+    HIPCHK(hipMemsetAsync(w1, 0, sizeof(cplx<T>) * nt * 3 * p->nz * p->zplane, p->st));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_tw = tmax, best_ipw = 1;
+    for (int tw = tmax; tw >= 1; tw /= 2) {
+      for (int ipw = 1; ipw <= (p->zreg ? std::min(8, 4 * nt) : 1); ipw *= 2) {
+        zpass<T>(p, nt, w1, khat, tw, false, ipw);  // warm
+        HIPCHK(hipEventRecord(e0, p->st));
+        for (int rep = 0; rep < 3; ++rep) zpass<T>(p, nt, w1, khat, tw, false, ipw);
+        HIPCHK(hipEventRecord(e1, p->st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best * 0.97f) {
+          best = ms;
+          best_tw = tw;
+          best_ipw = ipw;
+        }
+      }
+      if (tw <= (p->zreg ? 1 : 2)) break;
     }
-    if (tw <= (p->zreg ? 1 : 2)) break;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->ztw[pi] = best_tw;
+    p->zipw[pi] = best_ipw;
+    std::lock_guard<std::mutex> lk(g_ztw_mu);
+    g_ztw[key] = std::make_pair(best_tw, best_ipw);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  p->ztw[sizeof(T) == 8 ? 0 : 1] = best_tw;
-  std::lock_guard<std::mutex> lk(g_ztw_mu);
-  g_ztw[key] = best_tw;
+  if (const char *f = getenv("DDA_ZPASS_FORCE")) {
+    int tw = 0, ipw = 0;
+    REQUIRE(sscanf(f, "%d,%d", &tw, &ipw) == 2 && tw >= 1 && tw <= tmax && (tw & (tw - 1)) == 0 &&
+                ipw >= 1,
+            DDA_EINVAL, "DDA_ZPASS_FORCE=\"%s\": want \"tw,ipw\" with tw a power of two <= %d and ipw >= 1",
+            f, tmax);
+    p->ztw[pi] = tw;
+    p->zipw[pi] = ipw;
+  }
 }
 
 // kind 0: DDA operator; kind 1: Im G convolution (scattering sum)

@@ -1,4 +1,4 @@
-// Instantiations and launcher of the mixed-radix register z pass.
+// Instantiations and launcher of the register z pass.
 #include "fft_kernels.h"
 #include "zpass_mr.h"
 
@@ -15,17 +15,18 @@ static_assert(cx_near(cx_sin2pi(5, 14), 0.78183148246802980871), "roots");
 static_assert(cx_cos2pi(5, 20) == 0.0 && cx_sin2pi(-3, 12) == -1.0, "roots");
 
 namespace {
-// Supported lengths n = G P: G, P even, P <= G <= 16 (registers per thread), G as small as
-// the factorisation allows.  Powers of two have their own register kernel; other lengths use
-// the LDS-staged z pass.
+// Supported lengths n = G P: G, P even and at most 16 (registers per thread), with P = 2 G
+// where that factorisation exists (no idle threads), else P <= G with G as small as the
+// factorisation allows.  Other lengths use the LDS-staged z pass.
 struct Split {
   int n, G, P;
 };
 constexpr Split kSplits[] = {
-    {24, 6, 4},    {36, 6, 6},    {40, 10, 4},   {48, 8, 6},    {56, 14, 4},
-    {60, 10, 6},   {72, 12, 6},   {80, 10, 8},   {84, 14, 6},   {96, 12, 8},
-    {100, 10, 10}, {112, 14, 8},  {120, 12, 10}, {140, 14, 10}, {144, 12, 12},
-    {160, 16, 10}, {168, 14, 12}, {192, 16, 12}, {196, 14, 14}, {224, 16, 14},
+    {24, 6, 4},    {32, 4, 8},    {36, 6, 6},    {40, 10, 4},   {48, 8, 6},
+    {56, 14, 4},   {60, 10, 6},   {64, 8, 8},    {72, 6, 12},   {80, 10, 8},
+    {84, 14, 6},   {96, 12, 8},   {100, 10, 10}, {112, 14, 8},  {120, 12, 10},
+    {128, 8, 16},  {140, 14, 10}, {144, 12, 12}, {160, 16, 10}, {168, 14, 12},
+    {192, 16, 12}, {196, 14, 14}, {224, 16, 14}, {256, 16, 16},
 };
 
 template <typename T, int I = 0>

@@ -23,13 +23,15 @@ OP_CASES = [
     ((1, 1, 1), 1.0, 6),
     ((7, 5, 3), 0.5, 7),
     ((12, 20, 9), 0.7, 8),
-    # z lengths 64, 128, 256: the register z pass, ragged tiles, a 1 x 1 column
+    # z lengths 64, 128, 256 (register z pass splits 8 x 8, 8 x 16, 16 x 16), ragged tiles, a
+    # 1 x 1 column
     ((32, 6, 9), 0.7, 9),
     ((64, 5, 3), 0.6, 10),
     ((128, 3, 4), 0.7, 11),
     ((32, 1, 1), 1.0, 12),
     # z lengths 36 .. 224 that are not powers of two: the mixed-radix register z pass, one
-    # case per (G, P) split shape, ragged tiles and a 1 x 1 column
+    # case per (G, P) split shape (P <= G with idle threads, P = 2 G with two frequency
+    # columns per thread), ragged tiles and a 1 x 1 column
     ((18, 5, 7), 0.7, 13),
     ((20, 3, 9), 0.6, 14),
     ((24, 7, 5), 0.7, 15),
@@ -42,6 +44,7 @@ OP_CASES = [
     ((98, 2, 2), 0.7, 22),
     ((112, 2, 2), 0.7, 23),
     ((48, 1, 1), 1.0, 24),
+    ((36, 4, 5), 0.7, 25),
 ]
 
 
@@ -71,6 +74,32 @@ def test_operator_vs_dense_matrix(shape, fill, seed):
     S = physics.lattice_S(dirs[0], pols[0])
     ref = system.box_operator_dense(s.mask, s.eps, s.k, s.d, S, x[0])
     assert rel_err(y[0], ref) < 1e-10
+
+
+@pytest.mark.parametrize("shape,force", [((16, 5, 7), "1,3"), ((16, 5, 7), "8,8"),
+                                         ((48, 3, 5), "4,5"), ((48, 3, 5), "1,1"),
+                                         ((64, 4, 3), "2,2"), ((128, 2, 3), "4,8")])
+def test_operator_register_zpass_schedules(shape, force, monkeypatch):
+    """The register z pass under forced tile widths and items per workgroup: several items per
+    workgroup with the next one's loads in flight, ragged last chunks, rows without a distinct
+    ky mirror; 5 right-hand sides, FP64 and FP32, against the oracle."""
+    nz, ny, nx = shape
+    s = w.random_mask(nx, ny, nz, 0.7, 71, k=1.3, d=0.3, eps_jitter=0.05)
+    dirs, pols = random_waves(5, 71)
+    dirs, pols = dirs[:5], pols[:5]
+    x = rand_field(shape, 5, 71)
+    monkeypatch.setenv("DDA_ZPASS_FORCE", force)
+    with make_problem(s, precond=0, max_rhs=5) as prob:
+        y64 = prob.apply_operator(to_dev(x), dirs, pols).cpu().numpy()
+        y32 = prob.apply_operator(to_dev(x), dirs, pols, fp32=True).cpu().numpy()
+    for r in range(5):
+        S = physics.lattice_S(dirs[r], pols[r])
+        ref = fftmatvec.fft_matvec(x[r], s.mask, s.eps, s.k, s.d, S)
+        assert rel_err(y64[r], ref) < 1e-10, (force, r)
+        assert rel_err(y32[r], ref) < 1e-5, (force, r)
+    monkeypatch.setenv("DDA_ZPASS_FORCE", "3,1")  # not a power of two: rejected at create
+    with pytest.raises(Exception, match="DDA_ZPASS_FORCE"):
+        make_problem(s, precond=0, max_rhs=5)
 
 
 @pytest.mark.parametrize("shape,seed", [((5, 6, 7), 21), ((16, 16, 16), 22), ((12, 20, 9), 23),
