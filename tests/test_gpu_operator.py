@@ -45,6 +45,7 @@ OP_CASES = [
     ((112, 2, 2), 0.7, 23),
     ((48, 1, 1), 1.0, 24),
     ((36, 4, 5), 0.7, 25),
+    ((256, 2, 3), 0.7, 26),
 ]
 
 
@@ -104,7 +105,7 @@ def test_operator_register_zpass_schedules(shape, force, monkeypatch):
 
 @pytest.mark.parametrize("shape,seed", [((5, 6, 7), 21), ((16, 16, 16), 22), ((12, 20, 9), 23),
                                         ((64, 6, 5), 24), ((128, 4, 3), 25), ((40, 5, 6), 26),
-                                        ((96, 4, 3), 27), ((72, 3, 4), 28)])
+                                        ((96, 4, 3), 27), ((72, 3, 4), 28), ((256, 3, 2), 29)])
 def test_operator_fp32_vs_oracle(shape, seed):
     nz, ny, nx = shape
     s = w.random_mask(nx, ny, nz, 0.7, seed, k=1.3, d=0.3)
