@@ -251,7 +251,7 @@ struct dda_problem {
   size_t lds_max = 65536;      // device LDS per workgroup
   size_t lds_zpass = 98304;    // LDS budget of the fused z pass
   int ztw[2] = {0, 0};         // z-pass columns per tile (FP64, FP32), chosen by autotune
-  int zipw[2] = {1, 1};        // register z pass: items per workgroup (FP64, FP32), autotuned
+  int zipw[2] = {0, 0};        // register z pass: forced items per workgroup (0: by the rule)
   int zreg = 0;                // 1: register z pass (2 nz = G P in its list of lengths); the
                                // kernel spectra are then stored z-major, [oy][ox][oz][6]
 

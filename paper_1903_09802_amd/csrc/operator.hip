@@ -398,8 +398,20 @@ static void ensure_imag_spectrum(dda_problem *p) {
 
 // ----------------------------------------------------------------------------- the product
 
-// Launch the fused z pass with `tw` columns per tile (a power of two) and, for the register
-// z pass, `ipw` items per workgroup; 0: the autotuned choice.
+// Items per workgroup of the register z pass: the most (a power of two up to 16) that still
+// leaves at least 2048 workgroups (8 per CU).  More items per workgroup stage the spectrum
+// slab fewer times and overlap more loads with arithmetic; measured at 128^3 (2 RHS) and at
+// 40^3 - 96^3 (32 RHS), this choice is within 5 % of the best fixed one.
+static int zpass_ipw(long long tiles, int nrhs) {
+  int ipw = 1;
+  while (ipw * 2 <= std::min(16, 4 * nrhs) &&
+         tiles * ((4LL * nrhs + 2 * ipw - 1) / (2 * ipw)) >= 2048)
+    ipw *= 2;
+  return ipw;
+}
+
+// Launch the fused z pass with `tw` columns per tile (a power of two; 0: the autotuned choice)
+// and, for the register z pass, `ipw` items per workgroup (0: zpass_ipw, or the forced value).
 template <typename T>
 static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, int tw = 0,
                   bool timed = true, int ipw = 0) {
@@ -410,7 +422,6 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, in
   if (tw <= 0) tw = p->ztw[sizeof(T) == 8 ? 0 : 1];
   if (tw <= 0) tw = 1;
   if (ipw <= 0) ipw = p->zipw[sizeof(T) == 8 ? 0 : 1];
-  if (ipw <= 0) ipw = 1;
   KTimer t(timed ? &p->prof : nullptr, p->st, sizeof(T) == 8 ? "zpass_f64" : "zpass_f32", bytes);
   if (p->zreg) {
     ZRArgs a;
@@ -421,6 +432,7 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, in
     a.tw = tw;
     a.tiles_x = (p->nx + 1 + tw - 1) / tw;
     a.nrhs = nrhs;
+    if (ipw <= 0) ipw = zpass_ipw((long long)a.tiles_x * (p->ny + 1), nrhs);
     a.ipw = std::min(ipw, 4 * nrhs);
     a.nch = (4 * nrhs + a.ipw - 1) / a.ipw;
     a.nblk = (long long)a.tiles_x * (p->ny + 1) * a.nch;
@@ -480,18 +492,17 @@ template <typename T> static int zpass_max_tw(dda_problem *p) {
   return tw;
 }
 
-// Time each power-of-two tile width (and, for the register z pass, each count of items per
-// workgroup) on the problem's own grid at min(max_rhs, 2) right-hand sides and keep the
-// fastest.  Choices already measured in this process, per (device, grid, max_rhs bucket,
-// precision), are reused: problems of a shape seen before skip the timing runs.  The
-// environment variable DDA_ZPASS_FORCE="tw,ipw" overrides the choice (for tests and
-// benchmarks of the z pass itself).
+// Time each power-of-two tile width on the problem's own grid at min(max_rhs, 8) right-hand
+// sides (the best width shifts with the RHS count) and keep the fastest.  Widths already measured in this process, per (device, grid,
+// RHS count, precision), are reused: problems of a shape seen before skip the timing runs.
+// The environment variable DDA_ZPASS_FORCE="tw,ipw" replaces the width and the items per
+// workgroup (for tests and benchmarks of the z pass itself).
 static std::mutex g_ztw_mu;
-static std::map<std::tuple<int, int, int, int, int, int>, std::pair<int, int>> g_ztw;
+static std::map<std::tuple<int, int, int, int, int, int>, int> g_ztw;
 
 template <typename T> static void zpass_autotune(dda_problem *p, const cplx<T> *khat) {
   const int pi = sizeof(T) == 8 ? 0 : 1;
-  const int nt = std::min(p->R, 2);
+  const int nt = std::min(p->R, 8);
   const int tmax = zpass_max_tw<T>(p);
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -501,8 +512,7 @@ template <typename T> static void zpass_autotune(dda_problem *p, const cplx<T> *
     std::lock_guard<std::mutex> lk(g_ztw_mu);
     const auto it = g_ztw.find(key);
     if (it != g_ztw.end()) {
-      p->ztw[pi] = it->second.first;
-      p->zipw[pi] = it->second.second;
+      p->ztw[pi] = it->second;
       cached = true;
     }
   }
@@ -513,30 +523,26 @@ template <typename T> static void zpass_autotune(dda_problem *p, const cplx<T> *
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
-    int best_tw = tmax, best_ipw = 1;
+    int best_tw = tmax;
     for (int tw = tmax; tw >= 1; tw /= 2) {
-      for (int ipw = 1; ipw <= (p->zreg ? std::min(8, 4 * nt) : 1); ipw *= 2) {
-        zpass<T>(p, nt, w1, khat, tw, false, ipw);  // warm
-        HIPCHK(hipEventRecord(e0, p->st));
-        for (int rep = 0; rep < 3; ++rep) zpass<T>(p, nt, w1, khat, tw, false, ipw);
-        HIPCHK(hipEventRecord(e1, p->st));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best * 0.97f) {
-          best = ms;
-          best_tw = tw;
-          best_ipw = ipw;
-        }
+      zpass<T>(p, nt, w1, khat, tw, false);  // warm
+      HIPCHK(hipEventRecord(e0, p->st));
+      for (int rep = 0; rep < 3; ++rep) zpass<T>(p, nt, w1, khat, tw, false);
+      HIPCHK(hipEventRecord(e1, p->st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best * 0.97f) {
+        best = ms;
+        best_tw = tw;
       }
       if (tw <= (p->zreg ? 1 : 2)) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p->ztw[pi] = best_tw;
-    p->zipw[pi] = best_ipw;
     std::lock_guard<std::mutex> lk(g_ztw_mu);
-    g_ztw[key] = std::make_pair(best_tw, best_ipw);
+    g_ztw[key] = best_tw;
   }
   if (const char *f = getenv("DDA_ZPASS_FORCE")) {
     int tw = 0, ipw = 0;
