@@ -26,6 +26,7 @@
 // the full halves are stored column-major.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "fft_kernels.h"
 
@@ -83,7 +84,8 @@ __global__ void k_chan_gen(double2 *gen, int nx, int ny, int nz, double k, doubl
 // Assemble the transposed half-blocks X = B_sigma^T (row-major) for matrices
 // [m0, m0 + count) of the list (mode u = m / 2, half = m % 2: 0 even, 1 odd).
 // With sym != 0 the block written is M = S B_sigma (symmetric) instead of B_sigma^T.
-__global__ void k_assemble(const double2 *lam, double2 *out, long long m0, int nx, int ny,
+template <typename TO>
+__global__ void k_assemble(const double2 *lam, TO *out, long long m0, int nx, int ny,
                            int nz, int umx, int hh, int n2, double2 ati, int sym) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double2 *L = reinterpret_cast<double2 *>(smem_raw);  // [6][2nz-1]
@@ -101,7 +103,7 @@ __global__ void k_assemble(const double2 *lam, double2 *out, long long m0, int n
   __syncthreads();
   const double sig = half == 0 ? 1.0 : -1.0;
   const int h = nz / 2;
-  double2 *X = out + (long long)blockIdx.x * n2 * n2;
+  TO *X = out + (long long)blockIdx.x * n2 * n2;
   for (long long e = threadIdx.x; e < (long long)n2 * n2; e += blockDim.x) {
     const int row = (int)(e / n2), col = (int)(e % n2);
     // X[row][col] = B_sigma[col][row]: B row index (a, iz) = col, column index (b, jz) = row
@@ -130,24 +132,24 @@ __global__ void k_assemble(const double2 *lam, double2 *out, long long m0, int n
       }
       if (sym && a == 2) val = make_double2(-val.x, -val.y);
     }
-    X[e] = val;
+    X[e] = to_c(val, TO{});
   }
 }
 
 // Gauss-Jordan step for one trailing column j and the panel [k0, k0 + kb): from the
 // column's (row-swapped) pivot-row entries, tv[kk] are the multiples of the panel's
 // eliminated columns it receives and aK its new pivot-row entries.
-template <int NB>
-__device__ __forceinline__ void gj_pivot_rows(const double2 *A, int n, int j, int k0, int kb,
-                                              const double2 *F, const double2 *ipv,
-                                              double2 (&aK)[NB], double2 (&tv)[NB]) {
+template <int NB, typename V>
+__device__ __forceinline__ void gj_pivot_rows(const V *A, int n, int j, int k0, int kb, const V *F,
+                                              const V *ipv, V (&aK)[NB], V (&tv)[NB]) {
+  using R = typename RealOf<V>::type;
 #pragma unroll
   for (int kk = 0; kk < NB; ++kk)
-    aK[kk] = kk < kb ? A[(long long)(k0 + kk) * n + j] : make_double2(0.0, 0.0);
+    aK[kk] = kk < kb ? A[(long long)(k0 + kk) * n + j] : mk<R>((R)0, (R)0);
 #pragma unroll
   for (int kk = 0; kk < NB; ++kk) {
-    if (kk >= kb) { tv[kk] = make_double2(0.0, 0.0); continue; }
-    const double2 t = cmul(aK[kk], ipv[kk]);
+    if (kk >= kb) { tv[kk] = mk<R>((R)0, (R)0); continue; }
+    const V t = cmul(aK[kk], ipv[kk]);
     tv[kk] = t;
 #pragma unroll
     for (int k2 = 0; k2 < NB; ++k2)
@@ -160,7 +162,7 @@ constexpr int kGJMaxOrder = 768;  // the largest half-block order, 3 * 256
 constexpr size_t kLdsMax = 160 * 1024;  // LDS of one gfx950 CU, the most one workgroup can take
 constexpr int kGJThreads = 256;
 
-// Batched in-place inverse of row-major n x n complex matrices, one workgroup each:
+// Batched in-place inverse of row-major n x n complex matrices (FP64 or FP32), one workgroup each:
 // Gauss-Jordan elimination with partial pivoting, blocked by NB columns.  For each panel of
 // NB columns the pivot steps run on rows held in registers (thread t owns rows t + r NT,
 // r < RPT); per step a wave-shuffle argmax picks the pivot, the pivot row and the old row k
@@ -168,46 +170,47 @@ constexpr int kGJThreads = 256;
 // receive the panel's row swaps, a short recurrence over the NB pivot rows and a rank-NB
 // update of the remaining rows.  Column interchanges are undone at the end.  A zero pivot
 // sets flag[0].
-template <int NB, int NT, int RPT>
-__global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *flag) {
+template <int NB, int NT, int RPT, typename V>
+__global__ void __launch_bounds__(NT) k_gj_inverse(V *mats, int n, int *flag) {
+  using R = typename RealOf<V>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double2 *F = reinterpret_cast<double2 *>(smem_raw);         // [n][NB]
+  V *F = reinterpret_cast<V *>(smem_raw);                     // [n][NB]
   int *pivall = reinterpret_cast<int *>(F + (size_t)n * NB);  // [n]
-  __shared__ double2 ipv_s[NB], prow[NB], krow[NB];
-  __shared__ double red_v[NT / 64];
+  __shared__ V ipv_s[NB], prow[NB], krow[NB];
+  __shared__ R red_v[NT / 64];
   __shared__ int red_i[NT / 64];
   const int tid = threadIdx.x;
-  double2 *A = mats + (long long)blockIdx.x * n * n;
+  V *A = mats + (long long)blockIdx.x * n * n;
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int kb = min(NB, n - k0);
-    double2 rv[RPT][NB];
+    V rv[RPT][NB];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int i = tid + r * NT;
 #pragma unroll
       for (int c = 0; c < NB; ++c)
-        rv[r][c] = (i < n && c < kb) ? A[(long long)i * n + k0 + c] : make_double2(0.0, 0.0);
+        rv[r][c] = (i < n && c < kb) ? A[(long long)i * n + k0 + c] : mk<R>((R)0, (R)0);
     }
-    for (int e = tid; e < n * NB; e += NT) F[e] = make_double2(0.0, 0.0);
+    for (int e = tid; e < n * NB; e += NT) F[e] = mk<R>((R)0, (R)0);
     __syncthreads();
     for (int kk = 0; kk < kb; ++kk) {
       const int k = k0 + kk;
       // pivot: argmax |row i, column kk| over rows i >= k, ties to the smallest row
-      double bv = -1.0;
+      R bv = (R)-1;
       int bi = n;
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
         const int i = tid + r * NT;
-        double2 v = rv[r][0];
+        V v = rv[r][0];
 #pragma unroll
         for (int c = 1; c < NB; ++c)
           if (c == kk) v = rv[r][c];
-        const double m2 = v.x * v.x + v.y * v.y;
+        const R m2 = v.x * v.x + v.y * v.y;
         if (i < n && i >= k && m2 > bv) { bv = m2; bi = i; }
       }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off, 64);
+        const R ov = __shfl_xor(bv, off, 64);
         const int oi = __shfl_xor(bi, off, 64);
         if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
       }
@@ -234,21 +237,21 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *fl
           for (int c = 0; c < NB; ++c) krow[c] = rv[r][c];
       }
       if (tid < kk && pr != k) {
-        const double2 t = F[k * NB + tid];
+        const V t = F[k * NB + tid];
         F[k * NB + tid] = F[pr * NB + tid];
         F[pr * NB + tid] = t;
       }
       __syncthreads();
-      double2 pv = prow[0];
+      V pv = prow[0];
 #pragma unroll
       for (int c = 1; c < NB; ++c)
         if (c == kk) pv = prow[c];
-      const double pm = pv.x * pv.x + pv.y * pv.y;
-      const double2 ipv = pm > 0.0 ? make_double2(pv.x / pm, -pv.y / pm) : make_double2(0.0, 0.0);
+      const R pm = pv.x * pv.x + pv.y * pv.y;
+      const V ipv = pm > (R)0 ? mk<R>(pv.x / pm, -pv.y / pm) : mk<R>((R)0, (R)0);
       if (tid == 0) {
         pivall[k] = pr;
         ipv_s[kk] = ipv;
-        if (pm == 0.0) atomicExch(flag, 1);
+        if (pm == (R)0) atomicExch(flag, 1);
       }
       // swap rows k and pr, scale the pivot row, eliminate column kk from the other rows
 #pragma unroll
@@ -258,20 +261,20 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *fl
         if (i == k) {
 #pragma unroll
           for (int c = 0; c < NB; ++c) rv[r][c] = (c == kk) ? ipv : cmul(prow[c], ipv);
-          F[k * NB + kk] = make_double2(0.0, 0.0);
+          F[k * NB + kk] = mk<R>((R)0, (R)0);
         } else {
           if (i == pr)
 #pragma unroll
             for (int c = 0; c < NB; ++c) rv[r][c] = krow[c];
-          double2 f = rv[r][0];
+          V f = rv[r][0];
 #pragma unroll
           for (int c = 1; c < NB; ++c)
             if (c == kk) f = rv[r][c];
           F[i * NB + kk] = f;
-          const double2 fi = cmul(f, ipv);
+          const V fi = cmul(f, ipv);
 #pragma unroll
           for (int c = 0; c < NB; ++c)
-            rv[r][c] = (c == kk) ? make_double2(-fi.x, -fi.y) : csub(rv[r][c], cmul(fi, prow[c]));
+            rv[r][c] = (c == kk) ? mk<R>(-fi.x, -fi.y) : csub(rv[r][c], cmul(fi, prow[c]));
         }
       }
       // the next step writes prow / krow only after its first barrier, which every thread
@@ -298,7 +301,7 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *fl
       for (int kk = 0; kk < kb; ++kk) {
         const int k = k0 + kk, pr = pivall[k];
         if (pr != k) {
-          double2 t = A[(long long)k * n + j];
+          V t = A[(long long)k * n + j];
           A[(long long)k * n + j] = A[(long long)pr * n + j];
           A[(long long)pr * n + j] = t;
         }
@@ -309,19 +312,19 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *fl
     for (int w = tid; w < kRG * ncol; w += NT) {
       const int cgrp = w / ncol, jj = w - cgrp * ncol;
       const int j = jj < k0 ? jj : jj + kb;
-      double2 aK[NB], tv[NB];
-      gj_pivot_rows<NB>(A, n, j, k0, kb, F, ipv_s, aK, tv);
+      V aK[NB], tv[NB];
+      gj_pivot_rows<NB, V>(A, n, j, k0, kb, F, ipv_s, aK, tv);
       const int i0 = cgrp * rows_per, i1 = min(n, i0 + rows_per);
       for (int ib = i0; ib < i1; ib += 16) {
-        double2 av[16];
+        V av[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u)
-          av[u] = ib + u < i1 ? A[(long long)(ib + u) * n + j] : make_double2(0.0, 0.0);
+          av[u] = ib + u < i1 ? A[(long long)(ib + u) * n + j] : mk<R>((R)0, (R)0);
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           const int i = ib + u;
           if (i >= i1 || (i >= k0 && i < k0 + kb)) continue;
-          double2 acc = av[u];
+          V acc = av[u];
 #pragma unroll
           for (int kk = 0; kk < NB; ++kk) acc = csub(acc, cmul(F[i * NB + kk], tv[kk]));
           A[(long long)i * n + j] = acc;
@@ -331,8 +334,8 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *fl
     __syncthreads();
     for (int jj = tid; jj < ncol; jj += NT) {
       const int j = jj < k0 ? jj : jj + kb;
-      double2 aK[NB], tv[NB];
-      gj_pivot_rows<NB>(A, n, j, k0, kb, F, ipv_s, aK, tv);
+      V aK[NB], tv[NB];
+      gj_pivot_rows<NB, V>(A, n, j, k0, kb, F, ipv_s, aK, tv);
 #pragma unroll
       for (int kk = 0; kk < NB; ++kk)
         if (kk < kb) A[(long long)(k0 + kk) * n + j] = aK[kk];
@@ -344,7 +347,7 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *fl
     for (int k = n - 1; k >= 0; --k) {
       const int pr = pivall[k];
       if (pr != k) {
-        double2 t = A[(long long)i * n + k];
+        V t = A[(long long)i * n + k];
         A[(long long)i * n + k] = A[(long long)i * n + pr];
         A[(long long)i * n + pr] = t;
       }
@@ -352,25 +355,32 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(double2 *mats, int n, int *fl
   }
 }
 
-// Launch k_gj_inverse with the panel width and rows per thread for order n: 16-column panels
-// up to n = 512 (256 threads, or 512 above n = 256, one row each), 8 columns above (three rows
-// per thread).  Wider panels mean fewer passes over the matrix, which bound the kernel.
-static int gj_nb(int n) { return n <= 2 * kGJThreads ? 16 : 8; }
-static size_t gj_lds(int n, int nb) { return sizeof(double2) * (size_t)n * nb + sizeof(int) * n; }
-static void gj_launch(dda_problem *p, double2 *mats, long long cnt, int n) {
+// Launch k_gj_inverse with the panel width and rows per thread for order n.  FP64: 16-column
+// panels up to n = 512 (256 threads, or 512 above n = 256, one row each), 8 columns above
+// (three rows per thread).  FP32 (half the bytes per entry, so twice the panel fits the same
+// LDS and registers): 32-column panels up to n = 512, 16 above.  Wider panels mean fewer
+// passes over the matrix, which bound the kernel.
+template <typename V> static int gj_nb(int n) {
+  return (n <= 2 * kGJThreads ? 16 : 8) * (sizeof(V) == sizeof(float2) ? 2 : 1);
+}
+template <typename V> static size_t gj_lds(int n) {
+  return sizeof(V) * (size_t)n * gj_nb<V>(n) + sizeof(int) * n;
+}
+template <typename V> static void gj_launch(dda_problem *p, V *mats, long long cnt, int n) {
+  constexpr int W = sizeof(V) == sizeof(float2) ? 2 : 1;  // panel width factor
+  const size_t lds = gj_lds<V>(n);
   if (n <= kGJThreads) {
-    auto fn = k_gj_inverse<16, kGJThreads, 1>;
-    set_lds_limit((const void *)fn, gj_lds(n, 16));
-    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(kGJThreads), gj_lds(n, 16), p->st, mats, n, p->dflag);
+    auto fn = k_gj_inverse<16 * W, kGJThreads, 1, V>;
+    set_lds_limit((const void *)fn, lds);
+    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(kGJThreads), lds, p->st, mats, n, p->dflag);
   } else if (n <= 2 * kGJThreads) {
-    auto fn = k_gj_inverse<16, 2 * kGJThreads, 1>;
-    set_lds_limit((const void *)fn, gj_lds(n, 16));
-    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(2 * kGJThreads), gj_lds(n, 16), p->st, mats, n,
-                       p->dflag);
+    auto fn = k_gj_inverse<16 * W, 2 * kGJThreads, 1, V>;
+    set_lds_limit((const void *)fn, lds);
+    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(2 * kGJThreads), lds, p->st, mats, n, p->dflag);
   } else {
-    auto fn = k_gj_inverse<8, kGJThreads, 3>;
-    set_lds_limit((const void *)fn, gj_lds(n, 8));
-    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(kGJThreads), gj_lds(n, 8), p->st, mats, n, p->dflag);
+    auto fn = k_gj_inverse<8 * W, kGJThreads, 3, V>;
+    set_lds_limit((const void *)fn, lds);
+    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(kGJThreads), lds, p->st, mats, n, p->dflag);
   }
   HIPCHK(hipGetLastError());
 }
@@ -389,10 +399,10 @@ __host__ __device__ __forceinline__ int tile_pos(int r, int c) { return r + 16 *
 
 // Pack the lower-triangle tiles (I >= J, tile t = I (I + 1) / 2 + J) of `cnt` symmetric
 // row-major n2 x n2 matrices into out + m0 * tiles * 256; entries beyond n2 are zero.
-template <typename TO>
-__global__ void k_pack_sym(const double2 *Y, TO *out, long long m0, int n2, int ntr) {
+template <typename TI, typename TO>
+__global__ void k_pack_sym(const TI *Y, TO *out, long long m0, int n2, int ntr) {
   const long long tiles = (long long)ntr * (ntr + 1) / 2;
-  const double2 *Ym = Y + (long long)blockIdx.x * n2 * n2;
+  const TI *Ym = Y + (long long)blockIdx.x * n2 * n2;
   TO *o = out + (m0 + blockIdx.x) * tiles * 256;
   for (long long e = threadIdx.x; e < tiles * 256; e += blockDim.x) {
     const long long t = e >> 8;
@@ -404,7 +414,7 @@ __global__ void k_pack_sym(const double2 *Y, TO *out, long long m0, int n2, int 
     // invert tile_pos: w = r + 16 (c % 4) + 64 (c / 4)
     const int r = w & 15, c = 4 * (w >> 6) + ((w >> 4) & 3);
     const int row = 16 * I + r, col = 16 * J + c;
-    const double2 v = (row < n2 && col < n2) ? Ym[(long long)row * n2 + col] : make_double2(0.0, 0.0);
+    const double2 v = (row < n2 && col < n2) ? to_d(Ym[(long long)row * n2 + col]) : make_double2(0.0, 0.0);
     o[t * 256 + w] = to_c(v, TO{});
   }
 }
@@ -461,48 +471,50 @@ void precond_build(dda_problem *p, double s_bar) {
 
     if (fp32) HIPCHK(hipMalloc(&p->binv32, final_bytes));
     else HIPCHK(hipMalloc(&p->binv64, final_bytes));
+    // Blocks are assembled and inverted in the precision they are applied in (FP32 blocks by
+    // FP32 Gauss-Jordan); symmetric halves go through scratch to be packed into tiles, full
+    // (odd nz) ones are inverted in place.
+    const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
     long long chunk = nmat;
-    const bool staged = fp32 || p->psym;  // inverses formed in FP64 scratch, then converted
-    if (staged) {
-      chunk = std::max<long long>(1, (long long)((1ULL << 31) / (msz * sizeof(double2))));
+    if (p->psym) {
+      chunk = std::max<long long>(1, (long long)((1ULL << 31) / (msz * esz)));
       chunk = std::min(chunk, nmat);
-      HIPCHK(hipMalloc(&scratch, sizeof(double2) * chunk * msz));
+      HIPCHK(hipMalloc(&scratch, esz * chunk * msz));
     }
     const size_t lds_asm = sizeof(double2) * 6 * S;
-    set_lds_limit((const void *)k_assemble, lds_asm);
-    const size_t lds_gj = gj_lds(p->n2, gj_nb(p->n2));
+    set_lds_limit((const void *)k_assemble<double2>, lds_asm);
+    set_lds_limit((const void *)k_assemble<float2>, lds_asm);
+    const size_t lds_gj = fp32 ? gj_lds<float2>(p->n2) : gj_lds<double2>(p->n2);
     REQUIRE(p->n2 <= kGJMaxOrder, DDA_EUNSUPPORTED, "half-block order %d above %d", p->n2, kGJMaxOrder);
     const size_t lds_cap = std::max(p->lds_max, kLdsMax);
     REQUIRE(lds_gj <= lds_cap && lds_asm <= lds_cap, DDA_EUNSUPPORTED,
             "preconditioner blocks too large for LDS (nz = %d)", nz);
     HIPCHK(hipMemsetAsync(p->dflag, 0, sizeof(int) * 4, p->st));
-    for (long long m0 = 0; m0 < nmat; m0 += chunk) {
-      const long long cnt = std::min(chunk, nmat - m0);
-      double2 *dst = staged ? scratch : p->binv64 + m0 * msz;
+    auto run = [&](auto *dst, auto *final_out, long long m0, long long cnt) {
+      using V = std::remove_pointer_t<decltype(dst)>;
       {
-        KTimer t(&p->prof, p->st, "pc_assemble", 16.0 * cnt * msz);
-        hipLaunchKernelGGL(k_assemble, dim3((unsigned)cnt), dim3(256), lds_asm, p->st, gen, dst, m0,
-                           nx, ny, nz, p->umx, p->hh, p->n2, p->ati, p->psym);
+        KTimer t(&p->prof, p->st, "pc_assemble", (double)esz * cnt * msz);
+        hipLaunchKernelGGL(k_assemble<V>, dim3((unsigned)cnt), dim3(256), lds_asm, p->st, gen, dst,
+                           m0, nx, ny, nz, p->umx, p->hh, p->n2, p->ati, p->psym);
         HIPCHK(hipGetLastError());
       }
       {
-        KTimer t(&p->prof, p->st, "pc_gj_inverse", 32.0 * cnt * msz);
-        gj_launch(p, dst, cnt, p->n2);
-        HIPCHK(hipGetLastError());
+        KTimer t(&p->prof, p->st, "pc_gj_inverse", 2.0 * esz * cnt * msz);
+        gj_launch<V>(p, dst, cnt, p->n2);
       }
       if (p->psym) {
-        if (fp32)
-          hipLaunchKernelGGL(k_pack_sym<float2>, dim3((unsigned)cnt), dim3(256), 0, p->st, dst,
-                             p->binv32, m0, p->n2, p->ntr);
-        else
-          hipLaunchKernelGGL(k_pack_sym<double2>, dim3((unsigned)cnt), dim3(256), 0, p->st, dst,
-                             p->binv64, m0, p->n2, p->ntr);
-        HIPCHK(hipGetLastError());
-      } else if (fp32) {
-        hipLaunchKernelGGL(k_to_f32, dim3(nblk(cnt * msz, 256)), dim3(256), 0, p->st, dst,
-                           p->binv32 + m0 * msz, cnt * msz);
+        hipLaunchKernelGGL((k_pack_sym<V, std::remove_pointer_t<decltype(final_out)>>),
+                           dim3((unsigned)cnt), dim3(256), 0, p->st, dst, final_out, m0, p->n2,
+                           p->ntr);
         HIPCHK(hipGetLastError());
       }
+    };
+    for (long long m0 = 0; m0 < nmat; m0 += chunk) {
+      const long long cnt = std::min(chunk, nmat - m0);
+      if (fp32)
+        run(p->psym ? reinterpret_cast<float2 *>(scratch) : p->binv32 + m0 * msz, p->binv32, m0, cnt);
+      else
+        run(p->psym ? scratch : p->binv64 + m0 * msz, p->binv64, m0, cnt);
     }
     int hflag[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(hflag, p->dflag, sizeof(int) * 4, hipMemcpyDeviceToHost, p->st));
@@ -596,7 +608,7 @@ static void precond1_build(dda_problem *p) {
       chunk = std::min(chunk, nmat);
       HIPCHK(hipMalloc(&scratch, sizeof(double2) * chunk * msz));
     }
-    REQUIRE(gj_lds(n1, gj_nb(n1)) <= std::max(p->lds_max, kLdsMax), DDA_EUNSUPPORTED,
+    REQUIRE(gj_lds<double2>(n1) <= std::max(p->lds_max, kLdsMax), DDA_EUNSUPPORTED,
             "1-level blocks too large for LDS (order %d)", n1);
     HIPCHK(hipMemsetAsync(p->dflag, 0, sizeof(int) * 4, p->st));
     for (long long m0 = 0; m0 < nmat; m0 += chunk) {
