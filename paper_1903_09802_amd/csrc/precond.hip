@@ -139,22 +139,38 @@ __global__ void k_assemble(const double2 *lam, TO *out, long long m0, int nx, in
 // Gauss-Jordan step for one trailing column j and the panel [k0, k0 + kb): from the
 // column's (row-swapped) pivot-row entries, tv[kk] are the multiples of the panel's
 // eliminated columns it receives and aK its new pivot-row entries.
+// Column j against the panel's NB pivot rows k0 .. k0 + kb - 1 (already swapped into place):
+// the multipliers t_kk that the panel's pivot steps apply to column j.  Step kk scales the
+// pivot-row entry by 1 / pivot and removes it from the later pivot rows' entries; earlier
+// pivot rows' entries are not needed for the multipliers and are left alone.
 template <int NB, typename V>
-__device__ __forceinline__ void gj_pivot_rows(const V *A, int n, int j, int k0, int kb, const V *F,
-                                              const V *ipv, V (&aK)[NB], V (&tv)[NB]) {
+__device__ __forceinline__ void gj_col_mult(const V *A, int n, int j, int k0, int kb, const V *F,
+                                            const V *ipv, V (&a)[NB]) {
   using R = typename RealOf<V>::type;
 #pragma unroll
   for (int kk = 0; kk < NB; ++kk)
-    aK[kk] = kk < kb ? A[(long long)(k0 + kk) * n + j] : mk<R>((R)0, (R)0);
+    a[kk] = kk < kb ? A[(long long)(k0 + kk) * n + j] : mk<R>((R)0, (R)0);
 #pragma unroll
   for (int kk = 0; kk < NB; ++kk) {
-    if (kk >= kb) { tv[kk] = mk<R>((R)0, (R)0); continue; }
-    const V t = cmul(aK[kk], ipv[kk]);
-    tv[kk] = t;
+    if (kk >= kb) continue;
+    const V t = cmul(a[kk], ipv[kk]);
+    a[kk] = t;
 #pragma unroll
-    for (int k2 = 0; k2 < NB; ++k2)
-      if (k2 != kk && k2 < kb) aK[k2] = csub(aK[k2], cmul(F[(k0 + k2) * NB + kk], t));
-    aK[kk] = t;
+    for (int k2 = kk + 1; k2 < NB; ++k2)
+      if (k2 < kb) a[k2] = csub(a[k2], cmul(F[(k0 + k2) * NB + kk], t));
+  }
+}
+
+// The pivot rows' final entries in column j from its multipliers (in place): row k0 + kk ends
+// as t_kk minus the later steps' multiples of it, t_kk - sum_{kk' > kk} F[k0 + kk][kk'] t_kk'.
+template <int NB, typename V>
+__device__ __forceinline__ void gj_pivot_vals(int k0, int kb, const V *F, V (&a)[NB]) {
+#pragma unroll
+  for (int kk = 0; kk < NB; ++kk) {
+    if (kk >= kb) continue;
+#pragma unroll
+    for (int k2 = kk + 1; k2 < NB; ++k2)
+      if (k2 < kb) a[kk] = csub(a[kk], cmul(F[(k0 + kk) * NB + k2], a[k2]));
   }
 }
 
@@ -290,9 +306,9 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(V *mats, int n, int *flag) {
     }
     // Trailing columns, in three barrier-separated phases so that no pivot-row value is read
     // after it has been replaced: (A) the panel's row swaps, one thread per column; (B) kRG
-    // threads per column each form the NB pivot-row values (the short recurrence) and
-    // update their share of the other rows, sixteen rows of loads in flight; (C) one thread
-    // per column forms them again and stores them in the pivot rows.
+    // threads per column each form the column's NB multipliers (a short recurrence over the
+    // pivot rows) and update their share of the other rows, sixteen rows of loads in flight;
+    // (C) one thread per column forms them again and stores the pivot rows' final entries.
     __syncthreads();
     constexpr int kRG = 4;
     const int ncol = n - kb;
@@ -312,8 +328,8 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(V *mats, int n, int *flag) {
     for (int w = tid; w < kRG * ncol; w += NT) {
       const int cgrp = w / ncol, jj = w - cgrp * ncol;
       const int j = jj < k0 ? jj : jj + kb;
-      V aK[NB], tv[NB];
-      gj_pivot_rows<NB, V>(A, n, j, k0, kb, F, ipv_s, aK, tv);
+      V tv[NB];
+      gj_col_mult<NB, V>(A, n, j, k0, kb, F, ipv_s, tv);
       const int i0 = cgrp * rows_per, i1 = min(n, i0 + rows_per);
       for (int ib = i0; ib < i1; ib += 16) {
         V av[16];
@@ -334,8 +350,9 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(V *mats, int n, int *flag) {
     __syncthreads();
     for (int jj = tid; jj < ncol; jj += NT) {
       const int j = jj < k0 ? jj : jj + kb;
-      V aK[NB], tv[NB];
-      gj_pivot_rows<NB, V>(A, n, j, k0, kb, F, ipv_s, aK, tv);
+      V aK[NB];
+      gj_col_mult<NB, V>(A, n, j, k0, kb, F, ipv_s, aK);
+      gj_pivot_vals<NB, V>(k0, kb, F, aK);
 #pragma unroll
       for (int kk = 0; kk < NB; ++kk)
         if (kk < kb) A[(long long)(k0 + kk) * n + j] = aK[kk];
