@@ -372,30 +372,27 @@ __global__ void __launch_bounds__(NT) k_gj_inverse(V *mats, int n, int *flag) {
   }
 }
 
-// Launch k_gj_inverse with the panel width and rows per thread for order n.  FP64: 16-column
-// panels up to n = 512 (256 threads, or 512 above n = 256, one row each), 8 columns above
-// (three rows per thread).  FP32 (half the bytes per entry, so twice the panel fits the same
-// LDS and registers): 32-column panels up to n = 512, 16 above.  Wider panels mean fewer
-// passes over the matrix, which bound the kernel.
-template <typename V> static int gj_nb(int n) {
-  return (n <= 2 * kGJThreads ? 16 : 8) * (sizeof(V) == sizeof(float2) ? 2 : 1);
-}
+// Launch k_gj_inverse with the panel width and rows per thread for order n: 16-column panels
+// up to n = 512 (256 threads, or 512 above n = 256, one row each), 8 columns above (three rows
+// per thread), in either precision.  Wider panels mean fewer passes over the matrix but more
+// LDS per workgroup: 32-column FP32 panels, which fit, ran slower (39.7 vs 21.8 ms at order
+// 192, 927 vs 837 ms at order 384 for a 256^3 build) because fewer workgroups share a CU.
+template <typename V> static int gj_nb(int n) { return n <= 2 * kGJThreads ? 16 : 8; }
 template <typename V> static size_t gj_lds(int n) {
   return sizeof(V) * (size_t)n * gj_nb<V>(n) + sizeof(int) * n;
 }
 template <typename V> static void gj_launch(dda_problem *p, V *mats, long long cnt, int n) {
-  constexpr int W = sizeof(V) == sizeof(float2) ? 2 : 1;  // panel width factor
   const size_t lds = gj_lds<V>(n);
   if (n <= kGJThreads) {
-    auto fn = k_gj_inverse<16 * W, kGJThreads, 1, V>;
+    auto fn = k_gj_inverse<16, kGJThreads, 1, V>;
     set_lds_limit((const void *)fn, lds);
     hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(kGJThreads), lds, p->st, mats, n, p->dflag);
   } else if (n <= 2 * kGJThreads) {
-    auto fn = k_gj_inverse<16 * W, 2 * kGJThreads, 1, V>;
+    auto fn = k_gj_inverse<16, 2 * kGJThreads, 1, V>;
     set_lds_limit((const void *)fn, lds);
     hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(2 * kGJThreads), lds, p->st, mats, n, p->dflag);
   } else {
-    auto fn = k_gj_inverse<8 * W, kGJThreads, 3, V>;
+    auto fn = k_gj_inverse<8, kGJThreads, 3, V>;
     set_lds_limit((const void *)fn, lds);
     hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(kGJThreads), lds, p->st, mats, n, p->dflag);
   }
