@@ -178,7 +178,8 @@ constexpr int kGJMaxOrder = 768;  // the largest half-block order, 3 * 256
 constexpr size_t kLdsMax = 160 * 1024;  // LDS of one gfx950 CU, the most one workgroup can take
 constexpr int kGJThreads = 256;
 
-// Batched in-place inverse of row-major n x n complex matrices (FP64 or FP32), one workgroup each:
+// Batched in-place inverse of row-major n x n complex matrices (FP64 or FP32), one workgroup each
+// (MINW: minimum waves per SIMD the register allocation must allow):
 // Gauss-Jordan elimination with partial pivoting, blocked by NB columns.  For each panel of
 // NB columns the pivot steps run on rows held in registers (thread t owns rows t + r NT,
 // r < RPT); per step a wave-shuffle argmax picks the pivot, the pivot row and the old row k
@@ -186,8 +187,8 @@ constexpr int kGJThreads = 256;
 // receive the panel's row swaps, a short recurrence over the NB pivot rows and a rank-NB
 // update of the remaining rows.  Column interchanges are undone at the end.  A zero pivot
 // sets flag[0].
-template <int NB, int NT, int RPT, typename V>
-__global__ void __launch_bounds__(NT) k_gj_inverse(V *mats, int n, int *flag) {
+template <int NB, int NT, int RPT, typename V, int MINW = 1>
+__global__ void __launch_bounds__(NT, MINW) k_gj_inverse(V *mats, int n, int *flag) {
   using R = typename RealOf<V>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *F = reinterpret_cast<V *>(smem_raw);                     // [n][NB]
@@ -388,7 +389,10 @@ template <typename V> static void gj_launch(dda_problem *p, V *mats, long long c
     set_lds_limit((const void *)fn, lds);
     hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(kGJThreads), lds, p->st, mats, n, p->dflag);
   } else if (n <= 2 * kGJThreads) {
-    auto fn = k_gj_inverse<16, 2 * kGJThreads, 1, V>;
+    // FP32: at least 4 waves per SIMD (128 VGPRs, a 4-register spill) fits two 512-thread
+    // workgroups on a CU instead of one: 837 -> 617 ms at order 384 (a 256^3 build).  The same
+    // bound costs FP64, and the 256-thread kernels, more than it gains.
+    auto fn = k_gj_inverse<16, 2 * kGJThreads, 1, V, sizeof(V) == sizeof(float2) ? 4 : 1>;
     set_lds_limit((const void *)fn, lds);
     hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(2 * kGJThreads), lds, p->st, mats, n, p->dflag);
   } else {

@@ -118,7 +118,9 @@ def test_operator_fp32_vs_oracle(shape, seed):
 
 
 PC_CASES = [((4, 5, 6), 31), ((5, 4, 3), 32), ((7, 6, 10), 33), ((1, 3, 4), 34),
-            ((16, 16, 16), 35), ((9, 8, 12), 36), ((3, 1, 1), 37), ((2, 7, 5), 38)]
+            ((16, 16, 16), 35), ((9, 8, 12), 36), ((3, 1, 1), 37), ((2, 7, 5), 38),
+            # half-block orders above 256: the 512-thread Gauss-Jordan kernel, even and odd nz
+            ((200, 2, 3), 39), ((175, 2, 2), 40)]
 
 
 @pytest.mark.parametrize("shape,seed", PC_CASES)
@@ -242,7 +244,8 @@ def test_preconditioner_brute_force_definition():
     assert rel_err(z[0], ref) < 1e-10
 
 
-@pytest.mark.parametrize("shape,seed", [((5, 6, 7), 51), ((16, 16, 16), 52)])
+@pytest.mark.parametrize("shape,seed", [((5, 6, 7), 51), ((16, 16, 16), 52), ((200, 3, 2), 53),
+                                        ((175, 2, 2), 54)])
 def test_preconditioner_fp32_vs_oracle(shape, seed):
     nz, ny, nx = shape
     s = w.random_mask(nx, ny, nz, 0.7, seed, k=1.3, d=0.3)
