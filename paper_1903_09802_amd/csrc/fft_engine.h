@@ -18,6 +18,16 @@
 
 namespace dda {
 
+// Workgroup barrier for LDS traffic only: it orders the workgroup's LDS accesses without
+// waiting for its outstanding global loads, so a prefetch stays in flight across it.  Every
+// global value these kernels load is consumed (written to LDS or used) before the barrier
+// that publishes it, so cross-thread reuse of global addresses stays ordered.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <typename V> struct RealOf;
 template <> struct RealOf<double2> { using type = double; };
 template <> struct RealOf<float2> { using type = float; };
@@ -156,7 +166,7 @@ __device__ __forceinline__ void fft_pass(V *s, int ld, const Lane &L, int n, int
       dft<R, V>(v[q], sign);
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
     const int j = L.jt + q * L.tpc;
@@ -168,7 +178,7 @@ __device__ __forceinline__ void fft_pass(V *s, int ld, const Lane &L, int n, int
       for (int r = 0; r < R; ++r) s[lrow(base + r * Ns, ld) + L.c] = v[q][r];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Full transform of all columns (caller synchronises before the call).
@@ -243,7 +253,7 @@ __device__ __forceinline__ void fft_pass_s(V *s, int ld, const Lane &L, const V 
       dft<R, V>(v[q], sign);
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
     const int j = L.jt + q * TPC;
@@ -253,7 +263,7 @@ __device__ __forceinline__ void fft_pass_s(V *s, int ld, const Lane &L, const V 
       for (int r = 0; r < R; ++r) s[lrow(base + r * NS, ld) + L.c] = v[q][r];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 template <typename V, int N, int P = 0, int NS = 1>

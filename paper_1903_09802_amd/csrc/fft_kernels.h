@@ -128,13 +128,16 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
 
 // ---------------------------------------------------------------------------- strided-axis FFT
 
-// Data [batch][len][width] (width contiguous); transform along len.
+// Data [batch][len][width] (width contiguous); transform along len.  A tile is tw consecutive
+// columns of one batch; tiles are numbered batch-major and a workgroup transforms tpw
+// consecutive tiles, issuing the next tile's loads before it transforms the current one.
 struct StrArgs {
   FftDesc pl;
   long long batch;
   long long width;
-  int tw;                 // columns per workgroup
-  long long ntiles;       // ceil(width / tw)
+  int tw;                 // columns per tile
+  long long ntiles;       // ceil(width / tw) tiles per batch
+  int tpw;                // tiles per workgroup
   int n_in, n_out;
   long long in_bstride, out_bstride;  // elements between batches
   int sign;
@@ -145,27 +148,47 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(const cplx<T> *in, 
                                                              const cplx<T> *__restrict__ tw,
                                                              StrArgs a) {
   using V = cplx<T>;
+  constexpr int EPT = EptOf<T>::value;  // rows per thread: n <= EPT tpc
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *s = reinterpret_cast<V *>(smem_raw);
   const int n = a.pl.n;
   const int ld = a.tw + 1;
-  const long long b = blockIdx.x / a.ntiles;
-  const long long c0 = (blockIdx.x - b * a.ntiles) * (long long)a.tw;
   const Lane L = make_lane(a.tw, tpc_of(n));
-  const bool colok = L.active && (c0 + L.c < a.width);
-  const V *src = in + b * a.in_bstride + c0 + L.c;
-  if (L.active) {
-    for (int i = L.jt; i < n; i += L.tpc) {
-      V val = mk<T>((T)0, (T)0);
-      if (i < a.n_in && colok) val = src[(long long)i * a.width];
-      s[lrow(i, ld) + L.c] = val;
+  const long long q0 = (long long)blockIdx.x * a.tpw;
+  const long long q1 = min(q0 + a.tpw, a.ntiles * a.batch);
+  auto load = [&](long long q, V (&v)[EPT]) {
+    const long long b = q / a.ntiles;
+    const long long c0 = (q - b * a.ntiles) * (long long)a.tw;
+    const bool colok = L.active && (c0 + L.c < a.width);
+    const V *src = in + b * a.in_bstride + c0 + L.c;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int i = L.jt + k * L.tpc;
+      v[k] = (colok && i < a.n_in) ? src[(long long)i * a.width] : mk<T>((T)0, (T)0);
     }
+  };
+  V cur[EPT], nxt[EPT];
+  if (q0 < q1) load(q0, cur);
+  for (long long q = q0; q < q1; ++q) {
+    if (q + 1 < q1) load(q + 1, nxt);  // in flight during this tile's transform
+    if (q > q0) lds_barrier();         // the previous tile's output reads are done
+    if (L.active) {
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const int i = L.jt + k * L.tpc;
+        if (i < n) s[lrow(i, ld) + L.c] = cur[k];
+      }
+    }
+    lds_barrier();
+    lds_fft_any<V, EPT, NF>(s, ld, L, a.pl, tw, a.sign);
+    const long long b = q / a.ntiles;
+    const long long c0 = (q - b * a.ntiles) * (long long)a.tw;
+    V *dst = out + b * a.out_bstride + c0 + L.c;
+    if (L.active && c0 + L.c < a.width)
+      for (int i = L.jt; i < a.n_out; i += L.tpc) dst[(long long)i * a.width] = s[lrow(i, ld) + L.c];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) cur[k] = nxt[k];
   }
-  __syncthreads();
-  lds_fft_any<V, EptOf<T>::value, NF>(s, ld, L, a.pl, tw, a.sign);
-  V *dst = out + b * a.out_bstride + c0 + L.c;
-  if (colok)
-    for (int i = L.jt; i < a.n_out; i += L.tpc) dst[(long long)i * a.width] = s[lrow(i, ld) + L.c];
 }
 
 // ---------------------------------------------------------------------------- fused z pass
@@ -340,6 +363,10 @@ inline void launch_strided(dda_problem *p, const FftPlan &pl, const cplx<T> *in,
   a.tw = tile_cols<T>(pl.n);
   if (a.tw > width) a.tw = (int)width;
   a.ntiles = (width + a.tw - 1) / a.tw;
+  // tiles per workgroup: the most (up to 8) that leave at least 2048 workgroups
+  const long long tiles = a.ntiles * batch;
+  a.tpw = 1;
+  while (a.tpw < 8 && (tiles + 2 * a.tpw - 1) / (2 * a.tpw) >= 2048) a.tpw *= 2;
   a.n_in = n_in;
   a.n_out = n_out;
   a.in_bstride = in_bstride;
@@ -351,8 +378,8 @@ inline void launch_strided(dda_problem *p, const FftPlan &pl, const cplx<T> *in,
   with_static_n(pl.n, [&](auto nf) {
     auto fn = k_fft_strided<T, decltype(nf)::value>;
     set_lds_limit((const void *)fn, lds);
-    hipLaunchKernelGGL(fn, dim3((unsigned)(a.ntiles * batch)), dim3(threads), lds, p->st, in,
-                       out, tw_of<T>(pl), a);
+    hipLaunchKernelGGL(fn, dim3((unsigned)((tiles + a.tpw - 1) / a.tpw)), dim3(threads), lds, p->st,
+                       in, out, tw_of<T>(pl), a);
   });
   HIPCHK(hipGetLastError());
 }

@@ -176,14 +176,6 @@ struct ZRArgs {
   long long nblk;     // (ny + 1) tiles_x nch, chunk fastest
 };
 
-// Workgroup barrier for LDS traffic only: it orders the workgroup's LDS accesses without
-// waiting for its outstanding global loads.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 template <typename T, int G, int P>
 __global__ void __launch_bounds__(256) k_zpass_mr(cplx<T> *data, const cplx<T> *__restrict__ tw,
                                                   const cplx<T> *__restrict__ khat, ZRArgs a) {
