@@ -1,11 +1,14 @@
-"""Restarted GMRES, right-preconditioned (paper Sec. 4 uses GMRES to tolerance 1e-5).
+"""Restarted GMRES, right- or left-preconditioned (paper Sec. 4 uses GMRES to tolerance 1e-5).
 
 Test infrastructure only.  Modified Gram-Schmidt Arnoldi with Givens rotations
 (the textbook form of Saad & Schultz), x0 = 0 unless given.  The paper keeps
 the full Krylov space; restarts every ``restart`` iterations are used here (the
-paper recommends trying restarts, Sec. 4-5).  Stopping: the Givens estimate of
-the residual of A P^{-1} u = b is checked after every iteration; at the end of
-each cycle the true residual ||b - A x|| / ||b|| decides convergence.
+paper recommends trying restarts, Sec. 4-5).  Right preconditioning (the
+default): the Givens estimate of the residual of A P^{-1} u = b is checked after
+every iteration; at the end of each cycle the true residual ||b - A x|| / ||b||
+decides convergence.  Left preconditioning, the paper's eq. (general_prec),
+P^{-1} A x = P^{-1} b: plain GMRES on that system, so every test is on
+||P^{-1} (b - A x)|| / ||P^{-1} b||.
 """
 
 from __future__ import annotations
@@ -14,12 +17,23 @@ import numpy as np
 
 
 def gmres(matvec, b, precond=None, restart: int = 30, tol: float = 1e-5, maxit: int = 2000,
-          x0=None):
+          x0=None, side: str = "right"):
     """Solve A x = b.  ``matvec`` and ``precond`` (x -> P^{-1} x) act on arrays of b's shape.
 
     Returns (x, info) with info = dict(converged, iters, cycles, rel_residual,
-    history) where history is the per-iteration Givens estimate / ||b||.
+    history) where history is the per-iteration Givens estimate / ||b||.  With
+    side="left" the system solved is P^{-1} A x = P^{-1} b: rel_residual and history
+    are those of that system, and info["true_rel_residual"] is ||b - A x|| / ||b||.
     """
+    if side == "left" and precond is not None:
+        pb = precond(b)
+        x, info = gmres(lambda v: precond(matvec(v)), pb, None, restart, tol, maxit, x0)
+        r = b.ravel() - matvec(x).ravel()
+        bn = np.linalg.norm(b.ravel())
+        info["true_rel_residual"] = np.linalg.norm(r) / bn if bn > 0 else 0.0
+        return x, info
+    if side not in ("left", "right"):
+        raise ValueError(f"side must be 'left' or 'right', got {side!r}")
     if precond is None:
         def precond(v):
             return v

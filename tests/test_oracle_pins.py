@@ -389,6 +389,47 @@ def test_gmres_exact_when_restart_exceeds_dimension():
     assert np.abs(A @ x - b).max() < 1e-11
 
 
+def test_left_gmres_exact_preconditioner_one_step():
+    """Left preconditioning (Sec. 1, eq. general_prec) with P^{-1} = A^{-1}: P^{-1} A = I, so
+    the first Krylov step solves the system; right-preconditioned GMRES does the same."""
+    rng = np.random.default_rng(11)
+    n = 15
+    A = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)) + 4 * np.eye(n)
+    b = rng.normal(size=n) + 1j * rng.normal(size=n)
+    Ainv = np.linalg.inv(A)
+    for side in ("left", "right"):
+        x, info = gmres.gmres(lambda v: A @ v, b, precond=lambda v: Ainv @ v, tol=1e-12,
+                              side=side)
+        assert info["converged"] and info["iters"] == 1, (side, info["iters"])
+        assert np.abs(A @ x - b).max() < 1e-10 * np.abs(b).max()
+
+
+def test_left_gmres_residuals_are_those_of_the_preconditioned_system():
+    """Left GMRES on a small DDA system with a non-trivial P (the 2-level circulant one):
+    the solution is the LU one, the reported residual is ||P^{-1}(b - A x)|| / ||P^{-1} b||
+    recomputed from x, the true residual is reported beside it, and P = I reproduces
+    right-preconditioned GMRES iteration for iteration."""
+    s, dv, pv, b = _small_problem(8)
+    S = physics.lattice_S(dv, pv)
+    A = system.dense_matrix(s.mask, s.eps, s.k, s.d, S)
+    c = system.compact_to_box(np.linalg.solve(A, system.box_to_compact(b, s.mask)), s.mask)
+    mv = lambda x: fftmatvec.fft_matvec(x, s.mask, s.eps, s.k, s.d, S)
+    ati = complex(physics.alpha_inv(s.eps[s.mask.astype(bool)].mean(), s.k * s.d, 0.0))
+    z0, Bi = circulant.blocks_for_mask(s.mask, s.k, s.d, ati)
+    pc = lambda v: circulant.apply_blocks_layers(v, s.mask, Bi, z0)
+    x, info = gmres.gmres(mv, b, precond=pc, restart=8, tol=1e-11, side="left")
+    assert info["converged"]
+    assert np.abs(x - c).max() < 1e-8 * np.abs(c).max()
+    prel = np.linalg.norm(pc(b - mv(x))) / np.linalg.norm(pc(b))
+    assert abs(prel - info["rel_residual"]) < 1e-12 and prel <= 1e-11
+    true = np.linalg.norm(b - mv(x)) / np.linalg.norm(b)
+    assert abs(true - info["true_rel_residual"]) < 1e-13
+    ident = lambda v: v
+    _, il = gmres.gmres(mv, b, precond=ident, restart=6, tol=1e-6, side="left")
+    _, ir = gmres.gmres(mv, b, precond=ident, restart=6, tol=1e-6, side="right")
+    assert il["iters"] == ir["iters"] and np.allclose(il["history"], ir["history"], rtol=0, atol=1e-14)
+
+
 # --------------------------------------------------------------------------- cross sections
 
 def test_optical_theorem_exact_solution():
