@@ -190,6 +190,9 @@ def main():
                     help="plates: also run the unpreconditioned solvers")
     ap.add_argument("--plates-plain-max-x", type=float, default=1e9,
                     help="plates: run the unpreconditioned solvers only up to this size parameter")
+    ap.add_argument("--plates-left", action="store_true",
+                    help="plates: also run preconditioned GMRES with left preconditioning (the "
+                         "paper's P^-1 A x = P^-1 b, stopping on the preconditioned residual)")
     ap.add_argument("--plates-restart", type=int, default=500,
                     help="plates: GMRES restart length (500 keeps the whole Krylov space for every "
                          "case the paper's unrestarted GMRES solved)")
@@ -540,12 +543,17 @@ def bench_plates(args):
         try:
             for tag, pc in runs:
                 res = {}
-                for solver, cap in (("gmres", 2000), ("bicgstab", 4000)):
+                solvers = [("gmres", "gmres", 2000, "right"), ("bicgstab", "bicgstab", 4000, "right")]
+                if pc and args.plates_left:
+                    # the paper's side: GMRES on P^-1 A x = P^-1 b, stopping on the
+                    # preconditioned residual
+                    solvers.append(("gmres_left", "gmres", 2000, "left"))
+                for key, solver, cap, side in solvers:
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
                     prob = Problem(mask, eps, s.k, s.d, precond=pc, tol=cfg["tol"],
                                    restart=args.plates_restart if solver == "gmres" else 30,
-                                   max_iter=cap, solver=solver)
+                                   max_iter=cap, solver=solver, precond_side=side)
                     try:
                         torch.cuda.synchronize()
                         t1 = time.perf_counter()
@@ -559,7 +567,7 @@ def bench_plates(args):
                     finally:
                         prob.close()
                     st = o["stats"][0]
-                    res[solver] = dict(its=st["iters"], converged=bool(st["converged"]),
+                    res[key] = dict(its=st["iters"], converged=bool(st["converged"]),
                                        rel_residual=st["rel_residual"], setup_s=t1 - t0,
                                        build_s=(t2 - t1) if pc else None, solve_s=t3 - t2,
                                        cext=float(o["cext"][0]))

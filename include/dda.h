@@ -89,6 +89,13 @@ typedef struct {
                        the cyclically rotated frame whose z axis is dense_axis; every buffer at
                        this interface stays in the caller's [.][3][nz][ny][nx] layout and
                        frame.  default 2 */
+  int left_precond; /* GMRES only.  0: right preconditioning, A P^{-1} u = b, stopping on the
+                       true residual ||b - A x|| / ||b||.  1: left preconditioning, the paper's
+                       P^{-1} A x = P^{-1} b (Sec. 1, eq. general_prec): the Krylov space is
+                       that of P^{-1} A and every stopping test (per iteration and at each
+                       restart) is on ||P^{-1}(b - A x)|| / ||P^{-1} b||; dda_stats still
+                       reports the true residual.  No effect without a preconditioner.
+                       default 0 */
 } dda_options;
 
 typedef struct {

@@ -81,6 +81,7 @@ void dda_default_options(dda_options *opt) {
   opt->max_rhs = 1;
   opt->solver = 0;
   opt->dense_axis = 2;
+  opt->left_precond = 0;
 }
 
 const char *dda_last_error(void) { return get_error(); }
@@ -113,6 +114,9 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
     REQUIRE(o.solver == 0 || o.precision == 0, DDA_EUNSUPPORTED, "BiCGStab runs in FP64 only (precision 0)");
     REQUIRE(o.solver == 0 || o.restart >= 7, DDA_EINVAL, "BiCGStab needs restart >= 7 (work vectors)");
     REQUIRE(o.dense_axis >= 0 && o.dense_axis <= 2, DDA_EINVAL, "dense_axis must be 0, 1 or 2");
+    REQUIRE(o.left_precond == 0 || o.left_precond == 1, DDA_EINVAL, "left_precond must be 0 or 1");
+    REQUIRE(o.left_precond == 0 || o.solver == 0, DDA_EINVAL,
+            "left preconditioning is a GMRES option (solver 0)");
     {
       FftPlan t;
       REQUIRE(factor_7smooth(nx, t) && factor_7smooth(ny, t) && factor_7smooth(nz, t),

@@ -436,15 +436,28 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
         p->dflag + 4 + p->R};
   const long long vs_r = n3, vs_j = (long long)p->R * n3;  // V is [m+1][R][n3]
   const bool prec = p->opt.precond != 0;
+  // Left preconditioning (the paper's P^{-1} A x = P^{-1} b): Krylov space of P^{-1} A, the
+  // restart vector P^{-1}(b - A x), the update x += V y, and every test on the preconditioned
+  // residual relative to ||P^{-1} b||.  Right preconditioning: A P^{-1}, x += P^{-1} V y, tests
+  // on the true residual.  The preconditioner is applied in the precision it was built in.
+  const bool left = prec && p->opt.left_precond != 0;
+  const int pfp = p->prec_fp32;
   double2 *rv = p->V;  // the residual is written straight into basis block 0
   std::vector<int> all(nrhs, 1), act(nrhs, 1), incyc(nrhs, 0), jcut(nrhs, 0), iters(nrhs, 0);
   std::vector<int> cycles(nrhs, 0), conv(nrhs, 0);
-  std::vector<double> bn2, rn2, rel(nrhs, 0.0);
+  std::vector<double> bn2, bt2, rn2, rel(nrhs, 0.0), trel(nrhs, 0.0);
   sync_active(p, K.d_active, all);
   norm2_dev(K, b, n3, p->hcol2);
-  read_scalars(p, p->hcol2, nrhs, bn2);
+  read_scalars(p, p->hcol2, nrhs, bt2);  // ||b||^2
+  bn2 = bt2;                             // norm the tests are relative to
+  if (left) {
+    apply_precond(p, nrhs, b, p->work2, pfp, nullptr);
+    norm2_dev(K, p->work2, n3, p->hcol2);
+    read_scalars(p, p->hcol2, nrhs, bn2);  // ||P^{-1} b||^2
+  }
   // The restart residual b - A x is always formed with the FP64 operator: with fp32 != 0 every
-  // restart is one step of iterative refinement (FP32 cycle, FP64 residual).
+  // restart is one step of iterative refinement (FP32 cycle, FP64 residual).  rel holds the
+  // residual the tests use, trel the true one; hcol2 ends with ||rv||^2 for the cycle start.
   auto true_residual = [&](void) {
     sync_active(p, K.d_active, all);
     apply_operator(p, nrhs, x, p->work, 0, nullptr);
@@ -455,6 +468,15 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
     }
     finalize(K, 1, p->hcol2, nullptr, nullptr);
     read_scalars(p, p->hcol2, nrhs, rn2);
+    for (int r = 0; r < nrhs; ++r) {
+      trel[r] = bt2[r] > 0 ? std::sqrt(rn2[r] / bt2[r]) : 0.0;
+      REQUIRE(std::isfinite(trel[r]), DDA_EDEVICE, "non-finite residual for right-hand side %d", r);
+    }
+    if (left) {
+      apply_precond(p, nrhs, rv, rv, pfp, nullptr);
+      norm2_dev(K, rv, n3, p->hcol2);
+      read_scalars(p, p->hcol2, nrhs, rn2);
+    }
     for (int r = 0; r < nrhs; ++r) {
       rel[r] = bn2[r] > 0 ? std::sqrt(rn2[r] / bn2[r]) : 0.0;
       REQUIRE(std::isfinite(rel[r]), DDA_EDEVICE, "non-finite residual for right-hand side %d", r);
@@ -480,8 +502,12 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
     for (int j = 0; j < m; ++j) {
       double2 *vj = p->V + (long long)j * vs_j;
       double2 *w = p->V + (long long)(j + 1) * vs_j;
-      // w = A P^{-1} (v~_j / ||v~_j||); block j is contiguous [nrhs][n3]
-      if (prec) {
+      // w = A P^{-1} (v~_j / ||v~_j||), or P^{-1} A (...) when left; block j is contiguous
+      // [nrhs][n3]
+      if (left) {
+        apply_operator(p, nrhs, vj, p->work2, fp32, p->vsc + j);
+        apply_precond(p, nrhs, p->work2, w, fp32, nullptr);
+      } else if (prec) {
         apply_precond(p, nrhs, vj, p->work2, fp32, p->vsc + j);
         apply_operator(p, nrhs, p->work2, w, fp32, nullptr);
       } else {
@@ -526,7 +552,7 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
       sync_active(p, K.d_active, incyc);
       if (!left) break;
     }
-    // x += P^{-1} (V y)
+    // x += P^{-1} (V y), or x += V y when left
     HIPCHK(hipMemcpyAsync(K.d_jcut, jcut.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, p->st));
     hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, p->st, p->H, p->gvec, m, K.d_jcut, p->vsc,
                        p->ycoef, nrhs);
@@ -538,7 +564,7 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
                          jmax, p->ycoef, p->work2, n3, n3);
     }
     HIPCHK(hipGetLastError());
-    if (prec) apply_precond(p, nrhs, p->work2, p->work2, fp32, nullptr);
+    if (prec && !left) apply_precond(p, nrhs, p->work2, p->work2, fp32, nullptr);
     hipLaunchKernelGGL(k_axpby, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, x, p->work2, 1.0, x,
                        n3, n3, nullptr, nullptr, K.B);
     HIPCHK(hipGetLastError());
@@ -546,8 +572,8 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
     if (verbose())
       for (int r = 0; r < nrhs; ++r)
         if (act[r])
-          fprintf(stderr, "[dda] %s rhs %d cycle %d iters %d true rel residual %.3e (tol %.1e)\n",
-                  fp32 ? "fp32" : "fp64", r, cycles[r], iters[r], rel[r], tol);
+          fprintf(stderr, "[dda] %s rhs %d cycle %d iters %d rel residual %.3e (true %.3e, tol %.1e)\n",
+                  fp32 ? "fp32" : "fp64", r, cycles[r], iters[r], rel[r], trel[r], tol);
     for (int r = 0; r < nrhs; ++r) {
       if (!act[r]) continue;
       if (rel[r] <= tol) { act[r] = 0; conv[r] = 1; }
@@ -556,7 +582,7 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
   for (int r = 0; r < nrhs; ++r) {
     st[r].iters += iters[r];
     st[r].cycles += cycles[r];
-    st[r].rel_residual = rel[r];
+    st[r].rel_residual = trel[r];
     st[r].converged = conv[r];
   }
 }

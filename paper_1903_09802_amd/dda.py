@@ -36,7 +36,8 @@ class Options(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
-                ("max_rhs", ctypes.c_int), ("solver", ctypes.c_int), ("dense_axis", ctypes.c_int)]
+                ("max_rhs", ctypes.c_int), ("solver", ctypes.c_int), ("dense_axis", ctypes.c_int),
+                ("left_precond", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -129,7 +130,7 @@ class Problem:
 
     def __init__(self, mask, eps, k: float, d: float, *, restart=30, max_iter=2000, tol=1e-5,
                  precond=2, precision=0, inner_tol=1e-4, max_refine=30, max_rhs=1, solver="gmres",
-                 dense_axis=2, stream=None):
+                 dense_axis=2, precond_side="right", stream=None):
         import torch
         L = load()
         self.mask = mask.to(device="cuda", dtype=torch.uint8).contiguous()
@@ -146,6 +147,10 @@ class Problem:
             raise ValueError(f"solver must be one of {sorted(solvers)}")
         o.solver = solvers[solver]
         o.dense_axis = int(dense_axis)
+        sides = {"right": 0, "left": 1}
+        if precond_side not in sides:
+            raise ValueError(f"precond_side must be one of {sorted(sides)}")
+        o.left_precond = sides[precond_side]
         self.opts = o
         self.stream = torch.cuda.current_stream() if stream is None else stream
         h = ctypes.c_void_p()
