@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(kRedThreads) k_multiaxpy(const double2 *V, lon
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
        n += (long long)gridDim.x * blockDim.x) {
     double2 v = wr[n];
-#pragma unroll 4
+#pragma unroll 8
     for (int i = 0; i < nvec; ++i) v = csub(v, cmul(Vr[i * vs_j + n], c[i]));
     wr[n] = v;
     acc[0].x += v.x * v.x + v.y * v.y;
