@@ -35,6 +35,10 @@ void free_all(dda_problem *p) {
   F(p->ainv); F(p->Sdev); F(p->V); F(p->work); F(p->work2); F(p->bvec); F(p->xvec); F(p->vsc);
   F(p->H); F(p->givens); F(p->gvec); F(p->hcol); F(p->hcol2);
   F(p->ycoef); F(p->hnrm); F(p->hraw); F(p->lmat); F(p->partial); F(p->dscal); F(p->dflag);
+  if (p->hpin) (void)hipHostFree(p->hpin);
+  if (p->est_ev) (void)hipEventDestroy(p->est_ev);
+  p->hpin = nullptr;
+  p->est_ev = nullptr;
   precond_free(p);
   plan_destroy(p->px); plan_destroy(p->py); plan_destroy(p->pz);
   plan_destroy(p->ux); plan_destroy(p->uy);

@@ -313,7 +313,8 @@ struct dda_problem {
   size_t partial_elems = 0;
   double *dscal = nullptr;   // [R][16] device scalars
   double *vsc = nullptr;     // [R][kMaxM] 1 / norm of each (unnormalised) basis vector
-  double *hpin = nullptr;    // pinned host mirror [R][16]
+  double *hpin = nullptr;    // pinned host mirror [R][16] of the per-iteration estimates
+  hipEvent_t est_ev = nullptr;  // recorded after the estimates' copy to hpin
   int *dflag = nullptr;      // device error flags [4]
 
   dda::Profiler prof;

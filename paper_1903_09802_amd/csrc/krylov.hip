@@ -485,7 +485,22 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
   true_residual();
   for (int r = 0; r < nrhs; ++r)
     if (rel[r] <= tol || bn2[r] == 0.0) { act[r] = 0; conv[r] = 1; }
-  std::vector<double> hp(8 * nrhs);
+  // w = A P^{-1} v~_j (or P^{-1} A v~_j when left) into basis block j + 1; block j is
+  // contiguous [nrhs][n3] and v~_j is scaled by 1 / ||v~_j|| on the way in
+  auto products = [&](int jj) {
+    double2 *vjj = p->V + (long long)jj * vs_j;
+    double2 *wjj = p->V + (long long)(jj + 1) * vs_j;
+    if (left) {
+      apply_operator(p, nrhs, vjj, p->work2, fp32, p->vsc + jj);
+      apply_precond(p, nrhs, p->work2, wjj, fp32, nullptr);
+    } else if (prec) {
+      apply_precond(p, nrhs, vjj, p->work2, fp32, p->vsc + jj);
+      apply_operator(p, nrhs, p->work2, wjj, fp32, nullptr);
+    } else {
+      apply_operator(p, nrhs, vjj, wjj, fp32, p->vsc + jj);
+    }
+  };
+  std::vector<double> last(nrhs, 0.0);  // latest residual (estimate) per RHS
   while (true) {
     bool any = false;
     for (int r = 0; r < nrhs; ++r) any = any || (act[r] && iters[r] < maxit);
@@ -499,20 +514,12 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
     hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, p->st, p->hcol2, p->gvec, m, p->vsc,
                        K.d_active, nrhs);
     HIPCHK(hipGetLastError());
+    for (int r = 0; r < nrhs; ++r) last[r] = rel[r];
+    bool issued = false;  // this step's products were enqueued during the previous step
     for (int j = 0; j < m; ++j) {
-      double2 *vj = p->V + (long long)j * vs_j;
       double2 *w = p->V + (long long)(j + 1) * vs_j;
-      // w = A P^{-1} (v~_j / ||v~_j||), or P^{-1} A (...) when left; block j is contiguous
-      // [nrhs][n3]
-      if (left) {
-        apply_operator(p, nrhs, vj, p->work2, fp32, p->vsc + j);
-        apply_precond(p, nrhs, p->work2, w, fp32, nullptr);
-      } else if (prec) {
-        apply_precond(p, nrhs, vj, p->work2, fp32, p->vsc + j);
-        apply_operator(p, nrhs, p->work2, w, fp32, nullptr);
-      } else {
-        apply_operator(p, nrhs, vj, w, fp32, p->vsc + j);
-      }
+      if (!issued) products(j);
+      issued = false;
       // MGS in one reduction: a = V^H w and row j of L, c = (I + L)^{-1} a, w -= V c
       {
         KTimer t(&p->prof, p->st, "kry_gs_dots", 16.0 * n3 * (j + 2) * nrhs);
@@ -532,25 +539,38 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
       hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, p->st, j, m, p->H, p->givens, p->gvec,
                          p->hcol, p->hcol, 0, p->hnrm, p->dscal, p->vsc, K.d_active, nrhs);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(hp.data(), p->dscal, sizeof(double) * 8 * nrhs, hipMemcpyDeviceToHost,
+      HIPCHK(hipMemcpyAsync(p->hpin, p->dscal, sizeof(double) * 8 * nrhs, hipMemcpyDeviceToHost,
                             p->st));
-      HIPCHK(hipStreamSynchronize(p->st));
-      bool left = false;
+      HIPCHK(hipEventRecord(p->est_ev, p->st));
+      // While the host waits for the estimates, enqueue the next step's products unless this
+      // step may end the cycle: its last step, or an RHS within 4 tol of converging.  Products
+      // that turn out unneeded only fill a basis block the cycle never reads.
+      bool spec = j + 1 < m;
+      for (int r = 0; r < nrhs && spec; ++r)
+        if (incyc[r] && (last[r] <= 4.0 * tol || iters[r] + 1 >= maxit)) spec = false;
+      if (spec) {
+        products(j + 1);
+        issued = true;
+      }
+      HIPCHK(hipEventSynchronize(p->est_ev));
+      const double *hp = p->hpin;
+      bool more = false;
       for (int r = 0; r < nrhs; ++r) {
         if (!incyc[r]) continue;
         iters[r] += 1;
         const double est = hp[8 * r] / std::sqrt(bn2[r]);
         REQUIRE(std::isfinite(est), DDA_EDEVICE, "non-finite residual estimate (RHS %d)", r);
+        last[r] = est;
         const bool brk = hp[8 * r + 2] == 0.0;
         if (est <= tol || brk || iters[r] >= maxit || j == m - 1) {
           jcut[r] = j + 1;
           incyc[r] = 0;
         } else {
-          left = true;
+          more = true;
         }
       }
       sync_active(p, K.d_active, incyc);
-      if (!left) break;
+      if (!more) break;
     }
     // x += P^{-1} (V y), or x += V y when left
     HIPCHK(hipMemcpyAsync(K.d_jcut, jcut.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, p->st));
@@ -911,6 +931,8 @@ void krylov_alloc(dda_problem *p) {
   HIPCHK(hipMalloc(&p->partial, sizeof(double) * p->partial_elems));
   HIPCHK(hipMalloc(&p->dscal, sizeof(double) * 16 * R));
   HIPCHK(hipMemset(p->dscal, 0, sizeof(double) * 16 * R));
+  HIPCHK(hipHostMalloc(&p->hpin, sizeof(double) * 16 * R, hipHostMallocDefault));
+  HIPCHK(hipEventCreateWithFlags(&p->est_ev, hipEventDisableTiming));
   HIPCHK(hipMalloc(&p->vsc, sizeof(double) * kMaxM * R));
   HIPCHK(hipMemset(p->vsc, 0, sizeof(double) * kMaxM * R));
   HIPCHK(hipMalloc(&p->dflag, sizeof(int) * (4 + 2 * R)));
