@@ -379,6 +379,14 @@ struct Kry {
 static void sync_active(dda_problem *p, int *d, const std::vector<int> &h) {
   HIPCHK(hipMemcpyAsync(d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, p->st));
 }
+// The same, skipped when the device copy `dev` already holds h (a copy from pageable memory can
+// wait for the stream; the flags change only when a right-hand side stops).
+static void sync_active_changed(dda_problem *p, int *d, const std::vector<int> &h,
+                                std::vector<int> &dev) {
+  if (h == dev) return;
+  sync_active(p, d, h);
+  dev = h;
+}
 
 static void finalize(Kry &K, int nvec, double2 *out, double2 *coef, const double *vsc,
                      int islot = -1) {
@@ -511,6 +519,7 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
       if (incyc[r]) cycles[r] += 1;
     }
     sync_active(p, K.d_active, incyc);
+    std::vector<int> dev_act = incyc;  // the flags on the device
     hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, p->st, p->hcol2, p->gvec, m, p->vsc,
                        K.d_active, nrhs);
     HIPCHK(hipGetLastError());
@@ -569,7 +578,7 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
           more = true;
         }
       }
-      sync_active(p, K.d_active, incyc);
+      sync_active_changed(p, K.d_active, incyc, dev_act);
       if (!more) break;
     }
     // x += P^{-1} (V y), or x += V y when left
@@ -797,6 +806,7 @@ void bicgstab_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, doub
                 r, runs[r], iters[r], rel[r], tol);
     if (!any) break;
     sync_active(p, K.d_active, act);
+    std::vector<int> dev_act = act;  // the flags on the device
     // hraw slot 0 = ||r||^2 for the active RHS, then rhat = r, p = v = 0, scalars
     {
       KTimer tm(&p->prof, p->st, "kry_norm", 16.0 * n3 * nrhs);
@@ -878,7 +888,7 @@ void bicgstab_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, doub
         // stop this run at the updated tolerance, omega = 0 or the cap
         if (est <= tol || (om.x == 0.0 && om.y == 0.0) || iters[r] >= maxit) act[r] = 0;
       }
-      sync_active(p, K.d_active, act);
+      sync_active_changed(p, K.d_active, act, dev_act);
     }
     for (int r = 0; r < nrhs; ++r)
       if (in_run[r] && iters[r] == run_start[r]) stuck[r] = 1;
