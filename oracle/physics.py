@@ -40,6 +40,30 @@ def alpha_inv_masked(eps, mask, kd: float, S: float):
     return np.where(occ, alpha_inv(safe, kd, S), 0.0)
 
 
+def alpha_tilde_inv(eps, mask, kd: float, S: float, variant: str = "mean_eps"):
+    """The constant diagonal alpha~^{-1} of the circulant preconditioner P = D~ + C (Sec. 1,
+    Sec. 3.1), from the occupied voxels' permittivities, in one of three readings:
+
+    * "mean_eps":   alpha^{-1} of the mean occupied permittivity;
+    * "mean_alpha": the mean of alpha^{-1} over the occupied voxels (the diagonal averaged);
+    * "mode":       alpha^{-1} of the most frequent occupied permittivity (the paper's modal
+                    average of the diagonal, over the body), ties to the first in voxel order.
+
+    All three equal the body's own value for a homogeneous body.
+    """
+    occ = np.asarray(mask).astype(bool).ravel()
+    e = np.asarray(eps, dtype=np.complex128).ravel()[occ]
+    if variant == "mean_eps":
+        return complex(alpha_inv(e.mean(), kd, S))
+    if variant == "mean_alpha":
+        return complex(alpha_inv(e, kd, S).mean())
+    if variant == "mode":
+        vals, first, counts = np.unique(e, return_index=True, return_counts=True)
+        best = max(range(len(vals)), key=lambda i: (counts[i], -first[i]))
+        return complex(alpha_inv(vals[best], kd, S))
+    raise ValueError(f"unknown variant {variant!r}")
+
+
 def dalpha_inv_deps(eps, kd: float, S: float):
     """d(1/alpha^LDR)/d eps of :func:`alpha_inv` (holomorphic in eps)."""
     eps = np.asarray(eps, dtype=np.complex128)

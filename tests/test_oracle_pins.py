@@ -389,6 +389,36 @@ def test_gmres_exact_when_restart_exceeds_dimension():
     assert np.abs(A @ x - b).max() < 1e-11
 
 
+def test_alpha_tilde_variants_closed_forms():
+    """The three readings of the preconditioner's constant diagonal (Sec. 1, Sec. 3.1) on a
+    two-material body: fraction f of the voxels at eps1, the rest at eps2.  mean_eps is
+    alpha^{-1}(f eps1 + (1-f) eps2); mean_alpha is f alpha^{-1}(eps1) + (1-f) alpha^{-1}(eps2);
+    mode is the majority's alpha^{-1}; for a homogeneous body all three are its value."""
+    rng = np.random.default_rng(5)
+    kd, S = 0.4, 0.3
+    mask = rng.random((6, 7, 8)) < 0.8
+    e1, e2 = 1.7161 + 0.0j, 3.1684 + 0.02j
+    eps = np.where(rng.random(mask.shape) < 0.7, e1, e2).astype(np.complex128)
+    occ = mask.astype(bool)
+    f = float(np.mean(eps[occ] == e1))
+    assert 0.5 < f < 0.9
+    a1 = complex(physics.alpha_inv(e1, kd, S))
+    a2 = complex(physics.alpha_inv(e2, kd, S))
+    am = physics.alpha_tilde_inv(eps, mask, kd, S, "mean_eps")
+    assert abs(am - complex(physics.alpha_inv(f * e1 + (1 - f) * e2, kd, S))) < 1e-12 * abs(am)
+    aa = physics.alpha_tilde_inv(eps, mask, kd, S, "mean_alpha")
+    assert abs(aa - (f * a1 + (1 - f) * a2)) < 1e-12 * abs(aa)
+    assert physics.alpha_tilde_inv(eps, mask, kd, S, "mode") == a1
+    assert abs(am - aa) > 1e-3 * abs(aa)  # the readings differ for an inhomogeneous body
+    hom = np.full(mask.shape, e2)
+    for v in ("mean_eps", "mean_alpha", "mode"):
+        assert abs(physics.alpha_tilde_inv(hom, mask, kd, S, v) - a2) < 1e-12 * abs(a2)
+    # a tie goes to the value met first in voxel order
+    tie = np.zeros((1, 1, 4), dtype=bool) | True
+    te = np.array([[[e2, e1, e1, e2]]])
+    assert physics.alpha_tilde_inv(te, tie, kd, S, "mode") == a2
+
+
 def test_left_gmres_exact_preconditioner_one_step():
     """Left preconditioning (Sec. 1, eq. general_prec) with P^{-1} = A^{-1}: P^{-1} A = I, so
     the first Krylov step solves the system; right-preconditioned GMRES does the same."""
