@@ -179,7 +179,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5", "plates", "axes", "levels"])
+                    choices=["c1", "c2", "c3", "c4", "c5", "plates", "axes", "levels", "alpha"])
     ap.add_argument("--c3-case", type=int, default=0, help="c3: 0 -> m = 1.31+0.001i, 1 -> m = 1.78")
     ap.add_argument("--c4-prisms", type=int, default=16)
     ap.add_argument("--c4-chunk", type=int, default=32, help="c4: right-hand sides per batched solve")
@@ -225,6 +225,9 @@ def main():
         return bench_plates(args)
     if args.workload == "axes":
         return bench_axes(args)
+    if args.workload == "alpha":
+        bench_alpha(args)
+        return
     if args.workload == "levels":
         return bench_levels(args)
     cfg, desc = workload(args.workload)
@@ -646,6 +649,64 @@ def bench_levels(args):
                 t0 = time.perf_counter()
                 if precond:
                     prob.build_preconditioner(0.0)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                o = prob.solve(dirs, pols, return_c=False, xsec=True)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+            finally:
+                prob.close()
+            st = o["stats"][0]
+            line.update(its=st["iters"], converged=bool(st["converged"]), build_s=t1 - t0,
+                        solve_s=t2 - t1, cext=float(o["cext"][0]))
+            _emit(line)
+        del mask, eps
+        torch.cuda.empty_cache()
+
+
+def bench_alpha(args):
+    """Readings of the preconditioner's constant diagonal (option alpha_avg) on inhomogeneous
+    prisms: 1/alpha of the mean permittivity, the mean of 1/alpha, and the paper's modal value
+    over the body.  GMRES(30) to 1e-5, one wave (+z, x-pol)."""
+    import numpy as np
+    import torch
+
+    import workloads as w
+    from paper_1903_09802_amd.dda import Problem
+
+    def inclusions(x, grid, m_host, m_inc, frac, seed):
+        s = w.hex_prism_grid(x, 1.0, grid, m_host)
+        occ = s.mask.astype(bool)
+        rng = np.random.default_rng(seed)
+        pick = occ & (rng.random(s.mask.shape) < frac)
+        s.eps = np.where(pick, m_inc ** 2, s.eps).astype(np.complex128)
+        return s
+
+    def core(x, grid, m_host, m_core, r_frac):
+        s = w.hex_prism_grid(x, 1.0, grid, m_host)
+        nz, ny, nx = s.shape
+        zz, yy, xx = np.meshgrid(*(np.arange(n) - (n - 1) / 2 for n in s.shape), indexing="ij")
+        inner = (xx / (nx / 2)) ** 2 + (yy / (ny / 2)) ** 2 + (zz / (nz / 2)) ** 2 < r_frac ** 2
+        s.eps = np.where(s.mask.astype(bool) & inner, m_core ** 2, s.eps).astype(np.complex128)
+        return s
+
+    cases = [("prism x=20 128^3, ice m=1.31 with 30% random voxels at m=1.78",
+              inclusions(20.0, 128, 1.31, 1.78, 0.30, 7)),
+             ("prism x=20 128^3, ice m=1.31 with a m=1.5 core (radius 0.6)",
+              core(20.0, 128, 1.31, 1.5, 0.6)),
+             ("prism x=10 64^3, eps 1.7161 (1 + U[-0.05, 0.05])", w.config_c5()["scatterer"])]
+    dirs, pols = w.plane_wave_z(("x",))
+    for desc, s in cases:
+        mask = torch.from_numpy(s.mask).cuda()
+        eps = torch.from_numpy(s.eps).cuda()
+        for avg in ("mean_eps", "mean_alpha", "mode"):
+            line = dict(workload="alpha", case=desc, grid=list(s.shape), alpha_avg=avg)
+            prob = Problem(mask, eps, s.k, s.d, precond=2, tol=1e-5, restart=30, max_iter=2000,
+                           alpha_avg=avg)
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                prob.build_preconditioner(0.0)
                 torch.cuda.synchronize()
                 t1 = time.perf_counter()
                 o = prob.solve(dirs, pols, return_c=False, xsec=True)

@@ -96,6 +96,12 @@ typedef struct {
                        restart) is on ||P^{-1}(b - A x)|| / ||P^{-1} b||; dda_stats still
                        reports the true residual.  No effect without a preconditioner.
                        default 0 */
+  int alpha_avg;    /* the constant diagonal alpha~^{-1} of the circulant preconditioners
+                       (Sec. 1, Sec. 3.1), from the occupied voxels: 0: 1/alpha of the mean
+                       permittivity; 1: the mean of 1/alpha (the diagonal averaged); 2: 1/alpha
+                       of the most frequent permittivity (the paper's modal average, over the
+                       body; a tie goes to the smallest value, real part first).  All equal the
+                       body's value for a homogeneous body.  default 0 */
 } dda_options;
 
 typedef struct {
@@ -142,8 +148,9 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
  * then y on the signed-offset kernel, FFTs along x and y, one dense 3nz x 3nz
  * block per Fourier mode with alpha~^{-1} on its diagonal, and explicit block
  * inverses by Gauss-Jordan elimination with partial pivoting.  alpha~ is the
- * LDR polarisability of the mean occupied permittivity (the "ice" value for a
- * homogeneous body, Sec. 3.1) with lattice factor S = s_bar.  Only the
+ * LDR polarisability averaged over the occupied voxels as opt.alpha_avg says
+ * (the "ice" value for a homogeneous body, Sec. 3.1) with lattice factor
+ * S = s_bar.  Only the
  * (nx/2+1)(ny/2+1) modes with non-negative frequencies are inverted; the
  * block symmetries under x, y and z reflections supply the rest exactly.  The
  * dense z level spans the box's occupied z layers.

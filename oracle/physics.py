@@ -47,7 +47,8 @@ def alpha_tilde_inv(eps, mask, kd: float, S: float, variant: str = "mean_eps"):
     * "mean_eps":   alpha^{-1} of the mean occupied permittivity;
     * "mean_alpha": the mean of alpha^{-1} over the occupied voxels (the diagonal averaged);
     * "mode":       alpha^{-1} of the most frequent occupied permittivity (the paper's modal
-                    average of the diagonal, over the body), ties to the first in voxel order.
+                    average of the diagonal, over the body); a tie goes to the smallest value
+                    (real part, then imaginary part), which no voxel ordering affects.
 
     All three equal the body's own value for a homogeneous body.
     """
@@ -58,9 +59,10 @@ def alpha_tilde_inv(eps, mask, kd: float, S: float, variant: str = "mean_eps"):
     if variant == "mean_alpha":
         return complex(alpha_inv(e, kd, S).mean())
     if variant == "mode":
-        vals, first, counts = np.unique(e, return_index=True, return_counts=True)
-        best = max(range(len(vals)), key=lambda i: (counts[i], -first[i]))
-        return complex(alpha_inv(vals[best], kd, S))
+        vals, counts = np.unique(e, return_counts=True)
+        top = counts.max()
+        cand = sorted((v.real, v.imag) for v, c in zip(vals, counts) if c == top)
+        return complex(alpha_inv(complex(*cand[0]), kd, S))
     raise ValueError(f"unknown variant {variant!r}")
 
 

@@ -86,6 +86,7 @@ void dda_default_options(dda_options *opt) {
   opt->solver = 0;
   opt->dense_axis = 2;
   opt->left_precond = 0;
+  opt->alpha_avg = 0;
 }
 
 const char *dda_last_error(void) { return get_error(); }
@@ -121,6 +122,7 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
     REQUIRE(o.left_precond == 0 || o.left_precond == 1, DDA_EINVAL, "left_precond must be 0 or 1");
     REQUIRE(o.left_precond == 0 || o.solver == 0, DDA_EINVAL,
             "left preconditioning is a GMRES option (solver 0)");
+    REQUIRE(o.alpha_avg >= 0 && o.alpha_avg <= 2, DDA_EINVAL, "alpha_avg must be 0, 1 or 2");
     {
       FftPlan t;
       REQUIRE(factor_7smooth(nx, t) && factor_7smooth(ny, t) && factor_7smooth(nz, t),

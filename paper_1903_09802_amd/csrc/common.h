@@ -89,6 +89,16 @@ __host__ __device__ __forceinline__ double2 ldr_alpha_inv(double2 eps, double kd
   r.y = f * q.y + eps.y * (DDA_B2 + DDA_B3 * S) * kd2 - (2.0 / 3.0) * kd2 * kd;
   return r;
 }
+// The same with the Clausius-Mossotti ratio q = (eps + 2)/(eps - 1) given: 1/alpha is linear in
+// eps apart from q, so the mean of 1/alpha over voxels is this at the means of q and eps.
+__host__ __device__ __forceinline__ double2 ldr_alpha_inv_q(double2 q, double2 eps, double kd, double S) {
+  const double f = 4.0 * DDA_PI / 3.0;
+  const double kd2 = kd * kd;
+  double2 r;
+  r.x = f * q.x + (DDA_B1 + eps.x * (DDA_B2 + DDA_B3 * S)) * kd2;
+  r.y = f * q.y + eps.y * (DDA_B2 + DDA_B3 * S) * kd2 - (2.0 / 3.0) * kd2 * kd;
+  return r;
+}
 // d(1/alpha)/d eps = -4 pi / (eps - 1)^2 + (b2 + b3 S)(k d)^2
 __host__ __device__ __forceinline__ double2 ldr_dalpha_inv(double2 eps, double kd, double S) {
   double2 em1 = make_double2(eps.x - 1.0, eps.y);
@@ -263,6 +273,7 @@ struct dda_problem {
   int *cidx = nullptr;          // [N]
   int *vox = nullptr;           // [nocc]
   double2 eps_mean{0.0, 0.0};   // mean permittivity over occupied voxels
+  double2 cm_mean{};            // mean over occupied voxels of (eps + 2) / (eps - 1)
 
   dda::FftPlan px, py, pz;   // padded lengths 2nx, 2ny, 2nz
   dda::FftPlan ux, uy;       // unpadded nx, ny (preconditioner)

@@ -106,8 +106,8 @@ static void extract_octant(dda_problem *p, const double2 *full, TO *oct) {
 
 // Occupancy, invalid permittivities and the occupied-permittivity sum, per block.
 __global__ void k_validate(const uint8_t *mask, const double2 *eps, long long N, double *partial) {
-  __shared__ double sh[4][256];
-  double occ = 0, bad = 0, sr = 0, si = 0;
+  __shared__ double sh[6][256];
+  double occ = 0, bad = 0, sr = 0, si = 0, qr = 0, qi = 0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
     if (mask[i]) {
@@ -116,21 +116,29 @@ __global__ void k_validate(const uint8_t *mask, const double2 *eps, long long N,
       sr += e.x;
       si += e.y;
       const double d1 = fabs(e.x - 1.0) + fabs(e.y), d2 = fabs(e.x + 2.0) + fabs(e.y);
-      if (d1 < 1e-12 || d2 < 1e-12 || !isfinite(e.x) || !isfinite(e.y)) bad += 1.0;
+      if (d1 < 1e-12 || d2 < 1e-12 || !isfinite(e.x) || !isfinite(e.y)) {
+        bad += 1.0;
+      } else {  // (eps + 2) / (eps - 1), the part of 1/alpha that is not linear in eps
+        const double2 q = cdiv(make_double2(e.x + 2.0, e.y), make_double2(e.x - 1.0, e.y));
+        qr += q.x;
+        qi += q.y;
+      }
     }
   }
   sh[0][threadIdx.x] = occ;
   sh[1][threadIdx.x] = bad;
   sh[2][threadIdx.x] = sr;
   sh[3][threadIdx.x] = si;
+  sh[4][threadIdx.x] = qr;
+  sh[5][threadIdx.x] = qi;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s)
-      for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+      for (int q = 0; q < 6; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    for (int q = 0; q < 4; ++q) partial[blockIdx.x * 4 + q] = sh[q][0];
+    for (int q = 0; q < 6; ++q) partial[blockIdx.x * 6 + q] = sh[q][0];
 }
 
 __global__ void k_alpha(const uint8_t *mask, const double2 *eps, long long N, double kd,
@@ -350,21 +358,23 @@ void operator_setup(dda_problem *p) {
   // validation, mean permittivity and the compact index map
   const int nb = 1024;
   double *part = nullptr;
-  HIPCHK(hipMalloc(&part, sizeof(double) * 4 * nb));
+  HIPCHK(hipMalloc(&part, sizeof(double) * 6 * nb));
   hipLaunchKernelGGL(k_validate, dim3(nb), dim3(256), 0, p->st, p->mask, p->eps, p->N, part);
-  std::vector<double> h(4 * nb);
+  std::vector<double> h(6 * nb);
   hipError_t e1 = hipGetLastError();
-  hipError_t e2 = hipMemcpyAsync(h.data(), part, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, p->st);
+  hipError_t e2 = hipMemcpyAsync(h.data(), part, sizeof(double) * 6 * nb, hipMemcpyDeviceToHost, p->st);
   hipError_t e3 = hipStreamSynchronize(p->st);
   (void)hipFree(part);
   REQUIRE(e1 == hipSuccess && e2 == hipSuccess && e3 == hipSuccess, DDA_EDEVICE,
           "validation kernel failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3)));
-  double occ = 0, bad = 0, sr = 0, si = 0;
+  double occ = 0, bad = 0, sr = 0, si = 0, qr = 0, qi = 0;
   for (int b = 0; b < nb; ++b) {
-    occ += h[4 * b];
-    bad += h[4 * b + 1];
-    sr += h[4 * b + 2];
-    si += h[4 * b + 3];
+    occ += h[6 * b];
+    bad += h[6 * b + 1];
+    sr += h[6 * b + 2];
+    si += h[6 * b + 3];
+    qr += h[6 * b + 4];
+    qi += h[6 * b + 5];
   }
   REQUIRE(occ > 0, DDA_EINVAL, "the mask has no occupied voxel");
   REQUIRE(bad == 0, DDA_EINVAL,
@@ -373,6 +383,7 @@ void operator_setup(dda_problem *p) {
   p->n_occ = (long long)occ;
   p->nocc = p->n_occ;
   p->eps_mean = make_double2(sr / occ, si / occ);
+  p->cm_mean = make_double2(qr / occ, qi / occ);
   build_compact_map(p);
 }
 

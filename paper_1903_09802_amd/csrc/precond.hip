@@ -26,6 +26,7 @@
 // the full halves are stored column-major.
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <type_traits>
 
 #include "fft_kernels.h"
@@ -449,15 +450,41 @@ void precond_free(dda_problem *p) {
 
 static void precond1_build(dda_problem *p);
 
+// The preconditioner's constant diagonal alpha~^{-1} (Sec. 1, Sec. 3.1) from the occupied
+// voxels, by opt.alpha_avg: 1/alpha of the mean permittivity; the mean of 1/alpha (exact from
+// the setup's means of eps and of (eps + 2)/(eps - 1)); or 1/alpha of the most frequent
+// permittivity, ties to the smallest value (real part first).
+static double2 alpha_tilde_inv(dda_problem *p, double s_bar) {
+  const double kd = p->k * p->d;
+  if (p->opt.alpha_avg == 1) return ldr_alpha_inv_q(p->cm_mean, p->eps_mean, kd, s_bar);
+  if (p->opt.alpha_avg != 2) return ldr_alpha_inv(p->eps_mean, kd, s_bar);
+  std::vector<uint8_t> m(p->N);
+  std::vector<double2> e(p->N);
+  HIPCHK(hipMemcpyAsync(m.data(), p->mask, p->N, hipMemcpyDeviceToHost, p->st));
+  HIPCHK(hipMemcpyAsync(e.data(), p->eps, sizeof(double2) * p->N, hipMemcpyDeviceToHost, p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
+  std::map<std::pair<double, double>, long long> count;
+  for (long long v = 0; v < p->N; ++v)
+    if (m[v]) ++count[std::make_pair(e[v].x, e[v].y)];
+  std::pair<double, double> best{0.0, 0.0};
+  long long top = -1;
+  for (const auto &kv : count)  // ascending values: a tie keeps the smallest
+    if (kv.second > top) {
+      top = kv.second;
+      best = kv.first;
+    }
+  return ldr_alpha_inv(make_double2(best.first, best.second), kd, s_bar);
+}
+
 void precond_build(dda_problem *p, double s_bar) {
   precond_free(p);
   if (p->opt.precond == 1) {
-    p->ati = ldr_alpha_inv(p->eps_mean, p->k * p->d, s_bar);
+    p->ati = alpha_tilde_inv(p, s_bar);
     precond1_build(p);
     return;
   }
   const int nx = p->nx, ny = p->ny, nz = p->pbz;  // the dense level's extent
-  p->ati = ldr_alpha_inv(p->eps_mean, p->k * p->d, s_bar);
+  p->ati = alpha_tilde_inv(p, s_bar);
   p->hh = (nz + 1) / 2;
   p->n2 = 3 * p->hh;
   p->umx = nx / 2 + 1;

@@ -38,11 +38,11 @@ def random_waves(n, seed):
     return w.random_directions((n + 1) // 2, rng)
 
 
-def oracle_precond(s, s_bar=0.0):
+def oracle_precond(s, s_bar=0.0, variant="mean_eps"):
     """v -> M P^{-1} M v of the oracle's 2-level preconditioner on the occupied z layers, with
-    alpha~^{-1} of the mean occupied permittivity (what build_preconditioner(s_bar) builds)."""
+    alpha~^{-1} averaged over the occupied voxels as ``variant`` says (by default of the mean
+    occupied permittivity: what build_preconditioner(s_bar) builds with alpha_avg 0)."""
     from oracle import circulant, physics
-    occ = s.mask.astype(bool)
-    ati = complex(physics.alpha_inv(s.eps[occ].mean(), s.k * s.d, s_bar))
+    ati = physics.alpha_tilde_inv(s.eps, s.mask, s.k * s.d, s_bar, variant)
     z0, Binv = circulant.blocks_for_mask(s.mask, s.k, s.d, ati)
     return lambda v: circulant.apply_blocks_layers(v, s.mask, Binv, z0)

@@ -39,7 +39,7 @@ def test_default_options(lib):
     o = dda.default_options()
     assert (o.restart, o.max_iter, o.tol, o.precond, o.precision, o.max_rhs) == (30, 2000, 1e-5, 2, 0, 1)
     assert abs(o.inner_tol - 1e-4) < 1e-18 and o.max_refine == 30
-    assert o.solver == 0 and o.dense_axis == 2 and o.left_precond == 0
+    assert o.solver == 0 and o.dense_axis == 2 and o.left_precond == 0 and o.alpha_avg == 0
 
 
 @pytest.mark.parametrize("precond", [-1, 3])
@@ -75,6 +75,18 @@ def test_create_rejects_bad_left_precond(lib, left, solver):
     st = lib.dda_create(4, 4, 4, dummy, dummy, 1.0, 0.1, ctypes.byref(o), None, ctypes.byref(h))
     assert st == -1 and h.value is None
     assert b"left" in lib.dda_last_error()
+
+
+@pytest.mark.parametrize("avg", [-1, 3])
+def test_create_rejects_bad_alpha_avg(lib, avg):
+    from paper_1903_09802_amd import dda
+    o = dda.default_options()
+    o.alpha_avg = avg
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: option validation fails first
+    st = lib.dda_create(4, 4, 4, dummy, dummy, 1.0, 0.1, ctypes.byref(o), None, ctypes.byref(h))
+    assert st == -1 and h.value is None
+    assert b"alpha_avg" in lib.dda_last_error()
 
 
 @pytest.mark.parametrize("solver,precision,restart,status", [

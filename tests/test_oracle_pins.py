@@ -413,10 +413,10 @@ def test_alpha_tilde_variants_closed_forms():
     hom = np.full(mask.shape, e2)
     for v in ("mean_eps", "mean_alpha", "mode"):
         assert abs(physics.alpha_tilde_inv(hom, mask, kd, S, v) - a2) < 1e-12 * abs(a2)
-    # a tie goes to the value met first in voxel order
-    tie = np.zeros((1, 1, 4), dtype=bool) | True
-    te = np.array([[[e2, e1, e1, e2]]])
-    assert physics.alpha_tilde_inv(te, tie, kd, S, "mode") == a2
+    # a tie goes to the smallest value, whatever the voxel order
+    tie = np.ones((1, 1, 4), dtype=bool)
+    for te in (np.array([[[e2, e1, e1, e2]]]), np.array([[[e1, e2, e2, e1]]])):
+        assert physics.alpha_tilde_inv(te, tie, kd, S, "mode") == a1
 
 
 def test_left_gmres_exact_preconditioner_one_step():
