@@ -54,3 +54,35 @@ def test_alpha_variants_differ_and_solve_to_dense_lu():
             out = prob.solve(dirs, pols)
         assert out["stats"][0]["converged"] == 1
         assert rel_err(out["c"][0].cpu().numpy(), cref) < 1e-8, v
+
+
+@pytest.mark.parametrize("variant", ["mean_alpha", "mode"])
+def test_one_level_preconditioner_alpha_variants(variant):
+    """The 1-level preconditioner (precond = 1) takes the same alpha~ readings."""
+    from oracle import circulant
+    shape = (4, 5, 12)
+    s = _two_material(shape, 97)
+    with make_problem(s, precond=1, alpha_avg=variant) as prob:
+        prob.build_preconditioner(0.0)
+        x = rand_field(shape, 1, 97)
+        z = prob.apply_preconditioner(to_dev(x)).cpu().numpy()
+    ati = physics.alpha_tilde_inv(s.eps, s.mask, s.k * s.d, 0.0, variant)
+    Dinv = np.linalg.inv(circulant.one_level_blocks(shape, s.k, s.d, ati))
+    assert rel_err(z[0], circulant.apply_one_level(x[0], s.mask, Dinv)) < 1e-10
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("variant", ["mean_alpha", "mode"])
+def test_alpha_variants_in_rotated_frames(axis, variant):
+    """With another dense axis the library works in a rotated frame; the readings depend on
+    the permittivity values only (the mode's tie rule too), so the preconditioner is the
+    oracle's for the rotated box with the same alpha~."""
+    from test_gpu_dense_axis import _field_from_frame, _field_to_frame, _rotated
+    s = _two_material((6, 8, 10), 98, frac=0.5)
+    with make_problem(s, precond=2, alpha_avg=variant, dense_axis=axis) as prob:
+        prob.build_preconditioner(0.0)
+        x = rand_field(s.shape, 1, 98)
+        z = prob.apply_preconditioner(to_dev(x)).cpu().numpy()
+    pc = oracle_precond(_rotated(s, axis), 0.0, variant)
+    ref = _field_from_frame(pc(_field_to_frame(x[0], axis)), axis)
+    assert rel_err(z[0], ref) < 1e-10
