@@ -230,3 +230,25 @@ def apply_blocks_layers(vbox, mask, Binv, z0: int):
     out = np.zeros_like(vbox, dtype=np.complex128)
     out[:, z0:z0 + bz] = apply_blocks(vbox[:, z0:z0 + bz], mask[z0:z0 + bz], Binv)
     return out
+
+
+def diag_correction(eps, mask, kd: float, S: float, alpha_tilde_inv: complex):
+    """Delta = D - alpha~^{-1} I on the box (0 in air): the part of the true diagonal
+    D = diag(1/alpha_j) that the circulant preconditioner's constant diagonal misses (Sec. 1,
+    P = D~ + C; Sec. 5, circulant-plus-diagonal)."""
+    from . import physics
+    occ = np.asarray(mask).astype(bool)
+    return np.where(occ, physics.alpha_inv_masked(eps, mask, kd, S) - alpha_tilde_inv, 0.0)
+
+
+def apply_plus_diagonal(vbox, apply_B, delta, steps: int):
+    """z ~ (D + C)^{-1} v for the circulant-plus-diagonal P = D + C = B + Delta, where
+    B = alpha~^{-1} I + C is the circulant preconditioner, applied as Q = M B^{-1} M
+    (apply_B), and Delta = D - alpha~^{-1} I: the fixed point of z = Q (v - Delta z), i.e.
+    (Q^{-1} + Delta)^{-1} v on the occupied voxels, taken from z_0 = Q v in `steps` more steps
+    (the Neumann series of (I + Q Delta)^{-1} Q truncated after steps + 1 terms).  steps = 0
+    is the circulant preconditioner itself."""
+    z = apply_B(vbox)
+    for _ in range(steps):
+        z = apply_B(vbox - delta[None] * z)
+    return z

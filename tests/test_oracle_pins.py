@@ -419,6 +419,44 @@ def test_alpha_tilde_variants_closed_forms():
         assert physics.alpha_tilde_inv(te, tie, kd, S, "mode") == a1
 
 
+def test_circulant_plus_diagonal_neumann_steps():
+    """P = D + C (Sec. 1 P = D~ + C with the true diagonal; Sec. 5 circulant-plus-diagonal)
+    applied by z = Q(v - Delta z), Q = M B^{-1} M the circulant preconditioner as applied:
+    zero steps give Q itself; on a two-material body where Q Delta is a contraction the
+    steps converge to the dense solve (Q^{-1} + Delta)^{-1} v on the occupied voxels, the
+    error shrinking every step; for a homogeneous body Delta = 0."""
+    rng = np.random.default_rng(21)
+    shape = (4, 3, 5)
+    k, d = 1.1, 0.3
+    mask = (rng.random(shape) < 0.8).astype(np.uint8)
+    e1, e2 = 1.7161 + 0.0j, 1.9 + 0.01j
+    eps = np.where(rng.random(shape) < 0.6, e1, e2)
+    ati = physics.alpha_tilde_inv(eps, mask, k * d, 0.0, "mean_eps")
+    P = circulant.two_level_dense(shape, k, d, ati)  # alpha~^{-1} I - C2 on the whole box
+    delta = circulant.diag_correction(eps, mask, k * d, 0.0, ati)
+    occ = mask.astype(bool).ravel()
+    sel = np.repeat(occ[None], 3, axis=0).ravel()  # box order [3][nz][ny][nx]
+    Q = np.linalg.inv(P)[np.ix_(sel, sel)]  # M B^{-1} M on the occupied voxels
+    Dl = np.repeat(delta.ravel()[None], 3, axis=0).ravel()[sel]
+    apply_B = lambda v: circulant.apply_dense(v, mask, P)
+    v = rng.normal(size=(3,) + shape) + 1j * rng.normal(size=(3,) + shape)
+    v = v * mask[None]
+    z0 = circulant.apply_plus_diagonal(v, apply_B, delta, 0)
+    assert np.allclose(z0, apply_B(v), rtol=0, atol=1e-13)
+    exact = np.zeros(v.shape, dtype=np.complex128).ravel()
+    exact[sel] = np.linalg.solve(np.eye(sel.sum()) + Q * Dl[None, :], Q @ v.ravel()[sel])
+    exact = exact.reshape(v.shape)
+    rho = max(abs(np.linalg.eigvals(Q * Dl[None, :])))
+    assert rho < 0.6
+    errs = [np.abs(circulant.apply_plus_diagonal(v, apply_B, delta, s) - exact).max()
+            for s in (0, 4, 12, 48)]
+    assert errs[-1] < 1e-8 * np.abs(exact).max()
+    assert all(e2_ < e1_ for e1_, e2_ in zip(errs, errs[1:]))
+    hom = np.full(shape, e1)
+    dh = circulant.diag_correction(hom, mask, k * d, 0.0, complex(physics.alpha_inv(e1, k * d, 0.0)))
+    assert np.abs(dh).max() < 1e-12
+
+
 def test_left_gmres_exact_preconditioner_one_step():
     """Left preconditioning (Sec. 1, eq. general_prec) with P^{-1} = A^{-1}: P^{-1} A = I, so
     the first Krylov step solves the system; right-preconditioned GMRES does the same."""
