@@ -667,7 +667,8 @@ def bench_levels(args):
 def bench_alpha(args):
     """Readings of the preconditioner's constant diagonal (option alpha_avg) on inhomogeneous
     prisms: 1/alpha of the mean permittivity, the mean of 1/alpha, and the paper's modal value
-    over the body.  GMRES(30) to 1e-5, one wave (+z, x-pol)."""
+    over the body; and the circulant-plus-diagonal preconditioner (option diag_steps) around
+    the first two.  GMRES(30) to 1e-5, one wave (+z, x-pol)."""
     import numpy as np
     import torch
 
@@ -699,10 +700,13 @@ def bench_alpha(args):
     for desc, s in cases:
         mask = torch.from_numpy(s.mask).cuda()
         eps = torch.from_numpy(s.eps).cuda()
-        for avg in ("mean_eps", "mean_alpha", "mode"):
-            line = dict(workload="alpha", case=desc, grid=list(s.shape), alpha_avg=avg)
+        runs = [(a, 0) for a in ("mean_eps", "mean_alpha", "mode")]
+        runs += [(a, k) for a in ("mean_eps", "mean_alpha") for k in (1, 2, 4)]
+        for avg, steps in runs:
+            line = dict(workload="alpha", case=desc, grid=list(s.shape), alpha_avg=avg,
+                        diag_steps=steps)
             prob = Problem(mask, eps, s.k, s.d, precond=2, tol=1e-5, restart=30, max_iter=2000,
-                           alpha_avg=avg)
+                           alpha_avg=avg, diag_steps=steps)
             try:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()

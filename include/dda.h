@@ -102,6 +102,18 @@ typedef struct {
                        of the most frequent permittivity (the paper's modal average, over the
                        body; a tie goes to the smallest value, real part first).  All equal the
                        body's value for a homogeneous body.  default 0 */
+  int diag_steps;   /* 0 .. 32.  k > 0 makes the preconditioner the circulant-plus-diagonal
+                       P = D + C: the circulant part C of the chosen preconditioner with the
+                       true diagonal D = diag(1/alpha_j) of the occupied voxels (at the lattice
+                       factor the preconditioner is built with) in place of alpha~^{-1} I
+                       (Sec. 1, P = D~ + C; Sec. 5).  With Q the circulant preconditioner as
+                       applied (occupied voxels in and out) and Delta = D - alpha~^{-1} I, a
+                       preconditioner application returns z_k of z_0 = Q v,
+                       z_{i+1} = Q (v - Delta z_i): k + 1 circulant applications, the Neumann
+                       series of (I + Q Delta)^{-1} Q truncated after k + 1 terms.  Useful where
+                       Q Delta is a contraction (moderate permittivity contrast); 0 is the
+                       circulant preconditioner itself.  Needs a preconditioner (precond 1 or
+                       2).  default 0 */
 } dda_options;
 
 typedef struct {

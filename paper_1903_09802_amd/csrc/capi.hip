@@ -87,6 +87,7 @@ void dda_default_options(dda_options *opt) {
   opt->dense_axis = 2;
   opt->left_precond = 0;
   opt->alpha_avg = 0;
+  opt->diag_steps = 0;
 }
 
 const char *dda_last_error(void) { return get_error(); }
@@ -123,6 +124,9 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
     REQUIRE(o.left_precond == 0 || o.solver == 0, DDA_EINVAL,
             "left preconditioning is a GMRES option (solver 0)");
     REQUIRE(o.alpha_avg >= 0 && o.alpha_avg <= 2, DDA_EINVAL, "alpha_avg must be 0, 1 or 2");
+    REQUIRE(o.diag_steps >= 0 && o.diag_steps <= 32, DDA_EINVAL, "diag_steps must be in [0, 32]");
+    REQUIRE(o.diag_steps == 0 || o.precond != 0, DDA_EINVAL,
+            "diag_steps needs a preconditioner (precond 1 or 2)");
     {
       FftPlan t;
       REQUIRE(factor_7smooth(nx, t) && factor_7smooth(ny, t) && factor_7smooth(nz, t),

@@ -304,6 +304,10 @@ struct dda_problem {
   double2 *binv64 = nullptr; // psym 0: [umy][umx][2][n2][n2] column-major inverse halves;
                              // psym 1: [umy][umx][2][ntr (ntr+1) / 2][256] packed tiles
   float2 *binv32 = nullptr;
+  // circulant-plus-diagonal (opt.diag_steps > 0): Delta = 1/alpha_j - alpha~^{-1} per occupied
+  // voxel [nocc]; two compact [R][3][nocc] work vectors for the fixed-point steps
+  double2 *pdelta = nullptr;
+  double2 *pdt = nullptr, *pdz = nullptr;
 
   // Krylov state (FP64)
   double2 *V = nullptr;      // [restart+1][R][3N]

@@ -443,9 +443,52 @@ __global__ void k_pack_sym(const TI *Y, TO *out, long long m0, int n2, int ntr) 
 void precond_free(dda_problem *p) {
   if (p->binv64) (void)hipFree(p->binv64);
   if (p->binv32) (void)hipFree(p->binv32);
+  if (p->pdelta) (void)hipFree(p->pdelta);
+  if (p->pdt) (void)hipFree(p->pdt);
+  if (p->pdz) (void)hipFree(p->pdz);
   p->binv64 = nullptr;
   p->binv32 = nullptr;
+  p->pdelta = p->pdt = p->pdz = nullptr;
   p->prec_built = 0;
+}
+
+// Delta[c] = 1/alpha_j - alpha~^{-1} at the voxel j of compact entry c: what the circulant
+// preconditioner's constant diagonal misses of the true diagonal D (Sec. 1, P = D~ + C)
+__global__ void k_diag_delta(const double2 *eps, const int *vox, long long nocc, double kd,
+                             double s_bar, double2 ati, double2 *delta) {
+  const long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c < nocc) delta[c] = csub(ldr_alpha_inv(eps[vox[c]], kd, s_bar), ati);
+}
+
+// t = s_r x - Delta z on compact [nrhs][3][nocc] vectors, s_r = xscale[r * kMaxM] (or 1);
+// blockIdx.y = 3 r + component
+__global__ void k_diag_resid(const double2 *x, const double2 *z, const double2 *delta,
+                             double2 *t, long long nocc, const double *xscale) {
+  const long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= nocc) return;
+  const long long i = blockIdx.y * nocc + c;
+  double2 xv = x[i];
+  if (xscale) xv = cscale(xv, xscale[(blockIdx.y / 3) * kMaxM]);
+  t[i] = csub(xv, cmul(delta[c], z[i]));
+}
+
+// The circulant-plus-diagonal data (opt.diag_steps > 0), after the circulant part is built.
+static void diag_setup(dda_problem *p, double s_bar) {
+  if (p->opt.diag_steps <= 0) return;
+  try {
+    const size_t vec = sizeof(double2) * (size_t)p->R * 3 * (size_t)p->nocc;
+    HIPCHK(hipMalloc(&p->pdelta, sizeof(double2) * (size_t)std::max<long long>(p->nocc, 1)));
+    HIPCHK(hipMalloc(&p->pdt, std::max<size_t>(vec, 16)));
+    HIPCHK(hipMalloc(&p->pdz, std::max<size_t>(vec, 16)));
+    if (p->nocc > 0) {
+      hipLaunchKernelGGL(k_diag_delta, dim3(nblk(p->nocc, 256)), dim3(256), 0, p->st, p->eps,
+                         p->vox, p->nocc, p->k * p->d, s_bar, p->ati, p->pdelta);
+      HIPCHK(hipGetLastError());
+    }
+  } catch (...) {
+    precond_free(p);
+    throw;
+  }
 }
 
 static void precond1_build(dda_problem *p);
@@ -481,6 +524,7 @@ void precond_build(dda_problem *p, double s_bar) {
   if (p->opt.precond == 1) {
     p->ati = alpha_tilde_inv(p, s_bar);
     precond1_build(p);
+    diag_setup(p, s_bar);
     return;
   }
   const int nx = p->nx, ny = p->ny, nz = p->pbz;  // the dense level's extent
@@ -575,6 +619,7 @@ void precond_build(dda_problem *p, double s_bar) {
   if (scratch) HIPCHK(hipFree(scratch));
   p->prec_built = 1;
   p->prec_fp32 = fp32;
+  diag_setup(p, s_bar);
 }
 
 // ----------------------------------------------------------------------------- 1-level
@@ -1186,11 +1231,9 @@ static void pc_apply1(dda_problem *p, int nrhs, const double2 *x, double2 *y, co
   }
 }
 
-void apply_precond(dda_problem *p, int nrhs, const double2 *x, double2 *y, int fp32,
-                   const double *xscale) {
-  REQUIRE(p->prec_built, DDA_ESTATE, "preconditioner not built");
-  REQUIRE(fp32 == p->prec_fp32, DDA_ESTATE, "preconditioner was built in %s",
-          p->prec_fp32 ? "FP32" : "FP64");
+// Q: the circulant preconditioner as applied, occupied voxels in and out
+static void apply_circulant(dda_problem *p, int nrhs, const double2 *x, double2 *y, int fp32,
+                            const double *xscale) {
   if (p->opt.precond == 1) {
     if (fp32)
       pc_apply1<float>(p, nrhs, x, y, p->binv32, xscale);
@@ -1200,6 +1243,32 @@ void apply_precond(dda_problem *p, int nrhs, const double2 *x, double2 *y, int f
     pc_apply<float>(p, nrhs, x, y, p->binv32, xscale);
   } else {
     pc_apply<double>(p, nrhs, x, y, p->binv64, xscale);
+  }
+}
+
+void apply_precond(dda_problem *p, int nrhs, const double2 *x, double2 *y, int fp32,
+                   const double *xscale) {
+  REQUIRE(p->prec_built, DDA_ESTATE, "preconditioner not built");
+  REQUIRE(fp32 == p->prec_fp32, DDA_ESTATE, "preconditioner was built in %s",
+          p->prec_fp32 ? "FP32" : "FP64");
+  const int k = p->opt.diag_steps;
+  if (k <= 0) {
+    apply_circulant(p, nrhs, x, y, fp32, xscale);
+    return;
+  }
+  // circulant-plus-diagonal P = D + C = B + Delta (Sec. 1, Sec. 5): z_0 = Q v,
+  // z_{i+1} = Q (v - Delta z_i), v = s x.  x is read by every step, so an in-place call keeps
+  // z in pdz until the last step writes y.
+  double2 *z = x == y ? p->pdz : y;
+  apply_circulant(p, nrhs, x, z, fp32, xscale);
+  for (int i = 1; i <= k; ++i) {
+    {
+      KTimer t(&p->prof, p->st, "pc_diag_resid", (48.0 * 3 * nrhs + 16.0) * p->nocc);
+      hipLaunchKernelGGL(k_diag_resid, dim3(nblk(p->nocc, 256), 3 * nrhs), dim3(256), 0, p->st, x,
+                         z, p->pdelta, p->pdt, p->nocc, xscale);
+      HIPCHK(hipGetLastError());
+    }
+    apply_circulant(p, nrhs, p->pdt, i == k ? y : z, fp32, nullptr);
   }
 }
 

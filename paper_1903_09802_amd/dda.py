@@ -37,7 +37,8 @@ class Options(ctypes.Structure):
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
                 ("max_rhs", ctypes.c_int), ("solver", ctypes.c_int), ("dense_axis", ctypes.c_int),
-                ("left_precond", ctypes.c_int), ("alpha_avg", ctypes.c_int)]
+                ("left_precond", ctypes.c_int), ("alpha_avg", ctypes.c_int),
+                ("diag_steps", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -130,7 +131,8 @@ class Problem:
 
     def __init__(self, mask, eps, k: float, d: float, *, restart=30, max_iter=2000, tol=1e-5,
                  precond=2, precision=0, inner_tol=1e-4, max_refine=30, max_rhs=1, solver="gmres",
-                 dense_axis=2, precond_side="right", alpha_avg="mean_eps", stream=None):
+                 dense_axis=2, precond_side="right", alpha_avg="mean_eps", diag_steps=0,
+                 stream=None):
         import torch
         L = load()
         self.mask = mask.to(device="cuda", dtype=torch.uint8).contiguous()
@@ -155,6 +157,7 @@ class Problem:
         if alpha_avg not in avgs:
             raise ValueError(f"alpha_avg must be one of {sorted(avgs)}")
         o.alpha_avg = avgs[alpha_avg]
+        o.diag_steps = int(diag_steps)
         self.opts = o
         self.stream = torch.cuda.current_stream() if stream is None else stream
         h = ctypes.c_void_p()

@@ -40,6 +40,7 @@ def test_default_options(lib):
     assert (o.restart, o.max_iter, o.tol, o.precond, o.precision, o.max_rhs) == (30, 2000, 1e-5, 2, 0, 1)
     assert abs(o.inner_tol - 1e-4) < 1e-18 and o.max_refine == 30
     assert o.solver == 0 and o.dense_axis == 2 and o.left_precond == 0 and o.alpha_avg == 0
+    assert o.diag_steps == 0
 
 
 @pytest.mark.parametrize("precond", [-1, 3])
@@ -87,6 +88,19 @@ def test_create_rejects_bad_alpha_avg(lib, avg):
     st = lib.dda_create(4, 4, 4, dummy, dummy, 1.0, 0.1, ctypes.byref(o), None, ctypes.byref(h))
     assert st == -1 and h.value is None
     assert b"alpha_avg" in lib.dda_last_error()
+
+
+@pytest.mark.parametrize("steps,precond", [(-1, 2), (33, 2), (1, 0)])
+def test_create_rejects_bad_diag_steps(lib, steps, precond):
+    """diag_steps is in [0, 32] and needs a preconditioner."""
+    from paper_1903_09802_amd import dda
+    o = dda.default_options()
+    o.diag_steps, o.precond = steps, precond
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: option validation fails first
+    st = lib.dda_create(4, 4, 4, dummy, dummy, 1.0, 0.1, ctypes.byref(o), None, ctypes.byref(h))
+    assert st == -1 and h.value is None
+    assert b"diag_steps" in lib.dda_last_error()
 
 
 @pytest.mark.parametrize("solver,precision,restart,status", [
