@@ -210,10 +210,15 @@ dda_status dda_apply_operator(dda_problem *p, int nrhs, const double *dir_host,
                               int fp32);
 
 /*
- * y = M P^{-1} M x with P the 2-level circulant preconditioner and M the
- * occupancy mask (air entries of y are 0).  x_dev, y_dev: c128
+ * y = M P^{-1} M x with P the circulant preconditioner opt.precond selects
+ * (Sec. 3 1-level, Sec. 3.1 2-level) and M the occupancy mask (air entries of
+ * y are 0); with opt.diag_steps = k > 0, the k-step circulant-plus-diagonal
+ * approximation described at dda_options.  x_dev, y_dev: c128
  * [nrhs][3][nz][ny][nx] (may alias).  fp32 selects the FP32 blocks and must
  * match the precision the preconditioner was built in (else ESTATE).
+ * The environment variable DDA_GEMV_SINGLE_READ=1, read at every call, selects
+ * a 2-level block product that reads each stored tile once (one column block,
+ * dense extent up to 128 layers); same result, fewer HBM bytes, slower here.
  */
 dda_status dda_apply_preconditioner(dda_problem *p, int nrhs, const double *x_dev,
                                     double *y_dev, int fp32);
