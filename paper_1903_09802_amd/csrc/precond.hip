@@ -859,6 +859,105 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int q, int m) { return 4 * q + m; }
 };
 
+// One unique mode (ux, uy) of the x-y spectrum and its copies (nx - ux, ny - uy) that share
+// its blocks (up to four), for the right-hand sides r0 .. r0 + nr - 1; nv = copies x nr vectors.
+struct GemvMode {
+  int mx0, mx1, my0, my1, nmx, nv, nr, r0;
+  int nx, nzw, z0, nz, hh, n2, h;
+  long long plane;
+  // x-y offset of copy `mode` and the sign its flip gives component a
+  __device__ __forceinline__ long long off(int mode) const {
+    return (long long)(mode / nmx ? my1 : my0) * nx + (mode % nmx ? mx1 : mx0);
+  }
+  template <typename T> __device__ __forceinline__ T flip(int mode, int a) const {
+    const int fx = mode % nmx, fy = mode / nmx;
+    return ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
+  }
+};
+
+__device__ __forceinline__ GemvMode gemv_mode(long long u, int umx, int nx, int ny, int nzw, int z0,
+                                              int nz, int hh, int n2, int nr, int r0) {
+  GemvMode g;
+  const int uy = (int)(u / umx), ux = (int)(u % umx);
+  g.mx0 = ux;
+  g.mx1 = (nx - ux) % nx;
+  g.my0 = uy;
+  g.my1 = (ny - uy) % ny;
+  g.nmx = (g.mx1 != g.mx0) ? 2 : 1;
+  const int nmy = (g.my1 != g.my0) ? 2 : 1;
+  g.nv = g.nmx * nmy * nr;
+  g.nr = nr;
+  g.r0 = r0;
+  g.nx = nx;
+  g.nzw = nzw;
+  g.z0 = z0;
+  g.nz = nz;
+  g.hh = hh;
+  g.n2 = n2;
+  g.h = nz / 2;
+  g.plane = (long long)nx * ny;
+  return g;
+}
+
+// Gather the mode's vectors from the y-transformed work array, flip, fold the z mirror
+// halves and scale by S into Ub[2][NV][n2p] (zero beyond nv and n2).  GB elements per
+// thread are loaded before any is stored.
+template <typename T, int NV>
+__device__ __forceinline__ void gemv_gather(cplx<T> *Ub, const cplx<T> *W, const GemvMode &g,
+                                            int n2p, int tid, int nt) {
+  using V = cplx<T>;
+  constexpr int GB = 4;
+  const int ne = NV * n2p;
+  for (int e0 = 0; e0 < ne; e0 += GB * nt) {
+    V v1[GB], v2[GB];
+#pragma unroll
+    for (int k = 0; k < GB; ++k) {
+      const int e = e0 + k * nt + tid;
+      const int vi = e / n2p, row = e - (e / n2p) * n2p;
+      v1[k] = v2[k] = mk<T>((T)0, (T)0);
+      if (e < ne && row < g.n2 && vi < g.nv) {
+        const int a = row / g.hh, iz = row - a * g.hh;
+        const int mode = vi / g.nr, r = g.r0 + vi % g.nr;
+        const long long off = g.off(mode);
+        const long long cb = ((long long)r * 3 + a) * g.nzw + g.z0;
+        v1[k] = W[(cb + iz) * g.plane + off];
+        v2[k] = W[(cb + (g.nz - 1 - iz)) * g.plane + off];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < GB; ++k) {
+      const int e = e0 + k * nt + tid;
+      if (e >= ne) continue;
+      const int vi = e / n2p, row = e - (e / n2p) * n2p;
+      const int a = row < g.n2 ? row / g.hh : 0;
+      const T flip = g.flip<T>(vi / g.nr, a);
+      const T sa = a == 2 ? (T)-1 : (T)1;
+      Ub[vi * n2p + row] = cscale(cadd(v1[k], cscale(v2[k], sa)), (T)0.5 * flip * sa);
+      Ub[(NV + vi) * n2p + row] = cscale(csub(v1[k], cscale(v2[k], sa)), (T)0.5 * flip * sa);
+    }
+  }
+}
+
+// Store one product entry: e0, e1 are the halves' values of row i in this lane's column
+// (Re of vector v; the partner lane ^ 8 holds its Im).  Unfold the halves, flip, scatter to
+// the row's two mirror layers.  Every lane calls it (the shuffle).
+template <typename T>
+__device__ __forceinline__ void gemv_store(cplx<T> *W, const GemvMode &g, T e0, T e1, int i, int v,
+                                           bool im) {
+  using V = cplx<T>;
+  const T o0 = __shfl_xor(e0, 8, 64), o1 = __shfl_xor(e1, 8, 64);
+  if (im || v >= g.nv || i >= g.n2) return;
+  const V y0 = mk<T>(e0, o0), y1 = mk<T>(e1, o1);
+  const int a = i / g.hh, iz = i - a * g.hh;
+  const T sa = a == 2 ? (T)-1 : (T)1;
+  const int mode = v / g.nr, r = g.r0 + v % g.nr;
+  const long long off = g.off(mode);
+  const T flip = g.flip<T>(mode, a);
+  const long long cb = ((long long)r * 3 + a) * g.nzw + g.z0;
+  W[(cb + iz) * g.plane + off] = cscale(cadd(y0, y1), flip);
+  if (iz < g.h) W[(cb + (g.nz - 1 - iz)) * g.plane + off] = cscale(csub(y0, y1), sa * flip);
+}
+
 // Symmetric block product on the matrix cores (even nz).  One workgroup per (unique mode,
 // chunk of rc <= 2 NCB right-hand sides): the up to 4 mode copies x rc vectors form an
 // n2 x 8 NCB complex block U per half, and Y U is computed as the real product
@@ -884,49 +983,9 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
   const long long u = blk / nchunks;
   const int r0 = (int)(blk - u * nchunks) * rc;
   const int nr = min(rc, nrhs - r0);
-  const int uy = (int)(u / umx), ux = (int)(u % umx);
-  const int mxs[2] = {ux, (nx - ux) % nx};
-  const int mys[2] = {uy, (ny - uy) % ny};
-  const int nmx = (mxs[1] != mxs[0]) ? 2 : 1;
-  const int nmy = (mys[1] != mys[0]) ? 2 : 1;
-  const int nv = nmx * nmy * nr;
+  const GemvMode g = gemv_mode(u, umx, nx, ny, nzw, z0, nz, hh, n2, nr, r0);
   const int n2p = 16 * ntr;
-  const long long plane = (long long)nx * ny;
-  const int h = nz / 2;
-  // gather, flip, fold, S; GB elements per thread are loaded before any is stored
-  constexpr int GB = 4;
-  const int ne = NV * n2p;
-  for (int e0 = 0; e0 < ne; e0 += GB * nt) {
-    V v1[GB], v2[GB];
-#pragma unroll
-    for (int g = 0; g < GB; ++g) {
-      const int e = e0 + g * nt + tid;
-      const int vi = e / n2p, row = e - (e / n2p) * n2p;
-      v1[g] = v2[g] = mk<T>((T)0, (T)0);
-      if (e < ne && row < n2 && vi < nv) {
-        const int a = row / hh, iz = row - a * hh;
-        const int mode = vi / nr, r = r0 + vi % nr;
-        const int fx = mode % nmx, fy = mode / nmx;
-        const long long off = (long long)mys[fy] * nx + mxs[fx];
-        const long long cb = ((long long)r * 3 + a) * nzw + z0;
-        v1[g] = W[(cb + iz) * plane + off];
-        v2[g] = W[(cb + (nz - 1 - iz)) * plane + off];
-      }
-    }
-#pragma unroll
-    for (int g = 0; g < GB; ++g) {
-      const int e = e0 + g * nt + tid;
-      if (e >= ne) continue;
-      const int vi = e / n2p, row = e - (e / n2p) * n2p;
-      const int a = row < n2 ? row / hh : 0;
-      const int mode = vi / nr;
-      const int fx = mode % nmx, fy = mode / nmx;
-      const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
-      const T sa = a == 2 ? (T)-1 : (T)1;
-      Ub[vi * n2p + row] = cscale(cadd(v1[g], cscale(v2[g], sa)), (T)0.5 * flip * sa);
-      Ub[(NV + vi) * n2p + row] = cscale(csub(v1[g], cscale(v2[g], sa)), (T)0.5 * flip * sa);
-    }
-  }
+  gemv_gather<T, NV>(Ub, W, g, n2p, tid, nt);
   __syncthreads();
   const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
   const int r = lane & 15, q = lane >> 4;  // A: row r, k-slot q; B and D: column r
@@ -981,23 +1040,8 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const T e0 = c[0][cb][m], e1 = c[1][cb][m];
-      const T o0 = __shfl_xor(e0, 8, 64), o1 = __shfl_xor(e1, 8, 64);
-      const int i = 16 * I + Mfma<T>::row(q, m);
-      const int v = 8 * cb + vj;
-      if (im || v >= nv || i >= n2) continue;
-      const V y0 = mk<T>(e0, o0), y1 = mk<T>(e1, o1);
-      const int a = i / hh, iz = i - a * hh;
-      const T sa = a == 2 ? (T)-1 : (T)1;
-      const int mode = v / nr, rr = r0 + v % nr;
-      const int fx = mode % nmx, fy = mode / nmx;
-      const long long off = (long long)mys[fy] * nx + mxs[fx];
-      const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
-      const long long cb = ((long long)rr * 3 + a) * nzw + z0;
-      W[(cb + iz) * plane + off] = cscale(cadd(y0, y1), flip);
-      if (iz < h) W[(cb + (nz - 1 - iz)) * plane + off] = cscale(csub(y0, y1), sa * flip);
-    }
+      for (int m = 0; m < 4; ++m)
+        gemv_store<T>(W, g, c[0][cb][m], c[1][cb][m], 16 * I + Mfma<T>::row(q, m), 8 * cb + vj, im);
   }
 }
 
@@ -1026,49 +1070,9 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_own(cplx<T> *W, const cp
   const long long u = blk / nchunks;
   const int r0 = (int)(blk - u * nchunks) * rc;
   const int nr = min(rc, nrhs - r0);
-  const int uy = (int)(u / umx), ux = (int)(u % umx);
-  const int mxs[2] = {ux, (nx - ux) % nx};
-  const int mys[2] = {uy, (ny - uy) % ny};
-  const int nmx = (mxs[1] != mxs[0]) ? 2 : 1;
-  const int nmy = (mys[1] != mys[0]) ? 2 : 1;
-  const int nv = nmx * nmy * nr;
+  const GemvMode g = gemv_mode(u, umx, nx, ny, nzw, z0, nz, hh, n2, nr, r0);
   const int n2p = 16 * ntr;
-  const long long plane = (long long)nx * ny;
-  const int h = nz / 2;
-  // gather, flip, fold, S; GB elements per thread are loaded before any is stored
-  constexpr int GB = 4;
-  const int ne = NV * n2p;
-  for (int e0 = 0; e0 < ne; e0 += GB * nt) {
-    V v1[GB], v2[GB];
-#pragma unroll
-    for (int g = 0; g < GB; ++g) {
-      const int e = e0 + g * nt + tid;
-      const int vi = e / n2p, row = e - (e / n2p) * n2p;
-      v1[g] = v2[g] = mk<T>((T)0, (T)0);
-      if (e < ne && row < n2 && vi < nv) {
-        const int a = row / hh, iz = row - a * hh;
-        const int mode = vi / nr, r = r0 + vi % nr;
-        const int fx = mode % nmx, fy = mode / nmx;
-        const long long off = (long long)mys[fy] * nx + mxs[fx];
-        const long long cb = ((long long)r * 3 + a) * nzw + z0;
-        v1[g] = W[(cb + iz) * plane + off];
-        v2[g] = W[(cb + (nz - 1 - iz)) * plane + off];
-      }
-    }
-#pragma unroll
-    for (int g = 0; g < GB; ++g) {
-      const int e = e0 + g * nt + tid;
-      if (e >= ne) continue;
-      const int vi = e / n2p, row = e - (e / n2p) * n2p;
-      const int a = row < n2 ? row / hh : 0;
-      const int mode = vi / nr;
-      const int fx = mode % nmx, fy = mode / nmx;
-      const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
-      const T sa = a == 2 ? (T)-1 : (T)1;
-      Ub[vi * n2p + row] = cscale(cadd(v1[g], cscale(v2[g], sa)), (T)0.5 * flip * sa);
-      Ub[(NV + vi) * n2p + row] = cscale(csub(v1[g], cscale(v2[g], sa)), (T)0.5 * flip * sa);
-    }
-  }
+  gemv_gather<T, NV>(Ub, W, g, n2p, tid, nt);
   T *Yp = reinterpret_cast<T *>(Ub + 2 * NV * n2p);  // [n2p][16] partner sums of one half
   for (int e = tid; e < 16 * n2p; e += nt) Yp[e] = (T)0;
   __syncthreads();
@@ -1146,23 +1150,8 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_own(cplx<T> *W, const cp
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const T e0 = c[0][cb][m], e1 = c[1][cb][m];
-    const T o0 = __shfl_xor(e0, 8, 64), o1 = __shfl_xor(e1, 8, 64);
-    const int i = 16 * I + Mfma<T>::row(q, m);
-    const int v = 8 * cb + vj;
-    if (im || v >= nv || i >= n2) continue;
-    const V y0 = mk<T>(e0, o0), y1 = mk<T>(e1, o1);
-    const int a = i / hh, iz = i - a * hh;
-    const T sa = a == 2 ? (T)-1 : (T)1;
-    const int mode = v / nr, rr = r0 + v % nr;
-    const int fx = mode % nmx, fy = mode / nmx;
-    const long long off = (long long)mys[fy] * nx + mxs[fx];
-    const T flip = ((fx && a == 0) || (fy && a == 1)) ? (T)-1 : (T)1;
-    const long long cb = ((long long)rr * 3 + a) * nzw + z0;
-    W[(cb + iz) * plane + off] = cscale(cadd(y0, y1), flip);
-    if (iz < h) W[(cb + (nz - 1 - iz)) * plane + off] = cscale(csub(y0, y1), sa * flip);
-  }
+    for (int m = 0; m < 4; ++m)
+      gemv_store<T>(W, g, c[0][cb][m], c[1][cb][m], 16 * I + Mfma<T>::row(q, m), 8 * cb + vj, im);
 }
 
 // DDA_GEMV_SINGLE_READ=1 (read at every application) selects the single-read block product
