@@ -21,6 +21,6 @@ adjoint    dC_ext/d eps by one adjoint solve (complex-symmetric matrix).
 rows       sampled rows of the operator / preconditioner by direct summation,
            for grids too large for anything else.
 
-Readings where the paper is silent or garbled are listed in the design doc; each
-function's docstring names the passage it follows.
+Each function's docstring names the passage it follows and, where the paper is
+silent or garbled, the reading it takes.
 """
