@@ -209,23 +209,32 @@ template <typename T> struct EptOf { static constexpr int value = kEpt; };
 __host__ __device__ __forceinline__ int tpc_of(int n) { return (n + kEpt - 1) / kEpt; }
 
 // ---------------------------------------------------------------------------- static plans
-// Power-of-two lengths with the radix plan fixed at compile time (8s, then a 4 or a 2): the
-// spans, strides and twiddle steps become constants.
+// 7-smooth lengths with the radix plan fixed at compile time (8s, then a 4 or a 2, then 3s,
+// 5s and 7s): the spans, strides and twiddle steps become constants.
 
-__host__ __device__ constexpr int p2_nrad(int n) {
+__host__ __device__ constexpr int st_nrad(int n) {
   int k = 0, m = n;
   while (m % 8 == 0) { m /= 8; ++k; }
   if (m % 4 == 0) { m /= 4; ++k; }
   if (m % 2 == 0) { m /= 2; ++k; }
+  while (m % 3 == 0) { m /= 3; ++k; }
+  while (m % 5 == 0) { m /= 5; ++k; }
+  while (m % 7 == 0) { m /= 7; ++k; }
   return k;
 }
-__host__ __device__ constexpr int p2_rad(int n, int p) {
+__host__ __device__ constexpr int st_rad(int n, int p) {
   int m = n, k = 0;
   while (m % 8 == 0) { if (k == p) return 8; m /= 8; ++k; }
   if (m % 4 == 0) { if (k == p) return 4; m /= 4; ++k; }
   if (m % 2 == 0) { if (k == p) return 2; m /= 2; ++k; }
+  while (m % 3 == 0) { if (k == p) return 3; m /= 3; ++k; }
+  while (m % 5 == 0) { if (k == p) return 5; m /= 5; ++k; }
+  while (m % 7 == 0) { if (k == p) return 7; m /= 7; ++k; }
   return 1;
 }
+static_assert(st_nrad(192) == 3 && st_rad(192, 0) == 8 && st_rad(192, 1) == 8 && st_rad(192, 2) == 3);
+static_assert(st_nrad(80) == 3 && st_rad(80, 1) == 2 && st_rad(80, 2) == 5);
+static_assert(st_nrad(112) == 3 && st_rad(112, 2) == 7 && st_nrad(256) == 3 && st_rad(256, 2) == 4);
 
 template <int R, typename V, int N, int NS>
 __device__ __forceinline__ void fft_pass_s(V *s, int ld, const Lane &L, const V *__restrict__ tw,
@@ -239,7 +248,7 @@ __device__ __forceinline__ void fft_pass_s(V *s, int ld, const Lane &L, const V 
   for (int q = 0; q < BPT; ++q) {
     const int j = L.jt + q * TPC;
     if (L.active && j < NB) {
-      const int kk = j & (NS - 1);
+      const int kk = j % NS;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = s[lrow(j + r * NB, ld) + L.c];
       if (NS > 1 && kk != 0) {
@@ -258,7 +267,7 @@ __device__ __forceinline__ void fft_pass_s(V *s, int ld, const Lane &L, const V 
   for (int q = 0; q < BPT; ++q) {
     const int j = L.jt + q * TPC;
     if (L.active && j < NB) {
-      const int base = (j / NS) * (NS * R) + (j & (NS - 1));
+      const int base = (j / NS) * (NS * R) + j % NS;
 #pragma unroll
       for (int r = 0; r < R; ++r) s[lrow(base + r * NS, ld) + L.c] = v[q][r];
     }
@@ -269,8 +278,8 @@ __device__ __forceinline__ void fft_pass_s(V *s, int ld, const Lane &L, const V 
 template <typename V, int N, int P = 0, int NS = 1>
 __device__ __forceinline__ void lds_fft_s(V *s, int ld, const Lane &L, const V *__restrict__ tw,
                                           int sign) {
-  if constexpr (P < p2_nrad(N)) {
-    constexpr int R = p2_rad(N, P);
+  if constexpr (P < st_nrad(N)) {
+    constexpr int R = st_rad(N, P);
     fft_pass_s<R, V, N, NS>(s, ld, L, tw, sign);
     lds_fft_s<V, N, P + 1, NS * R>(s, ld, L, tw, sign);
   }

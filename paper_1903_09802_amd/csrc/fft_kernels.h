@@ -293,8 +293,9 @@ template <typename T> inline const cplx<T> *tw_of(const FftPlan &p);
 template <> inline const double2 *tw_of<double>(const FftPlan &p) { return p.tw64; }
 template <> inline const float2 *tw_of<float>(const FftPlan &p) { return p.tw32; }
 
-// Call f(std::integral_constant<int, NF>) with NF = n for the power-of-two lengths that have
-// a compile-time plan, NF = 0 (runtime plan) otherwise.
+// Call f(std::integral_constant<int, NF>) with NF = n for the lengths that have a
+// compile-time plan (powers of two 16 .. 512 and the mixed lengths 80, 96, 112, 160, 192),
+// NF = 0 (runtime plan) otherwise.
 template <typename F> inline void with_static_n(int n, F &&f) {
   switch (n) {
     case 16: f(std::integral_constant<int, 16>{}); break;
@@ -303,6 +304,11 @@ template <typename F> inline void with_static_n(int n, F &&f) {
     case 128: f(std::integral_constant<int, 128>{}); break;
     case 256: f(std::integral_constant<int, 256>{}); break;
     case 512: f(std::integral_constant<int, 512>{}); break;
+    case 80: f(std::integral_constant<int, 80>{}); break;
+    case 96: f(std::integral_constant<int, 96>{}); break;
+    case 112: f(std::integral_constant<int, 112>{}); break;
+    case 160: f(std::integral_constant<int, 160>{}); break;
+    case 192: f(std::integral_constant<int, 192>{}); break;
     default: f(std::integral_constant<int, 0>{}); break;
   }
 }
