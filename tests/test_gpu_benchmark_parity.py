@@ -1,0 +1,211 @@
+"""End-to-end parity on the benchmark prisms themselves, and the solver variants the benchmark
+workloads run: the GPU's solution is checked through the oracle (true residual by the oracle's FFT
+product or by sampled rows, cross sections by the oracle's formulas), and the 128^3 prism's cross
+sections against the oracle-only golden file ``tests/golden/c2_xsec.txt``.
+
+Tolerances: the GPU solves run to a true relative residual of 1e-10 so that the cross sections
+are compared well inside the 1e-5 target; the cross-section error is about the condition number
+times the residual.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import workloads as w
+from gpu_helpers import make_problem, rand_field, random_waves, rel_err, to_dev
+from oracle import fftmatvec, physics, rows, system, xsec
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN_C2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_xsec.txt")
+
+
+def _read_golden(path):
+    out = []
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            f = line.split()
+            out.append(dict(wave=int(f[0]), iters=int(f[7]), residual=float(f[8]),
+                            cext=float(f[9]), cabs=float(f[10]), csca=float(f[11])))
+    return out
+
+
+def test_c2_prism_end_to_end_vs_oracle():
+    """128^3 benchmark prism, both polarisations, 2-level preconditioner, FP64 to 1e-10: the
+    oracle's FFT product gives the true residual of the GPU's c, the oracle's formulas its cross
+    sections, and the oracle-only golden solve (to 1e-11) the reference values."""
+    cfg = w.config_c2()
+    s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
+    with make_problem(s, precond=2, tol=1e-10, max_rhs=2) as prob:
+        prob.build_preconditioner(0.0)
+        out = prob.solve(dirs, pols)
+    c = out["c"].cpu().numpy()
+    Kh = fftmatvec.kernel_padded_fft(s.shape, s.k, s.d)
+    gold = _read_golden(GOLDEN_C2)
+    for r in range(2):
+        st = out["stats"][r]
+        assert st["converged"] == 1 and st["rel_residual"] <= 1e-10, st
+        S = physics.lattice_S(dirs[r], pols[r])
+        b = system.incident_field(s.mask, s.k, s.d, dirs[r], pols[r])
+        res = np.linalg.norm(b - fftmatvec.fft_matvec(c[r], s.mask, s.eps, s.k, s.d, S, Khat=Kh))
+        res /= np.linalg.norm(b)
+        assert res <= 1e-9, (r, res)
+        assert abs(res - st["rel_residual"]) <= 0.05 * res + 1e-13, (r, res, st["rel_residual"])
+        assert np.all(c[r][:, s.mask == 0] == 0)
+        ce, ca, cs = xsec.cross_sections(c[r], s.mask, s.eps, s.k, s.d, dirs[r], pols[r])
+        assert abs(out["cext"][r] - ce) <= 1e-10 * ce
+        assert abs(out["csca"][r] - cs) <= 1e-10 * cs
+        assert abs(out["cabs"][r] - ca) <= 1e-12 * ce and abs(ca) <= 1e-12 * ce  # lossless ice
+        g = gold[r]
+        assert g["wave"] == r and g["residual"] <= 1e-11
+        for key in ("cext", "csca"):
+            dev = abs(out[key][r] - g[key]) / g[key]
+            assert dev <= 1e-5, (r, key, dev)   # the target
+            assert dev <= 1e-7, (r, key, dev)   # condition number x residual, with margin
+
+
+_C3 = {}
+
+
+def _c3_solutions():
+    """The 256^3 prism (m = 1.31 + 0.001i) solved to 1e-10 with FP32 products inside FP64
+    refinement and in plain FP64 (computed once for the tests below)."""
+    if not _C3:
+        cfg = w.config_c3(0)
+        s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
+        for precision in (1, 0):
+            with make_problem(s, precond=2, tol=1e-10, precision=precision) as prob:
+                prob.build_preconditioner(0.0)
+                out = prob.solve(dirs, pols, return_c=precision == 1)
+            if precision == 1:
+                out["c"] = out["c"][0].cpu().numpy()
+            _C3[precision] = out
+        _C3["cfg"] = cfg
+    return _C3
+
+
+def test_c3_fp32_refined_sampled_residual_rows():
+    """256^3 prism: rows of b - A c for the FP32-refined c, each by direct summation over all
+    2.7 million occupied voxels.  Any entry of the residual is bounded by its 2-norm, which the
+    GPU reports below 1e-10 ||b||."""
+    sol = _c3_solutions()
+    cfg = sol["cfg"]
+    s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
+    out = sol[1]
+    st = out["stats"][0]
+    assert st["converged"] == 1 and st["rel_residual"] <= 1e-10 and st["refinements"] >= 2, st
+    c = out["c"]
+    occ = np.flatnonzero(s.mask.ravel())
+    rng = np.random.default_rng(2561)
+    samples = np.concatenate([occ[[0, len(occ) // 2, -1]], rng.choice(occ, 5, replace=False)])
+    S = physics.lattice_S(dirs[0], pols[0])
+    Ac = rows.operator_rows(samples, c, s.mask, s.eps, s.k, s.d, S)
+    b = system.incident_field(s.mask, s.k, s.d, dirs[0], pols[0])
+    bs = np.stack([[b[a].ravel()[i] for a in range(3)] for i in samples])
+    bnorm = float(np.linalg.norm(b))
+    r = np.abs(bs - Ac)
+    assert r.max() <= 1.5 * st["rel_residual"] * bnorm, (r.max(), bnorm)
+    assert r.max() <= 1e-8, r.max()  # the residual is spread, not concentrated in a few rows
+
+
+def test_c3_fp32_refined_cross_sections_vs_oracle_and_fp64():
+    """256^3 prism: C_ext and C_abs of the FP32-refined c by the oracle's formulas, C_sca through
+    the optical theorem (an identity for the exact solution), and the all-FP64 GPU path."""
+    sol = _c3_solutions()
+    cfg = sol["cfg"]
+    s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
+    o32, o64 = sol[1], sol[0]
+    c = o32["c"]
+    ce = xsec.c_ext(c, s.mask, s.k, s.d, dirs[0], pols[0])
+    ca = xsec.c_abs(c, s.mask, s.eps, s.k, s.d, dirs[0], pols[0])
+    assert abs(o32["cext"][0] - ce) <= 1e-10 * ce
+    assert abs(o32["cabs"][0] - ca) <= 1e-10 * ca and ca > 0
+    assert abs(o32["csca"][0] - (ce - ca)) <= 1e-7 * ce
+    assert o64["stats"][0]["converged"] == 1 and o64["stats"][0]["rel_residual"] <= 1e-10
+    for key in ("cext", "cabs", "csca"):
+        assert abs(o32[key][0] - o64[key][0]) <= 1e-7 * abs(o64[key][0]), key
+
+
+def _dense_solution(s, dvec, pvec):
+    A = system.dense_matrix(s.mask, s.eps, s.k, s.d, physics.lattice_S(dvec, pvec))
+    b = system.incident_field(s.mask, s.k, s.d, dvec, pvec)
+    return system.compact_to_box(np.linalg.solve(A, system.box_to_compact(b, s.mask)), s.mask)
+
+
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_fp32_refinement_right_preconditioned_vs_dense_lu(nrhs):
+    """The default (right-preconditioned) FP32-in-FP64 refinement to 1e-11 reaches dense LU."""
+    s = w.hex_prism_grid(3.0, 1.2, 12, 1.31 + 0.02j)
+    dirs, pols = random_waves(nrhs, 23)
+    dirs, pols = dirs[:nrhs], pols[:nrhs]
+    with make_problem(s, precond=2, tol=1e-11, precision=1, max_rhs=nrhs) as prob:
+        prob.build_preconditioner(0.0)
+        out = prob.solve(dirs, pols)
+    for r in range(nrhs):
+        st = out["stats"][r]
+        assert st["converged"] == 1 and st["rel_residual"] <= 1e-11 and st["refinements"] >= 2, st
+        cref = _dense_solution(s, dirs[r], pols[r])
+        assert rel_err(out["c"][r].cpu().numpy(), cref) < 1e-8
+        ce, ca, cs = xsec.cross_sections(cref, s.mask, s.eps, s.k, s.d, dirs[r], pols[r])
+        assert abs(out["cext"][r] - ce) <= 1e-8 * ce
+        assert abs(out["cabs"][r] - ca) <= 1e-8 * ca
+
+
+def test_lossy_absorption_vs_dense_lu():
+    """Absorbing prism (m = 1.31 + 0.05i): every cross section against the dense-LU solution,
+    C_abs included, in FP64 and FP32-refined modes."""
+    s = w.hex_prism_grid(4.0, 1.0, 14, 1.31 + 0.05j)
+    dirs, pols = random_waves(2, 29)
+    dirs, pols = dirs[:2], pols[:2]
+    refs = []
+    for r in range(2):
+        cref = _dense_solution(s, dirs[r], pols[r])
+        refs.append((xsec.c_ext(cref, s.mask, s.k, s.d, dirs[r], pols[r]),
+                     xsec.c_abs(cref, s.mask, s.eps, s.k, s.d, dirs[r], pols[r]),
+                     xsec.c_sca_imag_dense(cref, s.mask, s.k, s.d)))
+    for precision in (0, 1):
+        with make_problem(s, precond=2, tol=1e-11, precision=precision, max_rhs=2) as prob:
+            prob.build_preconditioner(float(np.mean(np.sum((dirs * pols) ** 2, axis=1))))
+            out = prob.solve(dirs, pols, return_c=False)
+        for r in range(2):
+            ce, ca, cs = refs[r]
+            assert ca > 0.05 * ce
+            assert abs(out["cext"][r] - ce) <= 1e-8 * ce, (precision, r)
+            assert abs(out["cabs"][r] - ca) <= 1e-8 * ca, (precision, r)
+            assert abs(out["csca"][r] - cs) <= 1e-8 * cs, (precision, r)
+
+
+def test_32_rhs_operator_preconditioner_and_solve():
+    """One chunk of the batched workload: 32 right-hand sides with their own directions and LDR
+    factors through the operator (FP64 and FP32), the preconditioner (32 columns per mode block,
+    several column chunks) and a GMRES solve, each against the oracle."""
+    from gpu_helpers import oracle_precond
+    s = w.hex_prism_grid(3.0, 1.5, 10, 1.31)
+    dirs, pols = random_waves(32, 3232)
+    dirs, pols = dirs[:32], pols[:32]
+    S = np.sum((dirs * pols) ** 2, axis=1)
+    x = rand_field(s.shape, 32, 3232)
+    with make_problem(s, precond=2, tol=1e-11, max_rhs=32) as prob:
+        prob.build_preconditioner(float(S.mean()))
+        y64 = prob.apply_operator(to_dev(x), dirs, pols).cpu().numpy()
+        y32 = prob.apply_operator(to_dev(x), dirs, pols, fp32=True).cpu().numpy()
+        z = prob.apply_preconditioner(to_dev(x)).cpu().numpy()
+        out = prob.solve(dirs, pols)
+    pc = oracle_precond(s, float(S.mean()))
+    Kh = fftmatvec.kernel_padded_fft(s.shape, s.k, s.d)
+    c = out["c"].cpu().numpy()
+    for r in range(32):
+        ref = fftmatvec.fft_matvec(x[r], s.mask, s.eps, s.k, s.d, S[r], Khat=Kh)
+        assert rel_err(y64[r], ref) < 1e-10, r
+        assert rel_err(y32[r], ref) < 1e-5, r
+        assert rel_err(z[r], pc(x[r])) < 1e-10, r
+        st = out["stats"][r]
+        assert st["converged"] == 1 and st["rel_residual"] <= 1e-11, (r, st)
+        cref = _dense_solution(s, dirs[r], pols[r])
+        assert rel_err(c[r], cref) < 1e-8, r
+        ce = xsec.c_ext(cref, s.mask, s.k, s.d, dirs[r], pols[r])
+        assert abs(out["cext"][r] - ce) <= 1e-8 * ce, r

@@ -46,6 +46,13 @@ OP_CASES = [
     ((48, 1, 1), 1.0, 24),
     ((36, 4, 5), 0.7, 25),
     ((256, 2, 3), 0.7, 26),
+    # x and y lengths 40, 48, 56, 80, 96: the compile-time mixed-radix plans of the row and
+    # strided passes (padded lengths 80, 96, 112, 160, 192; radices 3, 5, 7)
+    ((3, 40, 56), 0.7, 27),
+    ((2, 80, 48), 0.7, 28),
+    ((2, 96, 40), 0.6, 29),
+    ((2, 5, 96), 0.7, 30),
+    ((3, 4, 80), 0.7, 31),
 ]
 
 
@@ -105,7 +112,9 @@ def test_operator_register_zpass_schedules(shape, force, monkeypatch):
 
 @pytest.mark.parametrize("shape,seed", [((5, 6, 7), 21), ((16, 16, 16), 22), ((12, 20, 9), 23),
                                         ((64, 6, 5), 24), ((128, 4, 3), 25), ((40, 5, 6), 26),
-                                        ((96, 4, 3), 27), ((72, 3, 4), 28), ((256, 3, 2), 29)])
+                                        ((96, 4, 3), 27), ((72, 3, 4), 28), ((256, 3, 2), 29),
+                                        ((3, 40, 56), 30), ((2, 80, 48), 31), ((2, 96, 40), 32),
+                                        ((2, 5, 96), 33), ((3, 4, 80), 34)])
 def test_operator_fp32_vs_oracle(shape, seed):
     nz, ny, nx = shape
     s = w.random_mask(nx, ny, nz, 0.7, seed, k=1.3, d=0.3)
@@ -120,7 +129,9 @@ def test_operator_fp32_vs_oracle(shape, seed):
 PC_CASES = [((4, 5, 6), 31), ((5, 4, 3), 32), ((7, 6, 10), 33), ((1, 3, 4), 34),
             ((16, 16, 16), 35), ((9, 8, 12), 36), ((3, 1, 1), 37), ((2, 7, 5), 38),
             # half-block orders above 256: the 512-thread Gauss-Jordan kernel, even and odd nz
-            ((200, 2, 3), 39), ((175, 2, 2), 40)]
+            ((200, 2, 3), 39), ((175, 2, 2), 40),
+            # unpadded x and y lengths 40 .. 96 of the preconditioner's compile-time plans
+            ((4, 6, 80), 41), ((3, 96, 5), 42), ((2, 40, 56), 43), ((3, 48, 96), 44)]
 
 
 @pytest.mark.parametrize("shape,seed", PC_CASES)
