@@ -238,8 +238,9 @@ def main():
     eps = torch.from_numpy(s.eps).cuda()
     torch.cuda.synchronize()
 
-    def step(profile=False):
-        prob = Problem(mask, eps, s.k, s.d, precond=2, tol=tol, restart=30, max_rhs=nrhs)
+    def step(profile=False, graph=True):
+        prob = Problem(mask, eps, s.k, s.d, precond=2, tol=tol, restart=30, max_rhs=nrhs,
+                       graph=graph)
         if profile:
             prob.profile_enable(True)
         prob.build_preconditioner(0.0)
@@ -289,6 +290,17 @@ def main():
                             GBps=(v["bytes"] / (v["total_ms"] / max(1, v["launches"]) * 1e-3) / 1e9)
                             if v["total_ms"] > 0 else None)
                     for k, v in kernels[:14]}
+
+    # the same step without per-kernel events: restart cycles replayed from HIP graphs, and
+    # launched one by one
+    unprofiled = {}
+    for graph in (True, False):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            step(profile=False, graph=graph)
+        torch.cuda.synchronize()
+        unprofiled["graph" if graph else "eager"] = (time.perf_counter() - t0) / 3
 
     # matvec throughput (FP64, both RHS) and preconditioner apply
     prob = Problem(mask, eps, s.k, s.d, precond=2, tol=tol, restart=30, max_rhs=nrhs)
@@ -362,7 +374,7 @@ def main():
                     size_parameter=s.meta.get("x"), restart=30, tol=tol),
         precond_iters=p_iters, precond_rel_residual=p_res, converged=converged,
         cext=last["cext"].tolist(), cabs=last["cabs"].tolist(), csca=last["csca"].tolist(),
-        plain=plain, bicgstab=bicg, matvec_ms=1000 * t_mv, matvec_GBps=matvec_gbps,
+        step_s_unprofiled=unprofiled, plain=plain, bicgstab=bicg, matvec_ms=1000 * t_mv, matvec_GBps=matvec_gbps,
         matvec_frac_hbm=matvec_gbps / HBM_PEAK_GBPS, precond_apply_ms=1000 * t_pc,
         roofline=roofline, kernels=kernel_table, cpu_baseline=cpu,
     )
@@ -420,7 +432,7 @@ def bench_c4(args):
     import torch
 
     import workloads as w
-    from paper_1903_09802_amd.dda import Problem
+    from paper_1903_09802_amd.dda import Problem, lattice_factor
 
     cfg = w.config_c4(n_prisms=args.c4_prisms)
     lat, solved, iters = [], 0, []
@@ -431,11 +443,10 @@ def bench_c4(args):
         t0 = time.perf_counter()
         mask = torch.from_numpy(s.mask).cuda()
         eps = torch.from_numpy(s.eps).cuda()
-        S = np.sum((dirs * pols) ** 2, axis=1)
         chunk = args.c4_chunk
         prob = Problem(mask, eps, s.k, s.d, precond=2, tol=cfg["tol"], restart=30,
                        precision=args.c4_precision, max_rhs=chunk)
-        prob.build_preconditioner(float(S.mean()))
+        prob.build_preconditioner(lattice_factor(dirs, pols)[1])
         for q0 in range(0, len(dirs), chunk):
             out = prob.solve(dirs[q0:q0 + chunk], pols[q0:q0 + chunk], return_c=False)
             solved += sum(st["converged"] for st in out["stats"])

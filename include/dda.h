@@ -75,8 +75,6 @@ typedef struct {
                           space with the FP32 operator and preconditioner on an FP64 basis
                           (FP64 Arnoldi), and every restart recomputes b - A x with the FP64
                           operator, so each cycle is one refinement step.  default 0 */
-  double inner_tol; /* reserved (kept for layout stability); must lie in (0, 1); default 1e-4 */
-  int max_refine;   /* reserved (kept for layout stability); must be >= 1; default 30 */
   int max_rhs;      /* largest nrhs accepted by dda_solve / dda_apply_*; sizes the workspace; default 1 */
   int solver;       /* 0: restarted GMRES(restart); 1: BiCGStab (Sec. 4's second solver), right-
                        preconditioned, restarted from the true residual when the updated one
@@ -114,6 +112,13 @@ typedef struct {
                        Q Delta is a contraction (moderate permittivity contrast); 0 is the
                        circulant preconditioner itself.  Needs a preconditioner (precond 1 or
                        2).  default 0 */
+  int graph;        /* GMRES only.  Every step decides on the device whether each right-hand
+                       side continues (its residual estimate against tol, breakdown, the step
+                       cap, the end of the cycle), so a restart cycle needs the host once, at
+                       its end.  1: each cycle is captured once into a HIP graph (per
+                       right-hand-side count and precision) and replayed; 0: the same kernels
+                       are launched one by one.  With per-kernel profiling on
+                       (dda_profile_enable) cycles are always launched one by one.  default 1 */
 } dda_options;
 
 typedef struct {
@@ -123,11 +128,30 @@ typedef struct {
   int refinements;     /* FP64 refinement steps = restart cycles (precision 1), else 0 */
   int converged;       /* 1 if rel_residual <= tol */
   double rel_residual; /* final true residual ||b - A x|| / ||b||, FP64 */
-  double seconds;      /* wall-clock time of the call */
+  double t_setup;      /* seconds spent in dda_create for this handle (operator set-up) */
+  double t_build;      /* seconds of the handle's last dda_build_preconditioner, 0 if none */
+  double t_solve;      /* wall-clock seconds of this call */
+  double *history;     /* in: NULL, or a caller-owned host array of history_cap doubles that
+                          receives the residual after each iteration, relative to the norm the
+                          stopping test uses (Sec. 4 plots these): the GMRES least-squares
+                          estimate of ||b - A x|| / ||b|| (of ||P^{-1}(b - A x)|| / ||P^{-1} b||
+                          when left preconditioned), or BiCGStab's updated residual */
+  int history_cap;     /* in: capacity of history (at most 65536 GMRES steps are kept) */
+  int history_len;     /* out: entries written, min(iters, history_cap) */
 } dda_stats;
 
 /* Fill *opt with the defaults listed above. */
 void dda_default_options(dda_options *opt);
+
+/*
+ * The lattice factor S = sum_j (dir_j pol_j)^2 of each incident wave (Sec. 2.1, the LDR
+ * polarisability's dependence on the direction and polarisation), and their mean: the s_bar to
+ * build one preconditioner for a batch of waves with (its constant diagonal is the LDR value
+ * at s_bar).  dir_host, pol_host: double [nrhs][3], checked as in dda_solve.  S_host: optional
+ * host double [nrhs]; S_mean: optional host double.  Errors: EINVAL (nrhs < 1, bad vectors).
+ */
+dda_status dda_lattice_factor(int nrhs, const double *dir_host, const double *pol_host,
+                              double *S_host, double *S_mean);
 
 /* Reason for the last failure on this thread ("" if none).  Static storage. */
 const char *dda_last_error(void);
@@ -188,7 +212,9 @@ dda_status dda_build_preconditioner(dda_problem *p, double s_bar);
  *    C_abs = 4 pi k d^3 sum |c|^2 (-Im alpha^{-1} - (2/3)(k d)^3),
  *    C_sca = 4 pi k d^3 [(2/3)(k d)^3 sum |c|^2 + sum_{i!=j} c_i^H d^3 Im G(r_i - r_j) c_j]
  *    (Draine-Flatau forms for this scaling; |E_0| = 1; area in length units^2).
- *  stats: optional host dda_stats [nrhs].
+ *  stats: optional host dda_stats [nrhs]; history / history_cap are read, the rest written.
+ * The solve allocates no device memory: every buffer it uses was allocated by dda_create or
+ * dda_build_preconditioner.
  * Returns OK when every right-hand side reached tol, NOT_CONVERGED (outputs
  * valid) when some hit max_iter.  Errors: EINVAL (nrhs < 1 or
  * > max_rhs, bad vectors), ESTATE (opt.precond == 2 and no preconditioner
@@ -216,9 +242,6 @@ dda_status dda_apply_operator(dda_problem *p, int nrhs, const double *dir_host,
  * approximation described at dda_options.  x_dev, y_dev: c128
  * [nrhs][3][nz][ny][nx] (may alias).  fp32 selects the FP32 blocks and must
  * match the precision the preconditioner was built in (else ESTATE).
- * The environment variable DDA_GEMV_SINGLE_READ=1, read at every call, selects
- * a 2-level block product that reads each stored tile once (one column block,
- * dense extent up to 128 layers); same result, fewer HBM bytes, slower here.
  */
 dda_status dda_apply_preconditioner(dda_problem *p, int nrhs, const double *x_dev,
                                     double *y_dev, int fp32);
@@ -238,7 +261,9 @@ dda_status dda_cross_sections(dda_problem *p, int nrhs, const double *dir_host,
  * matrix is complex symmetric, Sec. 2.2, so the adjoint system is A lambda =
  * conj(E^inc)).  grad_dev: c128 [nz][ny][nx] receiving dC/dRe(eps) +
  * i dC/dIm(eps) at occupied voxels and 0 in air.  cext: optional host double.
- * stats: optional host dda_stats [2] (forward, adjoint).
+ * stats: optional host dda_stats [2] (forward, adjoint).  Both solves use the handle's
+ * buffers (the forward solution is kept in one allocated by dda_create): no allocation.
+ * Errors: EINVAL, ESTATE (opt.precond != 0 and no preconditioner built), EDEVICE.
  */
 dda_status dda_grad_cext(dda_problem *p, const double *dir_host, const double *pol_host,
                          double *grad_dev, double *cext, dda_stats *stats);

@@ -13,7 +13,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .dda import Problem
+from .dda import Problem, lattice_factor
 
 
 class DDAExtinction(torch.autograd.Function):
@@ -24,8 +24,9 @@ class DDAExtinction(torch.autograd.Function):
         with Problem(mask, eps.detach(), k, d, **opts) as prob:
             dvec = np.asarray(direction, dtype=np.float64)
             pvec = np.asarray(polarisation, dtype=np.float64)
-            if precond == 2:
-                prob.build_preconditioner(float(np.sum((dvec * pvec) ** 2)))
+            if precond != 0:
+                # the preconditioner's diagonal at the wave's own lattice factor
+                prob.build_preconditioner(lattice_factor(dvec, pvec)[1])
             if ctx.needs_input_grad[0]:
                 g, cext, stats, _ = prob.grad_cext(dvec, pvec)
                 ctx.save_for_backward(g)

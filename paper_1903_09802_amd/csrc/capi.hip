@@ -35,10 +35,12 @@ void free_all(dda_problem *p) {
   F(p->ainv); F(p->Sdev); F(p->V); F(p->work); F(p->work2); F(p->bvec); F(p->xvec); F(p->vsc);
   F(p->H); F(p->givens); F(p->gvec); F(p->hcol); F(p->hcol2);
   F(p->ycoef); F(p->hnrm); F(p->hraw); F(p->lmat); F(p->partial); F(p->dscal); F(p->dflag);
+  F(p->ctl); F(p->ones); F(p->bnrm); F(p->cres); F(p->hist); F(p->adj);
   if (p->hpin) (void)hipHostFree(p->hpin);
-  if (p->est_ev) (void)hipEventDestroy(p->est_ev);
   p->hpin = nullptr;
-  p->est_ev = nullptr;
+  drop_graphs(p);
+  if (p->cap_st) (void)hipStreamDestroy(p->cap_st);
+  p->cap_st = nullptr;
   precond_free(p);
   plan_destroy(p->px); plan_destroy(p->py); plan_destroy(p->pz);
   plan_destroy(p->ux); plan_destroy(p->uy);
@@ -46,6 +48,7 @@ void free_all(dda_problem *p) {
 }
 
 void check_waves(int nrhs, const double *dir, const double *pol, std::vector<double> &S) {
+  REQUIRE(nrhs >= 1, DDA_EINVAL, "nrhs must be >= 1");
   REQUIRE(dir && pol, DDA_EINVAL, "dir_host and pol_host are required");
   S.resize(nrhs);
   for (int r = 0; r < nrhs; ++r) {
@@ -59,6 +62,24 @@ void check_waves(int nrhs, const double *dir, const double *pol, std::vector<dou
     for (int a = 0; a < 3; ++a) s += (d[a] * e[a]) * (d[a] * e[a]);
     S[r] = s;
   }
+}
+
+// A solve's stats record: counters zero, the caller's history buffer (input fields) kept.
+dda_stats stats_in(const dda_stats *caller) {
+  dda_stats s;
+  std::memset(&s, 0, sizeof s);
+  if (caller) {
+    s.history = caller->history;
+    s.history_cap = caller->history ? std::max(0, caller->history_cap) : 0;
+  }
+  return s;
+}
+
+dda_stats stats_out(const dda_problem *p, dda_stats s, double seconds) {
+  s.t_setup = p->t_setup;
+  s.t_build = p->prec_built ? p->t_build : 0.0;
+  s.t_solve = seconds;
+  return s;
 }
 
 // Wave vectors (3 per wave) in the library's rotated frame.
@@ -80,22 +101,37 @@ void dda_default_options(dda_options *opt) {
   opt->tol = 1e-5;
   opt->precond = 2;
   opt->precision = 0;
-  opt->inner_tol = 1e-4;
-  opt->max_refine = 30;
   opt->max_rhs = 1;
   opt->solver = 0;
   opt->dense_axis = 2;
   opt->left_precond = 0;
   opt->alpha_avg = 0;
   opt->diag_steps = 0;
+  opt->graph = 1;
 }
 
 const char *dda_last_error(void) { return get_error(); }
+
+dda_status dda_lattice_factor(int nrhs, const double *dir_host, const double *pol_host,
+                              double *S_host, double *S_mean) {
+  return guarded([&]() -> dda_status {
+    std::vector<double> S;
+    check_waves(nrhs, dir_host, pol_host, S);
+    double sum = 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+      if (S_host) S_host[r] = S[r];
+      sum += S[r];
+    }
+    if (S_mean) *S_mean = sum / nrhs;
+    return DDA_OK;
+  });
+}
 
 dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const double *eps_dev,
                       double k, double d, const dda_options *opt, void *stream,
                       dda_problem **out) {
   return guarded([&]() -> dda_status {
+    const auto t0 = std::chrono::steady_clock::now();
     REQUIRE(out, DDA_EINVAL, "out is NULL");
     *out = nullptr;
     REQUIRE(nx >= 1 && ny >= 1 && nz >= 1, DDA_EINVAL, "grid dimensions must be >= 1 (got %d %d %d)",
@@ -114,8 +150,7 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
     REQUIRE(o.precond >= 0 && o.precond <= 2, DDA_EINVAL, "precond must be 0, 1 or 2");
     REQUIRE(o.precision == 0 || o.precision == 1, DDA_EINVAL, "precision must be 0 or 1");
     REQUIRE(o.max_rhs >= 1 && o.max_rhs <= 64, DDA_EINVAL, "max_rhs must be in [1, 64]");
-    REQUIRE(o.inner_tol > 0.0 && o.inner_tol < 1.0, DDA_EINVAL, "inner_tol must be in (0, 1)");
-    REQUIRE(o.max_refine >= 1, DDA_EINVAL, "max_refine must be >= 1");
+    REQUIRE(o.graph == 0 || o.graph == 1, DDA_EINVAL, "graph must be 0 or 1");
     REQUIRE(o.solver == 0 || o.solver == 1, DDA_EINVAL, "solver must be 0 (GMRES) or 1 (BiCGStab)");
     REQUIRE(o.solver == 0 || o.precision == 0, DDA_EUNSUPPORTED, "BiCGStab runs in FP64 only (precision 0)");
     REQUIRE(o.solver == 0 || o.restart >= 7, DDA_EINVAL, "BiCGStab needs restart >= 7 (work vectors)");
@@ -150,6 +185,7 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
       p->R = o.max_rhs;
       int dev = 0;
       HIPCHK(hipGetDevice(&dev));
+      p->dev = dev;
       hipDeviceProp_t prop;
       HIPCHK(hipGetDeviceProperties(&prop, dev));
       p->lds_max = prop.sharedMemPerBlock > 0 ? (size_t)prop.sharedMemPerBlock : 65536;
@@ -157,10 +193,10 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
       const long long N = p->N, n3 = 3 * N, R = p->R, m = o.restart;
       double need = 0;
       need += N * 17.0;                                  // mask + eps
-      need += 6.0 * (nx + 1) * (ny + 1) * (nz + 1) * 24;  // khat64 + khat32
+      need += 6.0 * (nx + 1) * (ny + 1) * (nz + 1) * 40;  // khat64 + khat32 + khatI64
       need += 8.0 * N * 6 * 16;                          // setup transient
       need += R * 3.0 * N * 2 * 16 + R * 3.0 * nz * (4.0 * nx * ny + 64) * 16;  // w0 + w1
-      need += R * (m + 1.0) * n3 * 16 + R * 5.0 * n3 * 16 + R * 16.0 * N;
+      need += R * (m + 1.0) * n3 * 16 + R * 5.0 * n3 * 16 + R * 16.0 * N + n3 * 16.0;
       need += R * 2.0 * kMaxM * 1024 * 16 + R * (m + 1.0) * (m + 1.0) * 16;  // reductions, Gram
       size_t freeb = 0, totb = 0;
       HIPCHK(hipMemGetInfo(&freeb, &totb));
@@ -192,6 +228,7 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
       delete p;
       throw;
     }
+    p->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = p;
     return DDA_OK;
   });
@@ -201,8 +238,12 @@ dda_status dda_build_preconditioner(dda_problem *p, double s_bar) {
   return guarded([&]() -> dda_status {
     REQUIRE(p, DDA_EINVAL, "problem is NULL");
     REQUIRE(s_bar >= 0.0 && s_bar <= 1.0, DDA_EINVAL, "s_bar must be in [0, 1]");
+    const auto t0 = std::chrono::steady_clock::now();
+    drop_graphs(p);  // captured cycles read the blocks that the build replaces
+    p->t_build = 0.0;
     precond_build(p, s_bar);
     if (p->prof.on) p->prof.collect();
+    p->t_build = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return DDA_OK;
   });
 }
@@ -228,7 +269,9 @@ dda_status dda_solve(dda_problem *p, int nrhs, const double *dir_host, const dou
       to_compact(p, nrhs, reinterpret_cast<const double2 *>(x0_dev), p->xvec);
     else
       HIPCHK(hipMemsetAsync(p->xvec, 0, sizeof(double2) * n3 * nrhs, p->st));
-    std::vector<dda_stats> st(nrhs);
+    std::vector<dda_stats> st(nrhs, stats_in(nullptr));
+    if (stats)
+      for (int r = 0; r < nrhs; ++r) st[r] = stats_in(&stats[r]);
     dda_status res = solve_system(p, nrhs, p->bvec, p->xvec, st.data());
     if (c_dev) to_box(p, nrhs, p->xvec, nullptr, reinterpret_cast<double2 *>(c_dev));
     if (cext || cabs || csca) cross_sections(p, nrhs, dir_host, pol_host, p->xvec, cext, cabs, csca);
@@ -236,10 +279,7 @@ dda_status dda_solve(dda_problem *p, int nrhs, const double *dir_host, const dou
     if (p->prof.on) p->prof.collect();
     const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats)
-      for (int r = 0; r < nrhs; ++r) {
-        stats[r] = st[r];
-        stats[r].seconds = sec;
-      }
+      for (int r = 0; r < nrhs; ++r) stats[r] = stats_out(p, st[r], sec);
     return res;
   });
 }
@@ -313,36 +353,27 @@ dda_status dda_grad_cext(dda_problem *p, const double *dir_host, const double *p
     dir_host = dirs.data();
     pol_host = pols.data();
     const long long n3 = 3 * p->nocc;
-    double2 *cfwd = nullptr;
-    HIPCHK(hipMalloc(&cfwd, sizeof(double2) * n3));
-    dda_status res = DDA_OK;
-    dda_stats st[2];
-    try {
-      setup_alpha(p, 1, S.data());
-      // forward: A c = E_inc
-      setup_rhs(p, 1, dir_host, pol_host, p->bvec, 0);
-      HIPCHK(hipMemsetAsync(p->xvec, 0, sizeof(double2) * n3, p->st));
-      dda_status r1 = solve_system(p, 1, p->bvec, p->xvec, &st[0]);
-      HIPCHK(hipMemcpyAsync(cfwd, p->xvec, sizeof(double2) * n3, hipMemcpyDeviceToDevice, p->st));
-      if (cext) cross_sections(p, 1, dir_host, pol_host, cfwd, cext, nullptr, nullptr);
-      // adjoint: A lambda = conj(E_inc)
-      setup_rhs(p, 1, dir_host, pol_host, p->bvec, 1);
-      HIPCHK(hipMemsetAsync(p->xvec, 0, sizeof(double2) * n3, p->st));
-      dda_status r2 = solve_system(p, 1, p->bvec, p->xvec, &st[1]);
-      grad_kernel(p, cfwd, p->xvec, S[0], reinterpret_cast<double2 *>(grad_dev));
-      HIPCHK(hipStreamSynchronize(p->st));
-      res = (r1 == DDA_OK && r2 == DDA_OK) ? DDA_OK : DDA_NOT_CONVERGED;
-    } catch (...) {
-      (void)hipFree(cfwd);
-      throw;
-    }
-    HIPCHK(hipFree(cfwd));
+    double2 *cfwd = p->adj;
+    dda_stats st[2] = {stats_in(stats), stats_in(stats ? stats + 1 : nullptr)};
+    setup_alpha(p, 1, S.data());
+    // forward: A c = E_inc
+    setup_rhs(p, 1, dir_host, pol_host, p->bvec, 0);
+    HIPCHK(hipMemsetAsync(p->xvec, 0, sizeof(double2) * n3, p->st));
+    dda_status r1 = solve_system(p, 1, p->bvec, p->xvec, &st[0]);
+    HIPCHK(hipMemcpyAsync(cfwd, p->xvec, sizeof(double2) * n3, hipMemcpyDeviceToDevice, p->st));
+    if (cext) cross_sections(p, 1, dir_host, pol_host, cfwd, cext, nullptr, nullptr);
+    // adjoint: A lambda = conj(E_inc)
+    setup_rhs(p, 1, dir_host, pol_host, p->bvec, 1);
+    HIPCHK(hipMemsetAsync(p->xvec, 0, sizeof(double2) * n3, p->st));
+    dda_status r2 = solve_system(p, 1, p->bvec, p->xvec, &st[1]);
+    grad_kernel(p, cfwd, p->xvec, S[0], reinterpret_cast<double2 *>(grad_dev));
+    HIPCHK(hipStreamSynchronize(p->st));
+    const dda_status res = (r1 == DDA_OK && r2 == DDA_OK) ? DDA_OK : DDA_NOT_CONVERGED;
     if (p->prof.on) p->prof.collect();
     const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) {
-      stats[0] = st[0];
-      stats[1] = st[1];
-      stats[0].seconds = stats[1].seconds = sec;
+      stats[0] = stats_out(p, st[0], sec);
+      stats[1] = stats_out(p, st[1], sec);
     }
     return res;
   });

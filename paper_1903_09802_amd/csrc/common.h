@@ -258,6 +258,7 @@ struct dda_problem {
   hipStream_t st = nullptr;
   dda_options opt{};
   int R = 1;             // max right-hand sides
+  int dev = 0;           // the HIP device the handle lives on
   size_t lds_max = 65536;      // device LDS per workgroup
   size_t lds_zpass = 98304;    // LDS budget of the fused z pass
   int ztw[2] = {0, 0};         // z-pass columns per tile (FP64, FP32), chosen by autotune
@@ -328,9 +329,30 @@ struct dda_problem {
   size_t partial_elems = 0;
   double *dscal = nullptr;   // [R][16] device scalars
   double *vsc = nullptr;     // [R][kMaxM] 1 / norm of each (unnormalised) basis vector
-  double *hpin = nullptr;    // pinned host mirror [R][16] of the per-iteration estimates
-  hipEvent_t est_ev = nullptr;  // recorded after the estimates' copy to hpin
+  double *hpin = nullptr;    // pinned host buffer [R][16]: a restart cycle's results
   int *dflag = nullptr;      // device error flags [4]
+  int *ctl = nullptr;        // device control of a GMRES cycle [1 + 4R] (krylov.hip)
+  int *ones = nullptr;       // [R] ones: "every right-hand side" for the reductions
+  double *bnrm = nullptr;    // [R] the norm each right-hand side's stopping test is relative to
+  double *cres = nullptr;    // [3R] a cycle's results (squared residual norms, steps)
+  double *hist = nullptr;    // [R][hist_cap] residual estimate after every GMRES step
+  int hist_cap = 0;
+  double2 *adj = nullptr;    // [3 nocc] forward solution kept across dda_grad_cext's two solves
+  const int *live = nullptr; // inside a GMRES cycle: the device flag that turns the cycle's
+                             // operator and preconditioner launches into no-ops once every
+                             // right-hand side has stopped; null elsewhere
+  hipStream_t cap_st = nullptr;  // private stream on which restart cycles are captured
+  struct CycleGraph {
+    int nrhs, fp32;
+    double tol;
+    int maxit;
+    const double2 *b;
+    double2 *x;
+    hipGraphExec_t exec;
+  };
+  std::vector<CycleGraph> graphs;  // captured restart cycles (invalid once the preconditioner
+                                   // is rebuilt)
+  double t_setup = 0.0, t_build = 0.0;  // seconds in dda_create / the last build
 
   dda::Profiler prof;
 };
@@ -375,8 +397,8 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
                  int maxit, dda_stats *st);
 // Full solve including refinement mode.
 dda_status solve_system(dda_problem *p, int nrhs, const double2 *b, double2 *x, dda_stats *st);
-void residual(dda_problem *p, int nrhs, const double2 *b, const double2 *x, double2 *r,
-              double *rel_host);
+// Destroy the captured restart cycles (their launches hold the preconditioner's buffers).
+void drop_graphs(dda_problem *p);
 
 // xsec.hip
 void cross_sections(dda_problem *p, int nrhs, const double *dir, const double *pol,

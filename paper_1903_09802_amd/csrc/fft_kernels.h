@@ -40,6 +40,8 @@ struct RowArgs {
   const double2 *xin;  // FP64 field rows for ROW_OP_INV
   const double *xscale;// per-RHS input scale xscale[r * kMaxM], or null
   double scale;        // output scale of the transform
+  const int *live;     // null, or a device flag: 0 makes the launch a no-op (a solver cycle
+                       // whose right-hand sides have all stopped)
 };
 
 constexpr int kRowEpt = 8;  // elements per thread of a row tile: tw n <= 8 (tw tpc) threads
@@ -49,6 +51,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
                                                           const cplx<T> *__restrict__ tw,
                                                           RowArgs a) {
   using V = cplx<T>;
+  if (a.live && a.live[0] == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *s = reinterpret_cast<V *>(smem_raw);
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -141,6 +144,7 @@ struct StrArgs {
   int n_in, n_out;
   long long in_bstride, out_bstride;  // elements between batches
   int sign;
+  const int *live;        // as RowArgs::live
 };
 
 template <typename T, int NF>
@@ -149,6 +153,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(const cplx<T> *in, 
                                                              StrArgs a) {
   using V = cplx<T>;
   constexpr int EPT = EptOf<T>::value;  // rows per thread: n <= EPT tpc
+  if (a.live && a.live[0] == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *s = reinterpret_cast<V *>(smem_raw);
   const int n = a.pl.n;
@@ -207,12 +212,14 @@ struct ZArgs {
   int tw, twsh;     // columns per tile and log2(tw)
   long long ntiles;
   long long nrhs;
+  const int *live;  // as RowArgs::live
 };
 
 template <typename T, int EPT, int NF>
 __global__ void __launch_bounds__(768) k_zpass(cplx<T> *data, const cplx<T> *__restrict__ tw,
                                                const cplx<T> *__restrict__ khat, ZArgs a) {
   using V = cplx<T>;
+  if (a.live && a.live[0] == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *s = reinterpret_cast<V *>(smem_raw);
   const int n = a.pl.n;
@@ -339,6 +346,7 @@ template <typename T, int MODE, typename TI, typename TO>
 inline void launch_rows(dda_problem *p, const FftPlan &pl, const TI *in, TO *out, RowArgs a,
                         const char *name, double bytes) {
   a.pl = desc(pl);
+  a.live = p->live;
   a.tw = tile_cols<T>(pl.n);
   if (a.rows < a.tw) a.tw = (int)a.rows;
   a.nsh = ilog2_exact(pl.n);
@@ -378,6 +386,7 @@ inline void launch_strided(dda_problem *p, const FftPlan &pl, const cplx<T> *in,
   a.in_bstride = in_bstride;
   a.out_bstride = out_bstride;
   a.sign = sign;
+  a.live = p->live;
   const size_t lds = tile_lds<T>(pl.n, a.tw);
   const int threads = a.tw * tpc_of(pl.n);
   KTimer t(&p->prof, p->st, name, bytes);

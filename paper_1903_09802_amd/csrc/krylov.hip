@@ -220,17 +220,20 @@ __global__ void __launch_bounds__(kRedThreads) k_multiaxpy(const double2 *V, lon
   if (threadIdx.x == 0) nrm_partial[((long long)r * kSlots) * B + blockIdx.x] = sh[0];
 }
 
-// out = sum_i V_i y_i  (y = coef[r * kMaxM + i], zero beyond a RHS's cut)
+// out = sum_i V_i y_i  (y = coef[r * kMaxM + i], zero beyond a RHS's cut); with jcut, right-hand
+// side r combines only its first jcut[r] vectors
 __global__ void k_combine(const double2 *V, long long vs_r, long long vs_j, int nvec,
-                          const double2 *coef, double2 *out, long long os_r, long long n3) {
+                          const double2 *coef, double2 *out, long long os_r, long long n3,
+                          const int *jcut) {
   const int r = blockIdx.y;
   __shared__ double2 c[kMaxM];
-  for (int i = threadIdx.x; i < nvec; i += blockDim.x) c[i] = coef[r * kMaxM + i];
+  const int nv = jcut ? min(nvec, jcut[r]) : nvec;
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) c[i] = coef[r * kMaxM + i];
   __syncthreads();
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < n3;
        n += (long long)gridDim.x * blockDim.x) {
     double2 v = make_double2(0.0, 0.0);
-    for (int i = 0; i < nvec; ++i) v = cadd(v, cmul(V[r * vs_r + i * vs_j + n], c[i]));
+    for (int i = 0; i < nv; ++i) v = cadd(v, cmul(V[r * vs_r + i * vs_j + n], c[i]));
     out[r * os_r + n] = v;
   }
 }
@@ -285,64 +288,115 @@ __global__ void k_scale(const double2 *in, double2 *out, long long n3, long long
   }
 }
 
-// Start of a cycle (basis vector 0 is the residual itself): g = (beta, 0, ...),
-// vsc[0] = 1 / beta with beta = sqrt(rn2).
-__global__ void k_cycle_init(const double2 *rn2, double2 *g, int m, double *vsc, const int *active,
-                             int nrhs) {
-  const int r = threadIdx.x;
-  if (r >= nrhs || !active[r]) return;
-  const double beta = sqrt(rn2[r * kMaxM].x);
-  for (int i = 0; i <= m; ++i) g[r * (m + 1) + i] = make_double2(0.0, 0.0);
-  g[r * (m + 1)] = make_double2(beta, 0.0);
-  vsc[r * kMaxM] = beta > 0.0 ? 1.0 / beta : 0.0;
+// ----------------------------------------------------------------------------- device control
+
+// Every step's continue / stop decision is taken on the device, so a restart cycle runs without
+// the host: the control block ctl (ints) holds
+//   [0]                 live: some right-hand side is still iterating in this cycle; every
+//                       kernel of the operator and the preconditioner launched inside the cycle
+//                       returns at once when it is 0
+//   [1, 1 + R)          active: right-hand side r takes further steps in this cycle
+//   [1 + R, 1 + 2R)     jcut: steps r took in this cycle (the size of its least-squares problem)
+//   [1 + 2R, 1 + 3R)    iters: steps r took in this solve
+//   [1 + 3R, 1 + 4R)    want: r runs this cycle (set by the host between cycles)
+// The host reads the results once per cycle (true residuals and step counts).
+__host__ __device__ __forceinline__ int *ctl_active(int *c, int) { return c + 1; }
+__host__ __device__ __forceinline__ int *ctl_jcut(int *c, int R) { return c + 1 + R; }
+__host__ __device__ __forceinline__ int *ctl_iters(int *c, int R) { return c + 1 + 2 * R; }
+__host__ __device__ __forceinline__ int *ctl_want(int *c, int R) { return c + 1 + 3 * R; }
+
+// Start of a solve: no steps taken, nothing active.
+__global__ void k_ctl_reset(int *ctl, int R) {
+  for (int i = threadIdx.x; i < 1 + 4 * R; i += blockDim.x) ctl[i] = 0;
 }
 
-// Column j of the Hessenberg matrix from the two projections and ||w||^2, previous
-// rotations, a new rotation, the updated residual estimate |g_{j+1}| (dscal[r*8]),
-// ||w|| (dscal[r*8+2]) and the scale 1/||w|| of the new basis vector (vsc[r][j+1]).
-__global__ void k_arnoldi(int j, int m, double2 *H, double2 *giv, double2 *g, const double2 *h1,
-                          const double2 *h2, int use_h2, const double2 *nrm2, double *dscal,
-                          double *vsc, const int *active, int nrhs) {
+// Start of a cycle (basis vector 0 is the residual itself): active = want, g = (beta, 0, ...),
+// vsc[0] = 1 / beta with beta = sqrt(rn2), live = any active.  One 64-lane block (nrhs <= 64).
+__global__ void k_cycle_init(const double2 *rn2, double2 *g, int m, double *vsc, int *ctl, int R,
+                             int nrhs) {
   const int r = threadIdx.x;
-  if (r >= nrhs || !active[r]) return;
-  double2 *Hr = H + (long long)r * (m + 1) * m;
-  double2 *gr = g + r * (m + 1);
-  double2 *cs = giv + (long long)r * m * 2;
-  for (int i = 0; i <= j; ++i)
-    Hr[i * m + j] = use_h2 ? cadd(h1[r * kMaxM + i], h2[r * kMaxM + i]) : h1[r * kMaxM + i];
-  const double hn = sqrt(nrm2[r * kMaxM].x);
-  Hr[(j + 1) * m + j] = make_double2(hn, 0.0);
-  for (int i = 0; i < j; ++i) {
-    const double c = cs[2 * i].x;
-    const double2 s = cs[2 * i + 1];
-    const double2 a = Hr[i * m + j], b = Hr[(i + 1) * m + j];
-    const double2 t = cadd(cscale(a, c), cmul(s, b));
-    Hr[(i + 1) * m + j] = csub(cscale(b, c), cmulcj(s, a));
-    Hr[i * m + j] = t;
+  bool on = false;
+  if (r < nrhs) {
+    on = ctl_want(ctl, R)[r] != 0;
+    ctl_active(ctl, R)[r] = on ? 1 : 0;
+    ctl_jcut(ctl, R)[r] = 0;
+    if (on) {
+      const double beta = sqrt(rn2[r * kMaxM].x);
+      for (int i = 0; i <= m; ++i) g[r * (m + 1) + i] = make_double2(0.0, 0.0);
+      g[r * (m + 1)] = make_double2(beta, 0.0);
+      vsc[r * kMaxM] = beta > 0.0 ? 1.0 / beta : 0.0;
+    }
   }
-  const double2 a = Hr[j * m + j], b = Hr[(j + 1) * m + j];
-  const double aa = sqrt(a.x * a.x + a.y * a.y), bb = sqrt(b.x * b.x + b.y * b.y);
-  const double den = sqrt(aa * aa + bb * bb);
-  double c;
-  double2 s;
-  if (den == 0.0) { c = 1.0; s = make_double2(0.0, 0.0); }
-  else if (aa == 0.0) { c = 0.0; s = make_double2(1.0, 0.0); }
-  else {
-    c = aa / den;
-    const double2 ph = make_double2(a.x / aa, a.y / aa);
-    s = cscale(cmul(ph, cconj(b)), 1.0 / den);
+  const unsigned long long any = __ballot(on);
+  if (threadIdx.x == 0) ctl[0] = any != 0ull ? 1 : 0;
+}
+
+// Column j of the Hessenberg matrix from the projections and ||w||^2, previous rotations, a
+// new rotation, the updated residual estimate |g_{j+1}| (dscal[r*8]), ||w|| (dscal[r*8+2]) and
+// the scale 1/||w|| of the new basis vector (vsc[r][j+1]); then the step's decision: the
+// estimate relative to bnrm[r] is recorded in the history, and right-hand side r stops when it
+// is at most tol, w vanished (breakdown), the estimate is not finite, the step cap is reached
+// or the cycle is full.  live = some right-hand side continues.  One 64-lane block.
+__global__ void k_arnoldi(int j, int m, double2 *H, double2 *giv, double2 *g, const double2 *h1,
+                          const double2 *nrm2, double *dscal, double *vsc, int *ctl, int R,
+                          int nrhs, const double *bnrm, double tol, int maxit, double *hist,
+                          int hcap) {
+  const int r = threadIdx.x;
+  bool keep = false;
+  int *active = ctl_active(ctl, R);
+  if (r < nrhs && active[r]) {
+    double2 *Hr = H + (long long)r * (m + 1) * m;
+    double2 *gr = g + r * (m + 1);
+    double2 *cs = giv + (long long)r * m * 2;
+    for (int i = 0; i <= j; ++i) Hr[i * m + j] = h1[r * kMaxM + i];
+    const double hn = sqrt(nrm2[r * kMaxM].x);
+    Hr[(j + 1) * m + j] = make_double2(hn, 0.0);
+    for (int i = 0; i < j; ++i) {
+      const double c = cs[2 * i].x;
+      const double2 s = cs[2 * i + 1];
+      const double2 a = Hr[i * m + j], b = Hr[(i + 1) * m + j];
+      const double2 t = cadd(cscale(a, c), cmul(s, b));
+      Hr[(i + 1) * m + j] = csub(cscale(b, c), cmulcj(s, a));
+      Hr[i * m + j] = t;
+    }
+    const double2 a = Hr[j * m + j], b = Hr[(j + 1) * m + j];
+    const double aa = sqrt(a.x * a.x + a.y * a.y), bb = sqrt(b.x * b.x + b.y * b.y);
+    const double den = sqrt(aa * aa + bb * bb);
+    double c;
+    double2 s;
+    if (den == 0.0) { c = 1.0; s = make_double2(0.0, 0.0); }
+    else if (aa == 0.0) { c = 0.0; s = make_double2(1.0, 0.0); }
+    else {
+      c = aa / den;
+      const double2 ph = make_double2(a.x / aa, a.y / aa);
+      s = cscale(cmul(ph, cconj(b)), 1.0 / den);
+    }
+    cs[2 * j] = make_double2(c, 0.0);
+    cs[2 * j + 1] = s;
+    Hr[j * m + j] = cadd(cscale(a, c), cmul(s, b));
+    Hr[(j + 1) * m + j] = make_double2(0.0, 0.0);
+    const double2 gj = gr[j];
+    gr[j + 1] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));  // -conj(s) g_j
+    gr[j] = cscale(gj, c);
+    const double2 e = gr[j + 1];
+    const double en = sqrt(e.x * e.x + e.y * e.y);
+    dscal[r * 8 + 0] = en;
+    dscal[r * 8 + 2] = hn;
+    if (j + 1 < kMaxM) vsc[r * kMaxM + j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+    int *iters = ctl_iters(ctl, R);
+    const int it = iters[r] + 1;
+    iters[r] = it;
+    const double est = bnrm[r] > 0.0 ? en / bnrm[r] : en;
+    if (hist && it <= hcap) hist[(long long)r * hcap + it - 1] = est;
+    if (est <= tol || hn == 0.0 || !isfinite(est) || it >= maxit || j == m - 1) {
+      active[r] = 0;
+      ctl_jcut(ctl, R)[r] = j + 1;
+    } else {
+      keep = true;
+    }
   }
-  cs[2 * j] = make_double2(c, 0.0);
-  cs[2 * j + 1] = s;
-  Hr[j * m + j] = cadd(cscale(a, c), cmul(s, b));
-  Hr[(j + 1) * m + j] = make_double2(0.0, 0.0);
-  const double2 gj = gr[j];
-  gr[j + 1] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));  // -conj(s) g_j
-  gr[j] = cscale(gj, c);
-  const double2 e = gr[j + 1];
-  dscal[r * 8 + 0] = sqrt(e.x * e.x + e.y * e.y);
-  dscal[r * 8 + 2] = hn;
-  if (j + 1 < kMaxM) vsc[r * kMaxM + j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+  const unsigned long long any = __ballot(keep);
+  if (threadIdx.x == 0) ctl[0] = any != 0ull ? 1 : 0;
 }
 
 // y = H(0:jc, 0:jc)^{-1} g(0:jc) (upper triangular), zero beyond jc; stored as the
@@ -361,6 +415,24 @@ __global__ void k_trisolve(const double2 *H, const double2 *g, int m, const int 
     y[r * kMaxM + i] = cdiv(acc, Hr[i * m + i]);
   }
   for (int i = 0; i < jc; ++i) y[r * kMaxM + i] = cscale(y[r * kMaxM + i], vsc[r * kMaxM + i]);
+}
+
+// out[r] = sqrt(in[r * kMaxM].x)
+__global__ void k_sqrt_slot(const double2 *in, double *out, int nrhs) {
+  const int r = threadIdx.x;
+  if (r < nrhs) out[r] = sqrt(in[r * kMaxM].x);
+}
+
+// The results the host reads after a cycle: res[r] = ||b - A x||^2, res[R + r] = the squared
+// norm the stopping test uses (||P^{-1}(b - A x)||^2 when left preconditioned), res[2R + r] =
+// steps taken.
+__global__ void k_cycle_results(const double2 *tr2, const double2 *rr2, const int *ctl, int R,
+                                int nrhs, double *res) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  res[r] = tr2[r * kMaxM].x;
+  res[R + r] = rr2[r * kMaxM].x;
+  res[2 * R + r] = (double)ctl[1 + 2 * R + r];
 }
 
 // ----------------------------------------------------------------------------- host side
@@ -403,133 +475,89 @@ static void norm2_dev(Kry &K, const double2 *a, long long st_r, double2 *dst) {
     hipLaunchKernelGGL(k_norm2, grid_r(K.B, K.nrhs), dim3(kRedThreads), 0, p->st, a, K.n3, st_r,
                        K.partial, K.B);
   }
-  finalize(K, 1, dst, nullptr, nullptr);
+  hipLaunchKernelGGL(k_finalize, dim3(1, K.nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B, dst,
+                     nullptr, nullptr, p->ones, -1);
+  HIPCHK(hipGetLastError());
 }
 
 static void read_scalars(dda_problem *p, const double2 *src, int nrhs, std::vector<double> &out) {
-  std::vector<double2> tmp(nrhs * kMaxM);
-  HIPCHK(hipMemcpyAsync(tmp.data(), src, sizeof(double2) * nrhs * kMaxM, hipMemcpyDeviceToHost, p->st));
+  std::vector<double2> tmp(nrhs);
+  HIPCHK(hipMemcpy2DAsync(tmp.data(), sizeof(double2), src, sizeof(double2) * kMaxM,
+                          sizeof(double2), nrhs, hipMemcpyDeviceToHost, p->st));
   HIPCHK(hipStreamSynchronize(p->st));
   out.resize(nrhs);
-  for (int r = 0; r < nrhs; ++r) out[r] = tmp[r * kMaxM].x;
+  for (int r = 0; r < nrhs; ++r) out[r] = tmp[r].x;
 }
 
-// r = b - A x (FP64 operator) into r, relative norms ||r|| / ||b|| to the host.
-void residual(dda_problem *p, int nrhs, const double2 *b, const double2 *x, double2 *r,
-              double *rel_host) {
-  const long long n3 = 3 * p->nocc;
-  Kry K{p, nrhs, reduce_blocks(n3), p->opt.restart, n3, reinterpret_cast<double2 *>(p->partial),
-        p->dflag + 4, p->dflag + 4 + p->R};
-  std::vector<int> all(nrhs, 1);
-  sync_active(p, K.d_active, all);
-  apply_operator(p, nrhs, x, p->work, 0, nullptr);
+// One GMRES solve's fixed configuration: what a captured cycle depends on besides the handle.
+struct GmresCfg {
+  int nrhs, fp32, m, maxit;
+  double tol;
+  bool prec, left;
+  long long vs_r, vs_j;
+  const double2 *b;
+  double2 *x;
+};
+
+// r = b - A x (FP64 operator) into basis block 0 with ||r||^2 in hcol2; left preconditioned,
+// hnrm takes ||r||^2 and r becomes P^{-1} r with its squared norm in hcol2.  Then the results
+// the host reads (k_cycle_results).  Every right-hand side takes part (active = 1 for all is
+// not needed: the reductions here ignore the flags).
+static void enqueue_residual(Kry &K, const GmresCfg &c) {
+  dda_problem *p = K.p;
+  const int nrhs = c.nrhs;
+  double2 *rv = p->V;
+  apply_operator(p, nrhs, c.x, p->work, 0, nullptr);
   {
-    KTimer t(&p->prof, p->st, "kry_residual", 48.0 * n3 * nrhs);
-    hipLaunchKernelGGL(k_axpby, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, b, p->work, -1.0, r,
-                       n3, n3, nullptr, K.partial, K.B);
+    KTimer t(&p->prof, p->st, "kry_residual", 48.0 * K.n3 * nrhs);
+    hipLaunchKernelGGL(k_axpby, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, c.b, p->work, -1.0,
+                       rv, K.n3, K.n3, nullptr, K.partial, K.B);
   }
-  finalize(K, 1, p->hcol2, nullptr, nullptr);
-  std::vector<double> rn2, bn2;
-  read_scalars(p, p->hcol2, nrhs, rn2);
-  norm2_dev(K, b, n3, p->hcol2);
-  read_scalars(p, p->hcol2, nrhs, bn2);
-  for (int q = 0; q < nrhs; ++q) rel_host[q] = bn2[q] > 0 ? std::sqrt(rn2[q] / bn2[q]) : std::sqrt(rn2[q]);
+  hipLaunchKernelGGL(k_finalize, dim3(1, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
+                     c.left ? p->hnrm : p->hcol2, nullptr, nullptr, p->ones, -1);
+  HIPCHK(hipGetLastError());
+  if (c.left) {
+    apply_precond(p, nrhs, rv, rv, p->prec_fp32, nullptr);
+    {
+      KTimer t(&p->prof, p->st, "kry_norm", 16.0 * K.n3 * nrhs);
+      hipLaunchKernelGGL(k_norm2, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, rv, K.n3, K.n3,
+                         K.partial, K.B);
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
+                       p->hcol2, nullptr, nullptr, p->ones, -1);
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_cycle_results, dim3(1), dim3(64), 0, p->st, c.left ? p->hnrm : p->hcol2,
+                     p->hcol2, p->ctl, p->R, nrhs, p->cres);
+  HIPCHK(hipGetLastError());
 }
 
-void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp32, double tol,
-                 int maxit, dda_stats *st) {
-  const int m = p->opt.restart;
-  const long long n3 = 3 * p->nocc;
-  Kry K{p, nrhs, reduce_blocks(n3), m, n3, reinterpret_cast<double2 *>(p->partial), p->dflag + 4,
-        p->dflag + 4 + p->R};
-  const long long vs_r = n3, vs_j = (long long)p->R * n3;  // V is [m+1][R][n3]
-  const bool prec = p->opt.precond != 0;
-  // Left preconditioning (the paper's P^{-1} A x = P^{-1} b): Krylov space of P^{-1} A, the
-  // restart vector P^{-1}(b - A x), the update x += V y, and every test on the preconditioned
-  // residual relative to ||P^{-1} b||.  Right preconditioning: A P^{-1}, x += P^{-1} V y, tests
-  // on the true residual.  The preconditioner is applied in the precision it was built in.
-  const bool left = prec && p->opt.left_precond != 0;
-  const int pfp = p->prec_fp32;
-  double2 *rv = p->V;  // the residual is written straight into basis block 0
-  std::vector<int> all(nrhs, 1), act(nrhs, 1), incyc(nrhs, 0), jcut(nrhs, 0), iters(nrhs, 0);
-  std::vector<int> cycles(nrhs, 0), conv(nrhs, 0);
-  std::vector<double> bn2, bt2, rn2, rel(nrhs, 0.0), trel(nrhs, 0.0);
-  sync_active(p, K.d_active, all);
-  norm2_dev(K, b, n3, p->hcol2);
-  read_scalars(p, p->hcol2, nrhs, bt2);  // ||b||^2
-  bn2 = bt2;                             // norm the tests are relative to
-  if (left) {
-    apply_precond(p, nrhs, b, p->work2, pfp, nullptr);
-    norm2_dev(K, p->work2, n3, p->hcol2);
-    read_scalars(p, p->hcol2, nrhs, bn2);  // ||P^{-1} b||^2
-  }
-  // The restart residual b - A x is always formed with the FP64 operator: with fp32 != 0 every
-  // restart is one step of iterative refinement (FP32 cycle, FP64 residual).  rel holds the
-  // residual the tests use, trel the true one; hcol2 ends with ||rv||^2 for the cycle start.
-  auto true_residual = [&](void) {
-    sync_active(p, K.d_active, all);
-    apply_operator(p, nrhs, x, p->work, 0, nullptr);
-    {
-      KTimer t(&p->prof, p->st, "kry_residual", 48.0 * n3 * nrhs);
-      hipLaunchKernelGGL(k_axpby, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, b, p->work, -1.0,
-                         rv, n3, n3, nullptr, K.partial, K.B);
-    }
-    finalize(K, 1, p->hcol2, nullptr, nullptr);
-    read_scalars(p, p->hcol2, nrhs, rn2);
-    for (int r = 0; r < nrhs; ++r) {
-      trel[r] = bt2[r] > 0 ? std::sqrt(rn2[r] / bt2[r]) : 0.0;
-      REQUIRE(std::isfinite(trel[r]), DDA_EDEVICE, "non-finite residual for right-hand side %d", r);
-    }
-    if (left) {
-      apply_precond(p, nrhs, rv, rv, pfp, nullptr);
-      norm2_dev(K, rv, n3, p->hcol2);
-      read_scalars(p, p->hcol2, nrhs, rn2);
-    }
-    for (int r = 0; r < nrhs; ++r) {
-      rel[r] = bn2[r] > 0 ? std::sqrt(rn2[r] / bn2[r]) : 0.0;
-      REQUIRE(std::isfinite(rel[r]), DDA_EDEVICE, "non-finite residual for right-hand side %d", r);
-    }
-  };
-  true_residual();
-  for (int r = 0; r < nrhs; ++r)
-    if (rel[r] <= tol || bn2[r] == 0.0) { act[r] = 0; conv[r] = 1; }
-  // w = A P^{-1} v~_j (or P^{-1} A v~_j when left) into basis block j + 1; block j is
-  // contiguous [nrhs][n3] and v~_j is scaled by 1 / ||v~_j|| on the way in
-  auto products = [&](int jj) {
-    double2 *vjj = p->V + (long long)jj * vs_j;
-    double2 *wjj = p->V + (long long)(jj + 1) * vs_j;
-    if (left) {
-      apply_operator(p, nrhs, vjj, p->work2, fp32, p->vsc + jj);
-      apply_precond(p, nrhs, p->work2, wjj, fp32, nullptr);
-    } else if (prec) {
-      apply_precond(p, nrhs, vjj, p->work2, fp32, p->vsc + jj);
-      apply_operator(p, nrhs, p->work2, wjj, fp32, nullptr);
-    } else {
-      apply_operator(p, nrhs, vjj, wjj, fp32, p->vsc + jj);
-    }
-  };
-  std::vector<double> last(nrhs, 0.0);  // latest residual (estimate) per RHS
-  while (true) {
-    bool any = false;
-    for (int r = 0; r < nrhs; ++r) any = any || (act[r] && iters[r] < maxit);
-    if (!any) break;
-    for (int r = 0; r < nrhs; ++r) {
-      incyc[r] = act[r] && iters[r] < maxit;
-      jcut[r] = 0;
-      if (incyc[r]) cycles[r] += 1;
-    }
-    sync_active(p, K.d_active, incyc);
-    std::vector<int> dev_act = incyc;  // the flags on the device
-    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, p->st, p->hcol2, p->gvec, m, p->vsc,
-                       K.d_active, nrhs);
-    HIPCHK(hipGetLastError());
-    for (int r = 0; r < nrhs; ++r) last[r] = rel[r];
-    bool issued = false;  // this step's products were enqueued during the previous step
+// One restart cycle for the right-hand sides the host marked in `want`: up to m steps, each
+// w = A P^{-1} v~_j (or P^{-1} A v~_j when left) into basis block j + 1 with v~_j scaled by
+// 1 / ||v~_j|| on the way in, MGS in one reduction (a = V^H w and row j of L, c = (I + L)^{-1} a,
+// w -= V c), and the device decision of k_arnoldi; then x += P^{-1}(V y) (x += V y when left)
+// and the new residual.  Nothing here waits for the host.
+static void enqueue_cycle(Kry &K, const GmresCfg &c) {
+  dda_problem *p = K.p;
+  const int nrhs = c.nrhs, m = c.m;
+  const long long n3 = K.n3, vs_r = c.vs_r, vs_j = c.vs_j;
+  hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, p->st, p->hcol2, p->gvec, m, p->vsc,
+                     p->ctl, p->R, nrhs);
+  HIPCHK(hipGetLastError());
+  p->live = p->ctl;  // the products of a step return at once when no right-hand side is active
+  try {
     for (int j = 0; j < m; ++j) {
+      double2 *vjj = p->V + (long long)j * vs_j;
       double2 *w = p->V + (long long)(j + 1) * vs_j;
-      if (!issued) products(j);
-      issued = false;
-      // MGS in one reduction: a = V^H w and row j of L, c = (I + L)^{-1} a, w -= V c
+      if (c.left) {
+        apply_operator(p, nrhs, vjj, p->work2, c.fp32, p->vsc + j);
+        apply_precond(p, nrhs, p->work2, w, c.fp32, nullptr);
+      } else if (c.prec) {
+        apply_precond(p, nrhs, vjj, p->work2, c.fp32, p->vsc + j);
+        apply_operator(p, nrhs, p->work2, w, c.fp32, nullptr);
+      } else {
+        apply_operator(p, nrhs, vjj, w, c.fp32, p->vsc + j);
+      }
       {
         KTimer t(&p->prof, p->st, "kry_gs_dots", 16.0 * n3 * (j + 2) * nrhs);
         hipLaunchKernelGGL(k_gs_dots, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r,
@@ -537,8 +565,8 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
       }
       hipLaunchKernelGGL(k_finalize_dots, dim3(2 * j + 1, nrhs), dim3(kRedThreads), 0, p->st,
                          K.partial, K.B, p->hraw, K.d_active, j);
-      hipLaunchKernelGGL(k_mgs_coef, dim3(nrhs), dim3(64), 0, p->st, j, p->hraw, p->lmat, m + 1, p->vsc,
-                         p->hcol, p->ycoef, K.d_active, nrhs);
+      hipLaunchKernelGGL(k_mgs_coef, dim3(nrhs), dim3(64), 0, p->st, j, p->hraw, p->lmat, m + 1,
+                         p->vsc, p->hcol, p->ycoef, K.d_active, nrhs);
       {
         KTimer t(&p->prof, p->st, "kry_multiaxpy", 16.0 * n3 * (j + 3) * nrhs);
         hipLaunchKernelGGL(k_multiaxpy, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r,
@@ -546,61 +574,152 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
       }
       finalize(K, 1, p->hnrm, nullptr, nullptr, 0);  // ||w - V c||^2 -> hnrm[r][0]
       hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, p->st, j, m, p->H, p->givens, p->gvec,
-                         p->hcol, p->hcol, 0, p->hnrm, p->dscal, p->vsc, K.d_active, nrhs);
+                         p->hcol, p->hnrm, p->dscal, p->vsc, p->ctl, p->R, nrhs, p->bnrm, c.tol,
+                         c.maxit, p->hist, p->hist_cap);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(p->hpin, p->dscal, sizeof(double) * 8 * nrhs, hipMemcpyDeviceToHost,
-                            p->st));
-      HIPCHK(hipEventRecord(p->est_ev, p->st));
-      // While the host waits for the estimates, enqueue the next step's products unless this
-      // step may end the cycle: its last step, or an RHS within 4 tol of converging.  Products
-      // that turn out unneeded only fill a basis block the cycle never reads.
-      bool spec = j + 1 < m;
-      for (int r = 0; r < nrhs && spec; ++r)
-        if (incyc[r] && (last[r] <= 4.0 * tol || iters[r] + 1 >= maxit)) spec = false;
-      if (spec) {
-        products(j + 1);
-        issued = true;
-      }
-      HIPCHK(hipEventSynchronize(p->est_ev));
-      const double *hp = p->hpin;
-      bool more = false;
-      for (int r = 0; r < nrhs; ++r) {
-        if (!incyc[r]) continue;
-        iters[r] += 1;
-        const double est = hp[8 * r] / std::sqrt(bn2[r]);
-        REQUIRE(std::isfinite(est), DDA_EDEVICE, "non-finite residual estimate (RHS %d)", r);
-        last[r] = est;
-        const bool brk = hp[8 * r + 2] == 0.0;
-        if (est <= tol || brk || iters[r] >= maxit || j == m - 1) {
-          jcut[r] = j + 1;
-          incyc[r] = 0;
-        } else {
-          more = true;
-        }
-      }
-      sync_active_changed(p, K.d_active, incyc, dev_act);
-      if (!more) break;
     }
-    // x += P^{-1} (V y), or x += V y when left
-    HIPCHK(hipMemcpyAsync(K.d_jcut, jcut.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, p->st));
-    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, p->st, p->H, p->gvec, m, K.d_jcut, p->vsc,
-                       p->ycoef, nrhs);
-    int jmax = 0;
-    for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jcut[r]);
-    {
-      KTimer t(&p->prof, p->st, "kry_combine", 16.0 * n3 * (jmax + 1) * nrhs);
-      hipLaunchKernelGGL(k_combine, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r, vs_j,
-                         jmax, p->ycoef, p->work2, n3, n3);
+  } catch (...) {
+    p->live = nullptr;
+    throw;
+  }
+  p->live = nullptr;
+  hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, p->st, p->H, p->gvec, m, K.d_jcut, p->vsc,
+                     p->ycoef, nrhs);
+  {
+    KTimer t(&p->prof, p->st, "kry_combine", 16.0 * n3 * (m + 1) * nrhs);
+    hipLaunchKernelGGL(k_combine, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r, vs_j,
+                       m, p->ycoef, p->work2, n3, n3, K.d_jcut);
+  }
+  HIPCHK(hipGetLastError());
+  if (c.prec && !c.left) apply_precond(p, nrhs, p->work2, p->work2, c.fp32, nullptr);
+  hipLaunchKernelGGL(k_axpby, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, c.x, p->work2, 1.0,
+                     c.x, n3, n3, nullptr, nullptr, K.B);
+  HIPCHK(hipGetLastError());
+  enqueue_residual(K, c);
+}
+
+// Run one cycle: replay its HIP graph (captured on first use for this configuration), or
+// launch its kernels one by one when graphs are off or per-kernel profiling is on.
+static void run_cycle(Kry &K, const GmresCfg &c) {
+  dda_problem *p = K.p;
+  if (!p->opt.graph || p->prof.on) {
+    enqueue_cycle(K, c);
+    return;
+  }
+  hipGraphExec_t exec = nullptr;
+  for (const auto &g : p->graphs)
+    if (g.nrhs == c.nrhs && g.fp32 == c.fp32 && g.tol == c.tol && g.maxit == c.maxit &&
+        g.b == c.b && g.x == c.x) {
+      exec = g.exec;
+      break;
     }
-    HIPCHK(hipGetLastError());
-    if (prec && !left) apply_precond(p, nrhs, p->work2, p->work2, fp32, nullptr);
-    hipLaunchKernelGGL(k_axpby, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, x, p->work2, 1.0, x,
-                       n3, n3, nullptr, nullptr, K.B);
-    HIPCHK(hipGetLastError());
-    true_residual();
+  if (!exec) {
+    hipStream_t orig = p->st;
+    HIPCHK(hipStreamBeginCapture(p->cap_st, hipStreamCaptureModeRelaxed));
+    p->st = p->cap_st;
+    hipGraph_t graph = nullptr;
+    try {
+      enqueue_cycle(K, c);
+    } catch (...) {
+      p->st = orig;
+      if (hipStreamEndCapture(p->cap_st, &graph) == hipSuccess && graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    p->st = orig;
+    HIPCHK(hipStreamEndCapture(p->cap_st, &graph));
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(e);
+    p->graphs.push_back(dda_problem::CycleGraph{c.nrhs, c.fp32, c.tol, c.maxit, c.b, c.x, exec});
+  }
+  HIPCHK(hipGraphLaunch(exec, p->st));
+}
+
+void drop_graphs(dda_problem *p) {
+  for (auto &g : p->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  p->graphs.clear();
+}
+
+// Copy the cycle results to the host: true and test squared residual norms, steps per RHS.
+static void read_results(dda_problem *p, int nrhs, std::vector<double> &tr2, std::vector<double> &rr2,
+                         std::vector<int> &iters) {
+  const int R = p->R;
+  HIPCHK(hipMemcpyAsync(p->hpin, p->cres, sizeof(double) * 3 * R, hipMemcpyDeviceToHost, p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
+  for (int r = 0; r < nrhs; ++r) {
+    tr2[r] = p->hpin[r];
+    rr2[r] = p->hpin[R + r];
+    iters[r] = (int)p->hpin[2 * R + r];
+  }
+}
+
+void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp32, double tol,
+                 int maxit, dda_stats *st) {
+  const int m = p->opt.restart, R = p->R;
+  const long long n3 = 3 * p->nocc;
+  Kry K{p, nrhs, reduce_blocks(n3), m, n3, reinterpret_cast<double2 *>(p->partial),
+        ctl_active(p->ctl, R), ctl_jcut(p->ctl, R)};
+  GmresCfg c;
+  c.nrhs = nrhs;
+  c.fp32 = fp32;
+  c.m = m;
+  c.maxit = maxit;
+  c.tol = tol;
+  // Left preconditioning (the paper's P^{-1} A x = P^{-1} b): Krylov space of P^{-1} A, the
+  // restart vector P^{-1}(b - A x), the update x += V y, and every test on the preconditioned
+  // residual relative to ||P^{-1} b||.  Right preconditioning: A P^{-1}, x += P^{-1} V y, tests
+  // on the true residual.  The preconditioner is applied in the precision it was built in.
+  c.prec = p->opt.precond != 0;
+  c.left = c.prec && p->opt.left_precond != 0;
+  c.vs_r = n3;
+  c.vs_j = (long long)R * n3;  // V is [m+1][R][n3]
+  c.b = b;
+  c.x = x;
+  std::vector<int> act(nrhs, 1), incyc(nrhs, 0), iters(nrhs, 0), cycles(nrhs, 0), conv(nrhs, 0);
+  std::vector<double> bt2, bn2, tr2(nrhs), rr2(nrhs), rel(nrhs, 0.0), trel(nrhs, 0.0);
+  // ||b|| (and ||P^{-1} b||), the norms the tests are relative to, kept on the device too
+  norm2_dev(K, b, n3, p->hcol2);
+  if (c.left) {
+    read_scalars(p, p->hcol2, nrhs, bt2);
+    apply_precond(p, nrhs, b, p->work2, p->prec_fp32, nullptr);
+    norm2_dev(K, p->work2, n3, p->hcol2);
+  }
+  hipLaunchKernelGGL(k_sqrt_slot, dim3(1), dim3(64), 0, p->st, p->hcol2, p->bnrm, nrhs);
+  hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(256), 0, p->st, p->ctl, R);
+  HIPCHK(hipGetLastError());
+  read_scalars(p, p->hcol2, nrhs, bn2);
+  if (!c.left) bt2 = bn2;
+  // The restart residual b - A x is always formed with the FP64 operator: with fp32 != 0 every
+  // restart is one step of iterative refinement (FP32 cycle, FP64 residual).
+  auto take = [&]() {
+    read_results(p, nrhs, tr2, rr2, iters);
+    for (int r = 0; r < nrhs; ++r) {
+      trel[r] = bt2[r] > 0 ? std::sqrt(tr2[r] / bt2[r]) : 0.0;
+      rel[r] = bn2[r] > 0 ? std::sqrt(rr2[r] / bn2[r]) : 0.0;
+      REQUIRE(std::isfinite(trel[r]) && std::isfinite(rel[r]), DDA_EDEVICE,
+              "non-finite residual for right-hand side %d", r);
+    }
+  };
+  enqueue_residual(K, c);
+  take();
+  for (int r = 0; r < nrhs; ++r)
+    if (rel[r] <= tol || bn2[r] == 0.0) { act[r] = 0; conv[r] = 1; }
+  int *want = ctl_want(p->ctl, R);
+  while (true) {
+    bool any = false;
+    for (int r = 0; r < nrhs; ++r) {
+      incyc[r] = act[r] && iters[r] < maxit;
+      any = any || incyc[r];
+      if (incyc[r]) cycles[r] += 1;
+    }
+    if (!any) break;
+    HIPCHK(hipMemcpyAsync(want, incyc.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, p->st));
+    run_cycle(K, c);
+    take();
     if (verbose())
       for (int r = 0; r < nrhs; ++r)
-        if (act[r])
+        if (incyc[r])
           fprintf(stderr, "[dda] %s rhs %d cycle %d iters %d rel residual %.3e (true %.3e, tol %.1e)\n",
                   fp32 ? "fp32" : "fp64", r, cycles[r], iters[r], rel[r], trel[r], tol);
     for (int r = 0; r < nrhs; ++r) {
@@ -608,6 +727,16 @@ void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp3
       if (rel[r] <= tol) { act[r] = 0; conv[r] = 1; }
     }
   }
+  // per-step residual estimates of every right-hand side whose stats ask for them
+  for (int r = 0; r < nrhs; ++r) {
+    if (!st[r].history || st[r].history_cap <= 0) continue;
+    const int n = std::min({iters[r], st[r].history_cap, p->hist_cap});
+    if (n > 0)
+      HIPCHK(hipMemcpyAsync(st[r].history, p->hist + (long long)r * p->hist_cap, sizeof(double) * n,
+                            hipMemcpyDeviceToHost, p->st));
+    st[r].history_len = n;
+  }
+  HIPCHK(hipStreamSynchronize(p->st));
   for (int r = 0; r < nrhs; ++r) {
     st[r].iters += iters[r];
     st[r].cycles += cycles[r];
@@ -767,7 +896,7 @@ void bicgstab_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, doub
   const long long n3 = 3 * p->nocc;
   REQUIRE(p->opt.restart >= 7, DDA_EINVAL, "BiCGStab needs restart >= 7 (work vectors)");
   Kry K{p, nrhs, reduce_blocks(n3), p->opt.restart, n3, reinterpret_cast<double2 *>(p->partial),
-        p->dflag + 4, p->dflag + 4 + p->R};
+        ctl_active(p->ctl, p->R), ctl_jcut(p->ctl, p->R)};
   const bool prec = p->opt.precond != 0;
   const long long blk = (long long)p->R * n3;  // one basis block holds [R][n3]
   double2 *rr = p->V, *rh = p->V + blk, *pp = p->V + 2 * blk, *v = p->V + 3 * blk;
@@ -884,6 +1013,10 @@ void bicgstab_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, doub
         iters[r] += 1;
         const double est = bn2[r] > 0 ? std::sqrt(hb[r].x / bn2[r]) : 0.0;
         REQUIRE(std::isfinite(est), DDA_EDEVICE, "non-finite residual estimate (RHS %d)", r);
+        if (st[r].history && iters[r] <= st[r].history_cap) {
+          st[r].history[iters[r] - 1] = est;
+          st[r].history_len = iters[r];
+        }
         const double2 om = cb[r * 5 + 1];
         // stop this run at the updated tolerance, omega = 0 or the cap
         if (est <= tol || (om.x == 0.0 && om.y == 0.0) || iters[r] >= maxit) act[r] = 0;
@@ -902,7 +1035,12 @@ void bicgstab_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, doub
 }
 
 dda_status solve_system(dda_problem *p, int nrhs, const double2 *b, double2 *x, dda_stats *st) {
-  for (int r = 0; r < nrhs; ++r) st[r] = dda_stats{0, 0, 0, 0, 0.0, 0.0};
+  // counters start at zero; the caller's history buffers (in fields) are kept
+  for (int r = 0; r < nrhs; ++r) {
+    st[r].iters = st[r].cycles = st[r].refinements = st[r].converged = 0;
+    st[r].rel_residual = 0.0;
+    st[r].history_len = 0;
+  }
   // precision 1: each GMRES(m) cycle applies the operator and the preconditioner in FP32 to an
   // FP64 basis, and each restart recomputes b - A x in FP64 (one refinement step per cycle)
   const int fp32 = p->opt.precision == 1 ? 1 : 0;
@@ -917,6 +1055,11 @@ dda_status solve_system(dda_problem *p, int nrhs, const double2 *b, double2 *x, 
   return ok ? DDA_OK : DDA_NOT_CONVERGED;
 }
 
+__global__ void k_fill_int(int *a, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
 void krylov_alloc(dda_problem *p) {
   const int m = p->opt.restart;
   const int R = p->R;
@@ -927,6 +1070,7 @@ void krylov_alloc(dda_problem *p) {
   HIPCHK(hipMalloc(&p->work2, sizeof(double2) * (size_t)R * n3));
   HIPCHK(hipMalloc(&p->bvec, sizeof(double2) * (size_t)R * n3));
   HIPCHK(hipMalloc(&p->xvec, sizeof(double2) * (size_t)R * n3));
+  HIPCHK(hipMalloc(&p->adj, sizeof(double2) * (size_t)n3));
   HIPCHK(hipMalloc(&p->H, sizeof(double2) * (size_t)R * (m + 1) * m));
   HIPCHK(hipMalloc(&p->givens, sizeof(double2) * (size_t)R * m * 2));
   HIPCHK(hipMalloc(&p->gvec, sizeof(double2) * (size_t)R * (m + 1)));
@@ -942,11 +1086,21 @@ void krylov_alloc(dda_problem *p) {
   HIPCHK(hipMalloc(&p->dscal, sizeof(double) * 16 * R));
   HIPCHK(hipMemset(p->dscal, 0, sizeof(double) * 16 * R));
   HIPCHK(hipHostMalloc(&p->hpin, sizeof(double) * 16 * R, hipHostMallocDefault));
-  HIPCHK(hipEventCreateWithFlags(&p->est_ev, hipEventDisableTiming));
   HIPCHK(hipMalloc(&p->vsc, sizeof(double) * kMaxM * R));
   HIPCHK(hipMemset(p->vsc, 0, sizeof(double) * kMaxM * R));
-  HIPCHK(hipMalloc(&p->dflag, sizeof(int) * (4 + 2 * R)));
-  HIPCHK(hipMemset(p->dflag, 0, sizeof(int) * (4 + 2 * R)));
+  HIPCHK(hipMalloc(&p->dflag, sizeof(int) * 4));
+  HIPCHK(hipMemset(p->dflag, 0, sizeof(int) * 4));
+  HIPCHK(hipMalloc(&p->ctl, sizeof(int) * (1 + 4 * R)));
+  HIPCHK(hipMemset(p->ctl, 0, sizeof(int) * (1 + 4 * R)));
+  HIPCHK(hipMalloc(&p->ones, sizeof(int) * R));
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, p->st, p->ones, R, 1);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMalloc(&p->bnrm, sizeof(double) * R));
+  HIPCHK(hipMalloc(&p->cres, sizeof(double) * 3 * R));
+  // per-step residual history of the GMRES solves, up to the step cap (at most 2^16 steps)
+  p->hist_cap = std::min(p->opt.max_iter, 1 << 16);
+  HIPCHK(hipMalloc(&p->hist, sizeof(double) * (size_t)R * p->hist_cap));
+  HIPCHK(hipStreamCreateWithFlags(&p->cap_st, hipStreamNonBlocking));
 }
 
 }  // namespace dda

@@ -396,15 +396,11 @@ void operator_spectrum_setup(dda_problem *p) {
   HIPCHK(hipMalloc(&p->khat64, sizeof(double2) * oct));
   HIPCHK(hipMalloc(&p->khat32, sizeof(float2) * oct));
   kernel_spectrum(p, 0);
-  zpass_autotune<double>(p, p->khat64);
-  zpass_autotune<float>(p, p->khat32);
-}
-
-static void ensure_imag_spectrum(dda_problem *p) {
-  if (p->khatI64) return;
-  const long long oct = 6LL * (p->nx + 1) * (p->ny + 1) * (p->nz + 1);
+  // the Im G spectrum of the scattering sum, so that no later call allocates
   HIPCHK(hipMalloc(&p->khatI64, sizeof(double2) * oct));
   kernel_spectrum(p, 1);
+  zpass_autotune<double>(p, p->khat64);
+  zpass_autotune<float>(p, p->khat32);
 }
 
 // ----------------------------------------------------------------------------- the product
@@ -447,6 +443,7 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, in
     a.ipw = std::min(ipw, 4 * nrhs);
     a.nch = (4 * nrhs + a.ipw - 1) / a.ipw;
     a.nblk = (long long)a.tiles_x * (p->ny + 1) * a.nch;
+    a.live = p->live;
     int G = 0, P = 0;
     zmr_split(n, &G, &P);
     zmr_launch<T>(n, (unsigned)xcd_grid(a.nblk), 3 * tw * zmr_tpc(G, P), zmr_lds<T>(G, P, tw, p->nz),
@@ -466,6 +463,7 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, in
   a.twsh = ilog2_exact(tw);
   a.ntiles = (a.plane + tw - 1) / tw;
   a.nrhs = nrhs;
+  a.live = p->live;
   const int threads = 3 * tw * tpc_of(n);
   const size_t lds = (size_t)lds_elems(n, 3 * tw + 1) * sizeof(cplx<T>);
   with_static_n(n, [&](auto nf) {
@@ -647,7 +645,6 @@ void apply_operator(dda_problem *p, int nrhs, const double2 *x, double2 *y, int 
 }
 
 void apply_imag_conv(dda_problem *p, int nrhs, const double2 *x, double2 *y) {
-  ensure_imag_spectrum(p);
   op_passes<double>(p, nrhs, x, y, p->khatI64, nullptr, 1);
 }
 

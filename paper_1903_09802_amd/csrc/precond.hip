@@ -463,7 +463,8 @@ __global__ void k_diag_delta(const double2 *eps, const int *vox, long long nocc,
 // t = s_r x - Delta z on compact [nrhs][3][nocc] vectors, s_r = xscale[r * kMaxM] (or 1);
 // blockIdx.y = 3 r + component
 __global__ void k_diag_resid(const double2 *x, const double2 *z, const double2 *delta,
-                             double2 *t, long long nocc, const double *xscale) {
+                             double2 *t, long long nocc, const double *xscale, const int *live) {
+  if (live && live[0] == 0) return;
   const long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (c >= nocc) return;
   const long long i = blockIdx.y * nocc + c;
@@ -748,8 +749,10 @@ template <typename T, int NV>
 __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__restrict__ binv,
                                                  int nx, int ny, int nzw, int z0, int nz, int umx,
                                                  int hh, int n2,
-                                                 int nrhs, int rc, long long nchunks, long long U) {
+                                                 int nrhs, int rc, long long nchunks, long long U,
+                                                 const int *live) {
   using V = cplx<T>;
+  if (live && live[0] == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *Ub = reinterpret_cast<V *>(smem_raw);  // [2][nv][n2]
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -971,10 +974,12 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
                                                              int nx, int ny, int nzw, int z0, int nz,
                                                              int umx, int hh,
                                                              int n2, int ntr, int nrhs, int rc,
-                                                             long long nchunks, long long U) {
+                                                             long long nchunks, long long U,
+                                                             const int *live) {
   using V = cplx<T>;
   using v4 = typename Mfma<T>::v4;
   constexpr int NV = 8 * NCB;
+  if (live && live[0] == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *Ub = reinterpret_cast<V *>(smem_raw);  // [2][NV][n2p], zero beyond nv and n2
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -1045,124 +1050,6 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
   }
 }
 
-// The same symmetric block product with every stored tile read from memory once.  One wave
-// per tile row I (ntr <= NWMAX); the row pairs {I, J} of the step schedule above are shared
-// out so that each stored tile has one owner wave: J = I - o (mod ntr) for o = 0 .. ntr / 2,
-// o = ntr / 2 (even ntr) only for I >= ntr / 2.  The owner adds block (I, J) U_J to its own
-// row in registers and block (J, I) U_I, the same tile read transposed right after (a cache
-// hit), to row J's partner sums in LDS (LDS atomics: the waves do not run in step).  After
-// each half a barrier makes the partner sums complete; each wave adds its row's sums.  One
-// column block (rc <= 2 right-hand sides).
-template <typename T, int NWMAX>
-__global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_own(cplx<T> *W, const cplx<T> *__restrict__ pk,
-                                                            int nx, int ny, int nzw, int z0, int nz,
-                                                            int umx, int hh,
-                                                            int n2, int ntr, int nrhs, int rc,
-                                                            long long nchunks, long long U) {
-  using V = cplx<T>;
-  using v4 = typename Mfma<T>::v4;
-  constexpr int NCB = 1, NV = 8;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  V *Ub = reinterpret_cast<V *>(smem_raw);  // [2][NV][n2p], zero beyond nv and n2
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const long long blk = xcd_remap(blockIdx.x, U * nchunks);
-  if (blk >= U * nchunks) return;
-  const long long u = blk / nchunks;
-  const int r0 = (int)(blk - u * nchunks) * rc;
-  const int nr = min(rc, nrhs - r0);
-  const GemvMode g = gemv_mode(u, umx, nx, ny, nzw, z0, nz, hh, n2, nr, r0);
-  const int n2p = 16 * ntr;
-  gemv_gather<T, NV>(Ub, W, g, n2p, tid, nt);
-  T *Yp = reinterpret_cast<T *>(Ub + 2 * NV * n2p);  // [n2p][16] partner sums of one half
-  for (int e = tid; e < 16 * n2p; e += nt) Yp[e] = (T)0;
-  __syncthreads();
-  const int lane = tid & 63, I = tid >> 6;
-  const int r = lane & 15, q = lane >> 4;  // A: row r, k-slot q; B and D: column r
-  const int vj = r & 7;
-  const bool im = r >= 8;
-  const long long tiles = (long long)ntr * (ntr + 1) / 2;
-  const int nown = (ntr - 1) / 2 + 1 + ((ntr % 2 == 0 && 2 * I >= ntr) ? 1 : 0);
-  v4 c[2][NCB];
-#pragma unroll
-  for (int hf = 0; hf < 2; ++hf) {
-    const V *P = pk + (u * 2 + hf) * tiles * 256;
-    const V *Uh = Ub + (hf * NV + vj) * n2p + q;
-    // A fragment of block (X, Y) of the symmetric matrix: stored tile (max, min), read as
-    // stored or transposed
-    auto frag = [&](int X, int Y, V (&a)[4]) {
-      const long long t = Y <= X ? (long long)X * (X + 1) / 2 + Y : (long long)Y * (Y + 1) / 2 + X;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) a[k] = P[t * 256 + (Y <= X ? lane + 64 * k : tile_pos(4 * k + q, r))];
-    };
-    // acc + block A times the column block col of U
-    auto mul = [&](v4 acc, const V (&a)[4], int col) {
-      V x[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) x[k] = Uh[16 * col + 4 * k];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        acc = Mfma<T>::mma(a[k].x, im ? x[k].y : x[k].x, acc);
-        acc = Mfma<T>::mma(a[k].y, im ? x[k].x : -x[k].y, acc);
-      }
-      return acc;
-    };
-    // own and partner fragments, NS - 1 owned tiles ahead (FP64: one, within the registers)
-    constexpr int NS = sizeof(T) == 8 ? 2 : 3;
-    V fa[NS][4], fb[NS][4];
-    auto load = [&](int o, V (&a)[4], V (&b)[4]) {
-      const int J = (I - o + ntr) % ntr;
-      frag(I, J, a);
-      if (o != 0) frag(J, I, b);
-    };
-    v4 acc = v4{0, 0, 0, 0};
-#pragma unroll
-    for (int b = 0; b < NS - 1; ++b)
-      if (b < nown) load(b, fa[b], fb[b]);
-    for (int o = 0; o < nown; o += NS) {
-#pragma unroll
-      for (int b = 0; b < NS; ++b) {
-        if (o + b + NS - 1 < nown) load(o + b + NS - 1, fa[(b + NS - 1) % NS], fb[(b + NS - 1) % NS]);
-        if (o + b < nown) {
-          const int J = (I - (o + b) + ntr) % ntr;
-          acc = mul(acc, fa[b], J);
-          if (o + b != 0) {
-            const v4 pj = mul(v4{0, 0, 0, 0}, fb[b], I);
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-              __hip_atomic_fetch_add(&Yp[(16 * J + Mfma<T>::row(q, m)) * 16 + r], pj[m],
-                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          }
-        }
-      }
-    }
-    __syncthreads();  // every partner sum of this half is in Yp
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      T *e = &Yp[(16 * I + Mfma<T>::row(q, m)) * 16 + r];
-      acc[m] += *e;
-      *e = (T)0;
-    }
-    c[hf][0] = acc;
-    __syncthreads();  // Yp is clear before the next half adds to it
-  }
-  // D[i][j] sits in column lane j, item m, row Mfma<T>::row(q, m): lane j < 8 holds Re of
-  // vector j, lane j + 8 its Im.  Unfold the halves, flip, scatter.
-#pragma unroll
-  for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-      gemv_store<T>(W, g, c[0][cb][m], c[1][cb][m], 16 * I + Mfma<T>::row(q, m), 8 * cb + vj, im);
-}
-
-// DDA_GEMV_SINGLE_READ=1 (read at every application) selects the single-read block product
-// where it applies (one column block, ntr <= 12).  It fetches the model's bytes but, with one
-// 12-wave workgroup per compute unit and two barriers per half, waits longer on memory than
-// the paired-read kernel's extra L2 misses cost, so it is off by default.
-static bool gemv_own_enabled() {
-  const char *e = getenv("DDA_GEMV_SINGLE_READ");
-  return e && e[0] == '1';
-}
-
 template <typename T>
 static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, const cplx<T> *binv,
                      const double *xscale) {
@@ -1212,17 +1099,15 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
       const int threads = 64 * std::min(12, p->ntr);  // one wave per tile row up to 12 rows
       const dim3 grid((unsigned)xcd_grid(U * nchunks));
       KTimer t(&p->prof, p->st, nm, bytes);
-      // one column block with one wave per tile row: each stored tile is read once
-      const bool own = ncb == 1 && p->ntr <= 12 && gemv_own_enabled();
-      auto fn = own        ? k_pc_gemv_own<T, 12>
-                : ncb == 1 ? k_pc_gemv_mfma<T, 12, 1>
+      {
+      auto fn = ncb == 1 ? k_pc_gemv_mfma<T, 12, 1>
                 : ncb == 2 ? k_pc_gemv_mfma<T, 12, 2>
                            : k_pc_gemv_mfma<T, 12, sizeof(T) == 8 ? 2 : 4>;
-      const size_t lds_k = own ? lds + (size_t)16 * n2p * sizeof(T) : lds;
-      set_lds_limit((const void *)fn, lds_k);
-      hipLaunchKernelGGL(fn, grid, dim3(threads), lds_k, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
-                         p->umx, p->hh, p->n2, p->ntr, nrhs, rc, nchunks, U);
+      set_lds_limit((const void *)fn, lds);
+      hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
+                         p->umx, p->hh, p->n2, p->ntr, nrhs, rc, nchunks, U, p->live);
       HIPCHK(hipGetLastError());
+      }
     } else {
     // right-hand sides per workgroup: up to 4 mode copies x rc vectors <= 16, LDS <= 64 KB
     int rc = std::max(1, std::min(4, nrhs));
@@ -1239,17 +1124,17 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
       auto fn = k_pc_gemv<T, 4>;
       set_lds_limit((const void *)fn, lds);
       hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
-                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U);
+                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U, p->live);
     } else if (nvmax <= 8) {
       auto fn = k_pc_gemv<T, 8>;
       set_lds_limit((const void *)fn, lds);
       hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
-                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U);
+                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U, p->live);
     } else {
       auto fn = k_pc_gemv<T, 16>;
       set_lds_limit((const void *)fn, lds);
       hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
-                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U);
+                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U, p->live);
     }
     HIPCHK(hipGetLastError());
     }
@@ -1285,8 +1170,9 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
 template <typename T, int NV>
 __global__ void __launch_bounds__(256) k_pc1_gemv(cplx<T> *W, const cplx<T> *__restrict__ binv,
                                                   int nx, int ny, int nz, int umx, int n1, int nrhs,
-                                                  int rc, long long nchunks) {
+                                                  int rc, long long nchunks, const int *live) {
   using V = cplx<T>;
+  if (live && live[0] == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *Ub = reinterpret_cast<V *>(smem_raw);  // [nv][n1]
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -1384,7 +1270,7 @@ static void pc_apply1(dda_problem *p, int nrhs, const double2 *x, double2 *y, co
     auto fn = k_pc1_gemv<T, 4>;
     set_lds_limit((const void *)fn, lds);
     hipLaunchKernelGGL(fn, dim3((unsigned)xcd_grid((long long)p->umx * nchunks)), dim3(threads), lds,
-                       p->st, W, binv, nx, ny, nz, p->umx, n1, nrhs, rc, nchunks);
+                       p->st, W, binv, nx, ny, nz, p->umx, n1, nrhs, rc, nchunks, p->live);
     HIPCHK(hipGetLastError());
   }
   {
@@ -1431,7 +1317,7 @@ void apply_precond(dda_problem *p, int nrhs, const double2 *x, double2 *y, int f
     {
       KTimer t(&p->prof, p->st, "pc_diag_resid", (48.0 * 3 * nrhs + 16.0) * p->nocc);
       hipLaunchKernelGGL(k_diag_resid, dim3(nblk(p->nocc, 256), 3 * nrhs), dim3(256), 0, p->st, x,
-                         z, p->pdelta, p->pdt, p->nocc, xscale);
+                         z, p->pdelta, p->pdt, p->nocc, xscale, p->live);
       HIPCHK(hipGetLastError());
     }
     apply_circulant(p, nrhs, p->pdt, i == k ? y : z, fp32, nullptr);

@@ -174,6 +174,7 @@ struct ZRArgs {
   int ipw;            // items per workgroup (>= 1)
   int nch;            // workgroups per tile, ceil(4 nrhs / ipw)
   long long nblk;     // (ny + 1) tiles_x nch, chunk fastest
+  const int *live;    // null, or a device flag: 0 makes the launch a no-op
 };
 
 template <typename T, int G, int P>
@@ -185,6 +186,7 @@ __global__ void __launch_bounds__(256) k_zpass_mr(cplx<T> *data, const cplx<T> *
   static_assert(G % 2 == 0 && P % 2 == 0, "G and P must be even");
   static_assert(NC > 1 || P <= G, "P must be at most G or a multiple of it");
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (a.live && a.live[0] == 0) return;
   const long long blk = xcd_remap(blockIdx.x, a.nblk);
   if (blk >= a.nblk) return;
   const int ch = (int)(blk % a.nch);

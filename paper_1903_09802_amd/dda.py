@@ -20,7 +20,8 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "ED
 
 # every symbol declared in include/dda.h
 EXPORTS = (
-    "dda_default_options", "dda_last_error", "dda_create", "dda_build_preconditioner",
+    "dda_default_options", "dda_last_error", "dda_lattice_factor", "dda_create",
+    "dda_build_preconditioner",
     "dda_solve", "dda_apply_operator", "dda_apply_preconditioner", "dda_cross_sections",
     "dda_grad_cext", "dda_destroy", "dda_profile_enable", "dda_profile_count", "dda_profile_get",
 )
@@ -35,19 +36,23 @@ class DDAError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int),
-                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
                 ("max_rhs", ctypes.c_int), ("solver", ctypes.c_int), ("dense_axis", ctypes.c_int),
                 ("left_precond", ctypes.c_int), ("alpha_avg", ctypes.c_int),
-                ("diag_steps", ctypes.c_int)]
+                ("diag_steps", ctypes.c_int), ("graph", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("cycles", ctypes.c_int), ("refinements", ctypes.c_int),
                 ("converged", ctypes.c_int), ("rel_residual", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("t_setup", ctypes.c_double), ("t_build", ctypes.c_double),
+                ("t_solve", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double)),
+                ("history_cap", ctypes.c_int), ("history_len", ctypes.c_int)]
 
-    def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+    def as_dict(self, history=None):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("history", "history_cap")}
+        if history is not None:
+            d["history"] = history[:self.history_len].copy()
+        return d
 
 
 _lib = None
@@ -67,6 +72,8 @@ def load(path: str = LIB_PATH):
     L.dda_default_options.restype = None
     L.dda_last_error.argtypes = []
     L.dda_last_error.restype = ctypes.c_char_p
+    L.dda_lattice_factor.argtypes = [i, dp, dp, dp, dp]
+    L.dda_lattice_factor.restype = ip
     L.dda_create.argtypes = [i, i, i, vp, vp, ctypes.c_double, ctypes.c_double,
                              ctypes.POINTER(Options), vp, ctypes.POINTER(vp)]
     L.dda_create.restype = ip
@@ -119,6 +126,29 @@ def _waves(dirs, pols):
     return d, p
 
 
+def lattice_factor(dirs, pols):
+    """Per-wave LDR lattice factors S (Sec. 2.1) and their mean, from ``dda_lattice_factor``."""
+    d, p = _waves(dirs, pols)
+    S = np.zeros(d.shape[0])
+    mean = np.zeros(1)
+    _check(load().dda_lattice_factor(d.shape[0], _dptr(d), _dptr(p), _dptr(S), _dptr(mean)), False)
+    return S, float(mean[0])
+
+
+def _stats_array(n, history_cap):
+    st = (Stats * n)()
+    bufs = []
+    for r in range(n):
+        if history_cap > 0:
+            h = np.zeros(history_cap)
+            st[r].history = _dptr(h)
+            st[r].history_cap = history_cap
+            bufs.append(h)
+        else:
+            bufs.append(None)
+    return st, bufs
+
+
 def _dev(t, dtype):
     import torch
     if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
@@ -130,8 +160,8 @@ class Problem:
     """One voxelised scatterer on the GPU (handle of ``dda_create``)."""
 
     def __init__(self, mask, eps, k: float, d: float, *, restart=30, max_iter=2000, tol=1e-5,
-                 precond=2, precision=0, inner_tol=1e-4, max_refine=30, max_rhs=1, solver="gmres",
-                 dense_axis=2, precond_side="right", alpha_avg="mean_eps", diag_steps=0,
+                 precond=2, precision=0, max_rhs=1, solver="gmres", dense_axis=2,
+                 precond_side="right", alpha_avg="mean_eps", diag_steps=0, graph=True,
                  stream=None):
         import torch
         L = load()
@@ -142,8 +172,8 @@ class Problem:
         self.k, self.d = float(k), float(d)
         o = default_options()
         o.restart, o.max_iter, o.tol = restart, max_iter, tol
-        o.precond, o.precision, o.inner_tol = precond, precision, inner_tol
-        o.max_refine, o.max_rhs = max_refine, max_rhs
+        o.precond, o.precision, o.max_rhs = precond, precision, max_rhs
+        o.graph = int(bool(graph))
         solvers = {"gmres": 0, "bicgstab": 1}
         if solver not in solvers:
             raise ValueError(f"solver must be one of {sorted(solvers)}")
@@ -191,18 +221,20 @@ class Problem:
     def field_shape(self, nrhs):
         return (nrhs, 3) + self.shape
 
-    def solve(self, dirs, pols, x0=None, return_c=True, xsec=True):
+    def solve(self, dirs, pols, x0=None, return_c=True, xsec=True, history=False):
+        """Solve for the waves (dirs, pols); with history=True each stats entry carries the
+        residual after every iteration (``history``)."""
         import torch
         d, p = _waves(dirs, pols)
         n = d.shape[0]
         c = torch.empty(self.field_shape(n), dtype=torch.complex128, device="cuda") if return_c else None
         ce, ca, cs = (np.zeros(n) for _ in range(3))
-        st = (Stats * n)()
+        st, bufs = _stats_array(n, self.opts.max_iter if history else 0)
         x0p = _dev(x0, torch.complex128) if x0 is not None else None
         status = _check(load().dda_solve(
             self.h, n, _dptr(d), _dptr(p), x0p, _dev(c, torch.complex128) if c is not None else None,
             _dptr(ce) if xsec else None, _dptr(ca) if xsec else None, _dptr(cs) if xsec else None, st))
-        out = dict(status=status, stats=[s.as_dict() for s in st])
+        out = dict(status=status, stats=[s.as_dict(b) for s, b in zip(st, bufs)])
         if return_c:
             out["c"] = c
         if xsec:
@@ -239,7 +271,7 @@ class Problem:
         d, p = _waves(direction, polarisation)
         g = torch.empty(self.shape, dtype=torch.complex128, device="cuda")
         ce = np.zeros(1)
-        st = (Stats * 2)()
+        st, _ = _stats_array(2, 0)
         status = _check(load().dda_grad_cext(self.h, _dptr(d), _dptr(p), _dev(g, torch.complex128),
                                              _dptr(ce), st))
         return g, float(ce[0]), [s.as_dict() for s in st], status

@@ -38,9 +38,58 @@ def test_default_options(lib):
     from paper_1903_09802_amd import dda
     o = dda.default_options()
     assert (o.restart, o.max_iter, o.tol, o.precond, o.precision, o.max_rhs) == (30, 2000, 1e-5, 2, 0, 1)
-    assert abs(o.inner_tol - 1e-4) < 1e-18 and o.max_refine == 30
     assert o.solver == 0 and o.dense_axis == 2 and o.left_precond == 0 and o.alpha_avg == 0
-    assert o.diag_steps == 0
+    assert o.diag_steps == 0 and o.graph == 1
+
+
+def _struct_fields(name):
+    """Field names of ``typedef struct { ... } name;`` in the header, in declaration order."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", txt).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            out += [v.strip().lstrip("*") for v in re.sub(r"^[a-z_0-9 ]+?\s(?=\*?[a-z_]+(,|$))", "",
+                                                           decl).split(",")]
+    return out
+
+
+def test_binding_structs_mirror_the_header():
+    """The ctypes layouts of dda_options and dda_stats follow the header field by field."""
+    from paper_1903_09802_amd import dda
+    assert _struct_fields("dda_options") == [f for f, _ in dda.Options._fields_]
+    assert _struct_fields("dda_stats") == [f for f, _ in dda.Stats._fields_]
+    assert "t_setup" in _struct_fields("dda_stats") and "history" in _struct_fields("dda_stats")
+
+
+def test_lattice_factor(lib):
+    """S = sum_j (d_j e_j)^2 per wave (Sec. 2.1) and the batch mean, computed by the library on
+    the host; malformed waves are rejected."""
+    import numpy as np
+    from paper_1903_09802_amd import dda
+    d = np.array([[0, 0, 1.0], [1 / np.sqrt(2), 0, 1 / np.sqrt(2)], [1.0, 0, 0]])
+    e = np.array([[1.0, 0, 0], [1 / np.sqrt(2), 0, -1 / np.sqrt(2)], [0, 0.6, 0.8]])
+    S, mean = dda.lattice_factor(d, e)
+    ref = np.sum((d * e) ** 2, axis=1)
+    assert np.allclose(S, ref, atol=1e-15) and abs(mean - ref.mean()) < 1e-15
+    assert abs(S[1] - 0.5) < 1e-15 and S[0] == 0.0
+    with pytest.raises(dda.DDAError) as ei:
+        dda.lattice_factor([[0, 0, 1.0]], [[0, 0.6, 0.8]])  # not orthogonal
+    assert ei.value.status == -1
+    assert lib.dda_lattice_factor(0, None, None, None, None) == -1
+
+
+@pytest.mark.parametrize("graph", [-1, 2])
+def test_create_rejects_bad_graph(lib, graph):
+    from paper_1903_09802_amd import dda
+    o = dda.default_options()
+    o.graph = graph
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: option validation fails first
+    st = lib.dda_create(4, 4, 4, dummy, dummy, 1.0, 0.1, ctypes.byref(o), None, ctypes.byref(h))
+    assert st == -1 and h.value is None
+    assert b"graph" in lib.dda_last_error()
 
 
 @pytest.mark.parametrize("precond", [-1, 3])

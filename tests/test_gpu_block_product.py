@@ -1,9 +1,6 @@
-"""The block product of the 2-level preconditioner with every stored tile read once (one owner
-wave per stored tile, the partner row's share added through LDS; opt-in through
-DDA_GEMV_SINGLE_READ=1) against the default paired-read kernel and the oracle, over tile-row
-counts 1 .. 12, odd and even, both precisions."""
-
-import os
+"""The packed symmetric block product of the 2-level preconditioner (even dense extents) against
+the oracle, over tile-row counts ntr = ceil(3 nz / 32) of 1 .. 12, odd and even, one and two
+right-hand sides, both precisions."""
 
 import numpy as np
 import pytest
@@ -22,32 +19,16 @@ def _full_box(shape, seed):
     return s
 
 
-def _apply(s, x, fp32, paired):
-    old = os.environ.get("DDA_GEMV_SINGLE_READ")
-    os.environ["DDA_GEMV_SINGLE_READ"] = "0" if paired else "1"
-    try:
-        with make_problem(s, precond=2, max_rhs=x.shape[0], precision=fp32) as prob:
-            prob.build_preconditioner(0.1)
-            return prob.apply_preconditioner(to_dev(x), fp32=bool(fp32)).cpu().numpy()
-    finally:
-        if old is None:
-            del os.environ["DDA_GEMV_SINGLE_READ"]
-        else:
-            os.environ["DDA_GEMV_SINGLE_READ"] = old
-
-
 # nz even (packed symmetric tiles); tile rows ntr = ceil(3 nz / 32): 1, 2, 3, 7, 12
 @pytest.mark.parametrize("shape", [(2, 6, 5), (12, 4, 6), (24, 4, 3), (72, 3, 4), (128, 2, 3)])
 @pytest.mark.parametrize("nrhs,fp32", [(1, 0), (2, 0), (2, 1)])
-def test_single_read_block_product(shape, nrhs, fp32):
+def test_block_product_tile_rows(shape, nrhs, fp32):
     s = _full_box(shape, 300 + shape[0])
     x = rand_field(shape, nrhs, 301 + shape[0])
-    z1 = _apply(s, x, fp32, paired=False)
-    z2 = _apply(s, x, fp32, paired=True)
+    with make_problem(s, precond=2, max_rhs=nrhs, precision=fp32) as prob:
+        prob.build_preconditioner(0.1)
+        z = prob.apply_preconditioner(to_dev(x), fp32=bool(fp32)).cpu().numpy()
     pc = oracle_precond(s, 0.1)
     tol = 1e-5 if fp32 else 1e-10
     for r in range(nrhs):
-        ref = pc(x[r])
-        assert rel_err(z1[r], ref) < tol, r
-        assert rel_err(z2[r], ref) < tol, r
-    assert rel_err(z1, z2) < (1e-5 if fp32 else 1e-12)
+        assert rel_err(z[r], pc(x[r])) < tol, r
