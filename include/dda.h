@@ -256,6 +256,24 @@ dda_status dda_cross_sections(dda_problem *p, int nrhs, const double *dir_host,
                               double *cabs, double *csca);
 
 /*
+ * For callers that cannot allocate memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid allocation): C_ext and C_abs as dda_cross_sections computes them,
+ * with no allocation of any kind, device or host, in the call.  Its only scratch (per-block
+ * partial sums and the totals) lives in one static device array of 256.5 KiB per GPU, held
+ * until the process ends; its address is looked up once per device by dda_create.
+ *  nrhs: 1 .. min(max_rhs, 16) (the array holds 16 waves; larger nrhs is EINVAL).
+ *  dir_host, pol_host: double [nrhs][3] as in dda_solve.  c_dev: c128 [nrhs][3][nz][ny][nx]
+ *  (read at occupied voxels).  cext, cabs: optional host double [nrhs].
+ * The handle's device must be current (EDEVICE otherwise).  Calls on one GPU share the array:
+ * calls that overlap in time on one GPU (other streams, other threads) race; sequential calls
+ * need nothing cleared, as every call overwrites all of the array it reads.
+ * Errors: EINVAL, EDEVICE, ESTATE (array address not resolved on this device).
+ */
+dda_status dda_cross_sections_noalloc(dda_problem *p, int nrhs, const double *dir_host,
+                                      const double *pol_host, const double *c_dev, double *cext,
+                                      double *cabs);
+
+/*
  * Gradient of C_ext with respect to the per-voxel permittivity, by one forward
  * and one adjoint solve with the same operator and preconditioner (the
  * matrix is complex symmetric, Sec. 2.2, so the adjoint system is A lambda =

@@ -186,6 +186,7 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
       int dev = 0;
       HIPCHK(hipGetDevice(&dev));
       p->dev = dev;
+      HIPCHK(noalloc_scratch_init(dev));
       hipDeviceProp_t prop;
       HIPCHK(hipGetDeviceProperties(&prop, dev));
       p->lds_max = prop.sharedMemPerBlock > 0 ? (size_t)prop.sharedMemPerBlock : 65536;

@@ -408,4 +408,9 @@ void grad_kernel(dda_problem *p, const double2 *c, const double2 *lam, double S,
 // reductions (krylov.hip): per-RHS sums of n-length arrays
 int reduce_blocks(long long n);
 
+// xsec.hip: waves per call of dda_cross_sections_noalloc, and the one-time lookup (per device,
+// with it current) of the device address of that call's static scratch array
+constexpr int kNoallocMaxRhs = 16;
+hipError_t noalloc_scratch_init(int dev);
+
 }  // namespace dda

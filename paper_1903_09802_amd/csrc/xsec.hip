@@ -118,3 +118,168 @@ void grad_kernel(dda_problem *p, const double2 *c, const double2 *lam, double S,
 }
 
 }  // namespace dda
+
+// ----------------------------------------------------------------------------- allocation-free
+
+// dda_cross_sections_noalloc: C_ext and C_abs with every scratch byte in one static device
+// array per GPU (no allocation on the device or the host, no exception).  The array holds the
+// per-block partial sums [nrhs][kXsBlocks][2] and the scaled totals [2][nrhs]; every call
+// overwrites all of what it reads, so nothing is cleared between calls, and calls that overlap
+// on one GPU (other streams or threads) race on it.
+namespace dda {
+
+constexpr int kXsBlocks = 512;
+constexpr size_t kScratchDoubles = (size_t)kNoallocMaxRhs * kXsBlocks * 2 + 2 * kNoallocMaxRhs;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// The array's device address, one per GPU, resolved once with that GPU current.
+static constexpr int kMaxDevices = 64;
+static double *g_scratch_addr[kMaxDevices] = {nullptr};
+
+hipError_t noalloc_scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (__atomic_load_n(&g_scratch_addr[dev], __ATOMIC_ACQUIRE)) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  __atomic_store_n(&g_scratch_addr[dev], static_cast<double *>(ptr), __ATOMIC_RELEASE);
+  return hipSuccess;
+}
+
+struct XsWaves {
+  int nrhs;
+  double dir[kNoallocMaxRhs][3], pol[kNoallocMaxRhs][3], S[kNoallocMaxRhs];  // library frame
+};
+
+// Per block: sum over its compact entries q of Im(conj(E) . c) and |c|^2 (-Im alpha^{-1} -
+// (2/3)(k d)^3), with c read from the caller's box layout through the frame, E^inc and 1/alpha
+// computed in place.  part[(r * kXsBlocks + block) * 2 + {0, 1}].
+__global__ void __launch_bounds__(256) k_xsec_box(const double2 *cbox, const int *vox,
+                                                  const double2 *eps, long long N, long long nocc,
+                                                  Frame fr, double k, double d, XsWaves wv,
+                                                  double *part) {
+  const int r = blockIdx.y;
+  __shared__ double sh[2][256];
+  const double kd = k * d, rr = (2.0 / 3.0) * kd * kd * kd;
+  double s0 = 0.0, s1 = 0.0;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < nocc;
+       q += (long long)gridDim.x * blockDim.x) {
+    const long long v = vox[q];
+    const int ix = (int)(v % fr.nx), iy = (int)((v / fr.nx) % fr.ny),
+              iz = (int)(v / ((long long)fr.nx * fr.ny));
+    const double x = (ix - 0.5 * (fr.nx - 1)) * d, y = (iy - 0.5 * (fr.ny - 1)) * d,
+                 z = (iz - 0.5 * (fr.nz - 1)) * d;
+    double sn, cs;
+    sincos(k * (wv.dir[r][0] * x + wv.dir[r][1] * y + wv.dir[r][2] * z), &sn, &cs);
+    const long long e = fr.to_ext(v);
+    double c2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double2 cv = cbox[((long long)r * 3 + fr.comp_ext(a)) * N + e];
+      const double2 ev = make_double2(wv.pol[r][a] * cs, wv.pol[r][a] * sn);
+      s0 += ev.x * cv.y - ev.y * cv.x;
+      c2 += cv.x * cv.x + cv.y * cv.y;
+    }
+    s1 += c2 * (-ldr_alpha_inv(eps[v], kd, wv.S[r]).y - rr);
+  }
+  sh[0][threadIdx.x] = s0;
+  sh[1][threadIdx.x] = s1;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[((long long)r * kXsBlocks + blockIdx.x) * 2 + 0] = sh[0][0];
+    part[((long long)r * kXsBlocks + blockIdx.x) * 2 + 1] = sh[1][0];
+  }
+}
+
+// tot[q * nrhs + r] = pref * sum over the blocks of part (block order fixed); one block per r.
+__global__ void __launch_bounds__(256) k_xsec_total(const double *part, double pref, int nrhs,
+                                                    double *tot) {
+  const int r = blockIdx.x;
+  __shared__ double sh[2][256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < kXsBlocks; i += blockDim.x) {
+    a += part[((long long)r * kXsBlocks + i) * 2 + 0];
+    b += part[((long long)r * kXsBlocks + i) * 2 + 1];
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    tot[r] = pref * sh[0][0];
+    tot[nrhs + r] = pref * sh[1][0];
+  }
+}
+
+}  // namespace dda
+
+extern "C" dda_status dda_cross_sections_noalloc(dda_problem *p, int nrhs, const double *dir_host,
+                                                 const double *pol_host, const double *c_dev,
+                                                 double *cext, double *cabs) {
+  using namespace dda;
+  auto fail = [](dda_status st, const char *msg) {
+    set_error("%s", msg);
+    return st;
+  };
+  set_error("%s", "");
+  if (!p) return fail(DDA_EINVAL, "problem is NULL");
+  if (nrhs < 1 || nrhs > kNoallocMaxRhs || nrhs > p->R)
+    return fail(DDA_EINVAL, "dda_cross_sections_noalloc: nrhs must be in [1, min(max_rhs, 16)] "
+                            "(its static scratch holds 16 waves)");
+  if (!c_dev || !dir_host || !pol_host) return fail(DDA_EINVAL, "c_dev, dir_host and pol_host are required");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->dev)
+    return fail(DDA_EDEVICE, "dda_cross_sections_noalloc: the handle's device is not current");
+  double *base = dev < kMaxDevices ? __atomic_load_n(&g_scratch_addr[dev], __ATOMIC_ACQUIRE) : nullptr;
+  if (!base) return fail(DDA_ESTATE, "static scratch address not resolved on this device");
+  XsWaves wv;
+  wv.nrhs = nrhs;
+  for (int r = 0; r < nrhs; ++r) {
+    const double *dv = dir_host + 3 * r, *ev = pol_host + 3 * r;
+    const double nd = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    const double ne = std::sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
+    const double de = dv[0] * ev[0] + dv[1] * ev[1] + dv[2] * ev[2];
+    if (!(std::fabs(nd - 1.0) <= 1e-9 && std::fabs(ne - 1.0) <= 1e-9 && std::fabs(de) <= 1e-9))
+      return fail(DDA_EINVAL, "direction and polarisation must be orthogonal unit vectors");
+    double S = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      S += (dv[a] * ev[a]) * (dv[a] * ev[a]);
+      wv.dir[r][a] = dv[p->fr.comp_ext(a)];
+      wv.pol[r][a] = ev[p->fr.comp_ext(a)];
+    }
+    wv.S[r] = S;
+  }
+  double *part = base;
+  double *tot = base + (size_t)kNoallocMaxRhs * kXsBlocks * 2;
+  hipLaunchKernelGGL(k_xsec_box, dim3(kXsBlocks, nrhs), dim3(256), 0, p->st,
+                     reinterpret_cast<const double2 *>(c_dev), p->vox, p->eps, p->N, p->nocc,
+                     p->fr, p->k, p->d, wv, part);
+  const double pref = 4.0 * DDA_PI * p->k * p->d * p->d * p->d;
+  hipLaunchKernelGGL(k_xsec_total, dim3(nrhs), dim3(256), 0, p->st, part, pref, nrhs, tot);
+  double host[2 * kNoallocMaxRhs];
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host, tot, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, p->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->st);
+  if (e != hipSuccess) {
+    set_error("dda_cross_sections_noalloc: %s", hipGetErrorString(e));
+    return DDA_EDEVICE;
+  }
+  for (int r = 0; r < nrhs; ++r) {
+    if (cext) cext[r] = host[r];
+    if (cabs) cabs[r] = host[nrhs + r];
+  }
+  return DDA_OK;
+}

@@ -23,6 +23,7 @@ EXPORTS = (
     "dda_default_options", "dda_last_error", "dda_lattice_factor", "dda_create",
     "dda_build_preconditioner",
     "dda_solve", "dda_apply_operator", "dda_apply_preconditioner", "dda_cross_sections",
+    "dda_cross_sections_noalloc",
     "dda_grad_cext", "dda_destroy", "dda_profile_enable", "dda_profile_count", "dda_profile_get",
 )
 
@@ -87,6 +88,8 @@ def load(path: str = LIB_PATH):
     L.dda_apply_preconditioner.restype = ip
     L.dda_cross_sections.argtypes = [vp, i, dp, dp, vp, dp, dp, dp]
     L.dda_cross_sections.restype = ip
+    L.dda_cross_sections_noalloc.argtypes = [vp, i, dp, dp, vp, dp, dp]
+    L.dda_cross_sections_noalloc.restype = ip
     L.dda_grad_cext.argtypes = [vp, dp, dp, vp, dp, ctypes.POINTER(Stats)]
     L.dda_grad_cext.restype = ip
     L.dda_destroy.argtypes = [vp]
@@ -265,6 +268,17 @@ class Problem:
         _check(load().dda_cross_sections(self.h, n, _dptr(d), _dptr(p), _dev(c, torch.complex128),
                                          _dptr(ce), _dptr(ca), _dptr(cs)), False)
         return ce, ca, cs
+
+    def cross_sections_noalloc(self, c, dirs, pols):
+        """C_ext and C_abs through the allocation-free entry point (at most 16 waves)."""
+        import torch
+        d, p = _waves(dirs, pols)
+        n = d.shape[0]
+        ce, ca = np.zeros(n), np.zeros(n)
+        _check(load().dda_cross_sections_noalloc(self.h, n, _dptr(d), _dptr(p),
+                                                 _dev(c, torch.complex128), _dptr(ce), _dptr(ca)),
+               False)
+        return ce, ca
 
     def grad_cext(self, direction, polarisation):
         import torch
