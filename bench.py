@@ -56,6 +56,16 @@ def operator_bytes(s, nrhs, elem=16):
     return nrhs * (p1 + p2 + p3 + p4 + p5) + e * 6 * (nx + 1) * (ny + 1) * (nz + 1)
 
 
+def gemv_algorithmic_bytes(s, nrhs, elem=16):
+    """Algorithmic bytes of one block-product launch: the symmetric-packed inverse blocks,
+    l m (3n)^2 s / 16 (n the dense level's extent: the occupied z layers), and the mode vectors
+    read and written once, 2 * 3N * s per right-hand side."""
+    nz, ny, nx = s.shape
+    occ = s.mask.reshape(nz, -1).any(axis=1)
+    n = int(occ.nonzero()[0][-1] - occ.nonzero()[0][0] + 1)
+    return nx * ny * (3 * n) ** 2 * elem / 16.0 + nrhs * 2.0 * 3 * nx * ny * nz * elem
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_hex128_fp64.txt")
 
 
@@ -91,86 +101,71 @@ def measured_traffic(kernel):
     return rows.get(kernel)
 
 
-def cpu_baseline(cfg, gpu_iters, restart=30):
-    """The oracle timed on a bounded sample of the same workload and scaled to one step.
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
 
-    Timed oracle calls: the kernel spectrum (scipy FFTs of the padded Green tensor), one
-    FFT matvec, the Chan generator with its 2-D FFTs, the inversion and product of a sample
-    of mode blocks, and a few iterations of the oracle's own GMRES loop (modified
-    Gram-Schmidt) on vectors of the workload's length.  The step estimate is setup + build
-    (all modes) + the GPU's iteration count of matvec, block products and Gram-Schmidt work
-    (each Gram-Schmidt cost at its cycle position j).
+
+def cpu_baseline(cfg, plain_iters, restart=30, k_it=8):
+    """The oracle timed on a fixed, bounded piece of the same workload, scaled to one solve.
+
+    Timed oracle calls, all with the real 128^3 operator: the kernel spectrum (scipy FFTs of
+    the padded Green tensor), one FFT matvec, and ``k_it`` iterations of the oracle's own
+    restarted GMRES (FFT matvec + modified Gram-Schmidt) on the first wave.  The oracle's
+    preconditioner would need all 16,384 dense 384^2 mode blocks (38.7 GB), so its step is
+    quoted for its plain GMRES to the same tolerance: the spectrum once, then per wave the
+    iteration count the GPU's plain solve took, each iteration one matvec plus the Gram-Schmidt
+    projections of its position in the cycle, and one residual matvec per cycle.
     """
     import numpy as np
     import scipy.fft as sfft
 
-    from oracle import circulant, fftmatvec, gmres, physics, system
+    from oracle import fftmatvec, gmres, physics, system
 
     cores = len(os.sched_getaffinity(0))
     s = cfg["scatterer"]
     dirs, pols = cfg["dirs"], cfg["pols"]
-    nrhs = len(dirs)
-    nz, ny, nx = s.shape
     with sfft.set_workers(cores):
         t0 = time.perf_counter()
         Kh = fftmatvec.kernel_padded_fft(s.shape, s.k, s.d, workers=cores)
         t_setup = time.perf_counter() - t0
+        S = physics.lattice_S(dirs[0], pols[0])
         b = system.incident_field(s.mask, s.k, s.d, dirs[0], pols[0])
+
+        def mv(x):
+            return fftmatvec.fft_matvec(x, s.mask, s.eps, s.k, s.d, S, Khat=Kh, workers=cores)
+
+        mv(b)  # first call: FFT plans
         t0 = time.perf_counter()
-        fftmatvec.fft_matvec(b, s.mask, s.eps, s.k, s.d, 0.0, Khat=Kh, workers=cores)
+        mv(b)
         t_mv = time.perf_counter() - t0
-        del Kh
         t0 = time.perf_counter()
-        c2 = circulant.two_level_generator(s.shape, s.k, s.d)
-        lam = np.fft.fft2(c2, axes=(2, 3))
-        t_gen = time.perf_counter() - t0
-        ati = complex(physics.alpha_inv(1.31 ** 2, s.k * s.d, 0.0))
-        iz = np.arange(nz)
-        ds = (iz[:, None] - iz[None, :]) + nz - 1
-        n_sample = 8
-        v = np.ones((3 * nz, 4 * nrhs), dtype=np.complex128)
-        t_inv = t_gemv = 0.0
-        for q in range(n_sample):
-            t0 = time.perf_counter()
-            B = np.empty((3 * nz, 3 * nz), dtype=np.complex128)
-            for a in range(3):
-                for bb in range(3):
-                    B[a * nz:(a + 1) * nz, bb * nz:(bb + 1) * nz] = -lam[circulant.FULL[a, bb]][ds, q % ny, q % nx]
-            B[np.arange(3 * nz), np.arange(3 * nz)] += ati
-            Bi = circulant.invert_blocks(B[None, None])[0, 0]
-            t1 = time.perf_counter()
-            Bi @ v[:, :nrhs]
-            t_inv += t1 - t0
-            t_gemv += time.perf_counter() - t1
-        t_inv /= n_sample
-        t_gemv /= n_sample
-        del lam, c2
-        # Gram-Schmidt: the oracle's GMRES loop for k_it iterations with a diagonal operator
-        n3 = 3 * s.mask.size
-        rng = np.random.default_rng(0)
-        diag = 1.0 + 0.9 * np.exp(2j * np.pi * rng.random(n3))
-        rhs = rng.standard_normal(n3) + 0j
-        k_it = 6
-        t0 = time.perf_counter()
-        for _ in range(k_it + 1):
-            diag * rhs
-        t_diag = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        gmres.gmres(lambda u: diag * u, rhs, restart=restart, tol=0.0, maxit=k_it)
-        t_gs = max(0.0, time.perf_counter() - t0 - t_diag)
-        per_pair = t_gs / (k_it * (k_it + 1) / 2)   # one projection (dot + update) per basis vector
-    modes = nx * ny
-    t_build = t_gen + modes * t_inv
-    t_pc = modes * t_gemv + 2 * t_mv / 3          # per-mode products + 2-D FFTs (about a third of a 3-D pair)
-    pairs = sum((it % restart) + 1 for it in range(gpu_iters))
-    est = t_setup + t_build + nrhs * (gpu_iters * (t_mv + t_pc) + pairs * per_pair)
-    sample = (f"oracle on {cores} host cores: kernel-spectrum setup, one FFT matvec, Chan generator "
-              f"+ 2-D FFTs, {n_sample} of {modes} mode blocks inverted and applied (scaled to all "
-              f"modes), {k_it} iterations of the oracle GMRES loop on {n3} unknowns (Gram-Schmidt "
-              f"cost per projection); extrapolated to {gpu_iters} preconditioned iterations x {nrhs} RHS")
-    return dict(value=est, unit="s", cores=cores, kind="oracle", sample=sample,
-                parts=dict(setup_s=t_setup, matvec_s=t_mv, gen_s=t_gen, inv_per_mode_s=t_inv,
-                           apply_per_iter_s=t_pc, gs_per_projection_s=per_pair))
+        gmres.gmres(mv, b, restart=restart, tol=0.0, maxit=k_it)
+        t_run = time.perf_counter() - t0
+    # k_it iterations hold k_it + 2 matvecs (initial and final residual) and k_it (k_it + 1) / 2
+    # projections (dot + update each)
+    t_proj = max(0.0, t_run - (k_it + 2) * t_mv) / (k_it * (k_it + 1) / 2)
+    per_wave = []
+    for it in plain_iters:
+        cycles = -(-it // restart)
+        proj = sum((j % restart) + 1 for j in range(it))
+        per_wave.append((it + cycles + 1) * t_mv + proj * t_proj)
+    est = t_setup + sum(per_wave)
+    sample = (f"oracle (numpy/scipy, complex128) on {cores} host cores ({cpu_model()}): kernel "
+              f"spectrum of the 128^3 prism, one FFT matvec and {k_it} iterations of the oracle's "
+              f"GMRES({restart}) with the real operator, timed; quoted for its plain GMRES solve of "
+              f"both waves to the same tolerance ({'+'.join(str(i) for i in plain_iters)} "
+              f"iterations, the GPU's plain counts), since its preconditioner needs 38.7 GB of blocks")
+    return dict(value=est, unit="s", cores=cores, kind="oracle", sample=sample, cpu=cpu_model(),
+                parts=dict(setup_s=t_setup, matvec_s=t_mv, gs_projection_s=t_proj,
+                           gmres_iteration_s=(t_run - 2 * t_mv) / k_it, timed_s=t_setup + 2 * t_mv + t_run))
 
 
 def main():
@@ -179,11 +174,15 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5", "plates", "axes", "levels", "alpha"])
+                    choices=["c1", "c2", "c3", "c4", "c5", "plates", "axes", "levels", "alpha"],
+                    help="c2 (default): the 128^3 step; c1: solve latency at 16^3; c3: FP32-refined vs "
+                         "FP64 at 256^3; c4: batched prisms; c5: adjoint gradient; the rest: studies")
     ap.add_argument("--c3-case", type=int, default=0, help="c3: 0 -> m = 1.31+0.001i, 1 -> m = 1.78")
     ap.add_argument("--c4-prisms", type=int, default=16)
     ap.add_argument("--c4-chunk", type=int, default=32, help="c4: right-hand sides per batched solve")
     ap.add_argument("--c4-precision", type=int, default=0, help="c4: 0 FP64, 1 FP32 inside FP64 refinement")
+    ap.add_argument("--c4-streams", type=int, default=1,
+                    help="c4: prisms in flight at once, each on its own stream (worker threads)")
     ap.add_argument("--plates", default="0.1:1.2",
                     help="plates: 'all', or L/a[:mu[:x,x,...]] (e.g. 0.1, 0.2:1.4, 0.1:2.0:10,20)")
     ap.add_argument("--plates-plain", action="store_true",
@@ -215,6 +214,8 @@ def main():
     from paper_1903_09802_amd.dda import Problem, load
 
     load()
+    if args.workload == "c1":
+        return bench_c1(args)
     if args.workload == "c3":
         return bench_c3(args)
     if args.workload == "c4":
@@ -281,10 +282,16 @@ def main():
                                                          "fft_strided_setup"))]
     dom_name, dom = hbm[0]
     avg_ms = dom["total_ms"] / max(1, dom["launches"])
-    achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
+    # algorithmic bytes per launch: the traffic model of each pass (the library's figures), except
+    # the block product, whose stored layout (full diagonal tiles, (l/2+1)(m/2+1) modes) holds more
+    # than the packed count l m (3n)^2 s / 16 it is judged by
+    alg = gemv_algorithmic_bytes(s, nrhs) if dom_name == "pc_gemv_f64" else dom["bytes"]
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom_name)
     roofline = dict(bound="hbm", kernel=dom_name, achieved=achieved, peak=HBM_PEAK_GBPS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBPS, traffic=measured_traffic(dom_name),
-                    avg_launch_ms=avg_ms, bytes_per_launch=dom["bytes"])
+                    frac=achieved / HBM_PEAK_GBPS, traffic=traffic, avg_launch_ms=avg_ms,
+                    algorithmic_bytes_per_launch=alg, layout_bytes_per_launch=dom["bytes"],
+                    traffic_over_algorithmic=(traffic / alg) if traffic else None)
     kernel_table = {k: dict(launches=v["launches"], avg_ms=v["total_ms"] / max(1, v["launches"]),
                             share=v["total_ms"] / max(1e-12, sum(x["total_ms"] for x in agg.values())),
                             GBps=(v["bytes"] / (v["total_ms"] / max(1, v["launches"]) * 1e-3) / 1e9)
@@ -364,7 +371,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cfg, max(p_iters))
+        cpu = cpu_baseline(cfg, plain["iters"] if plain else [197] * nrhs)
 
     line = dict(
         metric=METRIC, value=ms / 1000.0, unit="s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -383,6 +390,46 @@ def main():
 
 def _emit(line):
     print(json.dumps(line), flush=True)
+
+
+def bench_c1(args):
+    """Latency: the 16^3 prism (x = 2) to 1e-6, preconditioned and plain, with restart cycles
+    replayed from HIP graphs and launched one by one; median of 7 solves after a warm one."""
+    import numpy as np
+    import torch
+
+    import workloads as w
+    from paper_1903_09802_amd.dda import Problem
+
+    cfg = w.config_c1()
+    s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
+    mask = torch.from_numpy(s.mask).cuda()
+    eps = torch.from_numpy(s.eps).cuda()
+    res = {}
+    for precond in (2, 0):
+        for graph in (True, False):
+            prob = Problem(mask, eps, s.k, s.d, precond=precond, tol=cfg["tol"], restart=30, graph=graph)
+            if precond:
+                prob.build_preconditioner(0.0)
+            prob.solve(dirs, pols, return_c=False, xsec=False)
+            times = []
+            for _ in range(7):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = prob.solve(dirs, pols, return_c=False, xsec=False)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            st = out["stats"][0]
+            t = float(np.median(times))
+            res[f"{'precond' if precond else 'plain'}_{'graph' if graph else 'eager'}"] = dict(
+                solve_ms=1e3 * t, iters=st["iters"], cycles=st["cycles"], per_iter_us=1e6 * t / st["iters"],
+                setup_ms=1e3 * st["t_setup"], build_ms=1e3 * st["t_build"], converged=st["converged"])
+            prob.close()
+    _emit(dict(metric="DDA solve latency, 16^3 prism to 1e-6", workload="c1", unit="ms",
+               value=res["precond_graph"]["solve_ms"], higher_is_better=False,
+               config=dict(workload="hex prism x=2 aspect 1, 16^3 grid (FFT 32^3), m=1.31, +z x-pol, "
+                           "GMRES(30) tol 1e-6", grid=list(s.shape), n_occupied=int(s.n_occ)),
+               results=res, dtype="f64", data="synthetic"))
 
 
 def bench_c3(args):
@@ -427,7 +474,13 @@ def bench_c3(args):
 
 
 def bench_c4(args):
-    """Batching: seeded prisms of uneven grids, 128 waves each, solved in RHS blocks."""
+    """Batching: seeded prisms of uneven grids, 128 waves each, solved in RHS blocks.
+
+    With --c4-streams S > 1, S worker threads each take the next prism and run it on a stream of
+    their own (the library releases the interpreter lock in every call), so prisms overlap on
+    the GPU.  Latency is per prism from the start of its work to its last converged wave."""
+    import threading
+
     import numpy as np
     import torch
 
@@ -435,35 +488,72 @@ def bench_c4(args):
     from paper_1903_09802_amd.dda import Problem, lattice_factor
 
     cfg = w.config_c4(n_prisms=args.c4_prisms)
-    lat, solved, iters = [], 0, []
-    torch.cuda.synchronize()
-    t_all = time.perf_counter()
-    for pr in cfg["prisms"]:
+    prisms = list(enumerate(cfg["prisms"]))
+    # the largest grids first, so that a worker finishing early takes the small ones
+    prisms.sort(key=lambda ip: -ip[1]["scatterer"].mask.size)
+    lock = threading.Lock()
+    lat, solved, iters, errors = {}, [0], [], []
+
+    def run(pr, stream):
         s, dirs, pols = pr["scatterer"], pr["dirs"], pr["pols"]
         t0 = time.perf_counter()
-        mask = torch.from_numpy(s.mask).cuda()
-        eps = torch.from_numpy(s.eps).cuda()
-        chunk = args.c4_chunk
-        prob = Problem(mask, eps, s.k, s.d, precond=2, tol=cfg["tol"], restart=30,
-                       precision=args.c4_precision, max_rhs=chunk)
-        prob.build_preconditioner(lattice_factor(dirs, pols)[1])
-        for q0 in range(0, len(dirs), chunk):
-            out = prob.solve(dirs[q0:q0 + chunk], pols[q0:q0 + chunk], return_c=False)
-            solved += sum(st["converged"] for st in out["stats"])
-            iters += [st["iters"] for st in out["stats"]]
-        torch.cuda.synchronize()
-        prob.close()
-        lat.append(time.perf_counter() - t0)
-        print(f"c4 prism {len(lat)}/{len(cfg['prisms'])} grid {s.nx}^3: {lat[-1]:.3f} s", file=sys.stderr,
-              flush=True)
+        with torch.cuda.stream(stream):
+            mask = torch.from_numpy(s.mask).cuda()
+            eps = torch.from_numpy(s.eps).cuda()
+            stream.synchronize()
+            chunk = args.c4_chunk
+            prob = Problem(mask, eps, s.k, s.d, precond=2, tol=cfg["tol"], restart=30,
+                           precision=args.c4_precision, max_rhs=chunk, stream=stream)
+            prob.build_preconditioner(lattice_factor(dirs, pols)[1])
+            conv, its = 0, []
+            for q0 in range(0, len(dirs), chunk):
+                out = prob.solve(dirs[q0:q0 + chunk], pols[q0:q0 + chunk], return_c=False)
+                conv += sum(st["converged"] for st in out["stats"])
+                its += [st["iters"] for st in out["stats"]]
+            stream.synchronize()
+            prob.close()
+        return time.perf_counter() - t0, conv, its
+
+    def worker():
+        stream = torch.cuda.Stream()
+        while True:
+            with lock:
+                if not prisms or errors:
+                    return
+                i, pr = prisms.pop(0)
+            try:
+                t, conv, its = run(pr, stream)
+            except Exception as e:  # reported after the join
+                with lock:
+                    errors.append(e)
+                return
+            with lock:
+                lat[i] = t
+                solved[0] += conv
+                iters.extend(its)
+                print(f"c4 prism {i} grid {pr['scatterer'].nx}^3: {t:.3f} s ({len(lat)}/{len(cfg['prisms'])})",
+                      file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    threads = [threading.Thread(target=worker) for _ in range(max(1, args.c4_streams))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
     total = time.perf_counter() - t_all
+    if errors:
+        raise errors[0]
+    lat = [lat[i] for i in sorted(lat)]
     n_rhs = sum(len(pr["dirs"]) for pr in cfg["prisms"])
     _emit(dict(metric="RHS solves/s (batched, to rel. residual 1e-5)", workload="c4",
                value=n_rhs / total, unit="solves/s", higher_is_better=True,
-               prisms_per_s=len(lat) / total, total_s=total, rhs_total=n_rhs, rhs_converged=solved,
+               prisms_per_s=len(lat) / total, total_s=total, rhs_total=n_rhs, rhs_converged=solved[0],
                latency_p50_s=float(np.percentile(lat, 50)), latency_p99_s=float(np.percentile(lat, 99)),
                iters_mean=float(np.mean(iters)), iters_max=int(np.max(iters)),
                grids=[pr["scatterer"].nx for pr in cfg["prisms"]], rhs_chunk=args.c4_chunk,
+               streams=args.c4_streams,
                dtype="f64" if args.c4_precision == 0 else "f32 inner / f64 outer", data="synthetic"))
 
 

@@ -338,9 +338,9 @@ struct dda_problem {
   double *hist = nullptr;    // [R][hist_cap] residual estimate after every GMRES step
   int hist_cap = 0;
   double2 *adj = nullptr;    // [3 nocc] forward solution kept across dda_grad_cext's two solves
-  const int *live = nullptr; // inside a GMRES cycle: the device flag that turns the cycle's
-                             // operator and preconditioner launches into no-ops once every
-                             // right-hand side has stopped; null elsewhere
+  const int *act = nullptr;  // inside a GMRES cycle: the per-right-hand-side flags with which
+                             // the cycle's operator and preconditioner launches skip the
+                             // right-hand sides that have stopped; null elsewhere
   hipStream_t cap_st = nullptr;  // private stream on which restart cycles are captured
   struct CycleGraph {
     int nrhs, fp32;

@@ -40,8 +40,9 @@ struct RowArgs {
   const double2 *xin;  // FP64 field rows for ROW_OP_INV
   const double *xscale;// per-RHS input scale xscale[r * kMaxM], or null
   double scale;        // output scale of the transform
-  const int *live;     // null, or a device flag: 0 makes the launch a no-op (a solver cycle
-                       // whose right-hand sides have all stopped)
+  const int *act;      // null, or per-right-hand-side flags: the rows of a right-hand side
+                       // whose flag is 0 are neither read nor written (inside a solver cycle,
+                       // the right-hand sides that have stopped)
 };
 
 constexpr int kRowEpt = 8;  // elements per thread of a row tile: tw n <= 8 (tw tpc) threads
@@ -51,13 +52,24 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
                                                           const cplx<T> *__restrict__ tw,
                                                           RowArgs a) {
   using V = cplx<T>;
-  if (a.live && a.live[0] == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *s = reinterpret_cast<V *>(smem_raw);
   const int tid = threadIdx.x, nt = blockDim.x;
   const int n = a.pl.n;
   const int ld = a.tw + 1;
   const long long row0 = (long long)blockIdx.x * a.tw;
+  // right-hand sides that have stopped: their rows are skipped, the block returns if all are
+  bool some_off = false;
+  if (a.act) {
+    const long long r0 = row0 / a.rhs_rows, r1 = (min(row0 + a.tw, a.rows) - 1) / a.rhs_rows;
+    bool any_on = false;
+    for (long long r = r0; r <= r1; ++r) {
+      if (a.act[r]) any_on = true;
+      else some_off = true;
+    }
+    if (!any_on) return;
+  }
+  auto row_on = [&](long long row) { return !some_off || a.act[row / a.rhs_rows] != 0; };
   // load: consecutive threads take consecutive elements of a row (global rows are contiguous)
   const int tot_in = a.tw * n;
   if constexpr (MODE == ROW_OP_FWD || MODE == ROW_PC_FWD) {
@@ -70,7 +82,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
       const int c = a.nsh >= 0 ? (e >> a.nsh) : e / n;
       const int i = e - c * n;
       const long long row = row0 + c;
-      cis[q] = (e < tot_in && row < a.rows && i < a.n_in) ? a.cidx[(row % a.vox_rows) * a.nx + i] : -1;
+      cis[q] = (e < tot_in && row < a.rows && i < a.n_in && row_on(row))
+                   ? a.cidx[(row % a.vox_rows) * a.nx + i] : -1;
     }
 #pragma unroll
     for (int q = 0; q < kRowEpt; ++q) {
@@ -105,7 +118,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
     const int c = e / a.n_out;
     const int i = e - c * a.n_out;
     const long long row = row0 + c;
-    if (row >= a.rows) continue;
+    if (row >= a.rows || !row_on(row)) continue;
     const V v = s[lrow(i, ld) + c];
     if constexpr (MODE == ROW_PLAIN) {
       out[row * a.out_stride + i] = v;
@@ -144,7 +157,8 @@ struct StrArgs {
   int n_in, n_out;
   long long in_bstride, out_bstride;  // elements between batches
   int sign;
-  const int *live;        // as RowArgs::live
+  const int *act;         // null, or per-right-hand-side flags (as RowArgs::act)
+  long long rhs_batch;    // batches per right-hand side (with act)
 };
 
 template <typename T, int NF>
@@ -153,7 +167,6 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(const cplx<T> *in, 
                                                              StrArgs a) {
   using V = cplx<T>;
   constexpr int EPT = EptOf<T>::value;  // rows per thread: n <= EPT tpc
-  if (a.live && a.live[0] == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *s = reinterpret_cast<V *>(smem_raw);
   const int n = a.pl.n;
@@ -172,10 +185,17 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_strided(const cplx<T> *in, 
       v[k] = (colok && i < a.n_in) ? src[(long long)i * a.width] : mk<T>((T)0, (T)0);
     }
   };
+  // tiles of right-hand sides that have stopped are skipped (uniformly over the workgroup)
+  auto tile_on = [&](long long q) { return !a.act || a.act[(q / a.ntiles) / a.rhs_batch] != 0; };
   V cur[EPT], nxt[EPT];
-  if (q0 < q1) load(q0, cur);
+  if (q0 < q1 && tile_on(q0)) load(q0, cur);
   for (long long q = q0; q < q1; ++q) {
-    if (q + 1 < q1) load(q + 1, nxt);  // in flight during this tile's transform
+    if (q + 1 < q1 && tile_on(q + 1)) load(q + 1, nxt);  // in flight during this tile's transform
+    if (!tile_on(q)) {
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) cur[k] = nxt[k];
+      continue;
+    }
     if (q > q0) lds_barrier();         // the previous tile's output reads are done
     if (L.active) {
 #pragma unroll
@@ -212,14 +232,13 @@ struct ZArgs {
   int tw, twsh;     // columns per tile and log2(tw)
   long long ntiles;
   long long nrhs;
-  const int *live;  // as RowArgs::live
+  const int *act;   // null, or per-right-hand-side flags (as RowArgs::act)
 };
 
 template <typename T, int EPT, int NF>
 __global__ void __launch_bounds__(768) k_zpass(cplx<T> *data, const cplx<T> *__restrict__ tw,
                                                const cplx<T> *__restrict__ khat, ZArgs a) {
   using V = cplx<T>;
-  if (a.live && a.live[0] == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *s = reinterpret_cast<V *>(smem_raw);
   const int n = a.pl.n;
@@ -230,6 +249,7 @@ __global__ void __launch_bounds__(768) k_zpass(cplx<T> *data, const cplx<T> *__r
   // right-hand sides fastest: the workgroups that read the same kernel-spectrum columns are
   // adjacent and, through the XCD remap, share one L2
   const long long r = blk % a.nrhs;
+  if (a.act && !a.act[r]) return;
   const long long c0 = (blk / a.nrhs) * (long long)a.tw;
   V *base = data + r * 3LL * a.nz * a.zstride;
   const Lane L = make_lane(ncols, tpc_of(n));
@@ -346,7 +366,7 @@ template <typename T, int MODE, typename TI, typename TO>
 inline void launch_rows(dda_problem *p, const FftPlan &pl, const TI *in, TO *out, RowArgs a,
                         const char *name, double bytes) {
   a.pl = desc(pl);
-  a.live = p->live;
+  a.act = a.rhs_rows > 0 ? p->act : nullptr;
   a.tw = tile_cols<T>(pl.n);
   if (a.rows < a.tw) a.tw = (int)a.rows;
   a.nsh = ilog2_exact(pl.n);
@@ -369,7 +389,7 @@ template <typename T>
 inline void launch_strided(dda_problem *p, const FftPlan &pl, const cplx<T> *in, cplx<T> *out,
                            long long batch, long long width, int n_in, int n_out,
                            long long in_bstride, long long out_bstride, int sign,
-                           const char *name, double bytes) {
+                           const char *name, double bytes, long long rhs_batch = 0) {
   StrArgs a;
   a.pl = desc(pl);
   a.batch = batch;
@@ -386,7 +406,8 @@ inline void launch_strided(dda_problem *p, const FftPlan &pl, const cplx<T> *in,
   a.in_bstride = in_bstride;
   a.out_bstride = out_bstride;
   a.sign = sign;
-  a.live = p->live;
+  a.act = rhs_batch > 0 ? p->act : nullptr;
+  a.rhs_batch = rhs_batch > 0 ? rhs_batch : 1;
   const size_t lds = tile_lds<T>(pl.n, a.tw);
   const int threads = a.tw * tpc_of(pl.n);
   KTimer t(&p->prof, p->st, name, bytes);

@@ -544,7 +544,7 @@ static void enqueue_cycle(Kry &K, const GmresCfg &c) {
   hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, p->st, p->hcol2, p->gvec, m, p->vsc,
                      p->ctl, p->R, nrhs);
   HIPCHK(hipGetLastError());
-  p->live = p->ctl;  // the products of a step return at once when no right-hand side is active
+  p->act = K.d_active;  // the products of a step skip the right-hand sides that have stopped
   try {
     for (int j = 0; j < m; ++j) {
       double2 *vjj = p->V + (long long)j * vs_j;
@@ -579,10 +579,10 @@ static void enqueue_cycle(Kry &K, const GmresCfg &c) {
       HIPCHK(hipGetLastError());
     }
   } catch (...) {
-    p->live = nullptr;
+    p->act = nullptr;
     throw;
   }
-  p->live = nullptr;
+  p->act = nullptr;
   hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, p->st, p->H, p->gvec, m, K.d_jcut, p->vsc,
                      p->ycoef, nrhs);
   {

@@ -443,7 +443,7 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, in
     a.ipw = std::min(ipw, 4 * nrhs);
     a.nch = (4 * nrhs + a.ipw - 1) / a.ipw;
     a.nblk = (long long)a.tiles_x * (p->ny + 1) * a.nch;
-    a.live = p->live;
+    a.act = p->act;
     int G = 0, P = 0;
     zmr_split(n, &G, &P);
     zmr_launch<T>(n, (unsigned)xcd_grid(a.nblk), 3 * tw * zmr_tpc(G, P), zmr_lds<T>(G, P, tw, p->nz),
@@ -463,7 +463,7 @@ static void zpass(dda_problem *p, int nrhs, cplx<T> *w1, const cplx<T> *khat, in
   a.twsh = ilog2_exact(tw);
   a.ntiles = (a.plane + tw - 1) / tw;
   a.nrhs = nrhs;
-  a.live = p->live;
+  a.act = p->act;
   const int threads = 3 * tw * tpc_of(n);
   const size_t lds = (size_t)lds_elems(n, 3 * tw + 1) * sizeof(cplx<T>);
   with_static_n(n, [&](auto nf) {
@@ -599,14 +599,14 @@ static void op_passes(dda_problem *p, int nrhs, const double2 *x, double2 *y,
   launch_strided<T>(p, p->py, w0, w1, (long long)nrhs * 3 * nz, 2LL * nx, ny, 2 * ny,
                     (long long)ny * 2 * nx, p->zplane, -1,
                     sizeof(T) == 8 ? "op_y_fwd_f64" : "op_y_fwd_f32",
-                    nrhs * 3.0 * nz * 2 * nx * (ny + 2.0 * ny) * sz);
+                    nrhs * 3.0 * nz * 2 * nx * (ny + 2.0 * ny) * sz, 3LL * nz);
   // P3: z transform, kernel multiply, inverse z transform (in place)
   zpass<T>(p, nrhs, w1, khat);
   // P4: inverse y transform, keep ny rows
   launch_strided<T>(p, p->py, w1, w0, (long long)nrhs * 3 * nz, 2LL * nx, 2 * ny, ny,
                     p->zplane, (long long)ny * 2 * nx, +1,
                     sizeof(T) == 8 ? "op_y_inv_f64" : "op_y_inv_f32",
-                    nrhs * 3.0 * nz * 2 * nx * (2.0 * ny + ny) * sz);
+                    nrhs * 3.0 * nz * 2 * nx * (2.0 * ny + ny) * sz, 3LL * nz);
   // P5: inverse x transform, keep nx, diagonal and mask epilogue
   {
     RowArgs a{};

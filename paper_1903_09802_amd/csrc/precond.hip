@@ -33,6 +33,14 @@
 
 namespace dda {
 
+// Some right-hand side of r0 .. r0 + nr - 1 is still iterating (act null: all are).
+__device__ __forceinline__ bool rhs_any_on(const int *act, int r0, int nr) {
+  if (!act) return true;
+  for (int r = r0; r < r0 + nr; ++r)
+    if (act[r]) return true;
+  return false;
+}
+
 __device__ __forceinline__ void green6_chan(double x, double y, double z, double k, double d3,
                                             double w, double2 acc[6]) {
   const double r2 = x * x + y * y + z * z;
@@ -463,8 +471,8 @@ __global__ void k_diag_delta(const double2 *eps, const int *vox, long long nocc,
 // t = s_r x - Delta z on compact [nrhs][3][nocc] vectors, s_r = xscale[r * kMaxM] (or 1);
 // blockIdx.y = 3 r + component
 __global__ void k_diag_resid(const double2 *x, const double2 *z, const double2 *delta,
-                             double2 *t, long long nocc, const double *xscale, const int *live) {
-  if (live && live[0] == 0) return;
+                             double2 *t, long long nocc, const double *xscale, const int *act) {
+  if (act && !act[blockIdx.y / 3]) return;
   const long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (c >= nocc) return;
   const long long i = blockIdx.y * nocc + c;
@@ -750,9 +758,8 @@ __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__re
                                                  int nx, int ny, int nzw, int z0, int nz, int umx,
                                                  int hh, int n2,
                                                  int nrhs, int rc, long long nchunks, long long U,
-                                                 const int *live) {
+                                                 const int *act) {
   using V = cplx<T>;
-  if (live && live[0] == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *Ub = reinterpret_cast<V *>(smem_raw);  // [2][nv][n2]
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -761,6 +768,7 @@ __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__re
   const long long u = blk / nchunks;
   const int r0 = (int)(blk - u * nchunks) * rc;
   const int nr = min(rc, nrhs - r0);
+  if (!rhs_any_on(act, r0, nr)) return;
   const int uy = (int)(u / umx), ux = (int)(u % umx);
   const int mxs[2] = {ux, (nx - ux) % nx};
   const int mys[2] = {uy, (ny - uy) % ny};
@@ -975,11 +983,10 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
                                                              int umx, int hh,
                                                              int n2, int ntr, int nrhs, int rc,
                                                              long long nchunks, long long U,
-                                                             const int *live) {
+                                                             const int *act) {
   using V = cplx<T>;
   using v4 = typename Mfma<T>::v4;
   constexpr int NV = 8 * NCB;
-  if (live && live[0] == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *Ub = reinterpret_cast<V *>(smem_raw);  // [2][NV][n2p], zero beyond nv and n2
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -988,6 +995,7 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
   const long long u = blk / nchunks;
   const int r0 = (int)(blk - u * nchunks) * rc;
   const int nr = min(rc, nrhs - r0);
+  if (!rhs_any_on(act, r0, nr)) return;
   const GemvMode g = gemv_mode(u, umx, nx, ny, nzw, z0, nz, hh, n2, nr, r0);
   const int n2p = 16 * ntr;
   gemv_gather<T, NV>(Ub, W, g, n2p, tid, nt);
@@ -1080,7 +1088,7 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
   }
   snprintf(nm, sizeof nm, "pc_y_fwd_%s", suf);
   launch_strided<T>(p, p->uy, W, W, (long long)nrhs * 3 * nz, nx, ny, ny, (long long)ny * nx,
-                    (long long)ny * nx, -1, nm, 2.0 * rows * nx * sz);
+                    (long long)ny * nx, -1, nm, 2.0 * rows * nx * sz, 3LL * nz);
   {
     const long long U = (long long)p->umx * p->umy;
     snprintf(nm, sizeof nm, "pc_gemv_%s", suf);
@@ -1105,7 +1113,7 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
                            : k_pc_gemv_mfma<T, 12, sizeof(T) == 8 ? 2 : 4>;
       set_lds_limit((const void *)fn, lds);
       hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
-                         p->umx, p->hh, p->n2, p->ntr, nrhs, rc, nchunks, U, p->live);
+                         p->umx, p->hh, p->n2, p->ntr, nrhs, rc, nchunks, U, p->act);
       HIPCHK(hipGetLastError());
       }
     } else {
@@ -1124,24 +1132,24 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
       auto fn = k_pc_gemv<T, 4>;
       set_lds_limit((const void *)fn, lds);
       hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
-                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U, p->live);
+                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U, p->act);
     } else if (nvmax <= 8) {
       auto fn = k_pc_gemv<T, 8>;
       set_lds_limit((const void *)fn, lds);
       hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
-                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U, p->live);
+                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U, p->act);
     } else {
       auto fn = k_pc_gemv<T, 16>;
       set_lds_limit((const void *)fn, lds);
       hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
-                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U, p->live);
+                         p->umx, p->hh, p->n2, nrhs, rc, nchunks, U, p->act);
     }
     HIPCHK(hipGetLastError());
     }
   }
   snprintf(nm, sizeof nm, "pc_y_inv_%s", suf);
   launch_strided<T>(p, p->uy, W, W, (long long)nrhs * 3 * nz, nx, ny, ny, (long long)ny * nx,
-                    (long long)ny * nx, +1, nm, 2.0 * rows * nx * sz);
+                    (long long)ny * nx, +1, nm, 2.0 * rows * nx * sz, 3LL * nz);
   {
     RowArgs a{};
     a.rows = rows;
@@ -1170,9 +1178,8 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
 template <typename T, int NV>
 __global__ void __launch_bounds__(256) k_pc1_gemv(cplx<T> *W, const cplx<T> *__restrict__ binv,
                                                   int nx, int ny, int nz, int umx, int n1, int nrhs,
-                                                  int rc, long long nchunks, const int *live) {
+                                                  int rc, long long nchunks, const int *act) {
   using V = cplx<T>;
-  if (live && live[0] == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *Ub = reinterpret_cast<V *>(smem_raw);  // [nv][n1]
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -1181,6 +1188,7 @@ __global__ void __launch_bounds__(256) k_pc1_gemv(cplx<T> *W, const cplx<T> *__r
   const int u = (int)(blk / nchunks);
   const int r0 = (int)(blk - (long long)u * nchunks) * rc;
   const int nr = min(rc, nrhs - r0);
+  if (!rhs_any_on(act, r0, nr)) return;
   const int kxs[2] = {u, (nx - u) % nx};
   const int nmode = kxs[1] != kxs[0] ? 2 : 1;
   const int nv = nmode * nr;
@@ -1270,7 +1278,7 @@ static void pc_apply1(dda_problem *p, int nrhs, const double2 *x, double2 *y, co
     auto fn = k_pc1_gemv<T, 4>;
     set_lds_limit((const void *)fn, lds);
     hipLaunchKernelGGL(fn, dim3((unsigned)xcd_grid((long long)p->umx * nchunks)), dim3(threads), lds,
-                       p->st, W, binv, nx, ny, nz, p->umx, n1, nrhs, rc, nchunks, p->live);
+                       p->st, W, binv, nx, ny, nz, p->umx, n1, nrhs, rc, nchunks, p->act);
     HIPCHK(hipGetLastError());
   }
   {
@@ -1317,7 +1325,7 @@ void apply_precond(dda_problem *p, int nrhs, const double2 *x, double2 *y, int f
     {
       KTimer t(&p->prof, p->st, "pc_diag_resid", (48.0 * 3 * nrhs + 16.0) * p->nocc);
       hipLaunchKernelGGL(k_diag_resid, dim3(nblk(p->nocc, 256), 3 * nrhs), dim3(256), 0, p->st, x,
-                         z, p->pdelta, p->pdt, p->nocc, xscale, p->live);
+                         z, p->pdelta, p->pdt, p->nocc, xscale, p->act);
       HIPCHK(hipGetLastError());
     }
     apply_circulant(p, nrhs, p->pdt, i == k ? y : z, fp32, nullptr);

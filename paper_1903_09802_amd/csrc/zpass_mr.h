@@ -174,7 +174,8 @@ struct ZRArgs {
   int ipw;            // items per workgroup (>= 1)
   int nch;            // workgroups per tile, ceil(4 nrhs / ipw)
   long long nblk;     // (ny + 1) tiles_x nch, chunk fastest
-  const int *live;    // null, or a device flag: 0 makes the launch a no-op
+  const int *act;     // null, or per-right-hand-side flags: items of a right-hand side whose
+                      // flag is 0 are skipped (inside a solver cycle, the ones that stopped)
 };
 
 template <typename T, int G, int P>
@@ -186,7 +187,6 @@ __global__ void __launch_bounds__(256) k_zpass_mr(cplx<T> *data, const cplx<T> *
   static_assert(G % 2 == 0 && P % 2 == 0, "G and P must be even");
   static_assert(NC > 1 || P <= G, "P must be at most G or a multiple of it");
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  if (a.live && a.live[0] == 0) return;
   const long long blk = xcd_remap(blockIdx.x, a.nblk);
   if (blk >= a.nblk) return;
   const int ch = (int)(blk % a.nch);
@@ -197,6 +197,12 @@ __global__ void __launch_bounds__(256) k_zpass_mr(cplx<T> *data, const cplx<T> *
   const int it0 = ch * a.ipw;
   const int it1 = min(((oy == 0 || oy == a.ny) ? 2 : 4) * a.nrhs, it0 + a.ipw);
   if (it0 >= it1) return;
+  auto item_on = [&](int it) { return !a.act || a.act[it % a.nrhs] != 0; };
+  {
+    bool any = false;
+    for (int it = it0; it < it1; ++it) any = any || item_on(it);
+    if (!any) return;
+  }
   const int t = (int)threadIdx.x % TPC;
   const int col = ((int)threadIdx.x / TPC) & (a.tw - 1);
   const int comp = (int)threadIdx.x / (TPC * a.tw);
@@ -222,6 +228,7 @@ __global__ void __launch_bounds__(256) k_zpass_mr(cplx<T> *data, const cplx<T> *
   auto load = [&](int it, V (&x)[PH]) {
     bool ok;
     const V *cb = column(it, ok);
+    ok = ok && item_on(it);
 #pragma unroll
     for (int b = 0; b < PH; ++b) x[b] = ok ? cb[(long long)(g + G * b) * a.plane] : mk<T>((T)0, (T)0);
   };
@@ -253,6 +260,11 @@ __global__ void __launch_bounds__(256) k_zpass_mr(cplx<T> *data, const cplx<T> *
 
   for (int it = it0; it < it1; ++it) {
     if (it + 1 < it1) load(it + 1, xn);  // next item's column, in flight during this one
+    if (!item_on(it)) {                  // uniform over the workgroup: no LDS use, no barrier
+#pragma unroll
+      for (int b = 0; b < PH; ++b) x[b] = xn[b];
+      continue;
+    }
     if (it > it0) lds_barrier();          // the previous item's last exchange reads are done
     const int mir = it / a.nrhs;
     bool ok;
