@@ -174,10 +174,13 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5", "plates", "axes", "levels", "alpha"],
+                    choices=["c1", "c2", "c3", "c3study", "c4", "c5", "plates", "axes", "levels",
+                             "alpha"],
                     help="c2 (default): the 128^3 step; c1: solve latency at 16^3; c3: FP32-refined vs "
                          "FP64 at 256^3; c4: batched prisms; c5: adjoint gradient; the rest: studies")
     ap.add_argument("--c3-case", type=int, default=0, help="c3: 0 -> m = 1.31+0.001i, 1 -> m = 1.78")
+    ap.add_argument("--c3-variants", default="gmres30,gmres100,gmres300,bicgstab,gmres100_xdense",
+                    help="c3study: comma-separated solver variants")
     ap.add_argument("--c4-prisms", type=int, default=16)
     ap.add_argument("--c4-chunk", type=int, default=32, help="c4: right-hand sides per batched solve")
     ap.add_argument("--c4-precision", type=int, default=0, help="c4: 0 FP64, 1 FP32 inside FP64 refinement")
@@ -218,6 +221,8 @@ def main():
         return bench_c1(args)
     if args.workload == "c3":
         return bench_c3(args)
+    if args.workload == "c3study":
+        return bench_c3_study(args)
     if args.workload == "c4":
         return bench_c4(args)
     if args.workload == "c5":
@@ -422,7 +427,7 @@ def bench_c1(args):
             st = out["stats"][0]
             t = float(np.median(times))
             res[f"{'precond' if precond else 'plain'}_{'graph' if graph else 'eager'}"] = dict(
-                solve_ms=1e3 * t, iters=st["iters"], cycles=st["cycles"], per_iter_us=1e6 * t / st["iters"],
+                solve_ms=1e3 * t, iters=st["iters"], cycles=st["cycles"], per_iter_us=1e6 * t / max(1, st["iters"]),
                 setup_ms=1e3 * st["t_setup"], build_ms=1e3 * st["t_build"], converged=st["converged"])
             prob.close()
     _emit(dict(metric="DDA solve latency, 16^3 prism to 1e-6", workload="c1", unit="ms",
@@ -471,6 +476,47 @@ def bench_c3(args):
                            grid=list(s.shape), n_occupied=int(s.n_occ)),
                fp32_refined=res[1], fp64=res[0], speedup_fp32=res[0]["total_s"] / res[1]["total_s"],
                xsec_rel_dev_fp32_vs_fp64=dev, dtype="f32 inner / f64 outer", data="synthetic"))
+
+
+def bench_c3_study(args):
+    """The 256^3 prism (m = 1.78 by default): which solver settings converge.  One line per
+    variant: GMRES(m) for several m, BiCGStab, the other dense axis, FP32-refined."""
+    import torch
+
+    import workloads as w
+    from paper_1903_09802_amd.dda import Problem
+
+    cfg = w.config_c3(args.c3_case)
+    s, dirs, pols = cfg["scatterer"], cfg["dirs"], cfg["pols"]
+    mask = torch.from_numpy(s.mask).cuda()
+    eps = torch.from_numpy(s.eps).cuda()
+    variants = {
+        "gmres30": dict(restart=30), "gmres100": dict(restart=100), "gmres300": dict(restart=300),
+        "bicgstab": dict(solver="bicgstab", restart=30, max_iter=4000),
+        "gmres100_xdense": dict(restart=100, dense_axis=0),
+        "gmres300_fp32": dict(restart=300, precision=1),
+    }
+    for name in args.c3_variants.split(","):
+        kw = dict(precond=2, tol=cfg["tol"], max_iter=2000)
+        kw.update(variants[name])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob = Problem(mask, eps, s.k, s.d, **kw)
+        prob.build_preconditioner(0.0)
+        t1 = time.perf_counter()
+        out = prob.solve(dirs, pols, return_c=False, history=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        prob.close()
+        del prob
+        torch.cuda.empty_cache()
+        st = out["stats"][0]
+        h = st.pop("history")
+        _emit(dict(workload="c3_study", case=args.c3_case, variant=name, options=kw,
+                   build_s=t1 - t0, solve_s=t2 - t1, iters=st["iters"], cycles=st["cycles"],
+                   converged=st["converged"], rel_residual=st["rel_residual"],
+                   history_every_100=[float(v) for v in h[::100]], history_min=float(h.min()) if len(h) else None,
+                   cext=float(out["cext"][0]), csca=float(out["csca"][0]), cabs=float(out["cabs"][0])))
 
 
 def bench_c4(args):

@@ -295,7 +295,10 @@ void dda_destroy(dda_problem *p);
  * for kernel kind idx in [0, dda_profile_count()), its name (valid until the
  * handle is destroyed), the number of launches, their summed duration in ms,
  * and the mean algorithmic bytes per launch (read + write, per the traffic
- * model of the kernel; launches of one kind may differ in size).
+ * model of the kernel; launches of one kind may differ in size).  Only launches that did
+ * work are counted: inside a restart cycle whose right-hand sides have all stopped, the
+ * cycle's remaining launches return at once, and launches under 2 % of the kind's longest
+ * are left out.
  */
 dda_status dda_profile_enable(dda_problem *p, int on);
 int dda_profile_count(dda_problem *p);

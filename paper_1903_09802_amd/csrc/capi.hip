@@ -35,9 +35,11 @@ void free_all(dda_problem *p) {
   F(p->ainv); F(p->Sdev); F(p->V); F(p->work); F(p->work2); F(p->bvec); F(p->xvec); F(p->vsc);
   F(p->H); F(p->givens); F(p->gvec); F(p->hcol); F(p->hcol2);
   F(p->ycoef); F(p->hnrm); F(p->hraw); F(p->lmat); F(p->partial); F(p->dscal); F(p->dflag);
-  F(p->ctl); F(p->ones); F(p->bnrm); F(p->cres); F(p->hist); F(p->adj);
+  F(p->ctl); F(p->ones); F(p->bnrm); F(p->cres); F(p->hist); F(p->adj); F(p->stage);
   if (p->hpin) (void)hipHostFree(p->hpin);
+  if (p->hlive) (void)hipHostFree(p->hlive);
   p->hpin = nullptr;
+  p->hlive = nullptr;
   drop_graphs(p);
   if (p->cap_st) (void)hipStreamDestroy(p->cap_st);
   p->cap_st = nullptr;
@@ -412,9 +414,12 @@ dda_status dda_profile_get(dda_problem *p, int idx, const char **name, long long
     REQUIRE(idx >= 0 && idx < (int)p->prof.kinds.size(), DDA_EINVAL, "profile index out of range");
     const auto &k = p->prof.kinds[idx];
     if (name) *name = k.name.c_str();
-    if (launches) *launches = k.launches;
-    if (total_ms) *total_ms = k.total_ms;
-    if (bytes_per_launch) *bytes_per_launch = k.launches ? k.total_bytes / k.launches : 0.0;
+    long long n = 0;
+    double ms = 0.0, bytes = 0.0;
+    k.working(n, ms, bytes);
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = ms;
+    if (bytes_per_launch) *bytes_per_launch = n ? bytes / n : 0.0;
     return DDA_OK;
   });
 }

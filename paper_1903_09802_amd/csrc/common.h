@@ -187,9 +187,11 @@ struct Profiler {
   bool on = false;
   struct Kind {
     std::string name;
-    long long launches = 0;
-    double total_ms = 0.0;
-    double total_bytes = 0.0;  // algorithmic bytes summed over timed launches
+    std::vector<float> ms;      // duration of every timed launch
+    std::vector<double> bytes;  // its algorithmic bytes
+    // launches that did work (a launch inside a finished solver cycle returns at once: under
+    // 2 % of the kind's longest), their summed duration and algorithmic bytes
+    void working(long long &n, double &total_ms, double &total_bytes) const;
   };
   std::vector<Kind> kinds;
   struct Pending {
@@ -330,6 +332,8 @@ struct dda_problem {
   double *dscal = nullptr;   // [R][16] device scalars
   double *vsc = nullptr;     // [R][kMaxM] 1 / norm of each (unnormalised) basis vector
   double *hpin = nullptr;    // pinned host buffer [R][16]: a restart cycle's results
+  double2 *stage = nullptr;  // [R][8] device staging of small per-RHS results for hpin
+  int *hlive = nullptr;      // pinned host copy of the cycle's summary flag (read per segment)
   int *dflag = nullptr;      // device error flags [4]
   int *ctl = nullptr;        // device control of a GMRES cycle [1 + 4R] (krylov.hip)
   int *ones = nullptr;       // [R] ones: "every right-hand side" for the reductions
@@ -348,6 +352,7 @@ struct dda_problem {
     int maxit;
     const double2 *b;
     double2 *x;
+    int part;  // -1 start of a cycle, k >= 0 its k-th segment of steps, -2 its end
     hipGraphExec_t exec;
   };
   std::vector<CycleGraph> graphs;  // captured restart cycles (invalid once the preconditioner

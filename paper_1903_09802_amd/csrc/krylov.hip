@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "common.h"
@@ -480,11 +481,28 @@ static void norm2_dev(Kry &K, const double2 *a, long long st_r, double2 *dst) {
   HIPCHK(hipGetLastError());
 }
 
+// out[r * cnt + q] = in[r * stride + q] for r < nrhs, q < cnt: per-RHS slots made contiguous
+__global__ void k_pack_slots(const double2 *in, long long stride, int cnt, int nrhs, double2 *out) {
+  for (int e = threadIdx.x; e < cnt * nrhs; e += blockDim.x) {
+    const int r = e / cnt, q = e - r * cnt;
+    out[e] = in[r * stride + q];
+  }
+}
+
+// cnt complex slots per right-hand side (stride apart on the device) to host[r * cnt + q]:
+// packed on the device, then one plain copy into pinned memory
+static void copy_slots(dda_problem *p, const double2 *src, long long stride, int cnt, int nrhs,
+                       double2 *host) {
+  hipLaunchKernelGGL(k_pack_slots, dim3(1), dim3(256), 0, p->st, src, stride, cnt, nrhs, p->stage);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(p->hpin, p->stage, sizeof(double2) * cnt * nrhs, hipMemcpyDeviceToHost, p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
+  std::memcpy(host, p->hpin, sizeof(double2) * cnt * nrhs);
+}
+
 static void read_scalars(dda_problem *p, const double2 *src, int nrhs, std::vector<double> &out) {
   std::vector<double2> tmp(nrhs);
-  HIPCHK(hipMemcpy2DAsync(tmp.data(), sizeof(double2), src, sizeof(double2) * kMaxM,
-                          sizeof(double2), nrhs, hipMemcpyDeviceToHost, p->st));
-  HIPCHK(hipStreamSynchronize(p->st));
+  copy_slots(p, src, kMaxM, 1, nrhs, tmp.data());
   out.resize(nrhs);
   for (int r = 0; r < nrhs; ++r) out[r] = tmp[r].x;
 }
@@ -532,21 +550,51 @@ static void enqueue_residual(Kry &K, const GmresCfg &c) {
   HIPCHK(hipGetLastError());
 }
 
-// One restart cycle for the right-hand sides the host marked in `want`: up to m steps, each
-// w = A P^{-1} v~_j (or P^{-1} A v~_j when left) into basis block j + 1 with v~_j scaled by
-// 1 / ||v~_j|| on the way in, MGS in one reduction (a = V^H w and row j of L, c = (I + L)^{-1} a,
-// w -= V c), and the device decision of k_arnoldi; then x += P^{-1}(V y) (x += V y when left)
-// and the new residual.  Nothing here waits for the host.
-static void enqueue_cycle(Kry &K, const GmresCfg &c) {
+// A restart cycle runs in parts: its start, its steps in segments of growing length
+// (steps [0, 4), [4, 12), [12, 28), [28, 60), ... up to m), and its end.  Between two segments
+// the host reads one device flag (some right-hand side still iterating) and launches no more
+// segments once it is 0, so a cycle that finishes early does not launch its remaining steps;
+// within a segment, steps of stopped right-hand sides do no work.
+static int segment_end(int j0, int m) { return std::min(m, j0 == 0 ? 4 : 2 * j0 + 4); }
+
+// Part -1: start of the cycle for the right-hand sides the host marked in `want`.
+// Part  k: the steps of segment k, each w = A P^{-1} v~_j (or P^{-1} A v~_j when left) into
+//          basis block j + 1 with v~_j scaled by 1 / ||v~_j|| on the way in, MGS in one
+//          reduction (a = V^H w and row j of L, c = (I + L)^{-1} a, w -= V c), and the device
+//          decision of k_arnoldi.
+// Part -2: the end: x += P^{-1}(V y) (x += V y when left) and the new residual.
+static void enqueue_part(Kry &K, const GmresCfg &c, int part) {
   dda_problem *p = K.p;
   const int nrhs = c.nrhs, m = c.m;
   const long long n3 = K.n3, vs_r = c.vs_r, vs_j = c.vs_j;
-  hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, p->st, p->hcol2, p->gvec, m, p->vsc,
-                     p->ctl, p->R, nrhs);
-  HIPCHK(hipGetLastError());
+  if (part == -1) {
+    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, p->st, p->hcol2, p->gvec, m, p->vsc,
+                       p->ctl, p->R, nrhs);
+    HIPCHK(hipGetLastError());
+    return;
+  }
+  if (part == -2) {
+    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, p->st, p->H, p->gvec, m, K.d_jcut, p->vsc,
+                       p->ycoef, nrhs);
+    {
+      KTimer t(&p->prof, p->st, "kry_combine", 16.0 * n3 * (m + 1) * nrhs);
+      hipLaunchKernelGGL(k_combine, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r,
+                         vs_j, m, p->ycoef, p->work2, n3, n3, K.d_jcut);
+    }
+    HIPCHK(hipGetLastError());
+    if (c.prec && !c.left) apply_precond(p, nrhs, p->work2, p->work2, c.fp32, nullptr);
+    hipLaunchKernelGGL(k_axpby, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, c.x, p->work2, 1.0,
+                       c.x, n3, n3, nullptr, nullptr, K.B);
+    HIPCHK(hipGetLastError());
+    enqueue_residual(K, c);
+    return;
+  }
+  int j0 = 0;
+  for (int k = 0; k < part; ++k) j0 = segment_end(j0, m);
+  const int j1 = segment_end(j0, m);
   p->act = K.d_active;  // the products of a step skip the right-hand sides that have stopped
   try {
-    for (int j = 0; j < m; ++j) {
+    for (int j = j0; j < j1; ++j) {
       double2 *vjj = p->V + (long long)j * vs_j;
       double2 *w = p->V + (long long)(j + 1) * vs_j;
       if (c.left) {
@@ -583,33 +631,20 @@ static void enqueue_cycle(Kry &K, const GmresCfg &c) {
     throw;
   }
   p->act = nullptr;
-  hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, p->st, p->H, p->gvec, m, K.d_jcut, p->vsc,
-                     p->ycoef, nrhs);
-  {
-    KTimer t(&p->prof, p->st, "kry_combine", 16.0 * n3 * (m + 1) * nrhs);
-    hipLaunchKernelGGL(k_combine, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, p->V, vs_r, vs_j,
-                       m, p->ycoef, p->work2, n3, n3, K.d_jcut);
-  }
-  HIPCHK(hipGetLastError());
-  if (c.prec && !c.left) apply_precond(p, nrhs, p->work2, p->work2, c.fp32, nullptr);
-  hipLaunchKernelGGL(k_axpby, grid_r(K.B, nrhs), dim3(kRedThreads), 0, p->st, c.x, p->work2, 1.0,
-                     c.x, n3, n3, nullptr, nullptr, K.B);
-  HIPCHK(hipGetLastError());
-  enqueue_residual(K, c);
 }
 
-// Run one cycle: replay its HIP graph (captured on first use for this configuration), or
+// Enqueue one part: replay its HIP graph (captured on first use for this configuration), or
 // launch its kernels one by one when graphs are off or per-kernel profiling is on.
-static void run_cycle(Kry &K, const GmresCfg &c) {
+static void launch_part(Kry &K, const GmresCfg &c, int part) {
   dda_problem *p = K.p;
   if (!p->opt.graph || p->prof.on) {
-    enqueue_cycle(K, c);
+    enqueue_part(K, c, part);
     return;
   }
   hipGraphExec_t exec = nullptr;
   for (const auto &g : p->graphs)
     if (g.nrhs == c.nrhs && g.fp32 == c.fp32 && g.tol == c.tol && g.maxit == c.maxit &&
-        g.b == c.b && g.x == c.x) {
+        g.b == c.b && g.x == c.x && g.part == part) {
       exec = g.exec;
       break;
     }
@@ -619,7 +654,7 @@ static void run_cycle(Kry &K, const GmresCfg &c) {
     p->st = p->cap_st;
     hipGraph_t graph = nullptr;
     try {
-      enqueue_cycle(K, c);
+      enqueue_part(K, c, part);
     } catch (...) {
       p->st = orig;
       if (hipStreamEndCapture(p->cap_st, &graph) == hipSuccess && graph) (void)hipGraphDestroy(graph);
@@ -630,9 +665,25 @@ static void run_cycle(Kry &K, const GmresCfg &c) {
     const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     HIPCHK(e);
-    p->graphs.push_back(dda_problem::CycleGraph{c.nrhs, c.fp32, c.tol, c.maxit, c.b, c.x, exec});
+    p->graphs.push_back(dda_problem::CycleGraph{c.nrhs, c.fp32, c.tol, c.maxit, c.b, c.x, part, exec});
   }
   HIPCHK(hipGraphLaunch(exec, p->st));
+}
+
+// One restart cycle: start, segments until every right-hand side has stopped, end.  Nothing
+// in a segment waits for the host; the host waits once per segment for the summary flag.
+static void run_cycle(Kry &K, const GmresCfg &c) {
+  dda_problem *p = K.p;
+  launch_part(K, c, -1);
+  for (int part = 0, j0 = 0; j0 < c.m; ++part) {
+    launch_part(K, c, part);
+    j0 = segment_end(j0, c.m);
+    if (j0 >= c.m) break;
+    HIPCHK(hipMemcpyAsync(p->hlive, p->ctl, sizeof(int), hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    if (p->hlive[0] == 0) break;
+  }
+  launch_part(K, c, -2);
 }
 
 void drop_graphs(dda_problem *p) {
@@ -997,11 +1048,8 @@ void bicgstab_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, doub
       hipLaunchKernelGGL(k_finalize_n, dim3(2, nrhs), dim3(kRedThreads), 0, p->st, K.partial, K.B,
                          p->hraw, K.d_active);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpy2DAsync(hb.data(), sizeof(double2), p->hraw, sizeof(double2) * kSlots,
-                              sizeof(double2), nrhs, hipMemcpyDeviceToHost, p->st));
-      HIPCHK(hipMemcpy2DAsync(cb.data(), sizeof(double2) * 5, bc, sizeof(double2) * kMaxM,
-                              sizeof(double2) * 5, nrhs, hipMemcpyDeviceToHost, p->st));
-      HIPCHK(hipStreamSynchronize(p->st));
+      copy_slots(p, p->hraw, kSlots, 1, nrhs, hb.data());
+      copy_slots(p, bc, kMaxM, 5, nrhs, cb.data());
       for (int r = 0; r < nrhs; ++r) {
         if (!act[r]) continue;
         // a breakdown left x and r unchanged: it ends the run and is not counted as a step
@@ -1086,6 +1134,8 @@ void krylov_alloc(dda_problem *p) {
   HIPCHK(hipMalloc(&p->dscal, sizeof(double) * 16 * R));
   HIPCHK(hipMemset(p->dscal, 0, sizeof(double) * 16 * R));
   HIPCHK(hipHostMalloc(&p->hpin, sizeof(double) * 16 * R, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(&p->hlive, sizeof(int) * 16, hipHostMallocDefault));
+  HIPCHK(hipMalloc(&p->stage, sizeof(double2) * 8 * R));
   HIPCHK(hipMalloc(&p->vsc, sizeof(double) * kMaxM * R));
   HIPCHK(hipMemset(p->vsc, 0, sizeof(double) * kMaxM * R));
   HIPCHK(hipMalloc(&p->dflag, sizeof(int) * 4));

@@ -92,9 +92,8 @@ void Profiler::collect() {
   for (auto &pd : pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, pd.a, pd.b) == hipSuccess) {
-      kinds[pd.kind].launches += 1;
-      kinds[pd.kind].total_ms += ms;
-      kinds[pd.kind].total_bytes += pd.bytes;
+      kinds[pd.kind].ms.push_back(ms);
+      kinds[pd.kind].bytes.push_back(pd.bytes);
     }
     pool.push_back(pd.a);
     pool.push_back(pd.b);
@@ -102,11 +101,23 @@ void Profiler::collect() {
   pending.clear();
 }
 
+void Profiler::Kind::working(long long &n, double &total_ms, double &total_bytes) const {
+  float mx = 0.f;
+  for (float v : ms) mx = v > mx ? v : mx;
+  n = 0;
+  total_ms = total_bytes = 0.0;
+  for (size_t i = 0; i < ms.size(); ++i)
+    if (ms[i] >= 0.02f * mx) {
+      ++n;
+      total_ms += ms[i];
+      total_bytes += bytes[i];
+    }
+}
+
 void Profiler::reset() {
   for (auto &k : kinds) {
-    k.launches = 0;
-    k.total_ms = 0.0;
-    k.total_bytes = 0.0;
+    k.ms.clear();
+    k.bytes.clear();
   }
 }
 

@@ -98,9 +98,9 @@ def test_history_matches_oracle_gmres():
 
 
 def test_stop_inside_a_cycle_and_rebuild():
-    """A right-hand side that converges mid-cycle stops there (the remaining launches of the
-    cycle do nothing); rebuilding the preconditioner drops the captured cycles, and the next
-    solve runs with the new blocks."""
+    """A right-hand side that converges mid-cycle stops there (the cycle's remaining segments of
+    steps are not launched, and the rest of the current one does no work); rebuilding the
+    preconditioner drops the captured cycles, and the next solve runs with the new blocks."""
     s = w.hex_prism_grid(3.0, 1.0, 12, 1.31)
     dirs, pols = w.plane_wave_z(("x",))
     with make_problem(s, precond=2, tol=1e-6, restart=200) as prob:
