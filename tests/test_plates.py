@@ -70,3 +70,34 @@ def test_plate_rounding_picks_the_paper_total():
         assert abs(n / tot - 1) <= 0.05, (r, rnd, n)
     assert w.plate_fit_rounding(0.1, 1.6, 20, 4.5e4) == "round"
     assert w.plate_fit_rounding(0.1, 1.2, 30, 6.9e4) == "ceil"
+
+
+def test_occupied_voxel_vectors_reproduce_the_paper_counts():
+    """Reading Z1 against the paper's own counts (Table 3, L/a = 0.1, mu = 1.6, x = 10: 11
+    preconditioned GMRES iterations).  Unknowns on the occupied voxels with the preconditioner
+    applied as M P^{-1} M take the paper's count; Krylov vectors over the whole box, with P^{-1}
+    spilling into the air entries (air rows the identity), take more than twice as many on
+    either preconditioning side.  Oracle only."""
+    from oracle import circulant, fftmatvec, gmres, physics, system
+    tab = {(r[0], r[1], r[2]): r for r in _rows("paper_tables_3_4.txt")}
+    paper_its = int(tab[("0.1", "1.6", "10")][9])
+    c = w.plate_case(0.1, 1.6, 10, rounding=w.plate_fit_rounding(0.1, 1.6, 10, 6.7e3))
+    s, d, p = c["scatterer"], c["dirs"][0], c["pols"][0]
+    S = physics.lattice_S(d, p)
+    b = system.incident_field(s.mask, s.k, s.d, d, p)
+    Kh = fftmatvec.kernel_padded_fft(s.shape, s.k, s.d)
+    mv = lambda v: fftmatvec.fft_matvec(v, s.mask, s.eps, s.k, s.d, S, Khat=Kh)
+    ati = physics.alpha_tilde_inv(s.eps, s.mask, s.k * s.d, 0.0)
+    z0, Binv = circulant.blocks_for_mask(s.mask, s.k, s.d, ati)
+    masked = lambda v: circulant.apply_blocks_layers(v, s.mask, Binv, z0)
+    Bbox = circulant.invert_blocks(circulant.two_level_blocks(s.shape, s.k, s.d, ati))
+    ones = np.ones_like(s.mask)
+    boxp = lambda v: circulant.apply_blocks(v, ones, Bbox)
+    its = {}
+    for name, pc, side in (("masked", masked, "right"), ("box_right", boxp, "right"),
+                           ("box_left", boxp, "left")):
+        _, info = gmres.gmres(mv, b, precond=pc, restart=100, tol=1e-5, side=side)
+        assert info["converged"]
+        its[name] = info["iters"]
+    assert abs(its["masked"] - paper_its) <= 2, its
+    assert its["box_right"] >= 2 * paper_its and its["box_left"] >= 2 * paper_its, its
