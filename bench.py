@@ -67,6 +67,22 @@ def gemv_algorithmic_bytes(s, nrhs, elem=16):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_hex128_fp64.txt")
+GOLDEN_C2 = os.path.join(ROOT, "tests", "golden", "c2_xsec.txt")
+
+
+def golden_deviation(cext, csca):
+    """Relative deviation of the step's cross sections (solved to the workload's tolerance)
+    from the oracle-only reference solved to 1e-11, per wave; None without the file."""
+    if not os.path.exists(GOLDEN_C2):
+        return None
+    rows = [ln.split() for ln in open(GOLDEN_C2) if ln.strip() and not ln.startswith("#")]
+    out = {}
+    for f in rows:
+        r = int(f[0])
+        if r < len(cext):
+            out[f"wave{r}"] = dict(cext=abs(cext[r] - float(f[9])) / float(f[9]),
+                                   csca=abs(csca[r] - float(f[11])) / float(f[11]))
+    return out
 
 
 def source_digest():
@@ -386,6 +402,7 @@ def main():
                     size_parameter=s.meta.get("x"), restart=30, tol=tol),
         precond_iters=p_iters, precond_rel_residual=p_res, converged=converged,
         cext=last["cext"].tolist(), cabs=last["cabs"].tolist(), csca=last["csca"].tolist(),
+        xsec_rel_dev_vs_oracle_golden=golden_deviation(last["cext"].tolist(), last["csca"].tolist()),
         step_s_unprofiled=unprofiled, plain=plain, bicgstab=bicg, matvec_ms=1000 * t_mv, matvec_GBps=matvec_gbps,
         matvec_frac_hbm=matvec_gbps / HBM_PEAK_GBPS, precond_apply_ms=1000 * t_pc,
         roofline=roofline, kernels=kernel_table, cpu_baseline=cpu,
