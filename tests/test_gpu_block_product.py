@@ -1,6 +1,7 @@
 """The packed symmetric block product of the 2-level preconditioner (even dense extents) against
-the oracle, over tile-row counts ntr = ceil(3 nz / 32) of 1 .. 12, odd and even, one and two
-right-hand sides, both precisions."""
+the oracle, over tile-row counts ntr = ceil(3 nz / 32) from 1 to 24, odd and even, one to eight
+right-hand sides (full and partial chunks of one and two column blocks), both precisions."""
+
 
 import numpy as np
 import pytest
@@ -19,9 +20,13 @@ def _full_box(shape, seed):
     return s
 
 
-# nz even (packed symmetric tiles); tile rows ntr = ceil(3 nz / 32): 1, 2, 3, 7, 12
-@pytest.mark.parametrize("shape", [(2, 6, 5), (12, 4, 6), (24, 4, 3), (72, 3, 4), (128, 2, 3)])
-@pytest.mark.parametrize("nrhs,fp32", [(1, 0), (2, 0), (2, 1)])
+# nz even (packed symmetric tiles); tile rows ntr = ceil(3 nz / 32): 1, 2, 3, 7, 9, 12, 16, 24
+SHAPES = [(2, 6, 5), (12, 4, 6), (24, 4, 3), (72, 3, 4), (96, 2, 3), (128, 2, 3), (168, 2, 2),
+          (256, 2, 3)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("nrhs,fp32", [(1, 0), (2, 0), (2, 1), (3, 0), (5, 1), (8, 0), (8, 1)])
 def test_block_product_tile_rows(shape, nrhs, fp32):
     s = _full_box(shape, 300 + shape[0])
     x = rand_field(shape, nrhs, 301 + shape[0])
