@@ -1112,6 +1112,14 @@ void krylov_alloc(dda_problem *p) {
   const int m = p->opt.restart;
   const int R = p->R;
   const long long n3 = 3 * p->nocc;
+  {  // the basis and the work vectors, compact (3 N_occ entries per wave)
+    const double need = 16.0 * n3 * ((double)R * (m + 1) + 4.0 * R + 1.0);
+    size_t freeb = 0, totb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totb));
+    REQUIRE(need < 0.9 * (double)freeb, DDA_ENOMEM,
+            "Krylov basis of %d + 1 vectors x %d waves needs about %.2f GB, %.2f GB free", m, R,
+            need / 1e9, freeb / 1e9);
+  }
   HIPCHK(hipMalloc(&p->V, sizeof(double2) * (size_t)R * (m + 1) * n3));
   HIPCHK(hipMemsetAsync(p->V, 0, sizeof(double2) * (size_t)R * (m + 1) * n3, p->st));
   HIPCHK(hipMalloc(&p->work, sizeof(double2) * (size_t)R * n3));
