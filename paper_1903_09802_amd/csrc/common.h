@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -210,6 +211,17 @@ struct Profiler {
 };
 
 // RAII timer around one launch; no-op when profiling is off.
+// FFT passes whose tile shapes the autotuner picks (x rows and y columns of the operator and
+// of the preconditioner), and a shape: columns per tile and, along a strided axis, tiles per
+// workgroup (0: the launch rule).
+enum FftPass {
+  FP_OP_X_FWD, FP_OP_Y_FWD, FP_OP_Y_INV, FP_OP_X_INV,
+  FP_PC_X_FWD, FP_PC_Y_FWD, FP_PC_Y_INV, FP_PC_X_INV, FP_COUNT
+};
+struct TileShape {
+  int tw = 0, tpw = 0;
+};
+
 struct KTimer {
   Profiler *prof;
   hipStream_t st;
@@ -264,6 +276,7 @@ struct dda_problem {
   size_t lds_max = 65536;      // device LDS per workgroup
   size_t lds_zpass = 98304;    // LDS budget of the fused z pass
   int ztw[2] = {0, 0};         // z-pass columns per tile (FP64, FP32), chosen by autotune
+  dda::TileShape tile[dda::FP_COUNT][2];  // x / y pass shapes per pass (FP64, FP32), chosen by autotune
   int zipw[2] = {0, 0};        // register z pass: forced items per workgroup (0: by the rule)
   int zreg = 0;                // 1: register z pass (2 nz = G P in its list of lengths); the
                                // kernel spectra are then stored z-major, [oy][ox][oz][6]
@@ -397,6 +410,11 @@ void precond_free(dda_problem *p);
 
 // krylov.hip
 void krylov_alloc(dda_problem *p);
+// Pick the tile shapes of the four x / y passes of the operator (first = FP_OP_X_FWD) or of the
+// 2-level preconditioner (FP_PC_X_FWD) in precision pi (0 FP64, 1 FP32) by timing `apply` (one
+// application of that product on nrhs right-hand sides) with each candidate; cached per
+// (device, grid, nrhs, precision) for the process.  DDA_FFT_TUNE=0 keeps the launch rules.
+void fft_tile_autotune(dda_problem *p, int first, int pi, int nrhs, const std::function<void()> &apply);
 // Solve A x = b for nrhs RHS (b, x compact [nrhs][3 nocc]; x holds the initial guess).
 void gmres_solve(dda_problem *p, int nrhs, const double2 *b, double2 *x, int fp32, double tol,
                  int maxit, dda_stats *st);

@@ -362,12 +362,17 @@ template <typename T> inline size_t tile_lds(int n, int cols) {
 }
 
 // Launch a row transform.  `a` must have rows, n_in, n_out, strides and sign set.
+// `pass` (an FftPass, or -1) selects the autotuned rows per tile.
 template <typename T, int MODE, typename TI, typename TO>
 inline void launch_rows(dda_problem *p, const FftPlan &pl, const TI *in, TO *out, RowArgs a,
-                        const char *name, double bytes) {
+                        const char *name, double bytes, int pass = -1) {
   a.pl = desc(pl);
   a.act = a.rhs_rows > 0 ? p->act : nullptr;
   a.tw = tile_cols<T>(pl.n);
+  if (pass >= 0) {
+    const TileShape &ts = p->tile[pass][sizeof(T) == 8 ? 0 : 1];
+    if (ts.tw > 0 && ts.tw < a.tw) a.tw = ts.tw;
+  }
   if (a.rows < a.tw) a.tw = (int)a.rows;
   a.nsh = ilog2_exact(pl.n);
   const long long blocks = (a.rows + a.tw - 1) / a.tw;
@@ -385,22 +390,27 @@ inline void launch_rows(dda_problem *p, const FftPlan &pl, const TI *in, TO *out
   HIPCHK(hipGetLastError());
 }
 
+// `pass` (an FftPass, or -1) selects the autotuned columns per tile and tiles per workgroup.
 template <typename T>
 inline void launch_strided(dda_problem *p, const FftPlan &pl, const cplx<T> *in, cplx<T> *out,
                            long long batch, long long width, int n_in, int n_out,
                            long long in_bstride, long long out_bstride, int sign,
-                           const char *name, double bytes, long long rhs_batch = 0) {
+                           const char *name, double bytes, long long rhs_batch = 0, int pass = -1) {
   StrArgs a;
   a.pl = desc(pl);
   a.batch = batch;
   a.width = width;
   a.tw = tile_cols<T>(pl.n);
+  TileShape ts;
+  if (pass >= 0) ts = p->tile[pass][sizeof(T) == 8 ? 0 : 1];
+  if (ts.tw > 0 && ts.tw < a.tw) a.tw = ts.tw;
   if (a.tw > width) a.tw = (int)width;
   a.ntiles = (width + a.tw - 1) / a.tw;
-  // tiles per workgroup: the most (up to 8) that leave at least 2048 workgroups
+  // tiles per workgroup: the most (up to 8) that leave at least 2048 workgroups, or the tuned count
   const long long tiles = a.ntiles * batch;
   a.tpw = 1;
   while (a.tpw < 8 && (tiles + 2 * a.tpw - 1) / (2 * a.tpw) >= 2048) a.tpw *= 2;
+  if (ts.tpw > 0) a.tpw = ts.tpw;
   a.n_in = n_in;
   a.n_out = n_out;
   a.in_bstride = in_bstride;

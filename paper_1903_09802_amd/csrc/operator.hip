@@ -353,6 +353,9 @@ static void kernel_spectrum(dda_problem *p, int part) {
 }
 
 template <typename T> static void zpass_autotune(dda_problem *p, const cplx<T> *khat);
+template <typename T>
+static void op_passes(dda_problem *p, int nrhs, const double2 *x, double2 *y,
+                      const cplx<T> *khat, const double *xscale, int kind);
 
 void operator_setup(dda_problem *p) {
   // validation, mean permittivity and the compact index map
@@ -401,6 +404,13 @@ void operator_spectrum_setup(dda_problem *p) {
   kernel_spectrum(p, 1);
   zpass_autotune<double>(p, p->khat64);
   zpass_autotune<float>(p, p->khat32);
+  // x / y pass shapes of the operator, on the zero Krylov basis (FP32 only when it is used)
+  const int nt = std::min(p->R, 8);
+  fft_tile_autotune(p, FP_OP_X_FWD, 0, nt,
+                    [&] { op_passes<double>(p, nt, p->V, p->work, p->khat64, nullptr, 0); });
+  if (p->opt.precision == 1)
+    fft_tile_autotune(p, FP_OP_X_FWD, 1, nt,
+                      [&] { op_passes<float>(p, nt, p->V, p->work, p->khat32, nullptr, 0); });
 }
 
 // ----------------------------------------------------------------------------- the product
@@ -593,20 +603,20 @@ static void op_passes(dda_problem *p, int nrhs, const double2 *x, double2 *y,
     a.xscale = xscale;
     launch_rows<T, ROW_OP_FWD, double2, cplx<T>>(
         p, p->px, x, w0, a, sizeof(T) == 8 ? "op_x_fwd_f64" : "op_x_fwd_f32",
-        rows * (4.0 * nx + sz * 2 * nx) + nrhs * 48.0 * p->nocc);
+        rows * (4.0 * nx + sz * 2 * nx) + nrhs * 48.0 * p->nocc, FP_OP_X_FWD);
   }
   // P2: y transform, ny rows zero-padded to 2ny
   launch_strided<T>(p, p->py, w0, w1, (long long)nrhs * 3 * nz, 2LL * nx, ny, 2 * ny,
                     (long long)ny * 2 * nx, p->zplane, -1,
                     sizeof(T) == 8 ? "op_y_fwd_f64" : "op_y_fwd_f32",
-                    nrhs * 3.0 * nz * 2 * nx * (ny + 2.0 * ny) * sz, 3LL * nz);
+                    nrhs * 3.0 * nz * 2 * nx * (ny + 2.0 * ny) * sz, 3LL * nz, FP_OP_Y_FWD);
   // P3: z transform, kernel multiply, inverse z transform (in place)
   zpass<T>(p, nrhs, w1, khat);
   // P4: inverse y transform, keep ny rows
   launch_strided<T>(p, p->py, w1, w0, (long long)nrhs * 3 * nz, 2LL * nx, 2 * ny, ny,
                     p->zplane, (long long)ny * 2 * nx, +1,
                     sizeof(T) == 8 ? "op_y_inv_f64" : "op_y_inv_f32",
-                    nrhs * 3.0 * nz * 2 * nx * (2.0 * ny + ny) * sz, 3LL * nz);
+                    nrhs * 3.0 * nz * 2 * nx * (2.0 * ny + ny) * sz, 3LL * nz, FP_OP_Y_INV);
   // P5: inverse x transform, keep nx, diagonal and mask epilogue
   {
     RowArgs a{};
@@ -629,7 +639,7 @@ static void op_passes(dda_problem *p, int nrhs, const double2 *x, double2 *y,
     if (kind == 0)
       launch_rows<T, ROW_OP_INV, cplx<T>, double2>(
           p, p->px, w0, y, a, sizeof(T) == 8 ? "op_x_inv_f64" : "op_x_inv_f32",
-          rows * (sz * 2 * nx + 4.0 * nx) + nrhs * (96.0 * p->nocc + 16.0 * p->N));
+          rows * (sz * 2 * nx + 4.0 * nx) + nrhs * (96.0 * p->nocc + 16.0 * p->N), FP_OP_X_INV);
     else
       launch_rows<T, ROW_IMG_INV, cplx<T>, double2>(p, p->px, w0, y, a, "imag_x_inv",
                                                     rows * (sz * 2 * nx + 4.0 * nx) + nrhs * 48.0 * p->nocc);

@@ -528,6 +528,10 @@ static double2 alpha_tilde_inv(dda_problem *p, double s_bar) {
   return ldr_alpha_inv(make_double2(best.first, best.second), kd, s_bar);
 }
 
+template <typename T>
+static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, const cplx<T> *binv,
+                     const double *xscale);
+
 void precond_build(dda_problem *p, double s_bar) {
   precond_free(p);
   if (p->opt.precond == 1) {
@@ -629,6 +633,14 @@ void precond_build(dda_problem *p, double s_bar) {
   p->prec_built = 1;
   p->prec_fp32 = fp32;
   diag_setup(p, s_bar);
+  // x / y pass shapes of the apply, on the zero Krylov basis
+  const int nt = std::min(p->R, 8);
+  if (fp32)
+    fft_tile_autotune(p, FP_PC_X_FWD, 1, nt,
+                      [&] { pc_apply<float>(p, nt, p->V, p->work, p->binv32, nullptr); });
+  else
+    fft_tile_autotune(p, FP_PC_X_FWD, 0, nt,
+                      [&] { pc_apply<double>(p, nt, p->V, p->work, p->binv64, nullptr); });
 }
 
 // ----------------------------------------------------------------------------- 1-level
@@ -1084,11 +1096,12 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
     a.xscale = xscale;
     snprintf(nm, sizeof nm, "pc_x_fwd_%s", suf);
     launch_rows<T, ROW_PC_FWD, double2, cplx<T>>(p, p->ux, x, W, a, nm,
-                                                 rows * (4.0 * nx + sz * nx) + nrhs * 48.0 * p->nocc);
+                                                 rows * (4.0 * nx + sz * nx) + nrhs * 48.0 * p->nocc,
+                                                 FP_PC_X_FWD);
   }
   snprintf(nm, sizeof nm, "pc_y_fwd_%s", suf);
   launch_strided<T>(p, p->uy, W, W, (long long)nrhs * 3 * nz, nx, ny, ny, (long long)ny * nx,
-                    (long long)ny * nx, -1, nm, 2.0 * rows * nx * sz, 3LL * nz);
+                    (long long)ny * nx, -1, nm, 2.0 * rows * nx * sz, 3LL * nz, FP_PC_Y_FWD);
   {
     const long long U = (long long)p->umx * p->umy;
     snprintf(nm, sizeof nm, "pc_gemv_%s", suf);
@@ -1149,7 +1162,7 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
   }
   snprintf(nm, sizeof nm, "pc_y_inv_%s", suf);
   launch_strided<T>(p, p->uy, W, W, (long long)nrhs * 3 * nz, nx, ny, ny, (long long)ny * nx,
-                    (long long)ny * nx, +1, nm, 2.0 * rows * nx * sz, 3LL * nz);
+                    (long long)ny * nx, +1, nm, 2.0 * rows * nx * sz, 3LL * nz, FP_PC_Y_INV);
   {
     RowArgs a{};
     a.rows = rows;
@@ -1167,7 +1180,7 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
     a.scale = 1.0 / ((double)nx * ny);
     snprintf(nm, sizeof nm, "pc_x_inv_%s", suf);
     launch_rows<T, ROW_PC_INV, cplx<T>, double2>(p, p->ux, W, y, a, nm,
-                                                 rows * (sz * nx + 4.0 * nx) + nrhs * 48.0 * p->nocc);
+                                                 rows * (sz * nx + 4.0 * nx) + nrhs * 48.0 * p->nocc, FP_PC_X_INV);
   }
 }
 

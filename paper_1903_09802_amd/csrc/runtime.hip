@@ -3,6 +3,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "fft_kernels.h"
 
@@ -166,6 +169,115 @@ void fft_strided_plain(dda_problem *p, const FftPlan &pl, double2 *data, long lo
   launch_strided<double>(p, pl, data, data, batch, width, pl.n, pl.n, (long long)pl.n * width,
                          (long long)pl.n * width, inverse ? 1 : -1, "fft_strided_setup",
                          32.0 * batch * width * pl.n);
+}
+
+// ----------------------------------------------------------------------------- tile shapes
+
+// Candidate shapes of a pass: rows per tile (x passes) halved from the LDS-bound maximum; along
+// a strided axis (y passes) the maximum and half its columns, each with the launch rule's tiles
+// per workgroup and with 1, 2, 4 and 8.
+static std::vector<TileShape> tile_candidates(int max_tw, bool strided) {
+  std::vector<TileShape> c;
+  if (!strided) {
+    for (int tw = max_tw; tw >= 1 && c.size() < 3; tw /= 2) c.push_back(TileShape{tw, 0});
+    return c;
+  }
+  for (int tw : {max_tw, max_tw / 2}) {
+    if (tw < 1) continue;
+    for (int tpw : {0, 1, 2, 4, 8}) c.push_back(TileShape{tw, tpw});
+  }
+  return c;
+}
+
+static std::mutex g_tile_mu;
+static std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<TileShape>> g_tile;
+
+void fft_tile_autotune(dda_problem *p, int first, int pi, int nrhs,
+                       const std::function<void()> &apply) {
+  if (const char *e = getenv("DDA_FFT_TUNE"))
+    if (atoi(e) == 0) return;
+  if (const char *f = getenv("DDA_FFT_FORCE")) {  // "rows,columns,tiles": every pass, for tests
+    int rtw = 0, stw = 0, stpw = 0;
+    REQUIRE(sscanf(f, "%d,%d,%d", &rtw, &stw, &stpw) == 3 && rtw >= 1 && stw >= 1 && stpw >= 1,
+            DDA_EINVAL, "DDA_FFT_FORCE=\"%s\": want \"rows,columns,tiles\", each >= 1", f);
+    for (int k = 0; k < 4; ++k)
+      p->tile[first + k][pi] = (k == 1 || k == 2) ? TileShape{stw, stpw} : TileShape{rtw, 0};
+    return;
+  }
+  const bool op = first == FP_OP_X_FWD;
+  const auto key = std::make_tuple(p->dev, p->nx, p->ny, p->nz, nrhs, pi, first);
+  {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    const auto it = g_tile.find(key);
+    if (it != g_tile.end()) {
+      for (int k = 0; k < 4; ++k) p->tile[first + k][pi] = it->second[k];
+      return;
+    }
+  }
+  const FftPlan *plans[4] = {op ? &p->px : &p->ux, op ? &p->py : &p->uy, op ? &p->py : &p->uy,
+                             op ? &p->px : &p->ux};
+  const char *stem[4] = {"x_fwd", "y_fwd", "y_inv", "x_inv"};
+  std::vector<TileShape> cand[4];
+  char name[4][32];
+  size_t rounds = 0;
+  for (int k = 0; k < 4; ++k) {
+    const int n = plans[k]->n;
+    const int max_tw = pi == 0 ? tile_cols<double>(n) : tile_cols<float>(n);
+    cand[k] = tile_candidates(max_tw, k == 1 || k == 2);
+    rounds = std::max(rounds, cand[k].size());
+    snprintf(name[k], sizeof name[k], "%s_%s_%s", op ? "op" : "pc", stem[k], pi == 0 ? "f64" : "f32");
+  }
+  // time with a profiler of its own and every right-hand side live
+  Profiler saved;
+  std::swap(saved, p->prof);
+  p->prof.on = true;
+  const int *act = p->act;
+  p->act = nullptr;
+  TileShape best[4];
+  double best_ms[4] = {1e30, 1e30, 1e30, 1e30};
+  try {
+    for (int k = 0; k < 4; ++k) p->tile[first + k][pi] = TileShape{};
+    apply();  // warm
+    HIPCHK(hipStreamSynchronize(p->st));
+    p->prof.collect();
+    for (size_t c = 0; c < rounds; ++c) {
+      for (int k = 0; k < 4; ++k) p->tile[first + k][pi] = cand[k][std::min(c, cand[k].size() - 1)];
+      p->prof.reset();
+      for (int rep = 0; rep < 3; ++rep) apply();
+      HIPCHK(hipStreamSynchronize(p->st));
+      p->prof.collect();
+      for (int k = 0; k < 4; ++k) {
+        if (c >= cand[k].size()) continue;
+        for (const auto &kd : p->prof.kinds) {
+          if (kd.name != name[k] || kd.ms.empty()) continue;
+          double t = 0;
+          for (float v : kd.ms) t += v;
+          t /= kd.ms.size();
+          // a shape other than the first must win by 3 %, so timing noise keeps the rule's
+          if (t < best_ms[k] * (c == 0 ? 1.0 : 0.97)) {
+            best_ms[k] = t;
+            best[k] = cand[k][c];
+          }
+        }
+      }
+    }
+  } catch (...) {
+    p->prof.destroy();
+    std::swap(saved, p->prof);
+    p->act = act;
+    throw;
+  }
+  p->prof.destroy();
+  std::swap(saved, p->prof);
+  p->act = act;
+  std::vector<TileShape> chosen(4);
+  for (int k = 0; k < 4; ++k) {
+    // the first candidate is the launch rule's own shape: keep it as "rule" (zeros)
+    chosen[k] = (best[k].tw == cand[k][0].tw && best[k].tpw == cand[k][0].tpw) ? TileShape{} : best[k];
+    p->tile[first + k][pi] = chosen[k];
+  }
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tile[key] = chosen;
 }
 
 }  // namespace dda
