@@ -299,7 +299,7 @@ def main():
     for a in agg.values():
         a["bytes"] = a["total_bytes"] / max(1, a["launches"])
     kernels = sorted(agg.items(), key=lambda kv: -kv[1]["total_ms"])
-    hbm = [kv for kv in kernels if not kv[0].startswith(("pc_gj", "pc_assemble", "fft_rows_setup",
+    hbm = [kv for kv in kernels if not kv[0].startswith(("pc_gj", "pc_sweep", "pc_assemble", "fft_rows_setup",
                                                          "fft_strided_setup"))]
     dom_name, dom = hbm[0]
     avg_ms = dom["total_ms"] / max(1, dom["launches"])

@@ -412,6 +412,178 @@ template <typename V> static void gj_launch(dda_problem *p, V *mats, long long c
   HIPCHK(hipGetLastError());
 }
 
+// Batched inverse of complex symmetric n x n matrices (B^T = B, FP64 or FP32) by the blocked
+// symmetric sweep, one workgroup each: Gauss-Jordan elimination without row exchanges between
+// panels, which keeps every intermediate matrix symmetric, so only the upper triangle (row
+// major, column j >= row i) is read and written, half the passes over the matrix that
+// k_gj_inverse makes.  For each panel K of NB pivots:
+//   G = A_KK^{-1} (Gauss-Jordan with partial pivoting inside the NB x NB block, on [A_KK | I]),
+//   U_i = A_iK G for the rows i outside K,
+//   A_ij -= U_i A_Kj (i, j outside K), A_iK = U_i, A_KK = -G,
+// after which the upper triangle holds -B^{-1}.  A diagonal block whose pivot falls below
+// 1e-13 (FP64) or 1e-6 (FP32) of its largest entry sets flag[1]: the caller then inverts the
+// same blocks with k_gj_inverse (tiny2 is the squared bound).
+template <int NB, int NT, typename V>
+__global__ void __launch_bounds__(NT) k_sym_sweep(V *mats, int n, int *flag, double tiny2) {
+  using R = typename RealOf<V>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V *Pn = reinterpret_cast<V *>(smem_raw);  // [n][NB] panel columns A_iK before the panel
+  V *Un = Pn + (size_t)n * NB;              // [n][NB] U_i
+  __shared__ V aug[NB][2 * NB];             // [A_KK | I] -> [I | G]
+  const int tid = threadIdx.x;
+  V *A = mats + (long long)blockIdx.x * n * n;
+  const R tiny = (R)tiny2;  // squared relative pivot bound
+  for (int k0 = 0; k0 < n; k0 += NB) {
+    const int kb = min(NB, n - k0), k1 = k0 + kb;
+    // the panel's columns: rows above the block and the block by rows, rows below by columns
+    for (int e = tid; e < k1 * NB; e += NT) {
+      const int i = e / NB, c = e - i * NB, k = k0 + c;
+      Pn[e] = c < kb ? (i <= k ? A[(long long)i * n + k] : A[(long long)k * n + i]) : mk<R>((R)0, (R)0);
+    }
+    for (int e = tid; e < (n - k1) * NB; e += NT) {
+      const int c = e / (n - k1), i = k1 + (e - c * (n - k1));
+      Pn[i * NB + c] = c < kb ? A[(long long)(k0 + c) * n + i] : mk<R>((R)0, (R)0);
+    }
+    __syncthreads();
+    // G by one wave: Gauss-Jordan with partial pivoting on [A_KK | I]
+    if (tid < 64) {
+      for (int e = tid; e < NB * 2 * NB; e += 64) {
+        const int r = e / (2 * NB), c = e - r * 2 * NB;
+        V v = mk<R>((R)0, (R)0);
+        if (c < NB) v = (r < kb && c < kb) ? Pn[(k0 + r) * NB + c] : mk<R>(r == c ? (R)1 : (R)0, (R)0);
+        else v = mk<R>(c - NB == r ? (R)1 : (R)0, (R)0);
+        aug[r][c] = v;
+      }
+      R m = (R)0;
+      for (int e = tid; e < kb * kb; e += 64) {
+        const V v = aug[e / kb][e % kb];
+        m = fmax(m, v.x * v.x + v.y * v.y);
+      }
+      for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+      __builtin_amdgcn_wave_barrier();
+      for (int kk = 0; kk < kb; ++kk) {
+        // pivot row: largest |aug[r][kk]| over r >= kk (lanes < 16 hold the candidates)
+        R bv = (R)-1;
+        int bi = kk;
+        if (tid >= kk && tid < kb) {
+          const V v = aug[tid][kk];
+          bv = v.x * v.x + v.y * v.y;
+          bi = tid;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const R ov = __shfl_xor(bv, off, 64);
+          const int oi = __shfl_xor(bi, off, 64);
+          if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+          }
+        }
+        if (!(bv > tiny * m) && tid == 0) atomicExch(flag + 1, 1);
+        __builtin_amdgcn_wave_barrier();
+        // swap rows kk and bi, scale the pivot row
+        if (tid < 2 * NB) {
+          const V a = aug[kk][tid], b = aug[bi][tid];
+          aug[bi][tid] = a;
+          aug[kk][tid] = b;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        const V pv = aug[kk][kk];
+        const R pm = pv.x * pv.x + pv.y * pv.y;
+        const V ipv = pm > (R)0 ? mk<R>(pv.x / pm, -pv.y / pm) : mk<R>((R)0, (R)0);
+        __builtin_amdgcn_wave_barrier();
+        if (tid < 2 * NB) aug[kk][tid] = cmul(aug[kk][tid], ipv);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        // eliminate column kk from the other rows: lane handles columns c = lane % 32, rows
+        // r = lane / 32 + 2 q
+        V f[NB / 2], pr;
+        const int c = tid & 31, r0 = tid >> 5;
+        pr = c < 2 * NB ? aug[kk][c] : mk<R>((R)0, (R)0);
+#pragma unroll
+        for (int q = 0; q < NB / 2; ++q) f[q] = aug[r0 + 2 * q][kk];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < NB / 2; ++q) {
+          const int r = r0 + 2 * q;
+          if (r != kk && c < 2 * NB) aug[r][c] = csub(aug[r][c], cmul(f[q], pr));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    // U = A_iK G for the rows outside the block
+    for (int e = tid; e < n * NB; e += NT) {
+      const int i = e / NB, c = e - i * NB;
+      V u = mk<R>((R)0, (R)0);
+      if (c < kb && (i < k0 || i >= k1))
+        for (int cc = 0; cc < kb; ++cc) u = cadd(u, cmul(Pn[i * NB + cc], aug[cc][NB + c]));
+      Un[e] = u;
+    }
+    __syncthreads();
+    // the upper triangle in items of up to 16 rows of one column (row block b, column j >= 16 b;
+    // consecutive items are consecutive columns of a block, so loads coalesce): trailing
+    // update, the panel's entries, the block
+    const int nrb = (n + 15) / 16;
+    const int items = nrb * n - 8 * nrb * (nrb - 1);  // sum over b of n - 16 b
+    for (int w = tid; w < items; w += NT) {
+      int b = 0, rem = w;
+      while (rem >= n - 16 * b) {
+        rem -= n - 16 * b;
+        ++b;
+      }
+      const int j = 16 * b + rem;
+      const int i0 = 16 * b, i1 = min(j + 1, i0 + 16);
+      V *colj = A + j;
+      if (j >= k0 && j < k1) {  // a column of the block: rows above it take U, the block -G
+        for (int i = i0; i < i1; ++i)
+          colj[(long long)i * n] = i >= k0 ? mk<R>(-aug[i - k0][NB + j - k0].x, -aug[i - k0][NB + j - k0].y)
+                                           : Un[i * NB + (j - k0)];
+        continue;
+      }
+      V aj[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) aj[c] = Pn[j * NB + c];
+      V av[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) av[u] = i0 + u < i1 ? colj[(long long)(i0 + u) * n] : mk<R>((R)0, (R)0);
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int i = i0 + u;
+        if (i >= i1) continue;
+        V acc;
+        if (i >= k0 && i < k1) {
+          acc = Un[j * NB + (i - k0)];  // entry (i in K, j below K) is the panel's A_jK, now U_j
+        } else {
+          acc = av[u];
+#pragma unroll
+          for (int c = 0; c < NB; ++c) acc = csub(acc, cmul(Un[i * NB + c], aj[c]));
+        }
+        colj[(long long)i * n] = acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Launch k_sym_sweep: 16-pivot panels while the two n x NB panel arrays fit the LDS, 8 above.
+template <typename V> static int sweep_nb(int n) {
+  return (size_t)2 * n * 16 * sizeof(V) <= 96 * 1024 ? 16 : 8;
+}
+template <typename V> static size_t sweep_lds(int n) { return (size_t)2 * n * sweep_nb<V>(n) * sizeof(V); }
+template <typename V> static void sweep_launch(dda_problem *p, V *mats, long long cnt, int n) {
+  const size_t lds = sweep_lds<V>(n);
+  auto fn = sweep_nb<V>(n) == 16 ? k_sym_sweep<16, 512, V> : k_sym_sweep<8, 512, V>;
+  set_lds_limit((const void *)fn, lds);
+  // squared relative pivot bound; DDA_SWEEP_FALLBACK=1 flags every block (tests of the fallback)
+  double tiny2 = sizeof(V) == sizeof(double2) ? 1e-26 : 1e-12;
+  if (const char *e = getenv("DDA_SWEEP_FALLBACK"))
+    if (atoi(e) != 0) tiny2 = 1e30;
+  hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(512), lds, p->st, mats, n, p->dflag, tiny2);
+  HIPCHK(hipGetLastError());
+}
+
 __global__ void k_to_f32(const double2 *in, float2 *out, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
@@ -426,7 +598,8 @@ __host__ __device__ __forceinline__ int tile_pos(int r, int c) { return r + 16 *
 
 // Pack the lower-triangle tiles (I >= J, tile t = I (I + 1) / 2 + J) of `cnt` symmetric
 // row-major n2 x n2 matrices into out + m0 * tiles * 256; entries beyond n2 are zero.
-template <typename TI, typename TO>
+// With NEG_UPPER the matrices hold -B^{-1} in their upper triangle only (k_sym_sweep).
+template <typename TI, typename TO, bool NEG_UPPER>
 __global__ void k_pack_sym(const TI *Y, TO *out, long long m0, int n2, int ntr) {
   const long long tiles = (long long)ntr * (ntr + 1) / 2;
   const TI *Ym = Y + (long long)blockIdx.x * n2 * n2;
@@ -441,7 +614,15 @@ __global__ void k_pack_sym(const TI *Y, TO *out, long long m0, int n2, int ntr) 
     // invert tile_pos: w = r + 16 (c % 4) + 64 (c / 4)
     const int r = w & 15, c = 4 * (w >> 6) + ((w >> 4) & 3);
     const int row = 16 * I + r, col = 16 * J + c;
-    const double2 v = (row < n2 && col < n2) ? to_d(Ym[(long long)row * n2 + col]) : make_double2(0.0, 0.0);
+    double2 v = make_double2(0.0, 0.0);
+    if (row < n2 && col < n2) {
+      if (NEG_UPPER) {
+        v = to_d(Ym[(long long)min(row, col) * n2 + max(row, col)]);
+        v = make_double2(-v.x, -v.y);
+      } else {
+        v = to_d(Ym[(long long)row * n2 + col]);
+      }
+    }
     o[t * 256 + w] = to_c(v, TO{});
   }
 }
@@ -586,12 +767,18 @@ void precond_build(dda_problem *p, double s_bar) {
     const size_t lds_asm = sizeof(double2) * 6 * S;
     set_lds_limit((const void *)k_assemble<double2>, lds_asm);
     set_lds_limit((const void *)k_assemble<float2>, lds_asm);
-    const size_t lds_gj = fp32 ? gj_lds<float2>(p->n2) : gj_lds<double2>(p->n2);
+    const size_t lds_gj = std::max(fp32 ? gj_lds<float2>(p->n2) : gj_lds<double2>(p->n2),
+                                   p->psym ? (fp32 ? sweep_lds<float2>(p->n2) : sweep_lds<double2>(p->n2)) : 0);
     REQUIRE(p->n2 <= kGJMaxOrder, DDA_EUNSUPPORTED, "half-block order %d above %d", p->n2, kGJMaxOrder);
     const size_t lds_cap = std::max(p->lds_max, kLdsMax);
     REQUIRE(lds_gj <= lds_cap && lds_asm <= lds_cap, DDA_EUNSUPPORTED,
             "preconditioner blocks too large for LDS (nz = %d)", nz);
     HIPCHK(hipMemsetAsync(p->dflag, 0, sizeof(int) * 4, p->st));
+    // symmetric blocks (even nz) are inverted by the symmetric sweep, unless one of its
+    // diagonal blocks needs a row exchange from outside it: then the whole build is redone
+    // with pivoted Gauss-Jordan
+    bool sweep = p->psym != 0;
+    if (const char *e = getenv("DDA_GJ_ONLY")) sweep = sweep && atoi(e) == 0;
     auto run = [&](auto *dst, auto *final_out, long long m0, long long cnt) {
       using V = std::remove_pointer_t<decltype(dst)>;
       {
@@ -600,27 +787,37 @@ void precond_build(dda_problem *p, double s_bar) {
                            m0, nx, ny, nz, p->umx, p->hh, p->n2, p->ati, p->psym);
         HIPCHK(hipGetLastError());
       }
-      {
+      if (sweep) {
+        KTimer t(&p->prof, p->st, "pc_sweep_inverse", esz * cnt * (double)msz);
+        sweep_launch<V>(p, dst, cnt, p->n2);
+      } else {
         KTimer t(&p->prof, p->st, "pc_gj_inverse", 2.0 * esz * cnt * msz);
         gj_launch<V>(p, dst, cnt, p->n2);
       }
       if (p->psym) {
-        hipLaunchKernelGGL((k_pack_sym<V, std::remove_pointer_t<decltype(final_out)>>),
-                           dim3((unsigned)cnt), dim3(256), 0, p->st, dst, final_out, m0, p->n2,
+        using TO = std::remove_pointer_t<decltype(final_out)>;
+        auto pk = sweep ? k_pack_sym<V, TO, true> : k_pack_sym<V, TO, false>;
+        hipLaunchKernelGGL(pk, dim3((unsigned)cnt), dim3(256), 0, p->st, dst, final_out, m0, p->n2,
                            p->ntr);
         HIPCHK(hipGetLastError());
       }
     };
-    for (long long m0 = 0; m0 < nmat; m0 += chunk) {
-      const long long cnt = std::min(chunk, nmat - m0);
-      if (fp32)
-        run(p->psym ? reinterpret_cast<float2 *>(scratch) : p->binv32 + m0 * msz, p->binv32, m0, cnt);
-      else
-        run(p->psym ? scratch : p->binv64 + m0 * msz, p->binv64, m0, cnt);
-    }
     int hflag[4] = {0, 0, 0, 0};
-    HIPCHK(hipMemcpyAsync(hflag, p->dflag, sizeof(int) * 4, hipMemcpyDeviceToHost, p->st));
-    HIPCHK(hipStreamSynchronize(p->st));
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      for (long long m0 = 0; m0 < nmat; m0 += chunk) {
+        const long long cnt = std::min(chunk, nmat - m0);
+        if (fp32)
+          run(p->psym ? reinterpret_cast<float2 *>(scratch) : p->binv32 + m0 * msz, p->binv32, m0, cnt);
+        else
+          run(p->psym ? scratch : p->binv64 + m0 * msz, p->binv64, m0, cnt);
+      }
+      HIPCHK(hipMemcpyAsync(hflag, p->dflag, sizeof(int) * 4, hipMemcpyDeviceToHost, p->st));
+      HIPCHK(hipStreamSynchronize(p->st));
+      if (!(sweep && hflag[1])) break;
+      sweep = false;  // a diagonal block of the sweep needed an outside pivot: Gauss-Jordan
+      HIPCHK(hipMemsetAsync(p->dflag, 0, sizeof(int) * 4, p->st));
+    }
+    p->prec_sweep = sweep ? 1 : 0;
     REQUIRE(hflag[0] == 0, DDA_EDEVICE, "a preconditioner block is singular");
   } catch (...) {
     if (gen) (void)hipFree(gen);
