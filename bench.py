@@ -401,6 +401,8 @@ def main():
         config=dict(workload=desc, grid=list(s.shape), n_occupied=int(s.n_occ), nrhs=nrhs,
                     size_parameter=s.meta.get("x"), restart=30, tol=tol),
         precond_iters=p_iters, precond_rel_residual=p_res, converged=converged,
+        phases_ms=dict(create=1e3 * last["stats"][0]["t_setup"], build=1e3 * last["stats"][0]["t_build"],
+                       solve=1e3 * last["stats"][0]["t_solve"]),
         cext=last["cext"].tolist(), cabs=last["cabs"].tolist(), csca=last["csca"].tolist(),
         xsec_rel_dev_vs_oracle_golden=golden_deviation(last["cext"].tolist(), last["csca"].tolist()),
         step_s_unprofiled=unprofiled, plain=plain, bicgstab=bicg, matvec_ms=1000 * t_mv, matvec_GBps=matvec_gbps,

@@ -404,13 +404,16 @@ void operator_spectrum_setup(dda_problem *p) {
   kernel_spectrum(p, 1);
   zpass_autotune<double>(p, p->khat64);
   zpass_autotune<float>(p, p->khat32);
-  // x / y pass shapes of the operator, on the zero Krylov basis (FP32 only when it is used)
+  // x / y pass shapes of the operator, on the zero Krylov basis, in the precision the Krylov
+  // iterations run in (FP32 refinement applies the FP64 product only for its few outer
+  // residuals, which keep the launch rule's shapes)
   const int nt = std::min(p->R, 8);
-  fft_tile_autotune(p, FP_OP_X_FWD, 0, nt,
-                    [&] { op_passes<double>(p, nt, p->V, p->work, p->khat64, nullptr, 0); });
   if (p->opt.precision == 1)
     fft_tile_autotune(p, FP_OP_X_FWD, 1, nt,
                       [&] { op_passes<float>(p, nt, p->V, p->work, p->khat32, nullptr, 0); });
+  else
+    fft_tile_autotune(p, FP_OP_X_FWD, 0, nt,
+                      [&] { op_passes<double>(p, nt, p->V, p->work, p->khat64, nullptr, 0); });
 }
 
 // ----------------------------------------------------------------------------- the product

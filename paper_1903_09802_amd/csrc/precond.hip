@@ -26,6 +26,7 @@
 // the full halves are stored column-major.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <type_traits>
 
@@ -412,6 +413,90 @@ template <typename V> static void gj_launch(dda_problem *p, V *mats, long long c
   HIPCHK(hipGetLastError());
 }
 
+// 16 x 16 x 4 matrix instruction of each precision.  Lane l = r + 16 q supplies A[r][q] and
+// B[q][r]; item m of its result holds D[row(q, m)][r].
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of D held in item m of a lane of k-slot q (column = lane % 16)
+  static __device__ __forceinline__ int row(int q, int m) { return q + 4 * m; }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int m) { return 4 * q + m; }
+};
+
+// Gauss-Jordan with partial pivoting on the NB x 2NB block [A_KK | I] in aug, by the 64 lanes
+// of one wave (lane = tid < 64): on return aug[.][NB, 2NB) holds G = A_KK^{-1} for the
+// leading kb x kb block.  A pivot whose squared modulus falls below tiny times the block's
+// largest sets flag[1].
+template <int NB, typename V, typename R>
+__device__ __forceinline__ void sweep_gj_wave(V (*aug)[2 * NB], int kb, int tid, int *flag, R tiny) {
+  R m = (R)0;
+  for (int e = tid; e < kb * kb; e += 64) {
+    const V v = aug[e / kb][e % kb];
+    m = fmax(m, v.x * v.x + v.y * v.y);
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  __builtin_amdgcn_wave_barrier();
+  for (int kk = 0; kk < kb; ++kk) {
+    // pivot row: largest |aug[r][kk]| over r >= kk (lanes < 16 hold the candidates)
+    R bv = (R)-1;
+    int bi = kk;
+    if (tid >= kk && tid < kb) {
+      const V v = aug[tid][kk];
+      bv = v.x * v.x + v.y * v.y;
+      bi = tid;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const R ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (!(bv > tiny * m) && tid == 0) atomicExch(flag + 1, 1);
+    __builtin_amdgcn_wave_barrier();
+    // swap rows kk and bi, scale the pivot row
+    if (tid < 2 * NB) {
+      const V a = aug[kk][tid], b = aug[bi][tid];
+      aug[bi][tid] = a;
+      aug[kk][tid] = b;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    const V pv = aug[kk][kk];
+    const R pm = pv.x * pv.x + pv.y * pv.y;
+    const V ipv = pm > (R)0 ? mk<R>(pv.x / pm, -pv.y / pm) : mk<R>((R)0, (R)0);
+    __builtin_amdgcn_wave_barrier();
+    if (tid < 2 * NB) aug[kk][tid] = cmul(aug[kk][tid], ipv);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    // eliminate column kk from the other rows: lane handles columns c = lane % 32, rows
+    // r = lane / 32 + 2 q
+    V f[NB / 2], pr;
+    const int c = tid & 31, r0 = tid >> 5;
+    pr = c < 2 * NB ? aug[kk][c] : mk<R>((R)0, (R)0);
+#pragma unroll
+    for (int q = 0; q < NB / 2; ++q) f[q] = aug[r0 + 2 * q][kk];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < NB / 2; ++q) {
+      const int r = r0 + 2 * q;
+      if (r != kk && c < 2 * NB) aug[r][c] = csub(aug[r][c], cmul(f[q], pr));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // Batched inverse of complex symmetric n x n matrices (B^T = B, FP64 or FP32) by the blocked
 // symmetric sweep, one workgroup each: Gauss-Jordan elimination without row exchanges between
 // panels, which keeps every intermediate matrix symmetric, so only the upper triangle (row
@@ -454,63 +539,7 @@ __global__ void __launch_bounds__(NT) k_sym_sweep(V *mats, int n, int *flag, dou
         else v = mk<R>(c - NB == r ? (R)1 : (R)0, (R)0);
         aug[r][c] = v;
       }
-      R m = (R)0;
-      for (int e = tid; e < kb * kb; e += 64) {
-        const V v = aug[e / kb][e % kb];
-        m = fmax(m, v.x * v.x + v.y * v.y);
-      }
-      for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-      __builtin_amdgcn_wave_barrier();
-      for (int kk = 0; kk < kb; ++kk) {
-        // pivot row: largest |aug[r][kk]| over r >= kk (lanes < 16 hold the candidates)
-        R bv = (R)-1;
-        int bi = kk;
-        if (tid >= kk && tid < kb) {
-          const V v = aug[tid][kk];
-          bv = v.x * v.x + v.y * v.y;
-          bi = tid;
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-          const R ov = __shfl_xor(bv, off, 64);
-          const int oi = __shfl_xor(bi, off, 64);
-          if (ov > bv || (ov == bv && oi < bi)) {
-            bv = ov;
-            bi = oi;
-          }
-        }
-        if (!(bv > tiny * m) && tid == 0) atomicExch(flag + 1, 1);
-        __builtin_amdgcn_wave_barrier();
-        // swap rows kk and bi, scale the pivot row
-        if (tid < 2 * NB) {
-          const V a = aug[kk][tid], b = aug[bi][tid];
-          aug[bi][tid] = a;
-          aug[kk][tid] = b;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-        __builtin_amdgcn_wave_barrier();
-        const V pv = aug[kk][kk];
-        const R pm = pv.x * pv.x + pv.y * pv.y;
-        const V ipv = pm > (R)0 ? mk<R>(pv.x / pm, -pv.y / pm) : mk<R>((R)0, (R)0);
-        __builtin_amdgcn_wave_barrier();
-        if (tid < 2 * NB) aug[kk][tid] = cmul(aug[kk][tid], ipv);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-        __builtin_amdgcn_wave_barrier();
-        // eliminate column kk from the other rows: lane handles columns c = lane % 32, rows
-        // r = lane / 32 + 2 q
-        V f[NB / 2], pr;
-        const int c = tid & 31, r0 = tid >> 5;
-        pr = c < 2 * NB ? aug[kk][c] : mk<R>((R)0, (R)0);
-#pragma unroll
-        for (int q = 0; q < NB / 2; ++q) f[q] = aug[r0 + 2 * q][kk];
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int q = 0; q < NB / 2; ++q) {
-          const int r = r0 + 2 * q;
-          if (r != kk && c < 2 * NB) aug[r][c] = csub(aug[r][c], cmul(f[q], pr));
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-        __builtin_amdgcn_wave_barrier();
-      }
+      sweep_gj_wave<NB>(aug, kb, tid, flag, tiny);
     }
     __syncthreads();
     // U = A_iK G for the rows outside the block
@@ -567,20 +596,643 @@ __global__ void __launch_bounds__(NT) k_sym_sweep(V *mats, int n, int *flag, dou
   }
 }
 
-// Launch k_sym_sweep: 16-pivot panels while the two n x NB panel arrays fit the LDS, 8 above.
+// The symmetric sweep of k_sym_sweep with 16-pivot panels and every tile product on the matrix
+// cores.  The matrix is taken as 16 x 16 tiles (I, J), I <= J, padded to 16 nrb with the
+// identity; diagonal tiles are kept whole (both triangles).  For panel K:
+//   (1) wave 0 inverts A_KK by pivoted Gauss-Jordan (sweep_gj_wave), while the other waves
+//       store the previous panel (A_IK = U_I above the diagonal tile, A_KJ = U_J^T right of it);
+//   (2) -U_I = -A_IK G for every I != K, into LDS (16 x 16 x 16 complex products);
+//   (3) A_IJ -= U_I A_JK^T over the stored tiles outside row and column K, the tile held in
+//       the instruction's accumulators: complex products as four real ones,
+//       Re += (-Re U) Re P - (-Im U) Im P,  Im += (-Re U) Im P + (-Im U) Re P;
+// then A_KK = -G.  The result, flags and fallback are those of k_sym_sweep.
+template <typename T, int NW, bool PAD>
+__global__ void __launch_bounds__(64 * NW, 4) k_sym_sweep_mfma(cplx<T> *mats, int n, int *flag, double tiny2) {
+  using V = cplx<T>;
+  using MF = Mfma<T>;
+  using v4 = typename MF::v4;
+  constexpr int US = 17;  // row stride of Un (complex entries), padded against bank conflicts
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V *Un = reinterpret_cast<V *>(smem_raw);  // [16 nrb][US]: -U_i of the current panel
+  __shared__ V aug[16][32];                 // [A_KK | I] -> [I | G]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int nrb = (n + 15) / 16, tiles = nrb * (nrb + 1) / 2;
+  V *A = mats + (long long)blockIdx.x * n * n;
+  const T tiny = (T)tiny2;
+  // entry (row, col) of the identity-padded matrix (PAD: n not a multiple of 16); only stored
+  // tiles are addressed.  The load is unconditional (from the matrix's first entry when
+  // outside) and the padding is blended in arithmetically (a select would be turned back into
+  // a branch around the load), so that loads are not serialised behind branches.
+  auto at = [&](int row, int col) -> V {
+    if constexpr (!PAD) return A[(long long)row * n + col];
+    const bool in = row < n && col < n;
+    const V v = A[in ? (long long)row * n + col : 0LL];
+    const T w = in ? (T)1 : (T)0, id = (!in && row == col) ? (T)1 : (T)0;
+    return mk<T>(v.x * w + id, v.y * w);
+  };
+  auto put = [&](int row, int col, V v) {
+    if (!PAD || (row < n && col < n)) A[(long long)row * n + col] = v;
+  };
+  for (int K = 0; K <= nrb; ++K) {
+    const int Kp = K - 1;  // the previous panel, stored now
+    if (wv == 0) {
+      if (Kp >= 0)
+        for (int e = lane; e < 256; e += 64)
+          put(16 * Kp + (e >> 4), 16 * Kp + (e & 15), mk<T>(-aug[e >> 4][16 + (e & 15)].x, -aug[e >> 4][16 + (e & 15)].y));
+      if (K < nrb) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        for (int e = lane; e < 512; e += 64) {
+          const int a = e >> 5, c = e & 31;
+          aug[a][c] = c < 16 ? at(16 * K + a, 16 * K + c) : mk<T>(c - 16 == a ? (T)1 : (T)0, (T)0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        sweep_gj_wave<16>(aug, 16, lane, flag, tiny);
+      }
+    } else if (Kp >= 0) {
+      for (int e = tid - 64; e < nrb * 256; e += 64 * (NW - 1)) {
+        const int I = e >> 8, a = (e >> 4) & 15, b = e & 15;
+        if (I < Kp) {
+          const V u = Un[(16 * I + a) * US + b];
+          put(16 * I + a, 16 * Kp + b, mk<T>(-u.x, -u.y));
+        } else if (I > Kp) {
+          const V u = Un[(16 * I + b) * US + a];
+          put(16 * Kp + a, 16 * I + b, mk<T>(-u.x, -u.y));
+        }
+      }
+    }
+    if (K == nrb) break;
+    __syncthreads();
+    // (2) -U_I = -A_IK G
+    for (int I = wv; I < nrb; I += NW) {
+      if (I == K) continue;
+      v4 ur = {0, 0, 0, 0}, ui = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int k = 4 * kk + q;
+        const V a = at(I < K ? 16 * I + r : 16 * K + k, I < K ? 16 * K + k : 16 * I + r);  // A_IK[r][k]
+        const V g = aug[k][16 + r];
+        ur = MF::mma(a.x, g.x, ur);
+        ur = MF::mma(-a.y, g.y, ur);
+        ui = MF::mma(a.x, g.y, ui);
+        ui = MF::mma(a.y, g.x, ui);
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) Un[(16 * I + MF::row(q, m)) * US + r] = mk<T>(-ur[m], -ui[m]);
+    }
+    __syncthreads();
+    // (3) trailing update of the stored tiles outside row and column K (t = J (J + 1) / 2 + I),
+    // each tile's entries and panel operand loaded while the previous tile is multiplied
+    auto decode = [&](int t, int &I, int &J) {
+      J = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+      while (J * (J + 1) / 2 > t) --J;
+      while ((J + 1) * (J + 2) / 2 <= t) ++J;
+      I = t - J * (J + 1) / 2;
+    };
+    auto fetch = [&](int I, int J, v4 &cr, v4 &ci, V (&pj)[4]) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const V c = at(16 * I + MF::row(q, m), 16 * J + r);
+        cr[m] = c.x;
+        ci[m] = c.y;
+      }
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int k = 4 * kk + q;
+        pj[kk] = at(J < K ? 16 * J + r : 16 * K + k, J < K ? 16 * K + k : 16 * J + r);  // A_JK[r][k]
+      }
+    };
+    v4 cr, ci;
+    V pj[4];
+    int I = 0, J = 0;
+    if (wv < tiles) {
+      decode(wv, I, J);
+      fetch(I, J, cr, ci, pj);
+    }
+    for (int t = wv; t < tiles; t += NW) {
+      v4 ncr, nci;
+      V npj[4];
+      int nI = 0, nJ = 0;
+      if (t + NW < tiles) {
+        decode(t + NW, nI, nJ);
+        fetch(nI, nJ, ncr, nci, npj);
+      }
+      if (I != K && J != K) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const V nu = Un[(16 * I + r) * US + 4 * kk + q];  // -U_I[r][k]
+          cr = MF::mma(nu.x, pj[kk].x, cr);
+          cr = MF::mma(-nu.y, pj[kk].y, cr);
+          ci = MF::mma(nu.x, pj[kk].y, ci);
+          ci = MF::mma(nu.y, pj[kk].x, ci);
+          if (kk & 1) __builtin_amdgcn_sched_barrier(0);  // two LDS operands ahead at most
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) put(16 * I + MF::row(q, m), 16 * J + r, mk<T>(cr[m], ci[m]));
+      }
+      cr = ncr;
+      ci = nci;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) pj[kk] = npj[kk];
+      I = nI;
+      J = nJ;
+    }
+    __syncthreads();
+  }
+}
+
+// D = C0 + sgn op(A) op(B) for 16 x 16 complex matrices in LDS (row strides lda, ldb, ldc0, ldd;
+// op transposes when ta / tb; C0 may be null or equal to D), on the matrix cores by one wave.
+// D must not overlap A or B.
+template <typename T>
+__device__ __forceinline__ void wave_cmm16(const cplx<T> *A, int lda, bool ta, const cplx<T> *B, int ldb,
+                                           bool tb, const cplx<T> *C0, int ldc0, T sgn, cplx<T> *D,
+                                           int ldd, int lane) {
+  using MF = Mfma<T>;
+  using v4 = typename MF::v4;
+  using V = cplx<T>;
+  const int r = lane & 15, q = lane >> 4;
+  v4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = 4 * kk + q;
+    const V a = ta ? A[k * lda + r] : A[r * lda + k];  // op(A)[r][k]
+    const V b = tb ? B[r * ldb + k] : B[k * ldb + r];  // op(B)[k][r]
+    dr = MF::mma(a.x, b.x, dr);
+    dr = MF::mma(-a.y, b.y, dr);
+    di = MF::mma(a.x, b.y, di);
+    di = MF::mma(a.y, b.x, di);
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int row = MF::row(q, m);
+    const V c = C0 ? C0[row * ldc0 + r] : mk<T>((T)0, (T)0);
+    D[row * ldd + r] = mk<T>(c.x + sgn * dr[m], c.y + sgn * di[m]);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// The streamed sweep with 32-pivot panels (tile columns K0 = 2P and K1 = 2P + 1), which halves
+// the passes over the matrix.  The order is padded with the identity to an even number of
+// tiles.  The 32 x 32 diagonal block [[A00, A01], [A01^T, A11]] is inverted by wave 0 from its
+// two 16 x 16 blocks: G00 = A00^{-1} and G11 = S^{-1} with S = A11 - A01^T W, W = G00 A01, by
+// pivoted Gauss-Jordan (sweep_gj_wave, so pivoting and its flag are those of two 16-pivot
+// panels), then G01 = -W G11 and G00 += -G01 W^T.  Per panel:
+//   (2) -U_I = -[A_IK0 | A_IK1] G for the rows outside the panel, into LDS;
+//   (3a) the trailing update A_IJ -= U_I [A_JK0 | A_JK1]^T of the next panel's tiles;
+//   (3b) wave 0 stores -G of this panel and inverts the next panel's diagonal block, while the
+//        other waves update the remaining tiles (lookahead: the inversion is off the path);
+//   (4) A_IK = U_I above the panel, A_KJ = U_J^T right of it.
+// Result and flags are those of k_sym_sweep.
+template <typename T, int NW, bool PAD>
+__global__ void __launch_bounds__(64 * NW, 4) k_sym_sweep_mfma2(cplx<T> *mats, int n, int *flag, double tiny2) {
+  using V = cplx<T>;
+  using MF = Mfma<T>;
+  using v4 = typename MF::v4;
+  constexpr int US = 33;  // row stride of Un and Gs (complex entries), padded
+  constexpr int TS = 17;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nrb = (n + 15) / 16, nrb2 = nrb + (nrb & 1), tiles = nrb2 * (nrb2 + 1) / 2;
+  V *Un = reinterpret_cast<V *>(smem_raw);  // [16 nrb2][US]: -U_i of the current panel
+  V *Gs = Un + 16 * nrb2 * US;              // [32][US]: G = A_KK^{-1}
+  V *Ws = Gs + 32 * US;                     // [16][TS]: W = G00 A01
+  V *A01s = Ws + 16 * TS;                   // [16][TS]
+  V *A11s = A01s + 16 * TS;                 // [16][TS]
+  __shared__ V aug[16][32];                 // [block | I] -> [I | inverse]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  V *A = mats + (long long)blockIdx.x * n * n;
+  const T tiny = (T)tiny2;
+  // as in k_sym_sweep_mfma (PAD: n not a multiple of 32): unconditional loads, the identity
+  // padding blended in
+  auto at = [&](int row, int col) __attribute__((always_inline)) -> V {
+    if constexpr (!PAD) return A[(long long)row * n + col];
+    const bool in = row < n && col < n;
+    const V v = A[in ? (long long)row * n + col : 0LL];
+    const T w = in ? (T)1 : (T)0, id = (!in && row == col) ? (T)1 : (T)0;
+    return mk<T>(v.x * w + id, v.y * w);
+  };
+  auto put = [&](int row, int col, V v) __attribute__((always_inline)) {
+    if (!PAD || (row < n && col < n)) A[(long long)row * n + col] = v;
+  };
+  auto sync_wave = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+  };
+  // wave 0: G of the panel at tile column K0 into Gs
+  auto invert_block = [&](int K0) __attribute__((always_inline)) {
+    const int K1 = K0 + 1;
+    for (int e = lane; e < 512; e += 64) {
+      const int a = e >> 5, c = e & 31;
+      aug[a][c] = c < 16 ? at(16 * K0 + a, 16 * K0 + c) : mk<T>(c - 16 == a ? (T)1 : (T)0, (T)0);
+    }
+    for (int e = lane; e < 256; e += 64) {
+      const int a = e >> 4, b = e & 15;
+      A01s[a * TS + b] = at(16 * K0 + a, 16 * K1 + b);
+      A11s[a * TS + b] = at(16 * K1 + a, 16 * K1 + b);
+    }
+    sync_wave();
+    sweep_gj_wave<16>(aug, 16, lane, flag, tiny);  // G00
+    for (int e = lane; e < 256; e += 64) Gs[(e >> 4) * US + (e & 15)] = aug[e >> 4][16 + (e & 15)];
+    sync_wave();
+    wave_cmm16<T>(Gs, US, false, A01s, TS, false, nullptr, 0, (T)1, Ws, TS, lane);         // W = G00 A01
+    wave_cmm16<T>(A01s, TS, true, Ws, TS, false, A11s, TS, (T)-1, &aug[0][0], 32, lane);  // S
+    for (int e = lane; e < 256; e += 64) aug[e >> 4][16 + (e & 15)] = mk<T>((e >> 4) == (e & 15) ? (T)1 : (T)0, (T)0);
+    sync_wave();
+    sweep_gj_wave<16>(aug, 16, lane, flag, tiny);  // G11 = S^{-1}
+    for (int e = lane; e < 256; e += 64) Gs[(16 + (e >> 4)) * US + 16 + (e & 15)] = aug[e >> 4][16 + (e & 15)];
+    sync_wave();
+    wave_cmm16<T>(Ws, TS, false, Gs + 16 * US + 16, US, false, nullptr, 0, (T)-1, Gs + 16, US, lane);  // G01
+    wave_cmm16<T>(Gs + 16, US, false, Ws, TS, true, Gs, US, (T)-1, Gs, US, lane);  // G00 - G01 W^T
+    for (int e = lane; e < 256; e += 64) Gs[(16 + (e >> 4)) * US + (e & 15)] = Gs[(e & 15) * US + 16 + (e >> 4)];
+  };
+  // A_IJ -= U_I [A_JK0 | A_JK1]^T for one tile (I, J outside the panel at K0); cr / ci hold
+  // the tile's entries on entry
+  auto update = [&](int I, int J, int K0, v4 &cr, v4 &ci) __attribute__((always_inline)) {
+    const int K1 = K0 + 1;
+    const bool above = J < K0;
+    V pj[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int k = 4 * kk + q, Kc = kk < 4 ? K0 : K1, kc = k & 15;
+      pj[kk] = at(above ? 16 * J + r : 16 * Kc + kc, above ? 16 * Kc + kc : 16 * J + r);  // A_JK[r][k]
+    }
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const V nu = Un[(16 * I + r) * US + 4 * kk + q];  // -U_I[r][k]
+      cr = MF::mma(nu.x, pj[kk].x, cr);
+      cr = MF::mma(-nu.y, pj[kk].y, cr);
+      ci = MF::mma(nu.x, pj[kk].y, ci);
+      ci = MF::mma(nu.y, pj[kk].x, ci);
+      if (kk & 1) __builtin_amdgcn_sched_barrier(0);  // two LDS operands ahead at most
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) put(16 * I + MF::row(q, m), 16 * J + r, mk<T>(cr[m], ci[m]));
+  };
+  auto fetch = [&](int I, int J, v4 &cr, v4 &ci) __attribute__((always_inline)) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const V c = at(16 * I + MF::row(q, m), 16 * J + r);
+      cr[m] = c.x;
+      ci[m] = c.y;
+    }
+  };
+  auto decode = [&](int t, int &I, int &J) __attribute__((always_inline)) {
+    J = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while (J * (J + 1) / 2 > t) --J;
+    while ((J + 1) * (J + 2) / 2 <= t) ++J;
+    I = t - J * (J + 1) / 2;
+  };
+  const int np = nrb2 / 2;
+  if (wv == 0) invert_block(0);
+  __syncthreads();
+  for (int P = 0; P < np; ++P) {
+    const int K0 = 2 * P, K1 = K0 + 1, N0 = K0 + 2, N1 = K0 + 3;  // this panel, the next one
+    const bool next = P + 1 < np;
+    // (2) -U_I = -[A_IK0 | A_IK1] G
+    for (int I = wv; I < nrb2; I += NW) {
+      if (I == K0 || I == K1) continue;
+      const bool above = I < K0;
+      V pa[8];
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int k = 4 * kk + q, Kc = kk < 4 ? K0 : K1, kc = k & 15;
+        pa[kk] = at(above ? 16 * I + r : 16 * Kc + kc, above ? 16 * Kc + kc : 16 * I + r);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        v4 ur = {0, 0, 0, 0}, ui = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+          const V g = Gs[(4 * kk + q) * US + 16 * h + r];
+          ur = MF::mma(pa[kk].x, g.x, ur);
+          ur = MF::mma(-pa[kk].y, g.y, ur);
+          ui = MF::mma(pa[kk].x, g.y, ui);
+          ui = MF::mma(pa[kk].y, g.x, ui);
+          if (kk & 1) __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) Un[(16 * I + MF::row(q, m)) * US + 16 * h + r] = mk<T>(-ur[m], -ui[m]);
+      }
+    }
+    __syncthreads();
+    // (3a) the next panel's tiles: row / column N0 over X, then N1 over X != N0
+    if (next) {
+      for (int e = wv; e < 2 * nrb2; e += NW) {
+        const int h = e >= nrb2, X = e - h * nrb2, Nh = h ? N1 : N0;
+        if (X == K0 || X == K1 || (h && X == N0)) continue;
+        const int I = min(X, Nh), J = max(X, Nh);
+        v4 cr, ci;
+        fetch(I, J, cr, ci);
+        update(I, J, K0, cr, ci);
+      }
+    }
+    __syncthreads();
+    // (3b) wave 0: -G of this panel, then the next panel's G; the others: the remaining tiles
+    if (wv == 0) {
+      for (int e = lane; e < 768; e += 64) {
+        const int blk = e >> 8, a = (e >> 4) & 15, b = e & 15;
+        const int gr = blk == 2 ? 16 + a : a, gc = blk == 0 ? b : 16 + b;
+        const V g = Gs[gr * US + gc];
+        put(16 * (blk == 2 ? K1 : K0) + a, 16 * (blk == 0 ? K0 : K1) + b, mk<T>(-g.x, -g.y));
+      }
+      if (next) {
+        sync_wave();
+        invert_block(N0);
+      }
+    } else {
+      auto skip = [&](int I, int J) __attribute__((always_inline)) {
+        return I == K0 || I == K1 || J == K0 || J == K1 || (next && (I == N0 || I == N1 || J == N0 || J == N1));
+      };
+      v4 cr, ci;
+      int I = 0, J = 0;
+      const int w1 = wv - 1;
+      if (w1 < tiles) {
+        decode(w1, I, J);
+        if (!skip(I, J)) fetch(I, J, cr, ci);
+      }
+      for (int t = w1; t < tiles; t += NW - 1) {
+        v4 ncr, nci;
+        int nI = 0, nJ = 0;
+        if (t + NW - 1 < tiles) {
+          decode(t + NW - 1, nI, nJ);
+          if (!skip(nI, nJ)) fetch(nI, nJ, ncr, nci);
+        }
+        if (!skip(I, J)) update(I, J, K0, cr, ci);
+        cr = ncr;
+        ci = nci;
+        I = nI;
+        J = nJ;
+      }
+    }
+    __syncthreads();
+    // (4) this panel's other tiles: A_IK = U_I above it, A_KJ = U_J^T right of it
+    for (int e = tid; e < nrb2 * 512; e += 64 * NW) {
+      const int I = e >> 9, h = (e >> 8) & 1, a = (e >> 4) & 15, b = e & 15;
+      const int Kh = h ? K1 : K0;
+      if (I < K0) {
+        const V u = Un[(16 * I + a) * US + 16 * h + b];
+        put(16 * I + a, 16 * Kh + b, mk<T>(-u.x, -u.y));
+      } else if (I > K1) {
+        const V u = Un[(16 * I + b) * US + 16 * h + a];
+        put(16 * Kh + a, 16 * I + b, mk<T>(-u.x, -u.y));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// The same sweep with the whole matrix held on chip, for orders up to 192: every stored tile
+// (I <= J) lives in the accumulators of one wave for the whole inversion, so the matrix is
+// read once and written once.  Wave 0 only inverts the diagonal blocks (it holds no tiles, so
+// the pivoting code and the tiles never share registers); slot s of tile wave w = 1 .. NW - 1
+// holds tile t = w - 1 + (NW - 1) s, t = J (J + 1) / 2 + I.  Per panel K the owners of row and
+// column K copy them to LDS (A_iK by rows; A_KK into the Gauss-Jordan block), wave 0 inverts
+// A_KK, the tile waves put -U_I = -A_IK G in LDS and then update their tiles from the two LDS
+// panels (A_IJ -= U_I A_JK^T) or replace them (A_IK = U_I, A_KJ = U_J^T, A_KK = -G).  Both
+// kinds of wave pass the same four barriers per panel.
+template <typename T, int NW, int S>
+__global__ void __launch_bounds__(64 * NW) k_sym_sweep_res(cplx<T> *mats, int n, int *flag, double tiny2) {
+  using V = cplx<T>;
+  using MF = Mfma<T>;
+  using v4 = typename MF::v4;
+  constexpr int US = 17, NTW = NW - 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nrb = (n + 15) / 16, tiles = nrb * (nrb + 1) / 2;
+  V *Pn = reinterpret_cast<V *>(smem_raw);  // [16 nrb][US]: A_iK of the current panel
+  V *Un = Pn + 16 * nrb * US;               // [16 nrb][US]: -U_i
+  __shared__ V aug[16][32];                 // [A_KK | I] -> [I | G]
+  // the wave index as a scalar, so that the slots' tile coordinates stay in scalar registers
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (wv == 0) {
+    const T tiny = (T)tiny2;
+    for (int K = 0; K < nrb; ++K) {
+      __syncthreads();  // (1) A_KK in aug
+      sweep_gj_wave<16>(aug, 16, lane, flag, tiny);
+      __syncthreads();  // (2) G
+      __syncthreads();  // (3) -U
+      __syncthreads();  // (4) tiles updated, aug free
+    }
+    return;
+  }
+  const int tw = wv - 1;
+  V *A = mats + (long long)blockIdx.x * n * n;
+  int TI[S], TJ[S];  // the slots' tiles (TI < 0: none)
+  v4 cr[S], ci[S];
+  {
+    const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int t = tw + NTW * s;
+      int I = -1, J = 0;
+      if (t < tiles) {
+        J = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while (J * (J + 1) / 2 > t) --J;
+        while ((J + 1) * (J + 2) / 2 <= t) ++J;
+        I = t - J * (J + 1) / 2;
+      }
+      TI[s] = I;
+      TJ[s] = J;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int row = 16 * I + MF::row(q, m), col = 16 * J + r;
+        const bool in = I >= 0 && row < n && col < n;
+        const V v = A[in ? (long long)row * n + col : 0LL];  // unconditional, as in k_sym_sweep_mfma
+        const T w = in ? (T)1 : (T)0, id = (!in && row == col) ? (T)1 : (T)0;
+        cr[s][m] = v.x * w + id;
+        ci[s][m] = v.y * w;
+      }
+      __builtin_amdgcn_sched_barrier(0);  // one slot's loads in flight at a time
+    }
+  }
+  for (int K = 0; K < nrb; ++K) {
+    // lane coordinates re-derived each panel, so that no slot keeps LDS addresses of its own
+    int r = lane & 15, q = lane >> 4;
+    asm volatile("" : "+v"(r), "+v"(q));
+    // (1) row and column K to LDS
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int I = TI[s], J = TJ[s];
+      if (I < 0) continue;
+      if (J == K && I < K) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) Pn[(16 * I + MF::row(q, m)) * US + r] = mk<T>(cr[s][m], ci[s][m]);
+      } else if (I == K && J > K) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) Pn[(16 * J + r) * US + MF::row(q, m)] = mk<T>(cr[s][m], ci[s][m]);
+      } else if (I == K && J == K) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          aug[MF::row(q, m)][r] = mk<T>(cr[s][m], ci[s][m]);
+          aug[MF::row(q, m)][16 + r] = mk<T>(MF::row(q, m) == r ? (T)1 : (T)0, (T)0);
+        }
+      }
+    }
+    __syncthreads();
+    __syncthreads();  // (2) wave 0 has inverted A_KK
+    // (3) -U_I = -A_IK G
+    for (int I = tw; I < nrb; I += NTW) {
+      if (I == K) continue;
+      v4 ur = {0, 0, 0, 0}, ui = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const V a = Pn[(16 * I + r) * US + 4 * kk + q];
+        const V g = aug[4 * kk + q][16 + r];
+        ur = MF::mma(a.x, g.x, ur);
+        ur = MF::mma(-a.y, g.y, ur);
+        ui = MF::mma(a.x, g.y, ui);
+        ui = MF::mma(a.y, g.x, ui);
+        __builtin_amdgcn_sched_barrier(0);  // registers: every slot's tile is live here
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) Un[(16 * I + MF::row(q, m)) * US + r] = mk<T>(-ur[m], -ui[m]);
+    }
+    __syncthreads();
+    // (4) update or replace the slots' tiles
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int I = TI[s], J = TJ[s];
+      if (I < 0) continue;
+      if (I != K && J != K) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const V nu = Un[(16 * I + r) * US + 4 * kk + q];  // -U_I[r][k]
+          const V pj = Pn[(16 * J + r) * US + 4 * kk + q];  // A_JK[r][k]
+          cr[s] = MF::mma(nu.x, pj.x, cr[s]);
+          cr[s] = MF::mma(-nu.y, pj.y, cr[s]);
+          ci[s] = MF::mma(nu.x, pj.y, ci[s]);
+          ci[s] = MF::mma(nu.y, pj.x, ci[s]);
+          if (kk & 1) __builtin_amdgcn_sched_barrier(0);
+        }
+      } else if (I != K) {  // A_IK = U_I
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const V v = Un[(16 * I + MF::row(q, m)) * US + r];
+          cr[s][m] = -v.x;
+          ci[s][m] = -v.y;
+        }
+      } else if (J != K) {  // A_KJ = U_J^T
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const V v = Un[(16 * J + r) * US + MF::row(q, m)];
+          cr[s][m] = -v.x;
+          ci[s][m] = -v.y;
+        }
+      } else {  // A_KK = -G
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const V v = aug[MF::row(q, m)][16 + r];
+          cr[s][m] = -v.x;
+          ci[s][m] = -v.y;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);  // one slot's operands in registers at a time
+    }
+    __syncthreads();
+  }
+  const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int I = TI[s], J = TJ[s];
+    if (I < 0) continue;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int row = 16 * I + MF::row(q, m), col = 16 * J + r;
+      if (row < n && col < n) A[(long long)row * n + col] = mk<T>(cr[s][m], ci[s][m]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Launch the symmetric sweep.  Small orders keep the matrix on chip (k_sym_sweep_res: two
+// 16 nrb x 17 panels in LDS; up to 3 stored tiles per tile wave in FP64, order 144, and 6 in
+// FP32, order 192; 8 waves per workgroup up to 35 stored tiles, 16 above).  Larger orders
+// stream the tiles through HBM once per panel: in FP32 with 32-pivot panels
+// (k_sym_sweep_mfma2) where -U of the panel (16 nrb x 33) fits the LDS beside the 32 x 32
+// block's work arrays (up to order 512), otherwise with 16-pivot panels (k_sym_sweep_mfma,
+// 16 nrb x 17), with 8 waves per workgroup where two workgroups share a CU and 16 where one
+// fits.  In FP64 the 32-pivot kernel was measured no faster at order 192 (5.2 vs 5.1 ms per
+// launch of 2817 matrices; its operand loads, not its traffic, set its time), so FP64 takes
+// 16-pivot panels.  Orders whose 16-pivot panel exceeds the LDS (FP64 above 544) take the
+// vector kernel, with 16-pivot panels while its two n x NB panel arrays fit the LDS and 8
+// above.  DDA_SWEEP_KERNEL=stream2, =stream or =vector selects a kernel at every order it can
+// take.
+enum SweepKernel { SW_RES, SW_STREAM2, SW_STREAM, SW_VECTOR };
+template <typename V> static size_t sweep_panel_lds(int n) { return (size_t)16 * ((n + 15) / 16) * 17 * sizeof(V); }
+template <typename V> static size_t sweep_panel2_lds(int n) {
+  const int nrb = (n + 15) / 16, nrb2 = nrb + (nrb & 1);
+  return ((size_t)16 * nrb2 * 33 + 32 * 33 + 3 * 16 * 17) * sizeof(V);
+}
+template <typename V> static SweepKernel sweep_kernel(int n) {
+  const char *e = getenv("DDA_SWEEP_KERNEL");
+  const size_t aug = 16 * 32 * sizeof(V);
+  const bool stream_ok = sweep_panel_lds<V>(n) + aug <= kLdsMax;
+  const bool stream2_ok = sweep_panel2_lds<V>(n) + aug <= kLdsMax;
+  if (e && strcmp(e, "vector") == 0) return SW_VECTOR;
+  if (e && strcmp(e, "stream") == 0 && stream_ok) return SW_STREAM;
+  if (e && strcmp(e, "stream2") == 0 && stream2_ok) return SW_STREAM2;
+  const int nrb = (n + 15) / 16;
+  const bool fp64 = sizeof(V) == sizeof(double2);
+  if (nrb * (nrb + 1) / 2 <= 15 * (fp64 ? 3 : 6)) return SW_RES;
+  return (stream2_ok && !fp64) ? SW_STREAM2 : stream_ok ? SW_STREAM : SW_VECTOR;
+}
 template <typename V> static int sweep_nb(int n) {
   return (size_t)2 * n * 16 * sizeof(V) <= 96 * 1024 ? 16 : 8;
 }
-template <typename V> static size_t sweep_lds(int n) { return (size_t)2 * n * sweep_nb<V>(n) * sizeof(V); }
-template <typename V> static void sweep_launch(dda_problem *p, V *mats, long long cnt, int n) {
-  const size_t lds = sweep_lds<V>(n);
-  auto fn = sweep_nb<V>(n) == 16 ? k_sym_sweep<16, 512, V> : k_sym_sweep<8, 512, V>;
+template <typename V> static size_t sweep_lds(int n) {
+  switch (sweep_kernel<V>(n)) {
+    case SW_RES: return 2 * sweep_panel_lds<V>(n);
+    case SW_STREAM2: return sweep_panel2_lds<V>(n);
+    case SW_STREAM: return sweep_panel_lds<V>(n);
+    default: return (size_t)2 * n * sweep_nb<V>(n) * sizeof(V);
+  }
+}
+template <typename T, int NW>
+static void sweep_res_launch(dda_problem *p, cplx<T> *mats, long long cnt, int n, size_t lds, double tiny2) {
+  const int nrb = (n + 15) / 16, slots = (nrb * (nrb + 1) / 2 + NW - 2) / (NW - 1);
+  REQUIRE(slots <= 6, DDA_EUNSUPPORTED, "order %d: %d stored tiles per wave", n, slots);
+  using Fn = void (*)(cplx<T> *, int, int *, double);
+  Fn fn = slots <= 1 ? k_sym_sweep_res<T, NW, 1>
+        : slots == 2 ? k_sym_sweep_res<T, NW, 2>
+        : slots == 3 ? k_sym_sweep_res<T, NW, 3>
+        : slots == 4 ? k_sym_sweep_res<T, NW, 4>
+        : slots == 5 ? k_sym_sweep_res<T, NW, 5>
+                     : k_sym_sweep_res<T, NW, 6>;
   set_lds_limit((const void *)fn, lds);
+  hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(64 * NW), lds, p->st, mats, n, p->dflag, tiny2);
+}
+template <typename V> static void sweep_launch(dda_problem *p, V *mats, long long cnt, int n) {
+  using T = typename RealOf<V>::type;
+  const size_t lds = sweep_lds<V>(n);
   // squared relative pivot bound; DDA_SWEEP_FALLBACK=1 flags every block (tests of the fallback)
   double tiny2 = sizeof(V) == sizeof(double2) ? 1e-26 : 1e-12;
   if (const char *e = getenv("DDA_SWEEP_FALLBACK"))
     if (atoi(e) != 0) tiny2 = 1e30;
-  hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(512), lds, p->st, mats, n, p->dflag, tiny2);
+  const SweepKernel kind = sweep_kernel<V>(n);
+  if (kind == SW_RES) {
+    const int nrb = (n + 15) / 16;
+    if (nrb * (nrb + 1) / 2 <= 7 * 5) sweep_res_launch<T, 8>(p, mats, cnt, n, lds, tiny2);
+    else sweep_res_launch<T, 16>(p, mats, cnt, n, lds, tiny2);
+  } else if (kind == SW_STREAM2) {
+    const bool two = 2 * (lds + 16 * 32 * sizeof(V)) <= kLdsMax, pad = n % 32 != 0;
+    auto fn = two ? (pad ? k_sym_sweep_mfma2<T, 8, true> : k_sym_sweep_mfma2<T, 8, false>)
+                  : (pad ? k_sym_sweep_mfma2<T, 16, true> : k_sym_sweep_mfma2<T, 16, false>);
+    set_lds_limit((const void *)fn, lds);
+    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(two ? 512 : 1024), lds, p->st, mats, n, p->dflag, tiny2);
+  } else if (kind == SW_STREAM) {
+    const bool two = 2 * (lds + 16 * 32 * sizeof(V)) <= kLdsMax, pad = n % 16 != 0;
+    auto fn = two ? (pad ? k_sym_sweep_mfma<T, 8, true> : k_sym_sweep_mfma<T, 8, false>)
+                  : (pad ? k_sym_sweep_mfma<T, 16, true> : k_sym_sweep_mfma<T, 16, false>);
+    set_lds_limit((const void *)fn, lds);
+    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(two ? 512 : 1024), lds, p->st, mats, n, p->dflag, tiny2);
+  } else {
+    auto fn = sweep_nb<V>(n) == 16 ? k_sym_sweep<16, 512, V> : k_sym_sweep<8, 512, V>;
+    set_lds_limit((const void *)fn, lds);
+    hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(512), lds, p->st, mats, n, p->dflag, tiny2);
+  }
   HIPCHK(hipGetLastError());
 }
 
@@ -1061,23 +1713,6 @@ __global__ void __launch_bounds__(512) k_pc_gemv(cplx<T> *W, const cplx<T> *__re
     }
   }
 }
-
-template <typename T> struct Mfma;
-template <> struct Mfma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  // row of D held in item m of a lane of k-slot q (column = lane % 16)
-  static __device__ __forceinline__ int row(int q, int m) { return q + 4 * m; }
-};
-template <> struct Mfma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int q, int m) { return 4 * q + m; }
-};
 
 // One unique mode (ux, uy) of the x-y spectrum and its copies (nx - ux, ny - uy) that share
 // its blocks (up to four), for the right-hand sides r0 .. r0 + nr - 1; nv = copies x nr vectors.

@@ -175,7 +175,7 @@ void fft_strided_plain(dda_problem *p, const FftPlan &pl, double2 *data, long lo
 
 // Candidate shapes of a pass: rows per tile (x passes) halved from the LDS-bound maximum; along
 // a strided axis (y passes) the maximum and half its columns, each with the launch rule's tiles
-// per workgroup and with 1, 2, 4 and 8.
+// per workgroup and with 2 and 8.
 static std::vector<TileShape> tile_candidates(int max_tw, bool strided) {
   std::vector<TileShape> c;
   if (!strided) {
@@ -184,7 +184,7 @@ static std::vector<TileShape> tile_candidates(int max_tw, bool strided) {
   }
   for (int tw : {max_tw, max_tw / 2}) {
     if (tw < 1) continue;
-    for (int tpw : {0, 1, 2, 4, 8}) c.push_back(TileShape{tw, tpw});
+    for (int tpw : {0, 2, 8}) c.push_back(TileShape{tw, tpw});
   }
   return c;
 }
@@ -243,7 +243,7 @@ void fft_tile_autotune(dda_problem *p, int first, int pi, int nrhs,
     for (size_t c = 0; c < rounds; ++c) {
       for (int k = 0; k < 4; ++k) p->tile[first + k][pi] = cand[k][std::min(c, cand[k].size() - 1)];
       p->prof.reset();
-      for (int rep = 0; rep < 3; ++rep) apply();
+      apply();
       HIPCHK(hipStreamSynchronize(p->st));
       p->prof.collect();
       for (int k = 0; k < 4; ++k) {
