@@ -183,7 +183,10 @@ dda_status dda_create(int nx, int ny, int nz, const uint8_t *mask_dev, const dou
  * Build the 2-level circulant preconditioner (Sec. 3, 3.1): eq. Chan along x
  * then y on the signed-offset kernel, FFTs along x and y, one dense 3nz x 3nz
  * block per Fourier mode with alpha~^{-1} on its diagonal, and explicit block
- * inverses by Gauss-Jordan elimination with partial pivoting.  alpha~ is the
+ * inverses: for even nz (complex symmetric half blocks) by the blocked symmetric
+ * sweep with partial pivoting inside each 16 x 16 diagonal block, redone by
+ * Gauss-Jordan elimination with partial pivoting if a diagonal block needs a
+ * pivot from outside it; for odd nz by Gauss-Jordan.  alpha~ is the
  * LDR polarisability averaged over the occupied voxels as opt.alpha_avg says
  * (the "ice" value for a homogeneous body, Sec. 3.1) with lattice factor
  * S = s_bar.  Only the
