@@ -311,6 +311,8 @@ struct dda_problem {
   // preconditioner
   int prec_built = 0;
   int prec_sweep = 0;          // 1: the last 2-level build inverted by the symmetric sweep
+  int tune_xy = 0;             // 1 while the x / y tile tuner times its passes: the z pass and
+                               // the block product, whose times do not enter, are not launched
   int prec_fp32 = 0;
   double2 ati{0.0, 0.0};     // alpha~^{-1}
   int pz0 = 0, pbz = 0;      // occupied z layers [pz0, pz0 + pbz): the dense level's extent

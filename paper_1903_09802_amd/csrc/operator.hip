@@ -614,7 +614,7 @@ static void op_passes(dda_problem *p, int nrhs, const double2 *x, double2 *y,
                     sizeof(T) == 8 ? "op_y_fwd_f64" : "op_y_fwd_f32",
                     nrhs * 3.0 * nz * 2 * nx * (ny + 2.0 * ny) * sz, 3LL * nz, FP_OP_Y_FWD);
   // P3: z transform, kernel multiply, inverse z transform (in place)
-  zpass<T>(p, nrhs, w1, khat);
+  if (!p->tune_xy) zpass<T>(p, nrhs, w1, khat);
   // P4: inverse y transform, keep ny rows
   launch_strided<T>(p, p->py, w1, w0, (long long)nrhs * 3 * nz, 2LL * nx, 2 * ny, ny,
                     p->zplane, (long long)ny * 2 * nx, +1,

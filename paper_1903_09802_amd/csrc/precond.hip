@@ -1934,7 +1934,7 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
   snprintf(nm, sizeof nm, "pc_y_fwd_%s", suf);
   launch_strided<T>(p, p->uy, W, W, (long long)nrhs * 3 * nz, nx, ny, ny, (long long)ny * nx,
                     (long long)ny * nx, -1, nm, 2.0 * rows * nx * sz, 3LL * nz, FP_PC_Y_FWD);
-  {
+  if (!p->tune_xy) {
     const long long U = (long long)p->umx * p->umy;
     snprintf(nm, sizeof nm, "pc_gemv_%s", suf);
     if (p->psym) {
