@@ -52,38 +52,110 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
                                                           const cplx<T> *__restrict__ tw,
                                                           RowArgs a) {
   using V = cplx<T>;
+  constexpr bool kCompactIn = MODE == ROW_OP_FWD || MODE == ROW_PC_FWD;
+  constexpr bool kCompactOut = MODE == ROW_OP_INV || MODE == ROW_IMG_INV || MODE == ROW_PC_INV;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V *s = reinterpret_cast<V *>(smem_raw);
   const int tid = threadIdx.x, nt = blockDim.x;
   const int n = a.pl.n;
   const int ld = a.tw + 1;
   const long long row0 = (long long)blockIdx.x * a.tw;
-  // right-hand sides that have stopped: their rows are skipped, the block returns if all are
+  // right-hand sides that have stopped: their rows are skipped, the block returns if all are.
+  // The flags of the tile's right-hand sides (at most 32, checked at launch) are kept as a bit
+  // mask, so that no flag is loaded per element.
   bool some_off = false;
+  unsigned onmask = ~0u;
+  long long rfirst = 0;
   if (a.act) {
     const long long r0 = row0 / a.rhs_rows, r1 = (min(row0 + a.tw, a.rows) - 1) / a.rhs_rows;
     bool any_on = false;
+    rfirst = r0;
+    onmask = 0u;
     for (long long r = r0; r <= r1; ++r) {
-      if (a.act[r]) any_on = true;
-      else some_off = true;
+      if (a.act[r]) {
+        any_on = true;
+        onmask |= 1u << (r - r0);
+      } else {
+        some_off = true;
+      }
     }
     if (!any_on) return;
   }
-  auto row_on = [&](long long row) { return !some_off || a.act[row / a.rhs_rows] != 0; };
+  auto rhs_on = [&](long long r) { return !some_off || ((onmask >> (r - rfirst)) & 1u) != 0; };
+  auto row_on = [&](long long row) { return !some_off || rhs_on(row / a.rhs_rows); };
+  // compact modes: row0 + c = blk vox_rows + vrow with blk = 3 r + component, stepped from the
+  // tile's first row in 32-bit arithmetic (rows < 2^31, checked at launch)
+  int blk0 = 0, vrow0 = 0;
+  if constexpr (kCompactIn || kCompactOut) {
+    blk0 = (int)(row0 / a.vox_rows);
+    vrow0 = (int)(row0 - (long long)blk0 * a.vox_rows);
+  }
+  auto split = [&](int c, int &blk, int &vrow) {
+    const int vr = (int)a.vox_rows;
+    vrow = vrow0 + c;
+    blk = blk0;
+    while (vrow >= vr) {
+      vrow -= vr;
+      ++blk;
+    }
+  };
+  const int rows_here = (int)min((long long)a.tw, a.rows - row0);  // rows of this tile
   // load: consecutive threads take consecutive elements of a row (global rows are contiguous)
   const int tot_in = a.tw * n;
-  if constexpr (MODE == ROW_OP_FWD || MODE == ROW_PC_FWD) {
-    // compact input: all index-map loads of the thread first, then the value loads (at most
-    // kRowEpt elements per thread, checked at launch)
-    int cis[kRowEpt];
+  if constexpr (kCompactIn) {
+    // compact input: the index-map loads of the thread, then its value loads, then the LDS
+    // stores.  Loads are unconditional (from entry 0 where there is nothing to read), air is
+    // blended in as a factor 0 and -1 indices are formed by bit operations, so that no load
+    // waits behind a branch (at most kRowEpt elements per thread, checked at launch).
+    int cis[kRowEpt], bq[kRowEpt];
 #pragma unroll
     for (int q = 0; q < kRowEpt; ++q) {
       const int e = tid + q * nt;
       const int c = a.nsh >= 0 ? (e >> a.nsh) : e / n;
       const int i = e - c * n;
-      const long long row = row0 + c;
-      cis[q] = (e < tot_in && row < a.rows && i < a.n_in && row_on(row))
-                   ? a.cidx[(row % a.vox_rows) * a.nx + i] : -1;
+      // elements past the tile's last row keep the first row's block, so that the per-block
+      // loads below (the input scale) stay inside their arrays
+      int blk = blk0, vrow = vrow0;
+      if (e < tot_in && c < rows_here) split(c, blk, vrow);
+      bq[q] = blk;
+      const bool ok = e < tot_in && c < rows_here && i < a.n_in && rhs_on(blk / 3);
+      const int ci = a.cidx[ok ? vrow * a.nx + i : 0];
+      cis[q] = ci | -(int)!ok;  // -1 where nothing is read
+    }
+    double2 xv[kRowEpt];
+    auto load_values = [&](auto scaled) {
+#pragma unroll
+      for (int q = 0; q < kRowEpt; ++q) {
+        const bool has = cis[q] >= 0;
+        xv[q] = in[has ? (long long)bq[q] * a.nocc + cis[q] : 0LL];
+        if constexpr (decltype(scaled)::value) xv[q] = cscale(xv[q], a.xscale[(bq[q] / 3) * kMaxM]);
+        const double w = has ? 1.0 : 0.0;
+        xv[q] = make_double2(xv[q].x * w, xv[q].y * w);
+      }
+    };
+    if (a.xscale) load_values(std::true_type{});
+    else load_values(std::false_type{});
+#pragma unroll
+    for (int q = 0; q < kRowEpt; ++q) {
+      const int e = tid + q * nt;
+      if (e >= tot_in) continue;
+      const int c = a.nsh >= 0 ? (e >> a.nsh) : e / n;
+      const int i = e - c * n;
+      s[lrow(i, ld) + c] = to_c(xv[q], V{});
+    }
+  } else {
+    // all of the thread's loads, unconditional (from entry 0 past the rows or the input
+    // length, blended in as 0), before its LDS stores
+    V vals[kRowEpt];
+#pragma unroll
+    for (int q = 0; q < kRowEpt; ++q) {
+      const int e = tid + q * nt;
+      const int c = a.nsh >= 0 ? (e >> a.nsh) : e / n;
+      const int i = e - c * n;
+      const bool ok = e < tot_in && c < rows_here && i < a.n_in;
+      const V v = in[ok ? (row0 + c) * a.in_stride + i : 0LL];
+      const T w = ok ? (T)1 : (T)0;
+      vals[q] = mk<T>(v.x * w, v.y * w);
     }
 #pragma unroll
     for (int q = 0; q < kRowEpt; ++q) {
@@ -91,53 +163,63 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const TI *in, TO *out,
       if (e >= tot_in) continue;
       const int c = a.nsh >= 0 ? (e >> a.nsh) : e / n;
       const int i = e - c * n;
-      const long long row = row0 + c;
-      V val = mk<T>((T)0, (T)0);
-      if (cis[q] >= 0) {
-        double2 xv = in[(row / a.vox_rows) * a.nocc + cis[q]];
-        if (a.xscale) xv = cscale(xv, a.xscale[(row / a.rhs_rows) * kMaxM]);
-        val = to_c(xv, V{});
-      }
-      s[lrow(i, ld) + c] = val;
-    }
-  } else {
-    for (int e = tid; e < tot_in; e += nt) {
-      const int c = a.nsh >= 0 ? (e >> a.nsh) : e / n;
-      const int i = e - c * n;
-      const long long row = row0 + c;
-      V val = mk<T>((T)0, (T)0);
-      if (row < a.rows && i < a.n_in) val = in[row * a.in_stride + i];
-      s[lrow(i, ld) + c] = val;
+      s[lrow(i, ld) + c] = vals[q];
     }
   }
   __syncthreads();
   const Lane L = make_lane(a.tw, tpc_of(n));
   lds_fft_any<V, EptOf<T>::value, NF>(s, ld, L, a.pl, tw, a.sign);
   const int tot_out = a.tw * a.n_out;
-  for (int e = tid; e < tot_out; e += nt) {
-    const int c = e / a.n_out;
-    const int i = e - c * a.n_out;
-    const long long row = row0 + c;
-    if (row >= a.rows || !row_on(row)) continue;
-    const V v = s[lrow(i, ld) + c];
-    if constexpr (MODE == ROW_PLAIN) {
-      out[row * a.out_stride + i] = v;
-    } else if constexpr (MODE == ROW_OP_INV || MODE == ROW_IMG_INV || MODE == ROW_PC_INV) {
-      const long long vox = (row % a.vox_rows) * a.nx + i;
-      const int ci = a.cidx[vox];
-      if (ci < 0) continue;
-      const long long o = (row / a.vox_rows) * a.nocc + ci;
-      const double2 conv = cscale(to_d(v), a.scale);
+  if constexpr (kCompactOut) {
+    // compact output: the index-map loads, then the inputs of the update (unconditional, from
+    // entry 0 where nothing is written), then the stores of the occupied voxels
+    int ciq[kRowEpt], bq[kRowEpt], vq[kRowEpt];
+#pragma unroll
+    for (int q = 0; q < kRowEpt; ++q) {
+      const int e = tid + q * nt;
+      const int c = e / a.n_out;
+      const int i = e - c * a.n_out;
+      int blk = blk0, vrow = vrow0;  // past the last row: the first row's block (see above)
+      if (e < tot_out && c < rows_here) split(c, blk, vrow);
+      bq[q] = blk;
+      vq[q] = vrow * a.nx + i;
+      const bool ok = e < tot_out && c < rows_here && rhs_on(blk / 3);
+      const int ci = a.cidx[ok ? vq[q] : 0];
+      ciq[q] = ci | -(int)!ok;
+    }
+    double2 xq[kRowEpt], aq[kRowEpt];
+    if constexpr (MODE == ROW_OP_INV) {
+      auto load_inputs = [&](auto scaled) {
+#pragma unroll
+        for (int q = 0; q < kRowEpt; ++q) {
+          const bool has = ciq[q] >= 0;
+          const int r = bq[q] / 3;
+          xq[q] = a.xin[has ? (long long)bq[q] * a.nocc + ciq[q] : 0LL];
+          if constexpr (decltype(scaled)::value) xq[q] = cscale(xq[q], a.xscale[r * kMaxM]);
+          aq[q] = a.ainv[has ? (long long)r * a.N + vq[q] : 0LL];
+        }
+      };
+      if (a.xscale) load_inputs(std::true_type{});
+      else load_inputs(std::false_type{});
+    }
+#pragma unroll
+    for (int q = 0; q < kRowEpt; ++q) {
+      const int e = tid + q * nt;
+      if (e >= tot_out || ciq[q] < 0) continue;
+      const int c = e / a.n_out;
+      const int i = e - c * a.n_out;
+      const double2 conv = cscale(to_d(s[lrow(i, ld) + c]), a.scale);
       double2 y = conv;
-      if constexpr (MODE == ROW_OP_INV) {
-        const long long r = row / a.rhs_rows;
-        double2 xv = a.xin[o];
-        if (a.xscale) xv = cscale(xv, a.xscale[r * kMaxM]);
-        y = csub(cmul(a.ainv[r * a.N + vox], xv), conv);
-      }
-      out[o] = y;
-    } else {
-      out[row * a.out_stride + i] = v;
+      if constexpr (MODE == ROW_OP_INV) y = csub(cmul(aq[q], xq[q]), conv);
+      out[(long long)bq[q] * a.nocc + ciq[q]] = y;
+    }
+  } else {
+    for (int e = tid; e < tot_out; e += nt) {
+      const int c = e / a.n_out;
+      const int i = e - c * a.n_out;
+      const long long row = row0 + c;
+      if (row >= a.rows || !row_on(row)) continue;
+      out[row * a.out_stride + i] = s[lrow(i, ld) + c];
     }
   }
 }
@@ -374,12 +456,16 @@ inline void launch_rows(dda_problem *p, const FftPlan &pl, const TI *in, TO *out
     if (ts.tw > 0 && ts.tw < a.tw) a.tw = ts.tw;
   }
   if (a.rows < a.tw) a.tw = (int)a.rows;
+  // a tile spans at most 32 right-hand sides (the kernel keeps their flags as a bit mask)
+  if (a.rhs_rows > 0 && a.tw > 30 * a.rhs_rows) a.tw = (int)(30 * a.rhs_rows);
   a.nsh = ilog2_exact(pl.n);
   const long long blocks = (a.rows + a.tw - 1) / a.tw;
   const size_t lds = tile_lds<T>(pl.n, a.tw);
   const int threads = std::max(64, a.tw * tpc_of(pl.n));
   REQUIRE((long long)a.tw * pl.n <= (long long)kRowEpt * threads, DDA_EUNSUPPORTED,
           "row tile of %d x %d exceeds %d elements per thread", a.tw, pl.n, kRowEpt);
+  REQUIRE(a.rows < (1LL << 31) && (a.rhs_rows == 0 || a.rhs_rows == 3 * a.vox_rows), DDA_EUNSUPPORTED,
+          "row transform of %lld rows", a.rows);
   KTimer t(&p->prof, p->st, name, bytes);
   with_static_n(pl.n, [&](auto nf) {
     auto fn = k_fft_rows<T, MODE, TI, TO, decltype(nf)::value>;

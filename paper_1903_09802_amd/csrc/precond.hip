@@ -947,7 +947,7 @@ __global__ void __launch_bounds__(64 * NW, 4) k_sym_sweep_mfma2(cplx<T> *mats, i
       auto skip = [&](int I, int J) __attribute__((always_inline)) {
         return I == K0 || I == K1 || J == K0 || J == K1 || (next && (I == N0 || I == N1 || J == N0 || J == N1));
       };
-      v4 cr, ci;
+      v4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};  // a skipped tile's registers are never used
       int I = 0, J = 0;
       const int w1 = wv - 1;
       if (w1 < tiles) {
@@ -955,7 +955,7 @@ __global__ void __launch_bounds__(64 * NW, 4) k_sym_sweep_mfma2(cplx<T> *mats, i
         if (!skip(I, J)) fetch(I, J, cr, ci);
       }
       for (int t = w1; t < tiles; t += NW - 1) {
-        v4 ncr, nci;
+        v4 ncr = {0, 0, 0, 0}, nci = {0, 0, 0, 0};
         int nI = 0, nJ = 0;
         if (t + NW - 1 < tiles) {
           decode(t + NW - 1, nI, nJ);
