@@ -200,6 +200,9 @@ def main():
     ap.add_argument("--c4-prisms", type=int, default=16)
     ap.add_argument("--c4-chunk", type=int, default=32, help="c4: right-hand sides per batched solve")
     ap.add_argument("--c4-precision", type=int, default=0, help="c4: 0 FP64, 1 FP32 inside FP64 refinement")
+    ap.add_argument("--c4-compare", type=int, default=0,
+                    help="c4: after the timed batch, solve the first N waves of every prism one per "
+                         "solve in FP64 and compare their cross sections and rate with the batch's")
     ap.add_argument("--c4-streams", type=int, default=1,
                     help="c4: prisms in flight at once, each on its own stream (worker threads)")
     ap.add_argument("--plates", default="0.1:1.2",
@@ -561,6 +564,7 @@ def bench_c4(args):
     prisms.sort(key=lambda ip: -ip[1]["scatterer"].mask.size)
     lock = threading.Lock()
     lat, solved, iters, errors = {}, [0], [], []
+    first = {}  # prism -> (C_ext, C_sca) of its first waves in the batch, for --c4-compare
 
     def run(pr, stream):
         s, dirs, pols = pr["scatterer"], pr["dirs"], pr["pols"]
@@ -578,9 +582,11 @@ def bench_c4(args):
                 out = prob.solve(dirs[q0:q0 + chunk], pols[q0:q0 + chunk], return_c=False)
                 conv += sum(st["converged"] for st in out["stats"])
                 its += [st["iters"] for st in out["stats"]]
+                if q0 == 0:
+                    ce, cs = out["cext"].copy(), out["csca"].copy()
             stream.synchronize()
             prob.close()
-        return time.perf_counter() - t0, conv, its
+        return time.perf_counter() - t0, conv, its, (ce, cs)
 
     def worker():
         stream = torch.cuda.Stream()
@@ -590,13 +596,14 @@ def bench_c4(args):
                     return
                 i, pr = prisms.pop(0)
             try:
-                t, conv, its = run(pr, stream)
+                t, conv, its, xs = run(pr, stream)
             except Exception as e:  # reported after the join
                 with lock:
                     errors.append(e)
                 return
             with lock:
                 lat[i] = t
+                first[i] = xs
                 solved[0] += conv
                 iters.extend(its)
                 print(f"c4 prism {i} grid {pr['scatterer'].nx}^3: {t:.3f} s ({len(lat)}/{len(cfg['prisms'])})",
@@ -615,13 +622,37 @@ def bench_c4(args):
         raise errors[0]
     lat = [lat[i] for i in sorted(lat)]
     n_rhs = sum(len(pr["dirs"]) for pr in cfg["prisms"])
+    compare = None
+    if args.c4_compare > 0:
+        # the plain FP64 path: the same waves one per solve (solve time only; the batch's rate
+        # includes each prism's setup and build), against the batch's cross sections
+        K = args.c4_compare
+        dev_e, dev_s, t1, n1, its1 = [], [], 0.0, 0, []
+        for i, pr in enumerate(cfg["prisms"]):
+            s, dirs, pols = pr["scatterer"], pr["dirs"], pr["pols"]
+            prob = Problem(torch.from_numpy(s.mask).cuda(), torch.from_numpy(s.eps).cuda(), s.k, s.d,
+                           precond=2, tol=cfg["tol"], restart=30, precision=0, max_rhs=1)
+            prob.build_preconditioner(lattice_factor(dirs, pols)[1])
+            torch.cuda.synchronize()
+            for q in range(min(K, len(dirs))):
+                t0 = time.perf_counter()
+                out = prob.solve(dirs[q:q + 1], pols[q:q + 1], return_c=False)
+                t1 += time.perf_counter() - t0
+                n1 += 1
+                its1.append(out["stats"][0]["iters"])
+                dev_e.append(abs(first[i][0][q] - out["cext"][0]) / abs(out["cext"][0]))
+                dev_s.append(abs(first[i][1][q] - out["csca"][0]) / abs(out["csca"][0]))
+            prob.close()
+        compare = dict(waves_per_prism=K, single_fp64_solves_per_s_solve_only=n1 / t1,
+                       single_iters_mean=float(np.mean(its1)),
+                       max_rel_dev_cext=float(np.max(dev_e)), max_rel_dev_csca=float(np.max(dev_s)))
     _emit(dict(metric="RHS solves/s (batched, to rel. residual 1e-5)", workload="c4",
                value=n_rhs / total, unit="solves/s", higher_is_better=True,
                prisms_per_s=len(lat) / total, total_s=total, rhs_total=n_rhs, rhs_converged=solved[0],
                latency_p50_s=float(np.percentile(lat, 50)), latency_p99_s=float(np.percentile(lat, 99)),
                iters_mean=float(np.mean(iters)), iters_max=int(np.max(iters)),
                grids=[pr["scatterer"].nx for pr in cfg["prisms"]], rhs_chunk=args.c4_chunk,
-               streams=args.c4_streams,
+               streams=args.c4_streams, vs_single_fp64=compare,
                dtype="f64" if args.c4_precision == 0 else "f32 inner / f64 outer", data="synthetic"))
 
 
