@@ -85,6 +85,28 @@ def test_multi_rhs_batch_matches_single_solves():
         assert out["stats"][r]["converged"] == 1
 
 
+@pytest.mark.parametrize("grid,x", [(12, 3.0), (40, 8.0)])
+def test_batch_equals_one_wave_solves_bitwise(grid, x):
+    """A block of waves reproduces, bit for bit, the same waves solved one per call: every
+    per-RHS reduction has a fixed order that does not depend on the block, and a wave's
+    iterations do not depend on the others (the batch benchmark's comparison)."""
+    s = w.hex_prism_grid(x, 0.8, grid, 1.31)
+    dirs, pols = random_waves(6, 78 + grid)
+    sbar = float(np.mean(np.sum((dirs * pols) ** 2, axis=1)))
+    with make_problem(s, precond=2, tol=1e-5, max_rhs=6) as prob:
+        prob.build_preconditioner(sbar)
+        out = prob.solve(dirs, pols)
+    with make_problem(s, precond=2, tol=1e-5, max_rhs=1) as prob:
+        prob.build_preconditioner(sbar)
+        singles = [prob.solve(dirs[r:r + 1], pols[r:r + 1]) for r in range(6)]
+    c = out["c"].cpu().numpy()
+    for r, o in enumerate(singles):
+        assert out["stats"][r]["converged"] == 1 and o["stats"][0]["converged"] == 1
+        assert out["stats"][r]["iters"] == o["stats"][0]["iters"], r
+        assert np.array_equal(c[r], o["c"][0].cpu().numpy()), r
+        assert out["cext"][r] == o["cext"][0] and out["csca"][r] == o["csca"][0], r
+
+
 def test_optical_theorem_on_gpu_lossy():
     s = w.hex_prism_grid(4.0, 1.0, 16, 1.31 + 0.05j)
     dirs, pols = w.plane_wave_z(("y",))
