@@ -39,8 +39,8 @@ __device__ __forceinline__ void green6_d3(double x, double y, double z, double k
 
 // Embedding of K(p, q, s) = d^3 G(p d, q d, s d) on the (2nx, 2ny, 2nz) circulant grid:
 // index i <-> offset i (i < n), i - 2n (i > n); index n (offset +-n, never used) and the
-// origin hold 0.  part = 1 keeps only d^3 Im G (as a real-valued kernel).
-__global__ void k_green_pad(double2 *out, int nx, int ny, int nz, double k, double d, int part) {
+// origin hold 0.
+__global__ void k_green_pad(double2 *out, int nx, int ny, int nz, double k, double d) {
   const long long Lx = 2LL * nx, Ly = 2LL * ny, Lz = 2LL * nz;
   const long long tot = Lx * Ly * Lz;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -55,8 +55,6 @@ __global__ void k_green_pad(double2 *out, int nx, int ny, int nz, double k, doub
     const int q = iy < ny ? iy : iy - 2 * ny;
     const int s = iz < nz ? iz : iz - 2 * nz;
     green6_d3(p * d, q * d, s * d, k, d * d * d, g);
-    if (part == 1)
-      for (int c = 0; c < 6; ++c) g[c] = make_double2(g[c].y, 0.0);
   } else {
     for (int c = 0; c < 6; ++c) g[c] = make_double2(0.0, 0.0);
   }
@@ -64,8 +62,11 @@ __global__ void k_green_pad(double2 *out, int nx, int ny, int nz, double k, doub
 }
 
 // One octant (non-negative offsets) of the padded spectrum: component-major
-// [6][nz+1][ny+1][nx+1], or z-major [ny+1][nx+1][nz+1][6] for the register z pass.
-template <typename TO, bool ZMAJOR>
+// [6][nz+1][ny+1][nx+1], or z-major [ny+1][nx+1][nz+1][6] for the register z pass.  IMAG keeps
+// the imaginary part as a real spectrum: the embedded kernel is even under r -> -r (every
+// component), so its transform is a sum of K against real cosine products, and the imaginary
+// part of the spectrum is exactly the spectrum of d^3 Im G.
+template <typename TO, bool ZMAJOR, bool IMAG = false>
 __global__ void k_extract_octant(const double2 *full, TO *oct, int nx, int ny, int nz) {
   const long long ox_n = nx + 1, oy_n = ny + 1, oz_n = nz + 1;
   const long long per = ox_n * oy_n * oz_n;
@@ -86,21 +87,22 @@ __global__ void k_extract_octant(const double2 *full, TO *oct, int nx, int ny, i
     oz = (int)(rem / (ox_n * oy_n));
   }
   const long long Lx = 2LL * nx, Ly = 2LL * ny, Lz = 2LL * nz;
-  const double2 v = full[c * Lx * Ly * Lz + ((long long)oz * Ly + oy) * Lx + ox];
+  double2 v = full[c * Lx * Ly * Lz + ((long long)oz * Ly + oy) * Lx + ox];
+  if (IMAG) v = make_double2(v.y, 0.0);
   oct[idx] = to_c(v, TO{});
 }
 
 static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
-template <typename TO>
+template <typename TO, bool IMAG = false>
 static void extract_octant(dda_problem *p, const double2 *full, TO *oct) {
   const long long n = 6LL * (p->nx + 1) * (p->ny + 1) * (p->nz + 1);
   if (p->zreg)
-    hipLaunchKernelGGL((k_extract_octant<TO, true>), dim3(nblk(n, 256)), dim3(256), 0, p->st, full,
-                       oct, p->nx, p->ny, p->nz);
+    hipLaunchKernelGGL((k_extract_octant<TO, true, IMAG>), dim3(nblk(n, 256)), dim3(256), 0, p->st,
+                       full, oct, p->nx, p->ny, p->nz);
   else
-    hipLaunchKernelGGL((k_extract_octant<TO, false>), dim3(nblk(n, 256)), dim3(256), 0, p->st, full,
-                       oct, p->nx, p->ny, p->nz);
+    hipLaunchKernelGGL((k_extract_octant<TO, false, IMAG>), dim3(nblk(n, 256)), dim3(256), 0, p->st,
+                       full, oct, p->nx, p->ny, p->nz);
   HIPCHK(hipGetLastError());
 }
 
@@ -326,24 +328,23 @@ void setup_rhs(dda_problem *p, int nrhs, const double *dir, const double *pol, d
   HIPCHK(hipStreamSynchronize(p->st));  // dp is host-local
 }
 
-static void kernel_spectrum(dda_problem *p, int part) {
+// The padded kernel's 3-D spectrum, kept as octants: FP64 and FP32 for the product, and its
+// imaginary part (the spectrum of d^3 Im G) for the scattering sum.
+static void kernel_spectrum(dda_problem *p) {
   const int nx = p->nx, ny = p->ny, nz = p->nz;
   const long long L3 = 8LL * p->N;
   double2 *tmp = nullptr;
   HIPCHK(hipMalloc(&tmp, sizeof(double2) * 6 * L3));
   try {
     hipLaunchKernelGGL(k_green_pad, dim3(nblk(L3, 256)), dim3(256), 0, p->st, tmp, nx, ny, nz, p->k,
-                       p->d, part);
+                       p->d);
     HIPCHK(hipGetLastError());
     fft_rows_plain(p, p->px, tmp, 6LL * (2 * nz) * (2 * ny), 0);
     fft_strided_plain(p, p->py, tmp, 6LL * (2 * nz), 2LL * nx, 0);
     fft_strided_plain(p, p->pz, tmp, 6LL, 4LL * nx * ny, 0);
-    if (part == 0) {
-      extract_octant(p, tmp, p->khat64);
-      extract_octant(p, tmp, p->khat32);
-    } else {
-      extract_octant(p, tmp, p->khatI64);
-    }
+    extract_octant(p, tmp, p->khat64);
+    extract_octant(p, tmp, p->khat32);
+    extract_octant<double2, true>(p, tmp, p->khatI64);
     HIPCHK(hipStreamSynchronize(p->st));
   } catch (...) {
     (void)hipFree(tmp);
@@ -398,10 +399,9 @@ void operator_spectrum_setup(dda_problem *p) {
   p->zreg = zmr_split(nzz, &G, &P) ? 1 : 0;
   HIPCHK(hipMalloc(&p->khat64, sizeof(double2) * oct));
   HIPCHK(hipMalloc(&p->khat32, sizeof(float2) * oct));
-  kernel_spectrum(p, 0);
   // the Im G spectrum of the scattering sum, so that no later call allocates
   HIPCHK(hipMalloc(&p->khatI64, sizeof(double2) * oct));
-  kernel_spectrum(p, 1);
+  kernel_spectrum(p);
   zpass_autotune<double>(p, p->khat64);
   zpass_autotune<float>(p, p->khat32);
   // x / y pass shapes of the operator, on the zero Krylov basis, in the precision the Krylov
