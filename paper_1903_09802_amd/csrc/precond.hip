@@ -1412,9 +1412,17 @@ void precond_build(dda_problem *p, double s_bar) {
     const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
     long long chunk = nmat;
     if (p->psym) {
-      chunk = std::max<long long>(1, (long long)((1ULL << 31) / (msz * esz)));
-      chunk = std::min(chunk, nmat);
-      HIPCHK(hipMalloc(&scratch, esz * chunk * msz));
+      // up to 8 GiB of halves per launch, split evenly: fewer, equal launches leave less of
+      // the GPU idle in their last rounds of workgroups (at 128^3 all 8450 halves in one)
+      const long long per = std::max<long long>(1, (long long)((8ULL << 30) / (msz * esz)));
+      const long long nch = (nmat + per - 1) / per;
+      chunk = (nmat + nch - 1) / nch;
+      while (hipMalloc(&scratch, esz * chunk * msz) != hipSuccess) {
+        (void)hipGetLastError();
+        scratch = nullptr;
+        REQUIRE(chunk > 1, DDA_ENOMEM, "no device memory for one preconditioner block");
+        chunk = (chunk + 1) / 2;
+      }
     }
     const size_t lds_asm = sizeof(double2) * 6 * S;
     set_lds_limit((const void *)k_assemble<double2>, lds_asm);
