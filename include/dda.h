@@ -304,6 +304,10 @@ void dda_destroy(dda_problem *p);
  * are left out.
  */
 dda_status dda_profile_enable(dda_problem *p, int on);
+/* Restrict the timing to launches of kernel kind `name` (as dda_profile_get names it), so
+ * that the other launches carry no events; NULL or "" times every kind again.  Kinds already
+ * collected keep their counts.  EINVAL for a NULL handle. */
+dda_status dda_profile_only(dda_problem *p, const char *name);
 int dda_profile_count(dda_problem *p);
 dda_status dda_profile_get(dda_problem *p, int idx, const char **name, long long *launches,
                            double *total_ms, double *bytes_per_launch);

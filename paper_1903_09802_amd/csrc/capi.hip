@@ -404,6 +404,16 @@ dda_status dda_profile_enable(dda_problem *p, int on) {
   });
 }
 
+dda_status dda_profile_only(dda_problem *p, const char *name) {
+  return guarded([&]() -> dda_status {
+    REQUIRE(p, DDA_EINVAL, "problem is NULL");
+    HIPCHK(hipStreamSynchronize(p->st));
+    p->prof.collect();
+    p->prof.only = name ? name : "";
+    return DDA_OK;
+  });
+}
+
 int dda_profile_count(dda_problem *p) { return p ? (int)p->prof.kinds.size() : 0; }
 
 dda_status dda_profile_get(dda_problem *p, int idx, const char **name, long long *launches,

@@ -186,6 +186,7 @@ inline FftDesc desc(const FftPlan &p) {
 
 struct Profiler {
   bool on = false;
+  std::string only;  // when not empty, only launches of this kind are timed
   struct Kind {
     std::string name;
     std::vector<float> ms;      // duration of every timed launch

@@ -139,6 +139,10 @@ KTimer::KTimer(Profiler *p, hipStream_t s, const char *name, double bytes) : pro
     prof = nullptr;
     return;
   }
+  if (!prof->only.empty() && prof->only != name) {
+    prof = nullptr;
+    return;
+  }
   const int kind = prof->kind_id(name);
   a = prof->get_event();
   b = prof->get_event();

@@ -24,7 +24,8 @@ EXPORTS = (
     "dda_build_preconditioner",
     "dda_solve", "dda_apply_operator", "dda_apply_preconditioner", "dda_cross_sections",
     "dda_cross_sections_noalloc",
-    "dda_grad_cext", "dda_destroy", "dda_profile_enable", "dda_profile_count", "dda_profile_get",
+    "dda_grad_cext", "dda_destroy", "dda_profile_enable", "dda_profile_only", "dda_profile_count",
+    "dda_profile_get",
 )
 
 
@@ -96,6 +97,8 @@ def load(path: str = LIB_PATH):
     L.dda_destroy.restype = None
     L.dda_profile_enable.argtypes = [vp, i]
     L.dda_profile_enable.restype = ip
+    L.dda_profile_only.argtypes = [vp, ctypes.c_char_p]
+    L.dda_profile_only.restype = ip
     L.dda_profile_count.argtypes = [vp]
     L.dda_profile_count.restype = ip
     L.dda_profile_get.argtypes = [vp, i, ctypes.POINTER(ctypes.c_char_p),
@@ -292,6 +295,10 @@ class Problem:
 
     def profile_enable(self, on=True):
         _check(load().dda_profile_enable(self.h, int(bool(on))), False)
+
+    def profile_only(self, name=None):
+        """Time only launches of kernel kind ``name`` (None: every kind)."""
+        _check(load().dda_profile_only(self.h, name.encode() if name else None), False)
 
     def profile(self):
         L = load()

@@ -190,6 +190,7 @@ def test_create_rejects_bad_arguments_before_device_work(lib, dims, k, d, status
 def test_null_handle_calls(lib):
     assert lib.dda_build_preconditioner(None, 0.0) == -1
     assert lib.dda_profile_count(None) == 0
+    assert lib.dda_profile_only(None, b"pc_gemv_f64") == -1
     lib.dda_destroy(None)
 
 
