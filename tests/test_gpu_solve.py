@@ -107,6 +107,29 @@ def test_batch_equals_one_wave_solves_bitwise(grid, x):
         assert out["cext"][r] == o["cext"][0] and out["csca"][r] == o["csca"][0], r
 
 
+def test_fp32_refined_batch_matches_fp64_one_wave_solves():
+    """The FP32-refined form on a block of waves against the plain FP64 path (one wave per
+    solve) at the same tolerance: the same solution to that tolerance."""
+    s = w.hex_prism_grid(6.0, 1.0, 24, 1.31)
+    dirs, pols = random_waves(8, 91)
+    sbar = float(np.mean(np.sum((dirs * pols) ** 2, axis=1)))
+    tol = 1e-8
+    with make_problem(s, precond=2, tol=tol, max_rhs=8, precision=1) as prob:
+        prob.build_preconditioner(sbar)
+        out = prob.solve(dirs, pols)
+    with make_problem(s, precond=2, tol=tol, max_rhs=1) as prob:
+        prob.build_preconditioner(sbar)
+        singles = [prob.solve(dirs[r:r + 1], pols[r:r + 1]) for r in range(8)]
+    c = out["c"].cpu().numpy()
+    for r, o in enumerate(singles):
+        assert out["stats"][r]["converged"] == 1 and o["stats"][0]["converged"] == 1
+        assert out["stats"][r]["rel_residual"] <= tol
+        # both solutions are within the system's conditioning of the exact one
+        assert rel_err(c[r], o["c"][0].cpu().numpy()) < 1e-5, r
+        assert abs(out["cext"][r] - o["cext"][0]) < 1e-6 * abs(o["cext"][0]), r
+        assert abs(out["csca"][r] - o["csca"][0]) < 1e-6 * abs(o["csca"][0]), r
+
+
 def test_optical_theorem_on_gpu_lossy():
     s = w.hex_prism_grid(4.0, 1.0, 16, 1.31 + 0.05j)
     dirs, pols = w.plane_wave_z(("y",))
