@@ -1828,7 +1828,8 @@ __device__ __forceinline__ void gemv_store(cplx<T> *W, const GemvMode &g, T e0, 
 // 2 n2 x 16 each), with 16 x 16 x 4 MFMAs; each tile fragment feeds all NCB blocks.  Wave w
 // computes tile rows I = w, w + NW, ...; step s pairs row I with J = (s - I) mod ntr, taking the
 // stored tile (I, J) directly or (J, I) transposed, so the two rows that share a stored tile
-// read it in the same step.  Tiles are fetched three steps ahead of their use.
+// read it in the same step.  Tiles are fetched three steps ahead of their use (one step in
+// FP64 with four column blocks).
 template <typename T, int NWMAX, int NCB>
 __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const cplx<T> *__restrict__ pk,
                                                              int nx, int ny, int nzw, int z0, int nz,
@@ -1886,14 +1887,17 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
           }
         }
       };
-      V buf[4][4];
+      // D - 1 tiles in flight; FP64 with four column blocks keeps one (three would spill)
+      constexpr int D = (sizeof(T) == 8 && NCB >= 4) ? 2 : 4;
+      V buf[D][4];
       fetch(0, buf[0]);
-      if (1 < ntr) fetch(1, buf[1]);
-      if (2 < ntr) fetch(2, buf[2]);
-      for (int s = 0; s < ntr; s += 4) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          if (s + b + 3 < ntr) fetch(s + b + 3, buf[(b + 3) & 3]);
+      for (int d = 1; d < D - 1; ++d)
+        if (d < ntr) fetch(d, buf[d]);
+      for (int s = 0; s < ntr; s += D) {
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+          if (s + b + D - 1 < ntr) fetch(s + b + D - 1, buf[(b + D - 1) % D]);
           if (s + b < ntr) mac(s + b, buf[b]);
         }
       }
@@ -1950,7 +1954,7 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
       // column blocks stream each tile once for more right-hand sides, as LDS allows
       const int n2p = 16 * p->ntr;
       auto lds_of = [&](int ncb) { return (size_t)2 * 8 * ncb * n2p * sizeof(cplx<T>); };
-      int ncb = nrhs <= 2 ? 1 : (nrhs <= 4 || sizeof(T) == 8) ? 2 : 4;  // FP64: 4 would spill
+      int ncb = nrhs <= 2 ? 1 : nrhs <= 4 ? 2 : 4;
       while (ncb > 1 && lds_of(ncb) > kLdsMax) ncb /= 2;
       const int rc = std::max(1, std::min(2 * ncb, nrhs));
       const long long nchunks = (nrhs + rc - 1) / rc;
@@ -1963,7 +1967,7 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
       {
       auto fn = ncb == 1 ? k_pc_gemv_mfma<T, 12, 1>
                 : ncb == 2 ? k_pc_gemv_mfma<T, 12, 2>
-                           : k_pc_gemv_mfma<T, 12, sizeof(T) == 8 ? 2 : 4>;
+                           : k_pc_gemv_mfma<T, 12, 4>;
       set_lds_limit((const void *)fn, lds);
       hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
                          p->umx, p->hh, p->n2, p->ntr, nrhs, rc, nchunks, U, p->act);
