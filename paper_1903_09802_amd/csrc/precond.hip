@@ -1828,8 +1828,8 @@ __device__ __forceinline__ void gemv_store(cplx<T> *W, const GemvMode &g, T e0, 
 // 2 n2 x 16 each), with 16 x 16 x 4 MFMAs; each tile fragment feeds all NCB blocks.  Wave w
 // computes tile rows I = w, w + NW, ...; step s pairs row I with J = (s - I) mod ntr, taking the
 // stored tile (I, J) directly or (J, I) transposed, so the two rows that share a stored tile
-// read it in the same step.  Tiles are fetched three steps ahead of their use (one step in
-// FP64 with four column blocks).
+// read it in the same step.  Tiles are fetched three steps ahead of their use (one step with
+// four column blocks in FP64, eight in FP32).
 template <typename T, int NWMAX, int NCB>
 __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const cplx<T> *__restrict__ pk,
                                                              int nx, int ny, int nzw, int z0, int nz,
@@ -1887,8 +1887,8 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
           }
         }
       };
-      // D - 1 tiles in flight; FP64 with four column blocks keeps one (three would spill)
-      constexpr int D = (sizeof(T) == 8 && NCB >= 4) ? 2 : 4;
+      // D - 1 tiles in flight; FP64 with four column blocks and FP32 with eight keep one
+      constexpr int D = ((sizeof(T) == 8 && NCB >= 4) || NCB >= 8) ? 2 : 4;
       V buf[D][4];
       fetch(0, buf[0]);
 #pragma unroll
@@ -1954,7 +1954,7 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
       // column blocks stream each tile once for more right-hand sides, as LDS allows
       const int n2p = 16 * p->ntr;
       auto lds_of = [&](int ncb) { return (size_t)2 * 8 * ncb * n2p * sizeof(cplx<T>); };
-      int ncb = nrhs <= 2 ? 1 : nrhs <= 4 ? 2 : 4;
+      int ncb = nrhs <= 2 ? 1 : nrhs <= 4 ? 2 : (nrhs <= 8 || sizeof(T) == 8) ? 4 : 8;
       while (ncb > 1 && lds_of(ncb) > kLdsMax) ncb /= 2;
       const int rc = std::max(1, std::min(2 * ncb, nrhs));
       const long long nchunks = (nrhs + rc - 1) / rc;
@@ -1967,7 +1967,8 @@ static void pc_apply(dda_problem *p, int nrhs, const double2 *x, double2 *y, con
       {
       auto fn = ncb == 1 ? k_pc_gemv_mfma<T, 12, 1>
                 : ncb == 2 ? k_pc_gemv_mfma<T, 12, 2>
-                           : k_pc_gemv_mfma<T, 12, 4>;
+                : ncb == 4 ? k_pc_gemv_mfma<T, 12, 4>
+                           : k_pc_gemv_mfma<T, 12, sizeof(T) == 8 ? 4 : 8>;
       set_lds_limit((const void *)fn, lds);
       hipLaunchKernelGGL(fn, grid, dim3(threads), lds, p->st, W, binv, nx, ny, nz, p->pz0, p->pbz,
                          p->umx, p->hh, p->n2, p->ntr, nrhs, rc, nchunks, U, p->act);
