@@ -1828,8 +1828,7 @@ __device__ __forceinline__ void gemv_store(cplx<T> *W, const GemvMode &g, T e0, 
 // 2 n2 x 16 each), with 16 x 16 x 4 MFMAs; each tile fragment feeds all NCB blocks.  Wave w
 // computes tile rows I = w, w + NW, ...; step s pairs row I with J = (s - I) mod ntr, taking the
 // stored tile (I, J) directly or (J, I) transposed, so the two rows that share a stored tile
-// read it in the same step.  Tiles are fetched three steps ahead of their use (one step with
-// four column blocks in FP64, eight in FP32).
+// read it in the same step.  Tiles are fetched up to three steps ahead of their use.
 template <typename T, int NWMAX, int NCB>
 __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const cplx<T> *__restrict__ pk,
                                                              int nx, int ny, int nzw, int z0, int nz,
@@ -1887,8 +1886,10 @@ __global__ void __launch_bounds__(64 * NWMAX) k_pc_gemv_mfma(cplx<T> *W, const c
           }
         }
       };
-      // D - 1 tiles in flight; FP64 with four column blocks and FP32 with eight keep one
-      constexpr int D = ((sizeof(T) == 8 && NCB >= 4) || NCB >= 8) ? 2 : 4;
+      // D - 1 tiles in flight: three; two in FP64 with one column block (measured faster);
+      // one in FP64 with four column blocks and FP32 with eight (more would spill)
+      constexpr int D = ((sizeof(T) == 8 && NCB >= 4) || NCB >= 8) ? 2
+                        : (sizeof(T) == 8 && NCB == 1) ? 3 : 4;
       V buf[D][4];
       fetch(0, buf[0]);
 #pragma unroll
